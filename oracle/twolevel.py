@@ -1,0 +1,366 @@
+"""The spatiotemporal two-level method (paper Sections 3 and 4, Algorithm 1).
+
+Global (coarse) temperature T+ lives on the whole plate Omega+; local (fine)
+temperature T- lives on a window Omega- that follows the laser (Section 5.2
+moves the local mesh with the beam).  Within macro step t_n -> t_n + Dt:
+
+  1. place the window (rule below); on a move, copy the overlap of the old
+     fine field and fill newly covered fine nodes by trilinear interpolation
+     P of the coarse field (the paper moves the local mesh without any other
+     projection, Section 5.2);
+  2. predictor: one coarse implicit step over all elements with the load
+     averaged over the macro step, giving the intermediate T~+ (Algorithm 1);
+  3. micro steps j = 1..m-1: fine implicit steps of size dt = Dt/m whose
+     Dirichlet data on the immersed window boundary gamma_D blend the two
+     coarse fields, (1 - j/m) P T+^n + (j/m) P T~+ (the time-local problem of
+     Section 4);
+  4. correction at t_n + Dt: the two-level iteration of Section 3, solved
+     "possibly relaxed, until convergence".
+
+Readings adopted where the paper is silent, ambiguous or garbled:
+  * Indexing of Algorithm 1: its loop "i = 0..m-1 at t_n + i dt" is read as
+    implicit steps landing at t_n + j dt, j = 1..m-1, with boundary data at
+    the new time level; step j = m is the coupled correction.  With m = 1
+    there are no intermediate steps.
+  * Discrete two-level iteration: Dirichlet-Neumann.  The local problem takes
+    T- = T+ on gamma_D (Section 3, zero temperature jump); the global problem
+    is solved on the elements outside the window, with the coarse nodes
+    strictly inside the window fixed to the local solution and the local
+    side's reaction flux entering the coarse interface rows through the
+    transpose of P -- the discrete form of the interface functional xi_gamma
+    and of the zero flux jump (Section 3).  Both levels use the same material
+    law, so the alternate formulation's jump term (kappa+ - kappa-) vanishes;
+    this reading keeps the paper's statement that equal global and local
+    steps reproduce the single-level solution (Section 5.1).
+  * The interface load averages the reactions of all m micro steps (not only
+    the last), which makes the energy ledger exact for every m.
+  * Relaxation lambda <- lambda + theta (lambda' - lambda), with either a
+    fixed theta or (default) Aitken's delta-squared rule started from
+    r/(r+1); stopped when max |lambda' - lambda| <= dn_tol.  Any relaxation
+    converges to the same fixed point.
+  * Latent heat is kept on both levels (one material law).
+  * Window rule: whole coarse cells, flush with the top, centred on the beam
+    across the scan direction; along it the beam position at t_{n+1} sits one
+    third of the window length behind the leading edge; clamped inside the
+    plate; kept in place while the beam is off.
+  * Coarse load: the time average of the surface loads at the m micro times
+    (the intent of the paper's smeared global source, Section 5.2).
+"""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import grid as G
+from . import laser as L
+from . import material as M
+from .level import implicit_step, NoConvergence
+
+
+class Window:
+    """Geometry of one window position: fine grid, node classes, transfers."""
+
+    def __init__(self, coarse, mesh, I0, J0):
+        r = mesh.refine
+        self.I0, self.J0 = I0, J0
+        self.K0 = mesh.nz - mesh.win_nz
+        self.wx, self.wy, self.wz = mesh.win_nx, mesh.win_ny, mesh.win_nz
+        c = coarse
+        self.fine = G.Grid(r * self.wx, r * self.wy, r * self.wz,
+                           c.hx / r, c.hy / r, c.hz / r,
+                           I0 * c.hx, J0 * c.hy, self.K0 * c.hz)
+        f = self.fine
+        # which window faces are immersed (not on the plate boundary)
+        self.face_x0 = I0 > 0
+        self.face_x1 = I0 + self.wx < mesh.nx
+        self.face_y0 = J0 > 0
+        self.face_y1 = J0 + self.wy < mesh.ny
+        self.face_z0 = self.K0 > 0
+        # fine node classes
+        fi, fj, fk = f.node_ijk()
+        # a window reaching the plate bottom has its bottom row fixed at
+        # T_bottom; such nodes count as bottom, not as interface, nodes
+        self.bottom_f = (fk == 0) & (self.K0 == 0)
+        self.gamma_f = ((self.face_x0 & (fi == 0)) | (self.face_x1 & (fi == f.nx))
+                        | (self.face_y0 & (fj == 0)) | (self.face_y1 & (fj == f.ny))
+                        | (self.face_z0 & (fk == 0))) & ~self.bottom_f
+        self.dir_f = self.gamma_f | self.bottom_f
+        # coarse node classes
+        ci, cj, ck = c.node_ijk()
+        inwin = ((ci >= I0) & (ci <= I0 + self.wx) & (cj >= J0) & (cj <= J0 + self.wy)
+                 & (ck >= self.K0))
+        on_gamma = ((self.face_x0 & (ci == I0)) | (self.face_x1 & (ci == I0 + self.wx))
+                    | (self.face_y0 & (cj == J0)) | (self.face_y1 & (cj == J0 + self.wy))
+                    | (self.face_z0 & (ck == self.K0)))
+        self.gamma_c = inwin & on_gamma
+        self.interior_c = inwin & ~on_gamma
+        # coarse elements outside the window, coarse top faces outside it
+        ei, ej, ek = c.elem_ijk()
+        e_in = ((ei >= I0) & (ei < I0 + self.wx) & (ej >= J0) & (ej < J0 + self.wy)
+                & (ek >= self.K0))
+        self.outside_e = (~e_in).astype(np.float64)
+        fj2, fi2 = np.meshgrid(np.arange(c.ny), np.arange(c.nx), indexing="ij")
+        fi2, fj2 = fi2.ravel(), fj2.ravel()
+        self.outside_face = ~((fi2 >= I0) & (fi2 < I0 + self.wx)
+                              & (fj2 >= J0) & (fj2 < J0 + self.wy))
+        self.mass_out = G.lumped_mass(c, self.outside_e)
+        self.mass_f = G.lumped_mass(f)
+        # injection: coarse window-interior node -> fine node at its position
+        idx = np.flatnonzero(self.interior_c)
+        self.inject_c = idx
+        self.inject_f = f.node(r * (ci[idx] - I0), r * (cj[idx] - J0), r * (ck[idx] - self.K0))
+        self.P = prolongation(c, f, r, I0, J0, self.K0)
+
+
+def prolongation(coarse, fine, r, I0, J0, K0):
+    """Trilinear interpolation P from coarse nodes to the fine nodes of a
+    window whose fine grid starts at coarse node (I0, J0, K0); n_fine x
+    n_coarse sparse matrix."""
+    fi, fj, fk = fine.node_ijk()
+    axes = []
+    for loc, start, ncell in ((fi, I0, coarse.nx), (fj, J0, coarse.ny), (fk, K0, coarse.nz)):
+        g = r * start + loc                      # global fine index on this axis
+        cell = np.minimum(g // r, ncell - 1)     # coarse cell containing it
+        frac = (g - cell * r) / r                # position inside that cell
+        axes.append((cell, frac))
+    rows, cols, vals = [], [], []
+    for g_ in (0, 1):
+        for b in (0, 1):
+            for a in (0, 1):
+                (cx, fx), (cy, fy), (cz, fz) = axes
+                w = ((fx if a else 1.0 - fx) * (fy if b else 1.0 - fy)) * (fz if g_ else 1.0 - fz)
+                rows.append(np.arange(fine.n_nodes))
+                cols.append(coarse.node(cx + a, cy + b, cz + g_))
+                vals.append(w)
+    P = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(fine.n_nodes, coarse.n_nodes))
+    return P
+
+
+def window_origin(mesh, coarse, scan, t, current=None):
+    """Window position (I0, J0) in coarse cells for beam time t (rule in the
+    module docstring).  Returns `current` when the beam is off."""
+    spot = L.laser_at(scan, t)
+    if spot is None:
+        if current is not None:
+            return current
+        tr = scan.tracks[0]
+        spot = (tr.x0, tr.y0, tr.power, tr.radius, tr.absorptivity, 0)
+    xc, yc, k = spot[0], spot[1], spot[5]
+    tr = scan.tracks[k]
+    dx, dy = tr.x1 - tr.x0, tr.y1 - tr.y0
+    wx_len = mesh.win_nx * coarse.hx
+    wy_len = mesh.win_ny * coarse.hy
+    if abs(dx) >= abs(dy):
+        lead = (2.0 / 3.0) if dx >= 0 else (1.0 / 3.0)
+        x_lo = xc - lead * wx_len
+        y_lo = yc - 0.5 * wy_len
+    else:
+        lead = (2.0 / 3.0) if dy >= 0 else (1.0 / 3.0)
+        x_lo = xc - 0.5 * wx_len
+        y_lo = yc - lead * wy_len
+    I0 = int(math.floor(x_lo / coarse.hx + 0.5))
+    J0 = int(math.floor(y_lo / coarse.hy + 0.5))
+    I0 = min(max(I0, 0), mesh.nx - mesh.win_nx)
+    J0 = min(max(J0, 0), mesh.ny - mesh.win_ny)
+    return (I0, J0)
+
+
+def coarse_grid(mesh):
+    return G.Grid(mesh.nx, mesh.ny, mesh.nz, mesh.lx / mesh.nx, mesh.ly / mesh.ny,
+                  mesh.lz / mesh.nz)
+
+
+def micro_time(scan, opts, n, j):
+    """Time of micro step j (0..m) of macro step n."""
+    return scan.t_start + n * opts.dt_coarse + j * (opts.dt_coarse / opts.m_time)
+
+
+class TwoLevel:
+    """State and macro step of the spatiotemporal two-level method."""
+
+    def __init__(self, wl, newton_tol=None, dn_tol=None):
+        self.wl = wl
+        mesh, mat, opts = wl.mesh, wl.material, wl.options
+        if mesh.win_nx > mesh.nx or mesh.win_ny > mesh.ny or mesh.win_nz > mesh.nz:
+            raise ValueError("window larger than the plate")
+        self.mesh, self.mat, self.scan, self.opts = mesh, mat, wl.scan, opts
+        self.newton_tol = opts.newton_tol if newton_tol is None else newton_tol
+        self.dn_tol = opts.dn_tol if dn_tol is None else dn_tol
+        r = mesh.refine
+        self.fixed_theta = opts.dn_theta > 0
+        self.theta = opts.dn_theta if self.fixed_theta else r / (r + 1.0)
+        self.coarse = coarse_grid(mesh)
+        c = self.coarse
+        _, _, ck = c.node_ijk()
+        self.bottom_c = ck == 0
+        self.Tc = np.full(c.n_nodes, mat.T_init)
+        self.Tc[self.bottom_c] = mat.T_bottom
+        self.n = 0
+        origin = window_origin(mesh, c, self.scan, micro_time(self.scan, opts, 1, 0))
+        self.win = Window(c, mesh, *origin)
+        self.Tf = np.full(self.win.fine.n_nodes, mat.T_init)
+        self.Tf[self.win.bottom_f] = mat.T_bottom
+        self.ledger = dict(stored=self.energy(), absorbed=0.0, bottom=0.0, remap=0.0,
+                           stored0=0.0)
+        self.ledger["stored0"] = self.ledger["stored"]
+        self.stats = dict(newton_fine=0, newton_coarse=0, dn_iters=0, moves=0,
+                          fine_solves=0, coarse_solves=0)
+        self.history = []
+
+    # -- energy ledger ------------------------------------------------------
+    def energy(self):
+        """E = sum_J m_J^out H(T+_J) + sum_k m_k H(T-_k)."""
+        w = self.win
+        return float(np.dot(w.mass_out, M.enthalpy(self.Tc, self.mat))
+                     + np.dot(w.mass_f, M.enthalpy(self.Tf, self.mat)))
+
+    # -- window move --------------------------------------------------------
+    def move_window(self, origin):
+        old, mesh = self.win, self.mesh
+        new = Window(self.coarse, mesh, *origin)
+        r = mesh.refine
+        f = new.fine
+        fi, fj, fk = f.node_ijk()
+        oi = fi + r * (new.I0 - old.I0)
+        oj = fj + r * (new.J0 - old.J0)
+        inside_old = (oi >= 0) & (oi <= old.fine.nx) & (oj >= 0) & (oj <= old.fine.ny)
+        Tnew = new.P @ self.Tc
+        Tnew[inside_old] = self.Tf[old.fine.node(oi[inside_old], oj[inside_old], fk[inside_old])]
+        self.win = new
+        self.Tf = Tnew
+        self.stats["moves"] += 1
+
+    def relaxation(self, it, d, d_prev, theta):
+        """Relaxation factor of interface update `it` (1-based) given the
+        interface residual d = lambda' - lambda and the previous one.  Fixed
+        theta when dn_theta > 0, else Aitken's delta-squared rule
+            theta_k = -theta_{k-1} <d_{k-1}, d_k - d_{k-1}> / |d_k - d_{k-1}|^2
+        started from r/(r+1)."""
+        if self.fixed_theta or it == 1:
+            return theta
+        dd = d - d_prev
+        den = float(dd @ dd)
+        if den <= 0.0:
+            return theta
+        return -theta * float(d_prev @ dd) / den
+
+    # -- one macro step (Algorithm 1) ----------------------------------------
+    def fine_step(self, T_prev, tau, load, g, guess=None):
+        w = self.win
+        vals = np.where(w.bottom_f, self.mat.T_bottom, g)
+        T, R, it = implicit_step(w.fine, self.mat, T_prev, tau, load, None, w.dir_f, vals,
+                                 T_guess=guess, tol=self.newton_tol, maxit=self.opts.newton_max)
+        self.stats["newton_fine"] += it
+        self.stats["fine_solves"] += 1
+        return T, R
+
+    def step(self):
+        mesh, opts, scan, mat = self.mesh, self.opts, self.scan, self.mat
+        n, m, Dt = self.n, opts.m_time, opts.dt_coarse
+        dt = Dt / m
+        c = self.coarse
+        origin = window_origin(mesh, c, scan, micro_time(scan, opts, n + 1, 0),
+                               current=(self.win.I0, self.win.J0))
+        if origin != (self.win.I0, self.win.J0):
+            e0 = self.energy()
+            self.move_window(origin)
+            self.ledger["remap"] += self.energy() - e0
+        w = self.win
+        E_start = self.energy()
+        spots = [L.laser_at(scan, micro_time(scan, opts, n, j)) for j in range(1, m + 1)]
+        Fc_all = sum(L.top_load(c, s, opts.face_quad) for s in spots) / m
+        Fc_out = sum(L.top_load(c, s, opts.face_quad, w.outside_face) for s in spots) / m
+        # predictor over the whole plate
+        Tpred, _, it = implicit_step(c, mat, self.Tc, Dt, Fc_all, None, self.bottom_c,
+                                     np.full(c.n_nodes, mat.T_bottom), tol=self.newton_tol,
+                                     maxit=opts.newton_max)
+        self.stats["newton_coarse"] += it
+        self.stats["coarse_solves"] += 1
+        PTn = w.P @ self.Tc
+        PTp = w.P @ Tpred
+        T_prev = self.Tf
+        rho_sum = np.zeros(w.fine.n_nodes)
+        absorbed = 0.0
+        bottom = 0.0
+        for j in range(1, m):
+            g = (1.0 - j / m) * PTn + (j / m) * PTp
+            Ff = L.top_load(w.fine, spots[j - 1], opts.face_quad)
+            T_prev, R = self.fine_step(T_prev, dt, Ff, g)
+            rho_sum[w.gamma_f] += R[w.gamma_f]
+            bottom -= dt * R[w.bottom_f].sum()
+            absorbed += dt * Ff.sum()
+        # two-level correction at t_{n+1}
+        Ff = L.top_load(w.fine, spots[m - 1], opts.face_quad)
+        lam = Tpred.copy()
+        dir_c = self.bottom_c | w.interior_c
+        guess_f, guess_c = T_prev, Tpred
+        d_prev, theta = None, self.theta
+        for it in range(1, opts.dn_max + 1):
+            Tf_m, R_m = self.fine_step(T_prev, dt, Ff, w.P @ lam, guess_f)
+            rho = np.where(w.gamma_f, rho_sum + R_m, 0.0)
+            ext = -(w.P.T @ rho) / m
+            vals = np.full(c.n_nodes, mat.T_bottom)
+            vals[w.inject_c] = Tf_m[w.inject_f]
+            Tc_new, Rc, itc = implicit_step(c, mat, self.Tc, Dt, Fc_out + ext, w.outside_e,
+                                            dir_c, vals, T_guess=guess_c, tol=self.newton_tol,
+                                            maxit=opts.newton_max)
+            self.stats["newton_coarse"] += itc
+            self.stats["coarse_solves"] += 1
+            d = np.where(w.gamma_c, Tc_new - lam, 0.0)
+            diff = float(np.max(np.abs(d)))
+            theta = self.relaxation(it, d, d_prev, theta)
+            d_prev = d
+            lam = lam + theta * d
+            guess_f, guess_c = Tf_m, Tc_new
+            if diff <= self.dn_tol:
+                break
+        else:
+            raise NoConvergence("two-level iteration did not converge")
+        self.stats["dn_iters"] += it
+        bottom -= dt * R_m[w.bottom_f].sum()
+        absorbed += dt * Ff.sum()
+        bottom -= Dt * Rc[self.bottom_c].sum()
+        absorbed += Dt * Fc_out.sum()
+        self.Tc = Tc_new
+        self.Tf = Tf_m
+        self.n += 1
+        E_end = self.energy()
+        self.ledger["stored"] = E_end
+        self.ledger["absorbed"] += absorbed
+        self.ledger["bottom"] += bottom
+        self.history.append(dict(n=self.n, E_start=E_start, E_end=E_end, absorbed=absorbed,
+                                 bottom=bottom, dn_iters=it, origin=(w.I0, w.J0)))
+
+    def run(self, n_macro):
+        for _ in range(n_macro):
+            self.step()
+        return self
+
+    def fine_origin(self):
+        r = self.mesh.refine
+        return (r * self.win.I0, r * self.win.J0, r * self.win.K0)
+
+
+def run(wl, n_macro=None, **kw):
+    sim = TwoLevel(wl, **kw)
+    sim.run(wl.n_macro if n_macro is None else n_macro)
+    return sim
+
+
+def single_level_run(grid, mat, scan, dt, n_steps, t_start=None, nq=3, tol=1e-10, T0=None):
+    """Plain backward-Euler run of one level over all elements with Dirichlet
+    T_bottom at z = z0 and the surface load at each new time level.  Returns
+    the list of nodal fields after every step."""
+    _, _, k = grid.node_ijk()
+    bottom = k == 0
+    T = np.full(grid.n_nodes, mat.T_init) if T0 is None else np.array(T0, dtype=np.float64)
+    T[bottom] = mat.T_bottom
+    t0 = scan.t_start if t_start is None else t_start
+    out = []
+    for s in range(1, n_steps + 1):
+        F = L.top_load(grid, L.laser_at(scan, t0 + s * dt), nq)
+        T, _, _ = implicit_step(grid, mat, T, dt, F, None, bottom,
+                                np.full(grid.n_nodes, mat.T_bottom), tol=tol)
+        out.append(T.copy())
+    return out

@@ -1,0 +1,21 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds plain data only: problem descriptions (mesh, material,
+scan path, solver options) and the seeded random draws that build them.  It
+contains none of the method's arithmetic (no enthalpy, no element matrices,
+no laser flux, no window rule), so both the CPU oracle and the GPU binding
+can read it without sharing any computation.
+
+The five workloads mirror the method's single-track / raster / served /
+large-build cases on a laser powder-bed plate (Section 5 of the paper
+describes the single-track and multi-track experiments this imitates).
+"""
+from .spec import (Mesh, Material, Track, ScanPath, Options, Workload,
+                   FP64, MIXED, default_material)
+from .configs import (config0, config1, config2, config3_requests, config4,
+                      by_name, small_cases, k2_sweep_field)
+
+__all__ = ["Mesh", "Material", "Track", "ScanPath", "Options", "Workload",
+           "FP64", "MIXED", "default_material", "config0", "config1",
+           "config2", "config3_requests", "config4", "by_name",
+           "small_cases", "k2_sweep_field"]

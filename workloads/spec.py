@@ -1,0 +1,99 @@
+"""Plain records describing one thermal simulation request."""
+from dataclasses import dataclass, field, replace
+from typing import List
+
+FP64 = 0
+MIXED = 1
+
+
+@dataclass
+class Mesh:
+    """Coarse box [0,lx]x[0,ly]x[0,lz] (metres, z up, laser on z = lz) with
+    nx x ny x nz Q1 cells, and the fine window: win_* coarse cells refined
+    `refine` times per axis, flush with the top surface."""
+    lx: float
+    ly: float
+    lz: float
+    nx: int
+    ny: int
+    nz: int
+    refine: int
+    win_nx: int
+    win_ny: int
+    win_nz: int
+
+
+@dataclass
+class Material:
+    """rho [kg/m3]; c(T) and kappa(T) linear on [T_lo, T_hi], constant
+    outside; latent heat [J/kg] released by a tanh sigmoid of the given
+    sharpness [1/K] centred between T_sol and T_liq; temperatures in K."""
+    rho: float = 8000.0
+    T_lo: float = 300.0
+    T_hi: float = 1563.0
+    c_lo: float = 450.0
+    c_hi: float = 700.0
+    k_lo: float = 10.0
+    k_hi: float = 30.0
+    latent: float = 2.7e5
+    T_sol: float = 1563.0
+    T_liq: float = 1623.0
+    sharpness: float = 0.05
+    pc_kind: int = 0
+    T_init: float = 300.0
+    T_bottom: float = 300.0
+
+
+def default_material(**kw):
+    return replace(Material(), **kw)
+
+
+@dataclass
+class Track:
+    """Straight laser pass from (x0,y0) to (x1,y1) on the top surface at
+    `speed` [m/s], beam power [W], radius [m] and absorptivity."""
+    x0: float
+    y0: float
+    x1: float
+    y1: float
+    speed: float
+    power: float
+    radius: float
+    absorptivity: float
+
+
+@dataclass
+class ScanPath:
+    tracks: List[Track]
+    t_start: float = 0.0
+
+
+@dataclass
+class Options:
+    """Macro step dt_coarse [s] split into m_time micro steps; arithmetic of
+    the fine linear solves (FP64 or MIXED); Gauss points per face direction
+    for the laser load; tolerances (kelvin for Newton and the two-level
+    iteration, relative for CG); two-level relaxation theta (<= 0 selects
+    refine/(refine+1)); iteration caps."""
+    dt_coarse: float
+    m_time: int
+    precision: int = FP64
+    face_quad: int = 3
+    newton_tol: float = 1e-9
+    cg_rtol: float = 1e-10
+    dn_tol: float = 1e-9
+    dn_theta: float = 0.0
+    newton_max: int = 30
+    cg_max: int = 500
+    dn_max: int = 60
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    material: Material
+    scan: ScanPath
+    options: Options
+    n_macro: int
+    meta: dict = field(default_factory=dict)
