@@ -1,0 +1,185 @@
+/*
+ * tl.h -- C interface of the MI355X (gfx950) spatiotemporal two-level thermal
+ * solver for laser powder-bed fusion (arXiv 2110.12932).
+ *
+ * The library advances a global (coarse) temperature field on the whole plate
+ * and a local (fine) field on a window that follows the laser, with m implicit
+ * micro steps of the fine level per coarse macro step (the paper's
+ * Algorithm 1, Section 4).  Every step of the path runs in the library's HIP
+ * kernels; the caller supplies device memory and a HIP stream.
+ *
+ * Units are SI throughout (m, s, K, W, J, kg).  All calls return a tl_status;
+ * a description of the last failure on the calling thread is available from
+ * tl_last_error().  Calls are synchronous with respect to the host: they return
+ * after the work they queued on the caller's stream has finished.  A handle
+ * must not be used from two host threads at once.
+ */
+#ifndef TL_H
+#define TL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TL_OK = 0,
+  TL_EINVAL = -1,   /* invalid argument; nothing was queued on the device    */
+  TL_ENOMEM = -2,   /* workspace or host buffer too small                    */
+  TL_EDEVICE = -3,  /* a HIP runtime call failed                             */
+  TL_ENOCONV = -4,  /* Newton, CG or the two-level iteration did not converge
+                       within its cap; the state is rolled back to the last
+                       completed macro step                                  */
+  TL_ESTATE = -5,   /* call not valid in the handle's current state          */
+  TL_EBUSY = -6     /* server queue or slots are full                        */
+} tl_status;
+
+/* Arithmetic of the linear solves inside each Newton iteration.  The nonlinear
+ * residual, the Dirichlet data, the coarse level and the energy ledger are
+ * always FP64. */
+typedef enum { TL_FP64 = 0, TL_MIXED = 1 } tl_precision;
+
+/* Coarse plate [0,lx]x[0,ly]x[0,lz] with nx x ny x nz Q1 cells (spacing
+ * lx/nx, ly/ny, lz/nz; z up, laser on z = lz, Dirichlet T_bottom on z = 0,
+ * insulated elsewhere).  The fine window covers win_nx x win_ny x win_nz
+ * coarse cells, flush with the top surface, each refined `refine` times per
+ * axis (refine >= 1).  Requires 1 <= win_* <= n*. */
+typedef struct {
+  double lx, ly, lz;
+  int nx, ny, nz;
+  int refine;
+  int win_nx, win_ny, win_nz;
+} tl_mesh;
+
+/* Material law (paper Section 2): constant density rho; heat capacity c and
+ * conductivity kappa linear between (T_lo, c_lo / k_lo) and (T_hi, c_hi /
+ * k_hi) and constant outside; latent heat `latent` [J/kg] released by the
+ * sigmoid f_pc = (1 + tanh(sharpness (T - (T_sol + T_liq)/2))) / 2.
+ * pc_kind must be 0 (the sigmoid).  T_init is the initial temperature of the
+ * plate, T_bottom the fixed temperature of its bottom face. */
+typedef struct {
+  double rho, T_lo, T_hi, c_lo, c_hi, k_lo, k_hi;
+  double latent, T_sol, T_liq, sharpness;
+  int pc_kind;
+  double T_init, T_bottom;
+} tl_material;
+
+/* One straight laser pass from (x0,y0) to (x1,y1) on the top surface at
+ * `speed`.  The absorbed flux is the surface Gaussian
+ *   q = 3 absorptivity power / (pi radius^2) exp(-3 r^2 / radius^2)
+ * (the exponent convention of the paper's source terms, Section 5.2). */
+typedef struct {
+  double x0, y0, x1, y1, speed, power, radius, absorptivity;
+} tl_track;
+
+/* Tracks are run back to back starting at t_start; the beam is off before
+ * t_start and after the last track ends.  The array is copied at creation. */
+typedef struct {
+  int n_tracks;
+  const tl_track* tracks;
+  double t_start;
+} tl_scan_path;
+
+/* dt_coarse: macro step; m_time: micro steps per macro step (1..32);
+ * face_quad: Gauss points per direction for the surface load (1..4);
+ * newton_tol [K]: stop when the applied Newton step has max-norm <= tol;
+ * cg_rtol: relative reduction of the preconditioned residual norm in each
+ * linear solve; dn_tol [K]: two-level iteration stops when the interface
+ * update has max-norm <= dn_tol; dn_theta: fixed relaxation when > 0, else
+ * Aitken relaxation started from refine/(refine+1); *_max: iteration caps. */
+typedef struct {
+  double dt_coarse;
+  int m_time;
+  tl_precision precision;
+  int face_quad;
+  double newton_tol, cg_rtol, dn_tol, dn_theta;
+  int newton_max, cg_max, dn_max;
+} tl_options;
+
+/* Energy ledger in J (FP64).  stored = sum over coarse nodes of the outside
+ * lumped mass times H(T+) plus the same over fine nodes; absorbed = laser
+ * energy taken in; bottom = heat that left through the bottom face; remap =
+ * energy change caused by window moves.  Identity (to solver tolerance):
+ * stored - stored0 = absorbed - bottom + remap. */
+typedef struct {
+  double stored, stored0, absorbed, bottom, remap;
+} tl_ledger;
+
+/* Counters and timings accumulated over the handle's life. */
+typedef struct {
+  int64_t macro_steps, micro_steps;
+  int64_t newton_fine, newton_coarse;   /* Newton iterations                */
+  int64_t cg_fine, cg_coarse;           /* CG iterations                    */
+  int64_t line_search_halvings;
+  int64_t dn_iters, window_moves;
+  int64_t fine_solves, coarse_solves;
+  double fine_dof_steps;    /* sum over micro steps of free fine nodes        */
+  double step_ms;           /* wall time inside tl_step (host clock)         */
+  double fine_op_bytes;     /* algorithmic bytes moved by fine CG operator
+                               applies (read v,d,kappa + direction update,
+                               write q): the roofline numerator              */
+  int64_t fine_op_applies;
+  int fine_nodes[3];        /* fine grid nodes per axis                      */
+  int coarse_nodes[3];
+} tl_stats;
+
+typedef struct tl_sim tl_sim;
+
+/* Bytes of device workspace tl_create needs for this mesh and options. */
+size_t tl_workspace_bytes(const tl_mesh* mesh, const tl_options* opts);
+
+/* Create a simulation (paper Section 2 problem + Algorithm 1 set-up).  All
+ * structs and the track array are copied.  dev_workspace: device memory of at
+ * least tl_workspace_bytes() bytes, 256-byte aligned, owned by the caller and
+ * outliving the handle; the library never allocates device memory.
+ * hip_stream: the hipStream_t to queue work on (NULL = default stream).  The
+ * initial state is T_init everywhere with T_bottom on the bottom face; the
+ * window is placed by the laser position at t_start + dt_coarse.  Errors:
+ * TL_EINVAL for inconsistent geometry (window larger than the plate,
+ * refine < 1, non-positive sizes), non-finite or non-physical parameters
+ * (T_sol >= T_liq, T_lo >= T_hi, rho <= 0, ...), an empty scan path or
+ * unsupported options; TL_ENOMEM if ws_bytes is too small. */
+tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
+                    const tl_scan_path* scan, const tl_options* opts,
+                    void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                    tl_sim** out);
+
+/* Advance n_macro macro steps (Algorithm 1: window update, coarse predictor,
+ * m-1 fine micro steps with time-blended Dirichlet data, two-level
+ * correction).  On TL_ENOCONV the state is that of the last completed macro
+ * step. */
+tl_status tl_step(tl_sim* sim, int n_macro);
+
+/* Copy the coarse (level 0) or fine (level 1) temperature to host_out, node
+ * (i,j,k) at i + nx*(j + ny*k) with (nx,ny,nz) = dims_out.  cap is the
+ * capacity of host_out in doubles (TL_ENOMEM if too small).  fine_origin_out
+ * (may be NULL) receives the fine-grid index of the window's first node on
+ * the plate-wide fine lattice (refine * coarse cell origin). */
+tl_status tl_get_temperature(tl_sim* sim, int level, double* host_out,
+                             size_t cap, int dims_out[3],
+                             int fine_origin_out[3]);
+
+tl_status tl_get_ledger(tl_sim* sim, tl_ledger* out);
+tl_status tl_get_stats(tl_sim* sim, tl_stats* out);
+
+/* Simulation time of the committed state and the number of macro steps. */
+tl_status tl_get_time(tl_sim* sim, double* t, int64_t* n_macro);
+
+/* Checkpoint: serialise the committed state (coarse and fine temperatures,
+ * window origin, step counter, ledger, stats) into host memory; *used receives
+ * the byte count (call with host = NULL to query).  tl_load restores a buffer
+ * written by tl_save for a handle created with the same mesh and options. */
+tl_status tl_save(tl_sim* sim, void* host, size_t cap, size_t* used);
+tl_status tl_load(tl_sim* sim, const void* host, size_t n);
+
+void tl_destroy(tl_sim* sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* tl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TL_H */

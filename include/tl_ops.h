@@ -1,0 +1,55 @@
+/*
+ * tl_ops.h -- operator-level entry points of the two-level thermal library,
+ * on caller-owned device buffers.  These expose the fine-level heat operator
+ * on its own (for verification and bandwidth measurement); the simulation
+ * API in tl.h uses the same kernels.
+ *
+ * Device layout ("padded"): a grid of nx x ny x nz Q1 cells has
+ * (nx+1) x (ny+1) x (nz+1) nodes stored with one ghost layer on every side,
+ * node (i,j,k) at ((k+1)*(ny+3) + (j+1))*(nx+3) + (i+1); ghost entries are
+ * zero.  A per-element quantity of element (i,j,k) is stored at the padded
+ * index of its lowest corner node (i,j,k); all other entries are zero.
+ */
+#ifndef TL_OPS_H
+#define TL_OPS_H
+
+#include <stddef.h>
+#include "tl.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* nx x ny x nz Q1 cells of spacing hx, hy, hz [m]. */
+typedef struct {
+  int nx, ny, nz;
+  double hx, hy, hz;
+} tl_grid;
+
+/* Number of entries of a padded array of this grid. */
+size_t tl_op_padded_size(const tl_grid* grid);
+
+/* Copy between the plain layout (nodes: i + (nx+1)*(j + (ny+1)*k); elements:
+ * i + nx*(j + ny*k)) and the padded layout.  kind 0 = nodal, 1 = per-element;
+ * elem_bytes 4 (float) or 8 (double).  pack writes zeros into every padded
+ * entry it does not fill.  Both pointers are device pointers. */
+tl_status tl_op_pack(const tl_grid* grid, int kind, int elem_bytes,
+                     const void* plain, void* padded, void* hip_stream);
+tl_status tl_op_unpack(const tl_grid* grid, int kind, int elem_bytes,
+                       const void* padded, void* plain, void* hip_stream);
+
+/* Matrix-free Q1 heat operator on every node of the grid:
+ *   y_i = d_i v_i + sum_{elements e containing i} kappa_e (K_e v_e)_i
+ * with K_e the exact Q1 element stiffness of an hx x hy x hz box (the
+ * diffusion term of the paper's thermal model, Section 2.1, discretised
+ * with trilinear hexahedra).  d, kappa, v, y are padded device arrays of
+ * doubles (precision TL_FP64) or floats (TL_MIXED).  `repeat` >= 1 launches
+ * the operator that many times back to back (for timing). */
+tl_status tl_op_apply(const tl_grid* grid, int precision, const void* d,
+                      const void* kappa, const void* v, void* y, int repeat,
+                      void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TL_OPS_H */

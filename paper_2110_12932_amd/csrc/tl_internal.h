@@ -1,0 +1,174 @@
+// Internal declarations shared by the HIP kernels (tl_kernels.hip), the
+// solver runtime (tl_runtime.cpp) and the host-side geometry and scan-path
+// logic (tl_host.cpp).  Not part of the public interface.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tl {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
+constexpr int kMaxBlocks = 2048; // grid cap for grid-stride kernels
+constexpr int kMaxSpots = 32;    // laser positions averaged by one load call
+constexpr int kNumCounters = 16;
+
+// Structured Q1 grid in the padded layout: node (i,j,k) at
+// (k+1)*pxy + (j+1)*px + (i+1); the element whose lowest corner is node
+// (i,j,k) is stored at that node's index.
+struct Geo {
+  int nx, ny, nz;        // nodes per axis
+  int px, pxy;           // padded strides (nx+2, (nx+2)*(ny+2))
+  int nreal;             // nx*ny*nz
+  long npad;             // (nx+2)*(ny+2)*(nz+2)
+  double hx, hy, hz;     // spacing
+  double x0, y0;         // coordinates of node (0,0,*)
+  double vol8;           // element volume / 8
+  double w[8];           // element stiffness K_e[a][b] by the xor pattern a^b
+};
+
+// Which elements are active and which nodes are Dirichlet, as index rules.
+enum RegionMode {
+  kAllBottom = 0,   // all elements; Dirichlet on k = 0 (coarse predictor)
+  kOutside = 1,     // coarse elements outside the window box; Dirichlet on
+                    // k = 0 and on window nodes not on an immersed face
+  kWindow = 2       // fine window: all elements; Dirichlet on immersed faces
+                    // and, when the window reaches the plate bottom, k = 0
+};
+enum FaceBits { kFx0 = 1, kFx1 = 2, kFy0 = 4, kFy1 = 8, kFz0 = 16 };
+
+struct Region {
+  int mode;
+  int I0, I1, J0, J1, K0;  // kOutside: coarse window box in cells [I0,I1) ...
+  int faces;               // immersed faces (FaceBits) for kOutside/kWindow
+  int bottom;              // kWindow: 1 if node layer k = 0 is on the plate bottom
+};
+
+struct MatDev {
+  double rho, T_lo, T_hi, c_lo, c_hi, k_lo, k_hi, latent, Tm, S;
+  double cslope, kslope, sens_full;  // derived on the host
+};
+
+// One laser position with its flux parameters q0 = 3 eta P / (pi R^2) and
+// a3 = 3 / R^2, and the weight of this position in a time average.
+struct Spot { double xc, yc, q0, a3, weight; };
+
+struct SpotSet {
+  int n;
+  int nq;                  // Gauss points per face direction
+  double gx[4], gw[4];     // Gauss points and weights on [0, 1]
+  Spot s[kMaxSpots];
+};
+
+// Device-resident scalars of one level (written by last-block reductions).
+struct LevelScalars {
+  double rnorm2;     // |R_free|^2 at the last evaluated temperature
+  double dmax;       // max |alpha delta| over free nodes of the last trial
+  double rz, rz0;    // CG: r.z now and at the start
+  double alpha, beta, pq;
+  double sum0, sum1, sum2;   // generic reduction results
+  int iters, done, breakdown, pad;
+};
+
+// Energy ledger slots on the device.
+struct LedgerDev {
+  double stored, stored0, absorbed, bottom, remap;
+  double e_tmp0, e_tmp1;
+};
+
+// Fine window placement on the coarse plate and its transfer parameters.
+struct Window {
+  int I0, J0, K0;           // lowest coarse node of the window
+  int wx, wy, wz;           // window size in coarse cells
+  int r;                    // refinement
+  int faces;                // immersed faces
+  int bottom;               // window reaches the plate bottom
+};
+
+// ---- kernels launched from the runtime (tl_kernels.hip) -------------------
+struct Launch { void* stream; };
+
+void k_fill(Launch L, double* a, double v, long n);
+void k_zero_bytes(Launch L, void* a, size_t bytes);
+void k_copy(Launch L, double* dst, const double* src, long n);
+
+template <class R>
+void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R* y);
+
+// Residual of one implicit step at the trial T' = T - alpha*dx (dx may be
+// null for alpha = 0); writes T', R, the Jacobian coefficients for CG in
+// precision R_cg, and the CG initial residual; reduces |R_free|^2, max|alpha
+// dx| over free nodes and r.z into sc.
+template <class Rcg, class Rdx>
+void k_residual(Launch L, const Geo& g, const Region& rg, const MatDev& m,
+                double tau, const double* T, const Rdx* dx, double alpha,
+                const double* Told, const double* F, const double* Fext,
+                double* Tt, double* Rout, Rcg* kap, Rcg* d, Rcg* dinv, Rcg* r,
+                Rcg* z, LevelScalars* sc, double* partials, unsigned* counters);
+
+template <class R>
+void k_cg_iter(Launch L, const Geo& g, bool first, const R* z, const R* p_old,
+               R* p_new, R* q, const R* d, const R* kap, R* x, R* r, R* zout,
+               const R* dinv, double rtol2, int maxit, LevelScalars* sc,
+               double* partials, unsigned* counters);
+
+void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
+                  int fI1, int fJ0, int fJ1, double* F, double ledger_scale,
+                  double* ledger_slot, double* partials, unsigned* counters);
+
+void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+                      double T_bottom, const double* Ta, const double* Tb,
+                      double wb, double* Tf);
+
+void k_interface_accumulate(Launch L, const Geo& gf, const Window& w,
+                            const double* R, double* rho_acc, int init,
+                            double bottom_scale, double* ledger_bottom,
+                            double* partials, unsigned* counters);
+
+void k_restrict(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+                const double* rho_acc, const double* Rm, double scale,
+                double* ext);
+
+void k_inject(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+              const double* Tf, double* Tc);
+
+void k_window_shift(Launch L, const Geo& gf, const Geo& gc, const Window& wn,
+                    const Window& wo, const double* Tf_old, const double* Tc,
+                    double* Tf_new);
+
+// Sum over nodes of mass(region) * H(T) (+ into slot, or = when assign).
+void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
+              const double* T, double* slot, int assign, double* partials,
+              unsigned* counters);
+
+// Sum over nodes with k = 0 of R (scaled, added into slot).
+void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,
+                  double* slot, double* partials, unsigned* counters);
+
+// Interface update on the coarse nodes of the immersed window faces:
+// stage 0 reduces max|T - lam|, <dprev, d - dprev>, |d - dprev|^2 into
+// sc->sum0..2 (d = T - lam); stage 1 sets lam += theta d and dprev = d.
+void k_interface_lambda(Launch L, const Geo& gc, const Window& w, int stage,
+                        const double* T, double* lam, double* dprev,
+                        double theta, int first, LevelScalars* sc);
+
+void k_pack(Launch L, const Geo& g, int kind, int elem_bytes, const void* plain,
+            void* padded);
+void k_unpack(Launch L, const Geo& g, int kind, int elem_bytes,
+              const void* padded, void* plain);
+
+// ---- host-side geometry and scan path (tl_host.cpp) -----------------------
+struct TrackH { double x0, y0, x1, y1, speed, power, radius, absorptivity; };
+
+// Beam state at time t: returns 0 when off, else 1 and fills the fields.
+int laser_at(const TrackH* tr, int n, double t_start, double t, double* xc,
+             double* yc, double* P, double* R, double* eta, int* k);
+void window_origin(const TrackH* tr, int n, double t_start, double t,
+                   double hx, double hy, int nx, int ny, int wx, int wy,
+                   int have_current, int cur_I0, int cur_J0, int* I0, int* J0);
+double micro_time(double t_start, double dt, int m, long n, int j);
+void gauss01(int nq, double* x, double* w);
+
+Geo make_geo(int ncx, int ncy, int ncz, double hx, double hy, double hz,
+             double x0, double y0);
+
+}  // namespace tl

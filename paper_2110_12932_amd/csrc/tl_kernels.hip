@@ -1,0 +1,1067 @@
+// HIP kernels of the two-level thermal solver for gfx950 (MI355X).
+//
+// Every kernel works on structured Q1 grids in the padded layout described in
+// tl_internal.h (one ghost layer, zero-filled), so the 27-point gathers of the
+// matrix-free operator need no bounds checks: ghost elements carry zero
+// conductivity and ghost nodes hold zeros.  Work is spread with grid-stride
+// loops over the real nodes (workgroups of 256 = 4 wavefronts of 64).
+// Reductions are deterministic: fixed per-thread order, a fixed-shape
+// workgroup tree, and a final sum over the per-workgroup partials in index
+// order by the last workgroup to finish (arrival counted with a device-scope
+// atomic add).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "tl_internal.h"
+
+namespace tl {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+static inline int grid_for(long n) {
+  long b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  return (int)b;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+template <class T>
+__device__ inline T wave_max(T v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Block-wide sum of NV values per thread; result valid in thread 0.
+template <int NV, class T>
+__device__ inline void block_sum(T (&v)[NV], T* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = wave_sum(v[a]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) lds[wid * NV + a] = v[a];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+      T s = lds[a];
+      for (int w = 1; w < kBlock / 64; ++w) s += lds[w * NV + a];
+      v[a] = s;
+    }
+  }
+}
+
+// Thread 0 publishes its partials, then counts arrivals; returns true (in
+// every thread) in the last workgroup to arrive, after an acquire fence.
+__device__ inline bool arrive_last(unsigned* counter) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+__device__ inline double load_acquire(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum NV partial arrays (stride gridDim.x) in fixed order inside the last
+// workgroup; result valid in thread 0.
+template <int NV>
+__device__ inline void final_sum(const double* partials, double (&out)[NV],
+                                 double* lds) {
+  double v[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] += load_acquire(&partials[a * gridDim.x + b]);
+  }
+  block_sum<NV>(v, lds);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) out[a] = v[a];
+}
+
+__device__ inline void node_ijk(const Geo& g, int t, int& i, int& j, int& k) {
+  i = t % g.nx;
+  int r = t / g.nx;
+  j = r % g.ny;
+  k = r / g.ny;
+}
+__device__ inline int pidx(const Geo& g, int i, int j, int k) {
+  return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+}
+
+// ---------------------------------------------------------------------------
+// material law (paper Section 2)
+// ---------------------------------------------------------------------------
+__device__ inline double clampT(double T, const MatDev& m) {
+  return fmin(fmax(T, m.T_lo), m.T_hi);
+}
+__device__ inline double kappa_of(double T, const MatDev& m) {
+  return m.k_lo + m.kslope * (clampT(T, m) - m.T_lo);
+}
+__device__ inline double heatcap_of(double T, const MatDev& m) {
+  return m.c_lo + m.cslope * (clampT(T, m) - m.T_lo);
+}
+// H(T) = rho int_{T_lo}^T c + rho chi f_pc(T)
+__device__ inline double enthalpy(double T, const MatDev& m) {
+  double sens;
+  if (T < m.T_lo) {
+    sens = m.c_lo * (T - m.T_lo);
+  } else if (T > m.T_hi) {
+    sens = m.sens_full + m.c_hi * (T - m.T_hi);
+  } else {
+    double u = T - m.T_lo;
+    sens = m.c_lo * u + 0.5 * m.cslope * u * u;
+  }
+  double f = 0.5 * (1.0 + tanh(m.S * (T - m.Tm)));
+  return m.rho * (sens + m.latent * f);
+}
+__device__ inline double enthalpy_slope(double T, const MatDev& m) {
+  double th = tanh(m.S * (T - m.Tm));
+  return m.rho * (heatcap_of(T, m) + m.latent * 0.5 * m.S * (1.0 - th * th));
+}
+
+// ---------------------------------------------------------------------------
+// region rules (which elements are active, which nodes are Dirichlet)
+// ---------------------------------------------------------------------------
+__device__ inline bool elem_active(const Geo& g, const Region& rg, int ei,
+                                   int ej, int ek) {
+  if (ei < 0 || ej < 0 || ek < 0 || ei > g.nx - 2 || ej > g.ny - 2 ||
+      ek > g.nz - 2)
+    return false;
+  if (rg.mode == kOutside) {
+    bool in = ei >= rg.I0 && ei < rg.I1 && ej >= rg.J0 && ej < rg.J1 &&
+              ek >= rg.K0;
+    return !in;
+  }
+  return true;
+}
+__device__ inline bool on_immersed_face(const Region& rg, int i, int j, int k,
+                                        int i0, int i1, int j0, int j1,
+                                        int k0) {
+  return ((rg.faces & kFx0) && i == i0) || ((rg.faces & kFx1) && i == i1) ||
+         ((rg.faces & kFy0) && j == j0) || ((rg.faces & kFy1) && j == j1) ||
+         ((rg.faces & kFz0) && k == k0);
+}
+__device__ inline bool node_dirichlet(const Geo& g, const Region& rg, int i,
+                                      int j, int k) {
+  if (rg.mode == kAllBottom) return k == 0;
+  if (rg.mode == kOutside) {
+    if (k == 0) return true;
+    bool inwin = i >= rg.I0 && i <= rg.I1 && j >= rg.J0 && j <= rg.J1 &&
+                 k >= rg.K0;
+    return inwin && !on_immersed_face(rg, i, j, k, rg.I0, rg.I1, rg.J0,
+                                      rg.J1, rg.K0);
+  }
+  // kWindow
+  if (rg.bottom && k == 0) return true;
+  return on_immersed_face(rg, i, j, k, 0, g.nx - 1, 0, g.ny - 1, 0);
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(double* a, double v, long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+       t += (long)gridDim.x * blockDim.x)
+    a[t] = v;
+}
+__global__ void zero_kernel(uint32_t* a, long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+       t += (long)gridDim.x * blockDim.x)
+    a[t] = 0u;
+}
+__global__ void copy_kernel(double* dst, const double* src, long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+       t += (long)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+void k_fill(Launch L, double* a, double v, long n) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, a, v, n);
+}
+void k_zero_bytes(Launch L, void* a, size_t bytes) {
+  long n = (long)(bytes / 4);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, (uint32_t*)a, n);
+}
+void k_copy(Launch L, double* dst, const double* src, long n) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, dst, src, n);
+}
+
+// ---------------------------------------------------------------------------
+// the matrix-free Q1 heat operator
+// ---------------------------------------------------------------------------
+// Neighbour offset table: n27(dx,dy,dz) = (dx+1) + 3(dy+1) + 9(dz+1).
+#define N27(dx, dy, dz) (((dx) + 1) + 3 * ((dy) + 1) + 9 * ((dz) + 1))
+
+// y = d*v_c + sum over the 8 elements around the node of
+// kap_e * sum_corners W[pattern] v_corner, with v27 the 27 values around the
+// node and k8[e] the conductivity of element e (node is its corner e, i.e.
+// the element sits at offset (-ex, -ey, -ez)).
+template <class R>
+__device__ inline R stencil_apply(const R (&v27)[27], const R (&k8)[8],
+                                  const R (&w)[8]) {
+  R acc = (R)0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    R s = (R)0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+      s += w[e ^ c] * v27[N27(cx - ex, cy - ey, cz - ez)];
+    }
+    acc += k8[e] * s;
+  }
+  return acc;
+}
+
+template <class R>
+__device__ inline void gather27(const Geo& g, const R* __restrict__ a, int n,
+                                R (&v27)[27]) {
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx)
+        v27[N27(dx, dy, dz)] = a[n + dx + dy * g.px + dz * g.pxy];
+}
+
+template <class R>
+__device__ inline void gather8(const Geo& g, const R* __restrict__ kap, int n,
+                               R (&k8)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    k8[e] = kap[n - ex - ey * g.px - ez * g.pxy];
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+op_apply_kernel(Geo g, const R* __restrict__ d, const R* __restrict__ kap,
+                const R* __restrict__ v, R* __restrict__ y) {
+  R w[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) w[p] = (R)g.w[p];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    R v27[27], k8[8];
+    gather27(g, v, n, v27);
+    gather8(g, kap, n, k8);
+    y[n] = d[n] * v27[13] + stencil_apply(v27, k8, w);
+  }
+}
+
+template <class R>
+void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
+                R* y) {
+  hipLaunchKernelGGL(op_apply_kernel<R>, dim3(grid_for(g.nreal)), dim3(kBlock),
+                     0, (hipStream_t)L.stream, g, d, kap, v, y);
+}
+template void k_op_apply<float>(Launch, const Geo&, const float*, const float*,
+                                const float*, float*);
+template void k_op_apply<double>(Launch, const Geo&, const double*,
+                                 const double*, const double*, double*);
+
+// ---------------------------------------------------------------------------
+// K4 + K1: nonlinear residual at a trial temperature, Jacobian coefficients,
+// CG initialisation
+// ---------------------------------------------------------------------------
+template <class Rcg, class Rdx>
+__global__ void __launch_bounds__(kBlock)
+residual_kernel(Geo g, Region rg, MatDev m, double tau,
+                const double* __restrict__ T, const Rdx* __restrict__ dx,
+                double alpha, const double* __restrict__ Told,
+                const double* __restrict__ F, const double* __restrict__ Fext,
+                double* __restrict__ Tt, double* __restrict__ Rout,
+                Rcg* __restrict__ kap, Rcg* __restrict__ d,
+                Rcg* __restrict__ dinv, Rcg* __restrict__ r,
+                Rcg* __restrict__ z, LevelScalars* sc, double* partials,
+                unsigned* counters) {
+  __shared__ double lds[6 * kBlock / 64];
+  double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    double T27[27];
+    gather27(g, T, n, T27);
+    if (dx != nullptr) {
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dxx = -1; dxx <= 1; ++dxx)
+            T27[N27(dxx, dy, dz)] -=
+                alpha * (double)dx[n + dxx + dy * g.px + dz * g.pxy];
+    }
+    double k8[8];
+    double nact = 0.0;
+    double diagK = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+      double ke = 0.0;
+      if (elem_active(g, rg, i - ex, j - ey, k - ez)) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          s += T27[N27(cx - ex, cy - ey, cz - ez)];
+        }
+        ke = kappa_of(0.125 * s, m);
+        nact += 1.0;
+      }
+      k8[e] = ke;
+      diagK += ke;
+    }
+    double w[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) w[p] = g.w[p];
+    const double Tn = T27[13];
+    const double mass = g.vol8 * nact;
+    double Rn = mass * (enthalpy(Tn, m) - enthalpy(Told[n], m)) / tau +
+                stencil_apply(T27, k8, w) - F[n];
+    if (Fext != nullptr) Rn -= Fext[n];
+    Tt[n] = Tn;
+    Rout[n] = Rn;
+    // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
+    const bool dir = node_dirichlet(g, rg, i, j, k);
+    const double dn = mass * enthalpy_slope(Tn, m) / tau;
+    const double diag = dn + diagK * g.w[0];
+    // this node owns the element whose lowest corner it is (k8[0])
+    kap[n] = (Rcg)k8[0];
+    d[n] = (Rcg)dn;
+    const Rcg di = dir ? (Rcg)0 : (Rcg)(1.0 / diag);
+    dinv[n] = di;
+    const Rcg rn = dir ? (Rcg)0 : (Rcg)Rn;
+    const Rcg zn = di * rn;
+    r[n] = rn;
+    z[n] = zn;
+    if (!dir) {
+      acc[0] += Rn * Rn;
+      if (dx != nullptr) acc[1] = fmax(acc[1], fabs(alpha * (double)dx[n]));
+      acc[2] += (double)(rn * zn);
+    }
+  }
+  // max is taken separately from the two sums
+  double mx = wave_max(acc[1]);
+  double sums[2] = {acc[0], acc[2]};
+  block_sum<2>(sums, lds);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bm = lds[0];
+    for (int wv = 1; wv < kBlock / 64; ++wv) bm = fmax(bm, lds[wv]);
+    partials[blockIdx.x] = sums[0];
+    partials[gridDim.x + blockIdx.x] = bm;
+    partials[2 * gridDim.x + blockIdx.x] = sums[1];
+  }
+  __syncthreads();
+  if (arrive_last(&counters[0])) {
+    double s0 = 0.0, s2 = 0.0, bm = 0.0;
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+      v[0] += load_acquire(&partials[b]);
+      v[1] += load_acquire(&partials[2 * gridDim.x + b]);
+      bm = fmax(bm, load_acquire(&partials[gridDim.x + b]));
+    }
+    __syncthreads();
+    bm = wave_max(bm);
+    block_sum<2>(v, lds + 8);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = bm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s0 = v[0];
+      s2 = v[1];
+      double mm = lds[0];
+      for (int wv = 1; wv < kBlock / 64; ++wv) mm = fmax(mm, lds[wv]);
+      sc->rnorm2 = s0;
+      sc->dmax = mm;
+      sc->rz = s2;
+      sc->rz0 = s2;
+      sc->beta = 0.0;
+      sc->alpha = 0.0;
+      sc->iters = 0;
+      sc->breakdown = 0;
+      sc->done = (s2 == 0.0) ? 1 : 0;
+      atomicExch(&counters[0], 0u);
+    }
+  }
+}
+
+template <class Rcg, class Rdx>
+void k_residual(Launch L, const Geo& g, const Region& rg, const MatDev& m,
+                double tau, const double* T, const Rdx* dx, double alpha,
+                const double* Told, const double* F, const double* Fext,
+                double* Tt, double* Rout, Rcg* kap, Rcg* d, Rcg* dinv, Rcg* r,
+                Rcg* z, LevelScalars* sc, double* partials,
+                unsigned* counters) {
+  hipLaunchKernelGGL((residual_kernel<Rcg, Rdx>), dim3(grid_for(g.nreal)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, g, rg, m, tau, T,
+                     dx, alpha, Told, F, Fext, Tt, Rout, kap, d, dinv, r, z,
+                     sc, partials, counters);
+}
+template void k_residual<double, double>(Launch, const Geo&, const Region&,
+                                         const MatDev&, double, const double*,
+                                         const double*, double, const double*,
+                                         const double*, const double*, double*,
+                                         double*, double*, double*, double*,
+                                         double*, double*, LevelScalars*,
+                                         double*, unsigned*);
+template void k_residual<float, float>(Launch, const Geo&, const Region&,
+                                       const MatDev&, double, const double*,
+                                       const float*, double, const double*,
+                                       const double*, const double*, double*,
+                                       double*, float*, float*, float*, float*,
+                                       float*, LevelScalars*, double*,
+                                       unsigned*);
+
+// ---------------------------------------------------------------------------
+// K2 + K3: one Jacobi-preconditioned CG iteration in two kernels.
+//   spmv:   p_new = z + beta p_old (first: p_new = z), q = J p_new,
+//           alpha = rz / (p_new . q)
+//   update: x += alpha p_new (first: x = alpha p_new), r -= alpha q,
+//           z = Dinv r, beta = r.z / rz, convergence test
+// Every kernel returns at once once the device flag `done` is set.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+cg_spmv_kernel(Geo g, int first, const R* __restrict__ z,
+               const R* __restrict__ p_old, R* __restrict__ p_new,
+               R* __restrict__ q, const R* __restrict__ d,
+               const R* __restrict__ kap, LevelScalars* sc, double* partials,
+               unsigned* counters) {
+  __shared__ R lds[kBlock / 64];
+  __shared__ double ldsd[kBlock / 64];
+  if (sc->done) return;
+  const R beta = first ? (R)0 : (R)sc->beta;
+  R w[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) w[p] = (R)g.w[p];
+  R acc[1] = {(R)0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    R p27[27], k8[8];
+    if (first) {
+      gather27(g, z, n, p27);
+    } else {
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int o = n + dx + dy * g.px + dz * g.pxy;
+            p27[N27(dx, dy, dz)] = z[o] + beta * p_old[o];
+          }
+    }
+    gather8(g, kap, n, k8);
+    const R pc = p27[13];
+    const R qn = d[n] * pc + stencil_apply(p27, k8, w);
+    p_new[n] = pc;
+    q[n] = qn;
+    acc[0] += pc * qn;
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = (double)acc[0];
+  __syncthreads();
+  if (arrive_last(&counters[1])) {
+    // the cross-workgroup sum stays in the CG precision
+    R v[1] = {(R)0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+      v[0] += (R)load_acquire(&partials[b]);
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) {
+      const R pq = v[0];
+      const R rz = (R)sc->rz;
+      sc->pq = (double)pq;
+      if (!(pq > (R)0) || !isfinite((double)pq)) {
+        sc->breakdown = 1;
+        sc->done = 1;
+        sc->alpha = 0.0;
+      } else {
+        sc->alpha = (double)(rz / pq);
+      }
+      atomicExch(&counters[1], 0u);
+    }
+  }
+  (void)ldsd;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+cg_update_kernel(Geo g, int first, const R* __restrict__ p,
+                 const R* __restrict__ q, R* __restrict__ x,
+                 R* __restrict__ r, R* __restrict__ z,
+                 const R* __restrict__ dinv, double rtol2, int maxit,
+                 LevelScalars* sc, double* partials, unsigned* counters) {
+  __shared__ R lds[kBlock / 64];
+  if (sc->done) return;
+  const R alpha = (R)sc->alpha;
+  R acc[1] = {(R)0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    const R pn = p[n];
+    x[n] = first ? alpha * pn : x[n] + alpha * pn;
+    const R rn = r[n] - alpha * q[n];
+    const R zn = dinv[n] * rn;
+    r[n] = rn;
+    z[n] = zn;
+    acc[0] += rn * zn;
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = (double)acc[0];
+  __syncthreads();
+  if (arrive_last(&counters[2])) {
+    R v[1] = {(R)0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+      v[0] += (R)load_acquire(&partials[b]);
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) {
+      const R rz_new = v[0];
+      const R rz = (R)sc->rz;
+      sc->beta = (double)(rz_new / rz);
+      sc->rz = (double)rz_new;
+      const int it = sc->iters + 1;
+      sc->iters = it;
+      if (!isfinite((double)rz_new)) {
+        sc->breakdown = 2;
+        sc->done = 1;
+      } else if ((double)rz_new <= rtol2 * sc->rz0 || it >= maxit) {
+        sc->done = 1;
+      }
+      atomicExch(&counters[2], 0u);
+    }
+  }
+}
+
+template <class R>
+void k_cg_iter(Launch L, const Geo& g, bool first, const R* z, const R* p_old,
+               R* p_new, R* q, const R* d, const R* kap, R* x, R* r, R* zout,
+               const R* dinv, double rtol2, int maxit, LevelScalars* sc,
+               double* partials, unsigned* counters) {
+  const int nb = grid_for(g.nreal);
+  hipLaunchKernelGGL(cg_spmv_kernel<R>, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, first ? 1 : 0, z, p_old, p_new,
+                     q, d, kap, sc, partials, counters);
+  hipLaunchKernelGGL(cg_update_kernel<R>, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, first ? 1 : 0, p_new, q, x, r,
+                     zout, dinv, rtol2, maxit, sc, partials, counters);
+}
+template void k_cg_iter<float>(Launch, const Geo&, bool, const float*,
+                               const float*, float*, float*, const float*,
+                               const float*, float*, float*, float*,
+                               const float*, double, int, LevelScalars*,
+                               double*, unsigned*);
+template void k_cg_iter<double>(Launch, const Geo&, bool, const double*,
+                                const double*, double*, double*, const double*,
+                                const double*, double*, double*, double*,
+                                const double*, double, int, LevelScalars*,
+                                double*, unsigned*);
+
+// ---------------------------------------------------------------------------
+// K6: surface laser load F_i = sum over top faces of int q phi_i dA (n_q x n_q
+// Gauss per face), averaged over the spots with their weights.  Faces with
+// fI0 <= i < fI1 and fJ0 <= j < fJ1 are skipped (the window's faces in the
+// coarse outside load).  Adds scale * sum(F) into *ledger_slot.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+laser_load_kernel(Geo g, SpotSet sp, int fI0, int fI1, int fJ0, int fJ1,
+                  double* __restrict__ F, double scale, double* slot,
+                  double* partials, unsigned* counters) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  const int ntop = g.nx * g.ny;
+  const double area = g.hx * g.hy;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntop;
+       t += gridDim.x * blockDim.x) {
+    const int i = t % g.nx, j = t / g.nx;
+    double f = 0.0;
+    for (int fb = 0; fb < 2; ++fb) {
+      const int fj = j - 1 + fb;          // face row
+      if (fj < 0 || fj > g.ny - 2) continue;
+      for (int fa = 0; fa < 2; ++fa) {
+        const int fi = i - 1 + fa;        // face column
+        if (fi < 0 || fi > g.nx - 2) continue;
+        if (fi >= fI0 && fi < fI1 && fj >= fJ0 && fj < fJ1) continue;
+        // this node is corner (1-fa, 1-fb) of face (fi, fj)
+        const int ca = 1 - fa, cb = 1 - fb;
+        for (int s = 0; s < sp.n; ++s) {
+          const Spot S = sp.s[s];
+          double fs = 0.0;
+          for (int qa = 0; qa < sp.nq; ++qa) {
+            const double xi = sp.gx[qa];
+            const double x = g.x0 + (fi + xi) * g.hx;
+            const double phx = ca ? xi : 1.0 - xi;
+            for (int qb = 0; qb < sp.nq; ++qb) {
+              const double eta = sp.gx[qb];
+              const double y = g.y0 + (fj + eta) * g.hy;
+              const double phy = cb ? eta : 1.0 - eta;
+              const double rx = x - S.xc, ry = y - S.yc;
+              const double q = S.q0 * exp(-S.a3 * (rx * rx + ry * ry));
+              fs += q * (sp.gw[qa] * sp.gw[qb] * area) * (phx * phy);
+            }
+          }
+          f += S.weight * fs;
+        }
+      }
+    }
+    F[pidx(g, i, j, g.nz - 1)] = f;
+    acc[0] += f;
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+  __syncthreads();
+  if (arrive_last(&counters[3])) {
+    double v[1];
+    final_sum<1>(partials, v, lds);
+    if (threadIdx.x == 0) {
+      if (slot != nullptr) *slot += scale * v[0];
+      atomicExch(&counters[3], 0u);
+    }
+  }
+}
+
+void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
+                  int fI1, int fJ0, int fJ1, double* F, double ledger_scale,
+                  double* ledger_slot, double* partials, unsigned* counters) {
+  hipLaunchKernelGGL(laser_load_kernel, dim3(grid_for((long)g.nx * g.ny)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, g, spots, fI0,
+                     fI1, fJ0, fJ1, F, ledger_scale, ledger_slot, partials,
+                     counters);
+}
+
+// ---------------------------------------------------------------------------
+// K7: Dirichlet data of the fine window.  Bottom nodes of a window that
+// reaches the plate bottom get T_bottom; nodes on immersed faces get the
+// trilinear interpolant of (1 - wb) Ta + wb Tb (coarse fields), the time
+// blend of the paper's local problem (Section 4).
+// ---------------------------------------------------------------------------
+__device__ inline double prolong(const Geo& gc, const Window& w,
+                                 const double* __restrict__ Tc, int fi, int fj,
+                                 int fk) {
+  // global fine index on each axis, its coarse cell and position in it
+  const int gi = w.r * w.I0 + fi, gj = w.r * w.J0 + fj, gk = w.r * w.K0 + fk;
+  int ci = gi / w.r, cj = gj / w.r, ck = gk / w.r;
+  if (ci > gc.nx - 2) ci = gc.nx - 2;
+  if (cj > gc.ny - 2) cj = gc.ny - 2;
+  if (ck > gc.nz - 2) ck = gc.nz - 2;
+  const double fx = (double)(gi - ci * w.r) / (double)w.r;
+  const double fy = (double)(gj - cj * w.r) / (double)w.r;
+  const double fz = (double)(gk - ck * w.r) / (double)w.r;
+  const int n = pidx(gc, ci, cj, ck);
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int a = c & 1, b = (c >> 1) & 1, e = c >> 2;
+    const double wt = ((a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy)) *
+                      (e ? fz : 1.0 - fz);
+    acc += wt * Tc[n + a + b * gc.px + e * gc.pxy];
+  }
+  return acc;
+}
+
+__device__ inline bool fine_gamma(const Geo& gf, const Window& w, int i, int j,
+                                  int k) {
+  if (w.bottom && k == 0) return false;
+  return ((w.faces & kFx0) && i == 0) || ((w.faces & kFx1) && i == gf.nx - 1) ||
+         ((w.faces & kFy0) && j == 0) || ((w.faces & kFy1) && j == gf.ny - 1) ||
+         ((w.faces & kFz0) && k == 0);
+}
+
+__global__ void fine_dirichlet_kernel(Geo gf, Geo gc, Window w, double Tb_val,
+                                      const double* __restrict__ Ta,
+                                      const double* __restrict__ Tb, double wb,
+                                      double* __restrict__ Tf) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < gf.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(gf, t, i, j, k);
+    const int n = pidx(gf, i, j, k);
+    if (w.bottom && k == 0) {
+      Tf[n] = Tb_val;
+    } else if (fine_gamma(gf, w, i, j, k)) {
+      double v = prolong(gc, w, Ta, i, j, k);
+      if (wb != 0.0) v = (1.0 - wb) * v + wb * prolong(gc, w, Tb, i, j, k);
+      Tf[n] = v;
+    }
+  }
+}
+
+void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+                      double T_bottom, const double* Ta, const double* Tb,
+                      double wb, double* Tf) {
+  hipLaunchKernelGGL(fine_dirichlet_kernel, dim3(grid_for(gf.nreal)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, gf, gc, w,
+                     T_bottom, Ta, Tb, wb, Tf);
+}
+
+// ---------------------------------------------------------------------------
+// K9 (part 1): accumulate the fine interface reactions over micro steps and
+// the heat leaving through the plate bottom inside the window.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+interface_acc_kernel(Geo gf, Window w, const double* __restrict__ R,
+                     double* __restrict__ rho, int init, double bscale,
+                     double* bslot, double* partials, unsigned* counters) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < gf.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(gf, t, i, j, k);
+    const int n = pidx(gf, i, j, k);
+    if (fine_gamma(gf, w, i, j, k)) {
+      if (rho != nullptr) rho[n] = init ? R[n] : rho[n] + R[n];
+    } else if (w.bottom && k == 0) {
+      acc[0] += R[n];
+    }
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+  __syncthreads();
+  if (arrive_last(&counters[4])) {
+    double v[1];
+    final_sum<1>(partials, v, lds);
+    if (threadIdx.x == 0) {
+      if (bslot != nullptr) *bslot += bscale * v[0];
+      atomicExch(&counters[4], 0u);
+    }
+  }
+}
+
+void k_interface_accumulate(Launch L, const Geo& gf, const Window& w,
+                            const double* R, double* rho_acc, int init,
+                            double bottom_scale, double* ledger_bottom,
+                            double* partials, unsigned* counters) {
+  hipLaunchKernelGGL(interface_acc_kernel, dim3(grid_for(gf.nreal)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, gf, w, R, rho_acc,
+                     init, bottom_scale, ledger_bottom, partials, counters);
+}
+
+// ---------------------------------------------------------------------------
+// K9 (part 2): restriction of the interface reactions onto the coarse
+// interface nodes with the transpose of the trilinear prolongation:
+//   ext_J = scale * sum_k P_kJ (rho_acc_k + Rm_k)   over fine interface nodes k.
+// One workgroup per coarse node of the closed window box; nodes of the box
+// that are not interface nodes get 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+restrict_kernel(Geo gf, Geo gc, Window w, const double* __restrict__ rho,
+                const double* __restrict__ Rm, double scale,
+                double* __restrict__ ext) {
+  __shared__ double lds[kBlock / 64];
+  const int bx = w.wx + 1, by = w.wy + 1;
+  const int b = blockIdx.x;
+  const int li = b % bx, lj = (b / bx) % by, lk = b / (bx * by);
+  const int I = w.I0 + li, J = w.J0 + lj, K = w.K0 + lk;
+  Region rg;
+  rg.faces = w.faces;
+  const bool gamma = on_immersed_face(rg, I, J, K, w.I0, w.I0 + w.wx, w.J0,
+                                      w.J0 + w.wy, w.K0);
+  const int r = w.r;
+  const int span = 2 * r - 1;
+  const int fi0 = r * li, fj0 = r * lj, fk0 = r * lk;
+  double acc[1] = {0.0};
+  if (gamma) {
+    const int tot = span * span * span;
+    for (int t = threadIdx.x; t < tot; t += kBlock) {
+      const int di = t % span - (r - 1), dj = (t / span) % span - (r - 1),
+                dk = t / (span * span) - (r - 1);
+      const int fi = fi0 + di, fj = fj0 + dj, fk = fk0 + dk;
+      if (fi < 0 || fj < 0 || fk < 0 || fi > gf.nx - 1 || fj > gf.ny - 1 ||
+          fk > gf.nz - 1)
+        continue;
+      if (!fine_gamma(gf, w, fi, fj, fk)) continue;
+      const double wt = ((double)(r - abs(di)) / (double)r) *
+                        ((double)(r - abs(dj)) / (double)r) *
+                        ((double)(r - abs(dk)) / (double)r);
+      const int n = pidx(gf, fi, fj, fk);
+      acc[0] += wt * (rho != nullptr ? rho[n] + Rm[n] : Rm[n]);
+    }
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) ext[pidx(gc, I, J, K)] = gamma ? scale * acc[0] : 0.0;
+}
+
+void k_restrict(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+                const double* rho_acc, const double* Rm, double scale,
+                double* ext) {
+  const int nb = (w.wx + 1) * (w.wy + 1) * (w.wz + 1);
+  hipLaunchKernelGGL(restrict_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, gf, gc, w, rho_acc, Rm, scale, ext);
+}
+
+// ---------------------------------------------------------------------------
+// K9 (part 3): injection of the fine solution into the coarse nodes of the
+// window that are not on an immersed face.
+// ---------------------------------------------------------------------------
+__global__ void inject_kernel(Geo gf, Geo gc, Window w,
+                              const double* __restrict__ Tf,
+                              double* __restrict__ Tc) {
+  const int bx = w.wx + 1, by = w.wy + 1, bz = w.wz + 1;
+  Region rg;
+  rg.faces = w.faces;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < bx * by * bz;
+       t += gridDim.x * blockDim.x) {
+    const int li = t % bx, lj = (t / bx) % by, lk = t / (bx * by);
+    const int I = w.I0 + li, J = w.J0 + lj, K = w.K0 + lk;
+    if (on_immersed_face(rg, I, J, K, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy,
+                         w.K0))
+      continue;
+    if (K == 0) continue;  // plate bottom keeps its fixed value
+    Tc[pidx(gc, I, J, K)] = Tf[pidx(gf, w.r * li, w.r * lj, w.r * lk)];
+  }
+}
+
+void k_inject(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+              const double* Tf, double* Tc) {
+  const long n = (long)(w.wx + 1) * (w.wy + 1) * (w.wz + 1);
+  hipLaunchKernelGGL(inject_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, gf, gc, w, Tf, Tc);
+}
+
+// ---------------------------------------------------------------------------
+// K8: window move.  Fine nodes inside the old window copy the old fine value;
+// newly covered ones take the trilinear interpolant of the coarse field.
+// ---------------------------------------------------------------------------
+__global__ void window_shift_kernel(Geo gf, Geo gc, Window wn, Window wo,
+                                    const double* __restrict__ Tf_old,
+                                    const double* __restrict__ Tc,
+                                    double* __restrict__ Tf_new) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < gf.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(gf, t, i, j, k);
+    const int oi = i + wn.r * (wn.I0 - wo.I0), oj = j + wn.r * (wn.J0 - wo.J0);
+    double v;
+    if (oi >= 0 && oi <= gf.nx - 1 && oj >= 0 && oj <= gf.ny - 1)
+      v = Tf_old[pidx(gf, oi, oj, k)];
+    else
+      v = prolong(gc, wn, Tc, i, j, k);
+    Tf_new[pidx(gf, i, j, k)] = v;
+  }
+}
+
+void k_window_shift(Launch L, const Geo& gf, const Geo& gc, const Window& wn,
+                    const Window& wo, const double* Tf_old, const double* Tc,
+                    double* Tf_new) {
+  hipLaunchKernelGGL(window_shift_kernel, dim3(grid_for(gf.nreal)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, gf, gc, wn, wo,
+                     Tf_old, Tc, Tf_new);
+}
+
+// ---------------------------------------------------------------------------
+// K10: energy sum_i m_i(region) H(T_i) and bottom reaction sums.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+energy_kernel(Geo g, Region rg, MatDev m, const double* __restrict__ T,
+              double* slot, int assign, double* partials, unsigned* counters) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    double nact = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+      if (elem_active(g, rg, i - ex, j - ey, k - ez)) nact += 1.0;
+    }
+    if (nact > 0.0) acc[0] += g.vol8 * nact * enthalpy(T[pidx(g, i, j, k)], m);
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+  __syncthreads();
+  if (arrive_last(&counters[5])) {
+    double v[1];
+    final_sum<1>(partials, v, lds);
+    if (threadIdx.x == 0) {
+      if (assign)
+        *slot = v[0];
+      else
+        *slot += v[0];
+      atomicExch(&counters[5], 0u);
+    }
+  }
+}
+
+void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
+              const double* T, double* slot, int assign, double* partials,
+              unsigned* counters) {
+  hipLaunchKernelGGL(energy_kernel, dim3(grid_for(g.nreal)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, rg, m, T, slot, assign,
+                     partials, counters);
+}
+
+__global__ void __launch_bounds__(kBlock)
+bottom_sum_kernel(Geo g, const double* __restrict__ R, double scale,
+                  double* slot, double* partials, unsigned* counters) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  const int nb = g.nx * g.ny;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nb;
+       t += gridDim.x * blockDim.x)
+    acc[0] += R[pidx(g, t % g.nx, t / g.nx, 0)];
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+  __syncthreads();
+  if (arrive_last(&counters[6])) {
+    double v[1];
+    final_sum<1>(partials, v, lds);
+    if (threadIdx.x == 0) {
+      *slot += scale * v[0];
+      atomicExch(&counters[6], 0u);
+    }
+  }
+}
+
+void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,
+                  double* slot, double* partials, unsigned* counters) {
+  hipLaunchKernelGGL(bottom_sum_kernel, dim3(grid_for((long)g.nx * g.ny)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, g, R, scale, slot,
+                     partials, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Interface (lambda) update of the two-level iteration: one workgroup over
+// the coarse nodes of the closed window box.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+lambda_kernel(Geo gc, Window w, int stage, const double* __restrict__ T,
+              double* __restrict__ lam, double* __restrict__ dprev,
+              double theta, int first, LevelScalars* sc) {
+  __shared__ double lds[2 * kBlock / 64];
+  __shared__ double ldm[kBlock / 64];
+  const int bx = w.wx + 1, by = w.wy + 1, bz = w.wz + 1;
+  Region rg;
+  rg.faces = w.faces;
+  double mx = 0.0;
+  double acc[2] = {0.0, 0.0};
+  for (int t = threadIdx.x; t < bx * by * bz; t += kBlock) {
+    const int li = t % bx, lj = (t / bx) % by, lk = t / (bx * by);
+    const int I = w.I0 + li, J = w.J0 + lj, K = w.K0 + lk;
+    if (!on_immersed_face(rg, I, J, K, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy,
+                          w.K0))
+      continue;
+    const int n = pidx(gc, I, J, K);
+    const double dn = T[n] - lam[n];
+    if (stage == 0) {
+      mx = fmax(mx, fabs(dn));
+      if (!first) {
+        const double dd = dn - dprev[n];
+        acc[0] += dprev[n] * dd;
+        acc[1] += dd * dd;
+      }
+    } else {
+      lam[n] = lam[n] + theta * dn;
+      dprev[n] = dn;
+    }
+  }
+  if (stage != 0) return;
+  mx = wave_max(mx);
+  block_sum<2>(acc, lds);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) ldm[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = ldm[0];
+    for (int wv = 1; wv < kBlock / 64; ++wv) m = fmax(m, ldm[wv]);
+    sc->sum0 = m;
+    sc->sum1 = acc[0];
+    sc->sum2 = acc[1];
+  }
+}
+
+void k_interface_lambda(Launch L, const Geo& gc, const Window& w, int stage,
+                        const double* T, double* lam, double* dprev,
+                        double theta, int first, LevelScalars* sc) {
+  hipLaunchKernelGGL(lambda_kernel, dim3(1), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, gc, w, stage, T, lam, dprev, theta,
+                     first, sc);
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void pack_kernel(Geo g, int kind, const T* __restrict__ plain,
+                            T* __restrict__ padded, int to_padded) {
+  // kind 0: nodes (nx x ny x nz); kind 1: elements ((nx-1) x (ny-1) x (nz-1))
+  const int ex = kind ? g.nx - 1 : g.nx, ey = kind ? g.ny - 1 : g.ny,
+            ez = kind ? g.nz - 1 : g.nz;
+  const long tot = (long)ex * ey * ez;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < tot;
+       t += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % ex), j = (int)((t / ex) % ey), k = (int)(t / ((long)ex * ey));
+    const int n = pidx(g, i, j, k);
+    if (to_padded)
+      padded[n] = plain[t];
+    else
+      padded[t] = plain[n];  // here `plain` is the padded source
+  }
+}
+
+void k_pack(Launch L, const Geo& g, int kind, int elem_bytes, const void* plain,
+            void* padded) {
+  k_zero_bytes(L, padded, (size_t)g.npad * elem_bytes);
+  const long tot = (long)g.nreal;
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(pack_kernel<double>, dim3(grid_for(tot)), dim3(kBlock),
+                       0, (hipStream_t)L.stream, g, kind, (const double*)plain,
+                       (double*)padded, 1);
+  else
+    hipLaunchKernelGGL(pack_kernel<float>, dim3(grid_for(tot)), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, g, kind, (const float*)plain,
+                       (float*)padded, 1);
+}
+
+void k_unpack(Launch L, const Geo& g, int kind, int elem_bytes,
+              const void* padded, void* plain) {
+  const long tot = (long)g.nreal;
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(pack_kernel<double>, dim3(grid_for(tot)), dim3(kBlock),
+                       0, (hipStream_t)L.stream, g, kind, (const double*)padded,
+                       (double*)plain, 0);
+  else
+    hipLaunchKernelGGL(pack_kernel<float>, dim3(grid_for(tot)), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, g, kind, (const float*)padded,
+                       (float*)plain, 0);
+}
+
+}  // namespace tl

@@ -1,0 +1,85 @@
+"""CPU checks of the C interface: the library loads, exports every symbol of
+include/*.h, sizes workspaces, and rejects invalid input before touching the
+device."""
+import os
+import re
+from dataclasses import replace
+
+import pytest
+
+from paper_2110_12932_amd import tl
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in ("tl.h", "tl_ops.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(tl_[a-z_0-9]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    lib = tl.load()
+    declared = _declared_symbols()
+    assert declared == set(tl.SYMBOLS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes():
+    wl = W.config1()
+    n = tl.tl_workspace_bytes(wl.mesh, wl.options)
+    # 19 coarse + 8 fine FP64 arrays + 9 fine CG arrays, padded layouts
+    cpad = (50 + 3) * (25 + 3) * (13 + 3)
+    fpad = (81 + 2) * (41 + 2) * (25 + 2)
+    assert n >= (19 * cpad + 17 * fpad) * 8
+    assert n < (19 * cpad + 17 * fpad) * 8 + 10 ** 6
+    mixed = tl.tl_workspace_bytes(wl.mesh, replace(wl.options, precision=W.MIXED))
+    assert mixed < n
+    assert tl.tl_workspace_bytes(replace(wl.mesh, refine=0), wl.options) == 0
+
+
+class _FakeWorkspace:
+    def __init__(self, n):
+        self.n = n
+
+    def data_ptr(self):
+        return 256          # never dereferenced: validation fails first
+
+    def numel(self):
+        return self.n
+
+    def element_size(self):
+        return 1
+
+
+@pytest.mark.parametrize("mutate, what", [
+    (lambda wl: replace(wl, mesh=replace(wl.mesh, win_nx=wl.mesh.nx + 1)), "window"),
+    (lambda wl: replace(wl, mesh=replace(wl.mesh, refine=0)), "refine"),
+    (lambda wl: replace(wl, material=replace(wl.material, T_sol=1700.0)), "T_sol"),
+    (lambda wl: replace(wl, material=replace(wl.material, rho=float("nan"))), "non-finite"),
+    (lambda wl: replace(wl, material=replace(wl.material, pc_kind=1)), "pc_kind"),
+    (lambda wl: replace(wl, scan=W.ScanPath([])), "track"),
+    (lambda wl: replace(wl, options=replace(wl.options, m_time=0)), "m_time"),
+    (lambda wl: replace(wl, options=replace(wl.options, face_quad=7)), "face_quad"),
+    (lambda wl: replace(wl, options=replace(wl.options, dt_coarse=-1.0)), "dt_coarse"),
+])
+def test_create_rejects_invalid_input(mutate, what):
+    wl = mutate(W.config0())
+    with pytest.raises(tl.TLError) as e:
+        tl.tl_create(wl.mesh, wl.material, wl.scan, wl.options, _FakeWorkspace(1 << 30),
+                     stream=0)
+    assert e.value.status == tl.TL_EINVAL
+    assert tl.tl_last_error() != ""
+
+
+def test_create_rejects_small_workspace():
+    wl = W.config0()
+    with pytest.raises(tl.TLError) as e:
+        tl.tl_create(wl.mesh, wl.material, wl.scan, wl.options, _FakeWorkspace(1000), stream=0)
+    assert e.value.status == tl.TL_ENOMEM
