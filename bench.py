@@ -1,0 +1,193 @@
+"""Benchmark of the fine-level two-level time stepping on one MI355X.
+
+Workload (default): the single-track case at paper-like resolution -- a
+2 x 1 x 0.5 mm plate with 50 x 25 x 13 coarse Q1 cells, a window of 10 x 5 x 3
+coarse cells refined 8x (81 x 41 x 25 = 83,025 fine nodes), 8 micro steps per
+25 us macro step, FP64 linear solves.  One benchmark step is one macro step
+of the method (window update, coarse predictor, 7 fine micro steps, the
+two-level correction with its fine and coarse solves, injection, ledger).
+
+Metric: fine DOF-timesteps per second = (free fine nodes x micro steps) /
+wall time of the timed macro steps, inputs resident in HBM.  The result is
+checked against the FP64 CPU oracle by the parity tests, not here.
+
+Prints one JSON line.  `roofline` reports the fine CG iteration kernel (one
+Chronopoulos-Gear PCG iteration fused with the matrix-free Q1 apply):
+algorithmic bytes per launch (read r, w, s_old, p, x, d, kappa, Dinv; write
+r', w', s, p, x) over its average launch duration, timed with HIP events on
+the library's stream for a sample of the launches that did work inside the
+timed region.  `k2_sweep` times the bare operator apply (read v, d, kappa;
+write y) at the workloads' fine shapes and at an HBM-resident grid.
+`cpu_baseline` times the CPU oracle on one complete macro step of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed macro steps")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed macro steps (separate run)")
+    ap.add_argument("--workload", default="config1", choices=["config1", "config0", "config2",
+                                                              "config4"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time every Nth fine operator launch with HIP events (0: off)")
+    ap.add_argument("--k2-sweep", action="store_true",
+                    help="also time the bare operator apply at several shapes")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured HBM bytes per launch of the operator kernel")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl):
+    """The oracle on one complete macro step of the same workload, one core."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    with threadpool_limits(1):
+        sim = oracle.TwoLevel(wl)
+        t0 = time.perf_counter()
+        sim.step()
+        el = time.perf_counter() - t0
+    w = sim.win
+    free = int((~w.dir_f).sum())
+    dof_steps = free * wl.options.m_time
+    return {"value": dof_steps / el, "unit": "fine DOF-timesteps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{wl.name} macro step 0 in full ({wl.options.m_time} micro steps, "
+                      f"{free} free fine nodes, two-level correction included): "
+                      f"{el:.1f} s on 1 core of {os.cpu_count()} "
+                      f"(affinity {len(os.sched_getaffinity(0))})"}
+
+
+def k2_sweep(tl, W, torch):
+    """Bare operator apply y = d v + K[kappa] v, timed with events on the
+    current stream (the library launches on it) over repeated launches."""
+    out = []
+    shapes = [("config1 fine", 80, 40, 24), ("config4 fine", 120, 80, 30),
+              ("HBM-resident 640x640x160", 640, 640, 160)]
+    g = torch.Generator(device="cuda").manual_seed(0)
+    for name, nx, ny, nz in shapes:
+        for prec, dt, eb in ((W.FP64, torch.float64, 8), (W.MIXED, torch.float32, 4)):
+            grid = tl.to_grid(nx, ny, nz, 5e-6, 5e-6, 4.8e-6)
+            npad = tl.tl_op_padded_size(grid)
+            nodes = (nx + 1) * (ny + 1) * (nz + 1)
+            d = torch.rand(npad, dtype=dt, device="cuda", generator=g) * 1e-3
+            kap = 10 + 20 * torch.rand(npad, dtype=dt, device="cuda", generator=g)
+            v = torch.rand(npad, dtype=dt, device="cuda", generator=g) * 300
+            y = torch.empty_like(v)
+            reps = 20 if nodes > 1e7 else 200
+            tl.tl_op_apply(grid, prec, d, kap, v, y, 3)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tl.tl_op_apply(grid, prec, d, kap, v, y, reps)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            gbs = 4 * eb * nodes / (us * 1e-6) / 1e9
+            out.append({"shape": name, "nodes": nodes, "dtype": "f64" if eb == 8 else "f32",
+                        "us_per_launch": round(us, 3), "GB/s": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            del d, kap, v, y
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2110_12932_amd import tl
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    kw = {}
+    if args.precision:
+        kw["precision"] = W.FP64 if args.precision == "fp64" else W.MIXED
+    wl = W.by_name(args.workload, **kw)
+    steps = min(args.steps, wl.n_macro)
+    tl.load()
+
+    # warm-up on its own handle (first launches, code objects, caches)
+    if args.warmup > 0:
+        s = tl.Sim(wl)
+        s.step(min(args.warmup, wl.n_macro))
+        s.close()
+    torch.cuda.synchronize()
+
+    sim = tl.Sim(wl)
+    if args.profile_every > 0:
+        tl.tl_set_profiling(sim.h, args.profile_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = sim.stats()
+    led = sim.ledger()
+    sim.close()
+
+    value = st["fine_dof_steps"] / el
+    fine_nodes = st["fine_nodes"][0] * st["fine_nodes"][1] * st["fine_nodes"][2]
+    elem = 8 if wl.options.precision == W.FP64 else 4
+    # fused CG iteration: read r, w, s_old, p, x, d, kappa, Dinv; write r', w',
+    # s, p, x -- 13 arrays of the CG precision per node
+    bytes_per_launch = 13 * elem * fine_nodes
+    roofline = None
+    if st["fine_op_timed"] > 0:
+        avg_s = st["fine_op_timed_ms"] / st["fine_op_timed"] * 1e-3
+        achieved = bytes_per_launch / avg_s / 1e9
+        traffic = None
+        if args.traffic and os.path.exists(args.traffic):
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "kernel": "cg_iter_tiled_kernel<%s>" % ("double" if elem == 8 else "float"),
+                    "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
+                    "launches_timed": st["fine_op_timed"]}
+    out = {
+        "metric": "fine DOF-timesteps/s",
+        "value": value,
+        "unit": "fine DOF-timesteps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl.options.precision == W.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "fine_nodes": list(st["fine_nodes"]),
+                   "coarse_nodes": list(st["coarse_nodes"]), "m_time": wl.options.m_time,
+                   "dt_coarse": wl.options.dt_coarse,
+                   "precision": "fp64" if wl.options.precision == W.FP64 else "mixed",
+                   "macro_steps_timed": steps},
+        "roofline": roofline,
+        "counters": {k: st[k] for k in ("micro_steps", "newton_fine", "newton_coarse", "cg_fine",
+                                        "cg_coarse", "dn_iters", "window_moves", "fine_solves",
+                                        "coarse_solves", "line_search_halvings")},
+        "ledger_rel_defect": abs((led["stored"] - led["stored0"])
+                                 - (led["absorbed"] - led["bottom"] + led["remap"]))
+                             / max(abs(led["absorbed"]), 1e-300),
+    }
+    if args.k2_sweep:
+        out["k2_sweep"] = k2_sweep(tl, W, torch)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

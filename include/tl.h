@@ -88,7 +88,9 @@ typedef struct {
  * cg_rtol: relative reduction of the preconditioned residual norm in each
  * linear solve; dn_tol [K]: two-level iteration stops when the interface
  * update has max-norm <= dn_tol; dn_theta: fixed relaxation when > 0, else
- * Aitken relaxation started from refine/(refine+1); *_max: iteration caps. */
+ * interface quasi-Newton (IQN-ILS) acceleration whose first step is relaxed
+ * by refine/(refine+1); *_max: iteration caps.  Any relaxation converges to
+ * the same fixed point. */
 typedef struct {
   double dt_coarse;
   int m_time;
@@ -121,6 +123,9 @@ typedef struct {
                                applies (read v,d,kappa + direction update,
                                write q): the roofline numerator              */
   int64_t fine_op_applies;
+  int64_t fine_op_timed;    /* fine CG operator launches timed with events
+                               (tl_set_profiling) and their summed duration */
+  double fine_op_timed_ms;
   int fine_nodes[3];        /* fine grid nodes per axis                      */
   int coarse_nodes[3];
 } tl_stats;
@@ -173,6 +178,12 @@ tl_status tl_get_time(tl_sim* sim, double* t, int64_t* n_macro);
  * written by tl_save for a handle created with the same mesh and options. */
 tl_status tl_save(tl_sim* sim, void* host, size_t cap, size_t* used);
 tl_status tl_load(tl_sim* sim, const void* host, size_t n);
+
+/* Time every sample_every-th launch of the fine CG operator kernel (the
+ * fused direction update and matrix-free operator apply) with HIP events on
+ * the handle's stream; the count and summed duration appear in tl_stats.
+ * 0 switches timing off (the default). */
+tl_status tl_set_profiling(tl_sim* sim, int sample_every);
 
 void tl_destroy(tl_sim* sim);
 

@@ -10,7 +10,6 @@ namespace tl {
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxBlocks = 2048; // grid cap for grid-stride kernels
 constexpr int kMaxSpots = 32;    // laser positions averaged by one load call
-constexpr int kNumCounters = 16;
 
 // Structured Q1 grid in the padded layout: node (i,j,k) at
 // (k+1)*pxy + (j+1)*px + (i+1); the element whose lowest corner is node
@@ -59,14 +58,28 @@ struct SpotSet {
   Spot s[kMaxSpots];
 };
 
-// Device-resident scalars of one level (written by last-block reductions).
+// Device-resident scalars of one level.  Written only by single-workgroup
+// finalize kernels or by workgroup 0 of a CG kernel into a slot no other
+// workgroup of that kernel reads, so no grid-wide synchronisation is needed.
 struct LevelScalars {
   double rnorm2;     // |R_free|^2 at the last evaluated temperature
   double dmax;       // max |alpha delta| over free nodes of the last trial
-  double rz, rz0;    // CG: r.z now and at the start
-  double alpha, beta, pq;
+  double rz0;        // r.z at the start of the current CG solve
+  double gbuf[2];    // CG: gamma_k = r_k.u_k in gbuf[k & 1]
+  double abuf[2];    // CG: alpha_k in abuf[k & 1]
   double sum0, sum1, sum2;   // generic reduction results
-  int iters, done, breakdown, pad;
+  int iters, done, breakdown;
+  int accepted;      // line-search outcome of the last trial
+  int converged;     // Newton converged at the last trial
+  int pad;
+};
+
+// Per-workgroup partial sums: regions of kMaxBlocks doubles.
+enum PartialRegion {
+  kPartCG = 0,     // CG: gamma, delta partials of the last CG kernel (2 regions)
+  kPartRes = 2,    // residual kernel: |R|^2, max|alpha dx|, r.(Dinv r) (3 regions)
+  kPartGen = 5,    // generic sums (loads, energy, bottom reactions)
+  kPartRegions = 6
 };
 
 // Energy ledger slots on the device.
@@ -96,24 +109,42 @@ void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R*
 
 // Residual of one implicit step at the trial T' = T - alpha*dx (dx may be
 // null for alpha = 0); writes T', R, the Jacobian coefficients for CG in
-// precision R_cg, and the CG initial residual; reduces |R_free|^2, max|alpha
-// dx| over free nodes and r.z into sc.
+// precision R_cg and the CG initial residual r (zero on Dirichlet rows);
+// per-workgroup partials of |R_free|^2, max|alpha dx| and r.(Dinv r).
 template <class Rcg, class Rdx>
 void k_residual(Launch L, const Geo& g, const Region& rg, const MatDev& m,
                 double tau, const double* T, const Rdx* dx, double alpha,
                 const double* Told, const double* F, const double* Fext,
                 double* Tt, double* Rout, Rcg* kap, Rcg* d, Rcg* dinv, Rcg* r,
-                Rcg* z, LevelScalars* sc, double* partials, unsigned* counters);
+                double* partials);
 
+// Line-search decision and CG start.  From the residual partials every
+// workgroup decides (identically) whether the trial is accepted (first
+// evaluation, sufficient decrease (1 - 1e-4 alpha) rn0, step <= tol, or the
+// last halving) and whether Newton has converged (accepted and step <= tol);
+// workgroup 0 stores the outcome for the host.  If the Newton iteration
+// continues, w0 = J u0 with u0 = Dinv r0 and the partials of gamma0 = r.u
+// and delta0 = w.u are formed; otherwise `done` is set so the CG kernels of
+// this round return at once.
 template <class R>
-void k_cg_iter(Launch L, const Geo& g, bool first, const R* z, const R* p_old,
-               R* p_new, R* q, const R* d, const R* kap, R* x, R* r, R* zout,
-               const R* dinv, double rtol2, int maxit, LevelScalars* sc,
-               double* partials, unsigned* counters);
+void k_cg_start(Launch L, const Geo& g, int first, double alpha, double rn0,
+                double tol, int last_try, const R* r, const R* dinv,
+                const R* d, const R* kap, R* w, LevelScalars* sc,
+                double* partials);
+
+// One Chronopoulos-Gear PCG iteration k in a single kernel (one reduction):
+//   p = u + beta p, s = w + beta s_old, x += alpha p, r' = r - alpha s,
+//   w' = J u' with u' = Dinv r' formed on the fly at the 27 neighbours,
+//   partials of gamma' = r'.u' and delta' = w'.u'.
+// r, w and s are double-buffered by iteration parity.
+template <class R>
+void k_cg_iter(Launch L, const Geo& g, int k, R* const* rb, R* const* wb,
+               R* const* sb, R* p, R* x, const R* d, const R* kap,
+               const R* dinv, double rtol2, LevelScalars* sc, double* partials);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,
-                  double* ledger_slot, double* partials, unsigned* counters);
+                  double* ledger_slot, double* partials);
 
 void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                       double T_bottom, const double* Ta, const double* Tb,
@@ -122,7 +153,7 @@ void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
 void k_interface_accumulate(Launch L, const Geo& gf, const Window& w,
                             const double* R, double* rho_acc, int init,
                             double bottom_scale, double* ledger_bottom,
-                            double* partials, unsigned* counters);
+                            double* partials);
 
 void k_restrict(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                 const double* rho_acc, const double* Rm, double scale,
@@ -137,19 +168,19 @@ void k_window_shift(Launch L, const Geo& gf, const Geo& gc, const Window& wn,
 
 // Sum over nodes of mass(region) * H(T) (+ into slot, or = when assign).
 void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
-              const double* T, double* slot, int assign, double* partials,
-              unsigned* counters);
+              const double* T, double* slot, int assign, double* partials);
 
 // Sum over nodes with k = 0 of R (scaled, added into slot).
 void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,
-                  double* slot, double* partials, unsigned* counters);
+                  double* slot, double* partials);
 
-// Interface update on the coarse nodes of the immersed window faces:
-// stage 0 reduces max|T - lam|, <dprev, d - dprev>, |d - dprev|^2 into
-// sc->sum0..2 (d = T - lam); stage 1 sets lam += theta d and dprev = d.
-void k_interface_lambda(Launch L, const Geo& gc, const Window& w, int stage,
-                        const double* T, double* lam, double* dprev,
-                        double theta, int first, LevelScalars* sc);
+// Interface values: out[2q] = T[idx[q]], out[2q+1] = lam[idx[q]] for the
+// n coarse interface nodes listed in idx (padded indices); and the inverse
+// scatter lam[idx[q]] = in[q].
+void k_gamma_gather(Launch L, const int* idx, int n, const double* T,
+                    const double* lam, double* out);
+void k_gamma_scatter(Launch L, const int* idx, int n, const double* in,
+                     double* lam);
 
 void k_pack(Launch L, const Geo& g, int kind, int elem_bytes, const void* plain,
             void* padded);

@@ -6,11 +6,15 @@
 // conductivity and ghost nodes hold zeros.  Work is spread with grid-stride
 // loops over the real nodes (workgroups of 256 = 4 wavefronts of 64).
 // Reductions are deterministic: fixed per-thread order, a fixed-shape
-// workgroup tree, and a final sum over the per-workgroup partials in index
-// order by the last workgroup to finish (arrival counted with a device-scope
-// atomic add).
+// workgroup tree, then a sum of the per-workgroup partials in index order.
+// That last sum is never done with grid-wide fences or atomics (a
+// device-scope release on this multi-XCD part writes back the XCD's L2 and
+// costs more than the kernel): either the next kernel of the CG iteration
+// re-sums the partials in every workgroup (kernel boundaries make them
+// visible), or a one-workgroup finalize kernel does it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "tl_internal.h"
@@ -60,39 +64,22 @@ __device__ inline void block_sum(T (&v)[NV], T* lds) {
   }
 }
 
-// Thread 0 publishes its partials, then counts arrivals; returns true (in
-// every thread) in the last workgroup to arrive, after an acquire fence.
-__device__ inline bool arrive_last(unsigned* counter) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
+// One-workgroup finalize of a generic sum: *slot = scale * sum (assign) or
+// *slot += scale * sum.
+__global__ void __launch_bounds__(kBlock)
+finalize_sum_kernel(const double* __restrict__ part, int n, double scale,
+                    double* slot, int assign) {
+  __shared__ double lds[kBlock / 64];
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < n; b += kBlock) v[0] += part[b];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) *slot = assign ? scale * v[0] : *slot + scale * v[0];
 }
 
-__device__ inline double load_acquire(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum NV partial arrays (stride gridDim.x) in fixed order inside the last
-// workgroup; result valid in thread 0.
-template <int NV>
-__device__ inline void final_sum(const double* partials, double (&out)[NV],
-                                 double* lds) {
-  double v[NV];
-#pragma unroll
-  for (int a = 0; a < NV; ++a) v[a] = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
-#pragma unroll
-    for (int a = 0; a < NV; ++a) v[a] += load_acquire(&partials[a * gridDim.x + b]);
-  }
-  block_sum<NV>(v, lds);
-#pragma unroll
-  for (int a = 0; a < NV; ++a) out[a] = v[a];
+static void finalize_sum(Launch L, const double* part, int n, double scale,
+                         double* slot, int assign) {
+  hipLaunchKernelGGL(finalize_sum_kernel, dim3(1), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, part, n, scale, slot, assign);
 }
 
 __device__ inline void node_ijk(const Geo& g, int t, int& i, int& j, int& k) {
@@ -256,36 +243,6 @@ __device__ inline void gather8(const Geo& g, const R* __restrict__ kap, int n,
   }
 }
 
-template <class R>
-__global__ void __launch_bounds__(kBlock)
-op_apply_kernel(Geo g, const R* __restrict__ d, const R* __restrict__ kap,
-                const R* __restrict__ v, R* __restrict__ y) {
-  R w[8];
-#pragma unroll
-  for (int p = 0; p < 8; ++p) w[p] = (R)g.w[p];
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
-       t += gridDim.x * blockDim.x) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    const int n = pidx(g, i, j, k);
-    R v27[27], k8[8];
-    gather27(g, v, n, v27);
-    gather8(g, kap, n, k8);
-    y[n] = d[n] * v27[13] + stencil_apply(v27, k8, w);
-  }
-}
-
-template <class R>
-void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
-                R* y) {
-  hipLaunchKernelGGL(op_apply_kernel<R>, dim3(grid_for(g.nreal)), dim3(kBlock),
-                     0, (hipStream_t)L.stream, g, d, kap, v, y);
-}
-template void k_op_apply<float>(Launch, const Geo&, const float*, const float*,
-                                const float*, float*);
-template void k_op_apply<double>(Launch, const Geo&, const double*,
-                                 const double*, const double*, double*);
-
 // ---------------------------------------------------------------------------
 // K4 + K1: nonlinear residual at a trial temperature, Jacobian coefficients,
 // CG initialisation
@@ -298,9 +255,7 @@ residual_kernel(Geo g, Region rg, MatDev m, double tau,
                 const double* __restrict__ F, const double* __restrict__ Fext,
                 double* __restrict__ Tt, double* __restrict__ Rout,
                 Rcg* __restrict__ kap, Rcg* __restrict__ d,
-                Rcg* __restrict__ dinv, Rcg* __restrict__ r,
-                Rcg* __restrict__ z, LevelScalars* sc, double* partials,
-                unsigned* counters) {
+                Rcg* __restrict__ dinv, Rcg* __restrict__ r, double* partials) {
   __shared__ double lds[6 * kBlock / 64];
   double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
@@ -362,7 +317,6 @@ residual_kernel(Geo g, Region rg, MatDev m, double tau,
     const Rcg rn = dir ? (Rcg)0 : (Rcg)Rn;
     const Rcg zn = di * rn;
     r[n] = rn;
-    z[n] = zn;
     if (!dir) {
       acc[0] += Rn * Rn;
       if (dx != nullptr) acc[1] = fmax(acc[1], fabs(alpha * (double)dx[n]));
@@ -379,41 +333,10 @@ residual_kernel(Geo g, Region rg, MatDev m, double tau,
   if (threadIdx.x == 0) {
     double bm = lds[0];
     for (int wv = 1; wv < kBlock / 64; ++wv) bm = fmax(bm, lds[wv]);
-    partials[blockIdx.x] = sums[0];
-    partials[gridDim.x + blockIdx.x] = bm;
-    partials[2 * gridDim.x + blockIdx.x] = sums[1];
-  }
-  __syncthreads();
-  if (arrive_last(&counters[0])) {
-    double s0 = 0.0, s2 = 0.0, bm = 0.0;
-    double v[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
-      v[0] += load_acquire(&partials[b]);
-      v[1] += load_acquire(&partials[2 * gridDim.x + b]);
-      bm = fmax(bm, load_acquire(&partials[gridDim.x + b]));
-    }
-    __syncthreads();
-    bm = wave_max(bm);
-    block_sum<2>(v, lds + 8);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = bm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s0 = v[0];
-      s2 = v[1];
-      double mm = lds[0];
-      for (int wv = 1; wv < kBlock / 64; ++wv) mm = fmax(mm, lds[wv]);
-      sc->rnorm2 = s0;
-      sc->dmax = mm;
-      sc->rz = s2;
-      sc->rz0 = s2;
-      sc->beta = 0.0;
-      sc->alpha = 0.0;
-      sc->iters = 0;
-      sc->breakdown = 0;
-      sc->done = (s2 == 0.0) ? 1 : 0;
-      atomicExch(&counters[0], 0u);
-    }
+    double* part = partials + kPartRes * kMaxBlocks;
+    part[blockIdx.x] = sums[0];
+    part[kMaxBlocks + blockIdx.x] = bm;
+    part[2 * kMaxBlocks + blockIdx.x] = sums[1];
   }
 }
 
@@ -422,176 +345,439 @@ void k_residual(Launch L, const Geo& g, const Region& rg, const MatDev& m,
                 double tau, const double* T, const Rdx* dx, double alpha,
                 const double* Told, const double* F, const double* Fext,
                 double* Tt, double* Rout, Rcg* kap, Rcg* d, Rcg* dinv, Rcg* r,
-                Rcg* z, LevelScalars* sc, double* partials,
-                unsigned* counters) {
+                double* partials) {
   hipLaunchKernelGGL((residual_kernel<Rcg, Rdx>), dim3(grid_for(g.nreal)),
                      dim3(kBlock), 0, (hipStream_t)L.stream, g, rg, m, tau, T,
-                     dx, alpha, Told, F, Fext, Tt, Rout, kap, d, dinv, r, z,
-                     sc, partials, counters);
+                     dx, alpha, Told, F, Fext, Tt, Rout, kap, d, dinv, r,
+                     partials);
 }
 template void k_residual<double, double>(Launch, const Geo&, const Region&,
                                          const MatDev&, double, const double*,
                                          const double*, double, const double*,
                                          const double*, const double*, double*,
                                          double*, double*, double*, double*,
-                                         double*, double*, LevelScalars*,
-                                         double*, unsigned*);
+                                         double*, double*);
 template void k_residual<float, float>(Launch, const Geo&, const Region&,
                                        const MatDev&, double, const double*,
                                        const float*, double, const double*,
                                        const double*, const double*, double*,
                                        double*, float*, float*, float*, float*,
-                                       float*, LevelScalars*, double*,
-                                       unsigned*);
+                                       double*);
 
 // ---------------------------------------------------------------------------
-// K2 + K3: one Jacobi-preconditioned CG iteration in two kernels.
-//   spmv:   p_new = z + beta p_old (first: p_new = z), q = J p_new,
-//           alpha = rz / (p_new . q)
-//   update: x += alpha p_new (first: x = alpha p_new), r -= alpha q,
-//           z = Dinv r, beta = r.z / rz, convergence test
-// Every kernel returns at once once the device flag `done` is set.
+// LDS-tiled CG kernels.  A workgroup owns a TX x TY x TZ tile of nodes (one
+// node per thread).  The halo tile (TX+2)(TY+2)(TZ+2) of the operator input
+// is formed once into LDS from coalesced global loads, together with the
+// (TX+1)(TY+1)(TZ+1) element conductivities; the 27-point stencil then reads
+// LDS only.  Halo loads are issued before the scalar reduction so that both
+// latencies overlap.  Tiles past the grid's far edge are partially empty;
+// their out-of-range halo entries are zero.
+// ---------------------------------------------------------------------------
+constexpr int TX = 16, TY = 4, TZ = 4;
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HN = HX * HY * HZ;
+constexpr int EX = TX + 1, EY = TY + 1, EZ = TZ + 1, EN = EX * EY * EZ;
+constexpr int HPT = (HN + kBlock - 1) / kBlock;
+constexpr int EPT = (EN + kBlock - 1) / kBlock;
+static_assert(TX * TY * TZ == kBlock, "one node per thread");
+
+struct Tile {
+  int ox, oy, oz;   // first node of the tile
+  int tx, ty, tz;   // this thread's node inside the tile
+};
+
+__device__ inline Tile tile_of(int b, int ntx, int nty) {
+  Tile t;
+  t.ox = (b % ntx) * TX;
+  t.oy = ((b / ntx) % nty) * TY;
+  t.oz = (b / (ntx * nty)) * TZ;
+  t.tx = threadIdx.x % TX;
+  t.ty = (threadIdx.x / TX) % TY;
+  t.tz = threadIdx.x / (TX * TY);
+  return t;
+}
+
+// padded index of halo entry h of the tile, or -1 when it lies past the
+// ghost layer of the grid
+__device__ inline int halo_index(const Geo& g, const Tile& t, int h) {
+  const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+  const int i = t.ox + hx - 1, j = t.oy + hy - 1, k = t.oz + hz - 1;
+  if (i > g.nx || j > g.ny || k > g.nz) return -1;
+  return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+}
+// padded index of element entry e (element with lowest corner at
+// (ox-1+ex, ...)), or -1 past the ghost layer
+__device__ inline int elem_index(const Geo& g, const Tile& t, int e) {
+  const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
+  const int i = t.ox + ex - 1, j = t.oy + ey - 1, k = t.oz + ez - 1;
+  if (i > g.nx || j > g.ny || k > g.nz) return -1;
+  return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+}
+
+template <class R>
+__device__ inline void load_kappa_tile(const Geo& g, const Tile& t,
+                                       const R* __restrict__ kap, R* k_s) {
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    if (e < EN) {
+      const int n = elem_index(g, t, e);
+      k_s[e] = n >= 0 ? kap[n] : (R)0;
+    }
+  }
+}
+
+// stencil of the node (tx,ty,tz) from the LDS tiles
+template <class R>
+__device__ inline R stencil_lds(const Tile& t, const R* u_s, const R* k_s,
+                                const R (&w)[8]) {
+  R u27[27], k8[8];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx)
+        u27[N27(dx, dy, dz)] =
+            u_s[(t.tz + 1 + dz) * (HX * HY) + (t.ty + 1 + dy) * HX + (t.tx + 1 + dx)];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    k8[e] = k_s[(t.tz + 1 - ez) * (EX * EY) + (t.ty + 1 - ey) * EX + (t.tx + 1 - ex)];
+  }
+  return stencil_apply(u27, k8, w);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
+                     const R* __restrict__ r_in, const R* __restrict__ w_in,
+                     const R* __restrict__ s_old, R* __restrict__ r_out,
+                     R* __restrict__ w_out, R* __restrict__ s_out,
+                     R* __restrict__ p, R* __restrict__ x,
+                     const R* __restrict__ d, const R* __restrict__ kap,
+                     const R* __restrict__ dinv, double rtol2, int nparts,
+                     LevelScalars* sc, double* partials) {
+  __shared__ R u_s[HN];
+  __shared__ R k_s[EN];
+  __shared__ R lds[2 * kBlock / 64];
+  __shared__ R bc[2];
+  if (sc->done) return;
+  // 1. halo loads of the first tile, issued before the reduction so that
+  // both latencies overlap
+  R hr[HPT], hw[HPT], hs[HPT], hd[HPT];
+  auto load_halo = [&](const Tile& t) {
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      const int n = h < HN ? halo_index(g, t, h) : -1;
+      hr[q] = n >= 0 ? r_in[n] : (R)0;
+      hw[q] = n >= 0 ? w_in[n] : (R)0;
+      hs[q] = (n >= 0 && kit > 0) ? s_old[n] : (R)0;
+      hd[q] = n >= 0 ? dinv[n] : (R)0;
+    }
+  };
+  load_halo(tile_of(blockIdx.x, ntx, nty));
+  // 2. gamma_k, delta_k from the previous kernel's partials
+  {
+    R v[2] = {(R)0, (R)0};
+    const double* pg = partials + kPartCG * kMaxBlocks;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) {
+      v[0] += (R)pg[b];
+      v[1] += (R)pg[kMaxBlocks + b];
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+      bc[0] = v[0];
+      bc[1] = v[1];
+    }
+    __syncthreads();
+  }
+  const R gamma = bc[0], delta = bc[1];
+  R alpha, beta;
+  if (kit == 0) {
+    beta = (R)0;
+    alpha = gamma / delta;
+  } else {
+    const R gamma_prev = (R)sc->gbuf[(kit - 1) & 1];
+    const R alpha_prev = (R)sc->abuf[(kit - 1) & 1];
+    if ((double)gamma <= rtol2 * sc->rz0 || !isfinite((double)gamma)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->done = 1;
+        sc->iters = kit;
+        if (!isfinite((double)gamma)) sc->breakdown = 2;
+      }
+      return;
+    }
+    beta = gamma / gamma_prev;
+    alpha = gamma / (delta - beta * gamma / alpha_prev);
+  }
+  if (!(alpha > (R)0) || !isfinite((double)alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 1;
+      sc->iters = kit;
+      sc->breakdown = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->gbuf[kit & 1] = (double)gamma;
+    sc->abuf[kit & 1] = (double)alpha;
+    sc->iters = kit + 1;
+  }
+  R wts[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+  R acc[2] = {(R)0, (R)0};
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const Tile t = tile_of(tile, ntx, nty);
+    if (tile != (int)blockIdx.x) load_halo(t);
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    const bool active = i < g.nx && j < g.ny && k < g.nz;
+    const int n = active ? pidx(g, i, j, k) : 0;
+    R r_own = (R)0, w_own = (R)0, s_prev = (R)0, di_own = (R)0,
+      p_own = (R)0, x_own = (R)0, d_own = (R)0;
+    if (active) {
+      r_own = r_in[n];
+      w_own = w_in[n];
+      di_own = dinv[n];
+      d_own = d[n];
+      if (kit > 0) {
+        s_prev = s_old[n];
+        p_own = p[n];
+        x_own = x[n];
+      }
+    }
+    load_kappa_tile(g, t, kap, k_s);
+    // 3. u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      if (h < HN) u_s[h] = hd[q] * (hr[q] - alpha * (hw[q] + beta * hs[q]));
+    }
+    __syncthreads();
+    // 4. the node's own recurrences and w_{k+1} = J u_{k+1}
+    if (active) {
+      const R s_k = w_own + beta * s_prev;
+      const R u_k = di_own * r_own;
+      const R pn = u_k + beta * p_own;
+      p[n] = pn;
+      s_out[n] = s_k;
+      x[n] = x_own + alpha * pn;
+      const R r1 = r_own - alpha * s_k;
+      r_out[n] = r1;
+      const R u1 = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
+      const R w1 = d_own * u1 + stencil_lds(t, u_s, k_s, wts);
+      w_out[n] = w1;
+      acc[0] += r1 * u1;
+      acc[1] += w1 * u1;
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    partials[kPartCG * kMaxBlocks + blockIdx.x] = (double)acc[0];
+    partials[(kPartCG + 1) * kMaxBlocks + blockIdx.x] = (double)acc[1];
+  }
+}
+
+// Tiled matrix-free operator y = d v + K[kap] v (every node).
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+op_apply_tiled_kernel(Geo g, int ntx, int nty, const R* __restrict__ d,
+                      const R* __restrict__ kap, const R* __restrict__ v,
+                      R* __restrict__ y) {
+  __shared__ R u_s[HN];
+  __shared__ R k_s[EN];
+  const Tile t = tile_of(blockIdx.x, ntx, nty);
+#pragma unroll
+  for (int q = 0; q < HPT; ++q) {
+    const int h = threadIdx.x + q * kBlock;
+    if (h < HN) {
+      const int n = halo_index(g, t, h);
+      u_s[h] = n >= 0 ? v[n] : (R)0;
+    }
+  }
+  load_kappa_tile(g, t, kap, k_s);
+  __syncthreads();
+  const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+  if (i < g.nx && j < g.ny && k < g.nz) {
+    R wts[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+    const int n = pidx(g, i, j, k);
+    const R vc = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
+    y[n] = d[n] * vc + stencil_lds(t, u_s, k_s, wts);
+  }
+}
+
+static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
+  ntx = (g.nx + TX - 1) / TX;
+  nty = (g.ny + TY - 1) / TY;
+  ntz = (g.nz + TZ - 1) / TZ;
+}
+
+// ---------------------------------------------------------------------------
+// K1/K3: line-search decision and CG start; K2 + K3: one Chronopoulos-Gear
+// PCG iteration per kernel.
+//
+// CG recurrences (preconditioner M = diag(J)):
+//   u_k = Dinv r_k, w_k = J u_k, gamma_k = r_k.u_k, delta_k = w_k.u_k,
+//   beta_k = gamma_k / gamma_{k-1} (beta_0 = 0),
+//   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}) (alpha_0 =
+//   gamma_0 / delta_0),
+//   p_k = u_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}  (= J p_k),
+//   x_{k+1} = x_k + alpha_k p_k, r_{k+1} = r_k - alpha_k s_k.
+// Kernel k forms gamma_k, delta_k from kernel k-1's per-workgroup partials
+// (identically in every workgroup), updates the node's own p, s, x, r and
+// computes w_{k+1} = J u_{k+1} with u_{k+1} at the 27 neighbours rebuilt from
+// r_k, w_k, s_{k-1} -- so each iteration needs one kernel and one reduction.
+// Workgroup 0 records gamma_k and alpha_k in slot k & 1, which no other
+// workgroup of kernel k reads.  Once `done` is set later kernels return.
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-cg_spmv_kernel(Geo g, int first, const R* __restrict__ z,
-               const R* __restrict__ p_old, R* __restrict__ p_new,
-               R* __restrict__ q, const R* __restrict__ d,
-               const R* __restrict__ kap, LevelScalars* sc, double* partials,
-               unsigned* counters) {
-  __shared__ R lds[kBlock / 64];
-  __shared__ double ldsd[kBlock / 64];
-  if (sc->done) return;
-  const R beta = first ? (R)0 : (R)sc->beta;
-  R w[8];
+cg_start_kernel(Geo g, int first, double alpha, double rn0, double tol,
+                int last_try, int nparts, const R* __restrict__ r,
+                const R* __restrict__ dinv, const R* __restrict__ d,
+                const R* __restrict__ kap, R* __restrict__ w, LevelScalars* sc,
+                double* partials) {
+  __shared__ double lds[2 * kBlock / 64];
+  __shared__ double ldm[kBlock / 64];
+  __shared__ double bc[3];
+  __shared__ R ldr[2 * kBlock / 64];
+  // 1. residual reductions (every workgroup, same order)
+  {
+    const double* part = partials + kPartRes * kMaxBlocks;
+    double v[2] = {0.0, 0.0};
+    double bm = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) {
+      v[0] += part[b];
+      v[1] += part[2 * kMaxBlocks + b];
+      bm = fmax(bm, part[kMaxBlocks + b]);
+    }
+    bm = wave_max(bm);
+    block_sum<2>(v, lds);
+    if ((threadIdx.x & 63) == 0) ldm[threadIdx.x >> 6] = bm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mm = ldm[0];
+      for (int wv = 1; wv < kBlock / 64; ++wv) mm = fmax(mm, ldm[wv]);
+      bc[0] = v[0];
+      bc[1] = mm;
+      bc[2] = v[1];
+    }
+    __syncthreads();
+  }
+  const double rnorm2 = bc[0], dmax = bc[1], rz = bc[2];
+  const double rn = sqrt(rnorm2);
+  const bool finite = isfinite(rnorm2) && isfinite(dmax);
+  bool accepted, converged;
+  if (first) {
+    accepted = true;
+    converged = false;
+  } else {
+    accepted = !finite || rn <= (1.0 - 1e-4 * alpha) * rn0 || dmax <= tol ||
+               last_try;
+    converged = accepted && finite && dmax <= tol;
+  }
+  const bool run = accepted && !converged && finite && rz > 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rnorm2 = rnorm2;
+    sc->dmax = dmax;
+    sc->rz0 = rz;
+    sc->accepted = accepted ? 1 : 0;
+    sc->converged = converged ? 1 : 0;
+    sc->breakdown = finite ? 0 : 3;
+    sc->iters = 0;
+    sc->done = run ? 0 : 1;
+  }
+  if (!run) return;
+  // 2. w0 = J u0, u0 = Dinv r0
+  R wts[8];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) w[p] = (R)g.w[p];
-  R acc[1] = {(R)0};
+  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+  R acc[2] = {(R)0, (R)0};
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
        t += gridDim.x * blockDim.x) {
     int i, j, k;
     node_ijk(g, t, i, j, k);
     const int n = pidx(g, i, j, k);
-    R p27[27], k8[8];
-    if (first) {
-      gather27(g, z, n, p27);
-    } else {
+    R u27[27], k8[8];
 #pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
+    for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+      for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int o = n + dx + dy * g.px + dz * g.pxy;
-            p27[N27(dx, dy, dz)] = z[o] + beta * p_old[o];
-          }
-    }
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int o = n + dx + dy * g.px + dz * g.pxy;
+          u27[N27(dx, dy, dz)] = dinv[o] * r[o];
+        }
     gather8(g, kap, n, k8);
-    const R pc = p27[13];
-    const R qn = d[n] * pc + stencil_apply(p27, k8, w);
-    p_new[n] = pc;
-    q[n] = qn;
-    acc[0] += pc * qn;
+    const R un = u27[13];
+    const R wn = d[n] * un + stencil_apply(u27, k8, wts);
+    w[n] = wn;
+    acc[0] += r[n] * un;
+    acc[1] += wn * un;
   }
-  block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = (double)acc[0];
-  __syncthreads();
-  if (arrive_last(&counters[1])) {
-    // the cross-workgroup sum stays in the CG precision
-    R v[1] = {(R)0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
-      v[0] += (R)load_acquire(&partials[b]);
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) {
-      const R pq = v[0];
-      const R rz = (R)sc->rz;
-      sc->pq = (double)pq;
-      if (!(pq > (R)0) || !isfinite((double)pq)) {
-        sc->breakdown = 1;
-        sc->done = 1;
-        sc->alpha = 0.0;
-      } else {
-        sc->alpha = (double)(rz / pq);
-      }
-      atomicExch(&counters[1], 0u);
-    }
-  }
-  (void)ldsd;
-}
-
-template <class R>
-__global__ void __launch_bounds__(kBlock)
-cg_update_kernel(Geo g, int first, const R* __restrict__ p,
-                 const R* __restrict__ q, R* __restrict__ x,
-                 R* __restrict__ r, R* __restrict__ z,
-                 const R* __restrict__ dinv, double rtol2, int maxit,
-                 LevelScalars* sc, double* partials, unsigned* counters) {
-  __shared__ R lds[kBlock / 64];
-  if (sc->done) return;
-  const R alpha = (R)sc->alpha;
-  R acc[1] = {(R)0};
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
-       t += gridDim.x * blockDim.x) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    const int n = pidx(g, i, j, k);
-    const R pn = p[n];
-    x[n] = first ? alpha * pn : x[n] + alpha * pn;
-    const R rn = r[n] - alpha * q[n];
-    const R zn = dinv[n] * rn;
-    r[n] = rn;
-    z[n] = zn;
-    acc[0] += rn * zn;
-  }
-  block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = (double)acc[0];
-  __syncthreads();
-  if (arrive_last(&counters[2])) {
-    R v[1] = {(R)0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
-      v[0] += (R)load_acquire(&partials[b]);
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) {
-      const R rz_new = v[0];
-      const R rz = (R)sc->rz;
-      sc->beta = (double)(rz_new / rz);
-      sc->rz = (double)rz_new;
-      const int it = sc->iters + 1;
-      sc->iters = it;
-      if (!isfinite((double)rz_new)) {
-        sc->breakdown = 2;
-        sc->done = 1;
-      } else if ((double)rz_new <= rtol2 * sc->rz0 || it >= maxit) {
-        sc->done = 1;
-      }
-      atomicExch(&counters[2], 0u);
-    }
+  block_sum<2>(acc, ldr);
+  if (threadIdx.x == 0) {
+    partials[kPartCG * kMaxBlocks + blockIdx.x] = (double)acc[0];
+    partials[(kPartCG + 1) * kMaxBlocks + blockIdx.x] = (double)acc[1];
   }
 }
 
 template <class R>
-void k_cg_iter(Launch L, const Geo& g, bool first, const R* z, const R* p_old,
-               R* p_new, R* q, const R* d, const R* kap, R* x, R* r, R* zout,
-               const R* dinv, double rtol2, int maxit, LevelScalars* sc,
-               double* partials, unsigned* counters) {
+void k_cg_start(Launch L, const Geo& g, int first, double alpha, double rn0,
+                double tol, int last_try, const R* r, const R* dinv,
+                const R* d, const R* kap, R* w, LevelScalars* sc,
+                double* partials) {
   const int nb = grid_for(g.nreal);
-  hipLaunchKernelGGL(cg_spmv_kernel<R>, dim3(nb), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, g, first ? 1 : 0, z, p_old, p_new,
-                     q, d, kap, sc, partials, counters);
-  hipLaunchKernelGGL(cg_update_kernel<R>, dim3(nb), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, g, first ? 1 : 0, p_new, q, x, r,
-                     zout, dinv, rtol2, maxit, sc, partials, counters);
+  hipLaunchKernelGGL(cg_start_kernel<R>, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, first, alpha, rn0, tol,
+                     last_try, nb, r, dinv, d, kap, w, sc, partials);
 }
-template void k_cg_iter<float>(Launch, const Geo&, bool, const float*,
-                               const float*, float*, float*, const float*,
-                               const float*, float*, float*, float*,
-                               const float*, double, int, LevelScalars*,
-                               double*, unsigned*);
-template void k_cg_iter<double>(Launch, const Geo&, bool, const double*,
-                                const double*, double*, double*, const double*,
-                                const double*, double*, double*, double*,
-                                const double*, double, int, LevelScalars*,
-                                double*, unsigned*);
+template <class R>
+void k_cg_iter(Launch L, const Geo& g, int k, R* const* rb, R* const* wb,
+               R* const* sb, R* p, R* x, const R* d, const R* kap,
+               const R* dinv, double rtol2, LevelScalars* sc,
+               double* partials) {
+  const int a = k & 1;
+  int ntx, nty, ntz;
+  tiles_of(g, ntx, nty, ntz);
+  const int ntiles = ntx * nty * ntz;
+  const int nb = std::min(ntiles, kMaxBlocks);
+  // the previous kernel (CG start or iteration) wrote one partial per
+  // workgroup of its own grid
+  const int nprev = k == 0 ? grid_for(g.nreal) : nb;
+  hipLaunchKernelGGL(cg_iter_tiled_kernel<R>, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, ntx, nty, ntiles, k, rb[a],
+                     wb[a], sb[1 - a], rb[1 - a], wb[1 - a], sb[a], p, x, d,
+                     kap, dinv, rtol2, nprev, sc, partials);
+}
+template <class R>
+void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
+                R* y) {
+  int ntx, nty, ntz;
+  tiles_of(g, ntx, nty, ntz);
+  hipLaunchKernelGGL(op_apply_tiled_kernel<R>, dim3(ntx * nty * ntz),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, g, ntx, nty, d,
+                     kap, v, y);
+}
+template void k_op_apply<float>(Launch, const Geo&, const float*, const float*,
+                                const float*, float*);
+template void k_op_apply<double>(Launch, const Geo&, const double*,
+                                 const double*, const double*, double*);
+
+#define TL_CG_INST(R)                                                         \
+  template void k_cg_start<R>(Launch, const Geo&, int, double, double, double, \
+                              int, const R*, const R*, const R*, const R*, R*, \
+                              LevelScalars*, double*);                        \
+  template void k_cg_iter<R>(Launch, const Geo&, int, R* const*, R* const*,   \
+                             R* const*, R*, R*, const R*, const R*, const R*, \
+                             double, LevelScalars*, double*);
+TL_CG_INST(float)
+TL_CG_INST(double)
+#undef TL_CG_INST
 
 // ---------------------------------------------------------------------------
 // K6: surface laser load F_i = sum over top faces of int q phi_i dA (n_q x n_q
@@ -601,8 +787,7 @@ template void k_cg_iter<double>(Launch, const Geo&, bool, const double*,
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 laser_load_kernel(Geo g, SpotSet sp, int fI0, int fI1, int fJ0, int fJ1,
-                  double* __restrict__ F, double scale, double* slot,
-                  double* partials, unsigned* counters) {
+                  double* __restrict__ F, double* partials) {
   __shared__ double lds[kBlock / 64];
   double acc[1] = {0.0};
   const int ntop = g.nx * g.ny;
@@ -644,25 +829,19 @@ laser_load_kernel(Geo g, SpotSet sp, int fI0, int fI1, int fJ0, int fJ1,
     acc[0] += f;
   }
   block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-  __syncthreads();
-  if (arrive_last(&counters[3])) {
-    double v[1];
-    final_sum<1>(partials, v, lds);
-    if (threadIdx.x == 0) {
-      if (slot != nullptr) *slot += scale * v[0];
-      atomicExch(&counters[3], 0u);
-    }
-  }
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
 }
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,
-                  double* ledger_slot, double* partials, unsigned* counters) {
-  hipLaunchKernelGGL(laser_load_kernel, dim3(grid_for((long)g.nx * g.ny)),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, g, spots, fI0,
-                     fI1, fJ0, fJ1, F, ledger_scale, ledger_slot, partials,
-                     counters);
+                  double* ledger_slot, double* partials) {
+  const int nb = grid_for((long)g.nx * g.ny);
+  hipLaunchKernelGGL(laser_load_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, spots, fI0, fI1, fJ0, fJ1, F,
+                     partials);
+  if (ledger_slot != nullptr)
+    finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, ledger_scale,
+                 ledger_slot, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,8 +915,7 @@ void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 interface_acc_kernel(Geo gf, Window w, const double* __restrict__ R,
-                     double* __restrict__ rho, int init, double bscale,
-                     double* bslot, double* partials, unsigned* counters) {
+                     double* __restrict__ rho, int init, double* partials) {
   __shared__ double lds[kBlock / 64];
   double acc[1] = {0.0};
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < gf.nreal;
@@ -752,25 +930,19 @@ interface_acc_kernel(Geo gf, Window w, const double* __restrict__ R,
     }
   }
   block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-  __syncthreads();
-  if (arrive_last(&counters[4])) {
-    double v[1];
-    final_sum<1>(partials, v, lds);
-    if (threadIdx.x == 0) {
-      if (bslot != nullptr) *bslot += bscale * v[0];
-      atomicExch(&counters[4], 0u);
-    }
-  }
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
 }
 
 void k_interface_accumulate(Launch L, const Geo& gf, const Window& w,
                             const double* R, double* rho_acc, int init,
                             double bottom_scale, double* ledger_bottom,
-                            double* partials, unsigned* counters) {
-  hipLaunchKernelGGL(interface_acc_kernel, dim3(grid_for(gf.nreal)),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, gf, w, R, rho_acc,
-                     init, bottom_scale, ledger_bottom, partials, counters);
+                            double* partials) {
+  const int nb = grid_for(gf.nreal);
+  hipLaunchKernelGGL(interface_acc_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, gf, w, R, rho_acc, init, partials);
+  if (ledger_bottom != nullptr && w.bottom)
+    finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, bottom_scale,
+                 ledger_bottom, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -890,7 +1062,7 @@ void k_window_shift(Launch L, const Geo& gf, const Geo& gc, const Window& wn,
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 energy_kernel(Geo g, Region rg, MatDev m, const double* __restrict__ T,
-              double* slot, int assign, double* partials, unsigned* counters) {
+              double* partials) {
   __shared__ double lds[kBlock / 64];
   double acc[1] = {0.0};
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
@@ -906,32 +1078,19 @@ energy_kernel(Geo g, Region rg, MatDev m, const double* __restrict__ T,
     if (nact > 0.0) acc[0] += g.vol8 * nact * enthalpy(T[pidx(g, i, j, k)], m);
   }
   block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-  __syncthreads();
-  if (arrive_last(&counters[5])) {
-    double v[1];
-    final_sum<1>(partials, v, lds);
-    if (threadIdx.x == 0) {
-      if (assign)
-        *slot = v[0];
-      else
-        *slot += v[0];
-      atomicExch(&counters[5], 0u);
-    }
-  }
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
 }
 
 void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
-              const double* T, double* slot, int assign, double* partials,
-              unsigned* counters) {
-  hipLaunchKernelGGL(energy_kernel, dim3(grid_for(g.nreal)), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, g, rg, m, T, slot, assign,
-                     partials, counters);
+              const double* T, double* slot, int assign, double* partials) {
+  const int nb = grid_for(g.nreal);
+  hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, rg, m, T, partials);
+  finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, 1.0, slot, assign);
 }
 
 __global__ void __launch_bounds__(kBlock)
-bottom_sum_kernel(Geo g, const double* __restrict__ R, double scale,
-                  double* slot, double* partials, unsigned* counters) {
+bottom_sum_kernel(Geo g, const double* __restrict__ R, double* partials) {
   __shared__ double lds[kBlock / 64];
   double acc[1] = {0.0};
   const int nb = g.nx * g.ny;
@@ -939,81 +1098,49 @@ bottom_sum_kernel(Geo g, const double* __restrict__ R, double scale,
        t += gridDim.x * blockDim.x)
     acc[0] += R[pidx(g, t % g.nx, t / g.nx, 0)];
   block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-  __syncthreads();
-  if (arrive_last(&counters[6])) {
-    double v[1];
-    final_sum<1>(partials, v, lds);
-    if (threadIdx.x == 0) {
-      *slot += scale * v[0];
-      atomicExch(&counters[6], 0u);
-    }
-  }
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
 }
 
 void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,
-                  double* slot, double* partials, unsigned* counters) {
-  hipLaunchKernelGGL(bottom_sum_kernel, dim3(grid_for((long)g.nx * g.ny)),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, g, R, scale, slot,
-                     partials, counters);
+                  double* slot, double* partials) {
+  const int nb = grid_for((long)g.nx * g.ny);
+  hipLaunchKernelGGL(bottom_sum_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, R, partials);
+  finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, scale, slot, 0);
 }
 
 // ---------------------------------------------------------------------------
-// Interface (lambda) update of the two-level iteration: one workgroup over
-// the coarse nodes of the closed window box.
+// Interface values of the two-level iteration (coarse nodes on the immersed
+// window faces), gathered for the host-side relaxation and scattered back.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
-lambda_kernel(Geo gc, Window w, int stage, const double* __restrict__ T,
-              double* __restrict__ lam, double* __restrict__ dprev,
-              double theta, int first, LevelScalars* sc) {
-  __shared__ double lds[2 * kBlock / 64];
-  __shared__ double ldm[kBlock / 64];
-  const int bx = w.wx + 1, by = w.wy + 1, bz = w.wz + 1;
-  Region rg;
-  rg.faces = w.faces;
-  double mx = 0.0;
-  double acc[2] = {0.0, 0.0};
-  for (int t = threadIdx.x; t < bx * by * bz; t += kBlock) {
-    const int li = t % bx, lj = (t / bx) % by, lk = t / (bx * by);
-    const int I = w.I0 + li, J = w.J0 + lj, K = w.K0 + lk;
-    if (!on_immersed_face(rg, I, J, K, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy,
-                          w.K0))
-      continue;
-    const int n = pidx(gc, I, J, K);
-    const double dn = T[n] - lam[n];
-    if (stage == 0) {
-      mx = fmax(mx, fabs(dn));
-      if (!first) {
-        const double dd = dn - dprev[n];
-        acc[0] += dprev[n] * dd;
-        acc[1] += dd * dd;
-      }
-    } else {
-      lam[n] = lam[n] + theta * dn;
-      dprev[n] = dn;
-    }
-  }
-  if (stage != 0) return;
-  mx = wave_max(mx);
-  block_sum<2>(acc, lds);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) ldm[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = ldm[0];
-    for (int wv = 1; wv < kBlock / 64; ++wv) m = fmax(m, ldm[wv]);
-    sc->sum0 = m;
-    sc->sum1 = acc[0];
-    sc->sum2 = acc[1];
+__global__ void gamma_gather_kernel(const int* __restrict__ idx, int n,
+                                    const double* __restrict__ T,
+                                    const double* __restrict__ lam,
+                                    double* __restrict__ out) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += gridDim.x * blockDim.x) {
+    out[2 * q] = T[idx[q]];
+    out[2 * q + 1] = lam[idx[q]];
   }
 }
-
-void k_interface_lambda(Launch L, const Geo& gc, const Window& w, int stage,
-                        const double* T, double* lam, double* dprev,
-                        double theta, int first, LevelScalars* sc) {
-  hipLaunchKernelGGL(lambda_kernel, dim3(1), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, gc, w, stage, T, lam, dprev, theta,
-                     first, sc);
+__global__ void gamma_scatter_kernel(const int* __restrict__ idx, int n,
+                                     const double* __restrict__ in,
+                                     double* __restrict__ lam) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += gridDim.x * blockDim.x)
+    lam[idx[q]] = in[q];
+}
+void k_gamma_gather(Launch L, const int* idx, int n, const double* T,
+                    const double* lam, double* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gamma_gather_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, idx, n, T, lam, out);
+}
+void k_gamma_scatter(Launch L, const int* idx, int n, const double* in,
+                     double* lam) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gamma_scatter_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, idx, n, in, lam);
 }
 
 // ---------------------------------------------------------------------------

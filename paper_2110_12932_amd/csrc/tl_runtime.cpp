@@ -56,6 +56,7 @@ inline void hip_check(hipError_t e, const char* what) {
 }
 
 constexpr int kLineSearchMax = 12;  // halvings tried before a step is taken anyway
+constexpr int kProfPairs = 64;      // event pairs held between host syncs
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -63,15 +64,16 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Sizes of everything carved out of the caller's workspace.
 struct Layout {
   Geo gc, gf;
-  size_t off_c[19], off_fd[8], off_fcg[9];
-  size_t off_scal, off_ledger, off_partials, off_counters;
+  size_t off_c[22], off_fd[8], off_fcg[12];
+  size_t off_scal, off_ledger, off_partials, off_gidx, off_gbuf;
+  int gamma_cap;
   size_t total;
   int cg_bytes;
 };
 
-constexpr int kCoarseArrays = 19;  // Tn Tpred cur trial lam dprev R Fall Fout ext | kap d dinv r z x p0 p1 q
+constexpr int kCoarseArrays = 22;  // Tn Tpred cur trial lam dprev R Fall Fout ext | 12 CG arrays
 constexpr int kFineD = 8;          // state prev cur trial alt R F rho
-constexpr int kFineCG = 9;         // kap d dinv r z x p0 p1 q
+constexpr int kFineCG = 12;        // kap d dinv r0 r1 w0 w1 s0 s1 p x0 x1
 
 Layout make_layout(const tl_mesh& me, const tl_options& op) {
   Layout L;
@@ -90,8 +92,11 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   for (int a = 0; a < kFineCG; ++a) { L.off_fcg[a] = off; off += fcg; }
   L.off_scal = off; off += align_up(2 * sizeof(LevelScalars));
   L.off_ledger = off; off += align_up(sizeof(LedgerDev));
-  L.off_partials = off; off += align_up((size_t)kMaxBlocks * 4 * sizeof(double));
-  L.off_counters = off; off += align_up(kNumCounters * sizeof(unsigned));
+  L.off_partials = off;
+  off += align_up((size_t)kMaxBlocks * kPartRegions * sizeof(double));
+  L.gamma_cap = (me.win_nx + 1) * (me.win_ny + 1) * (me.win_nz + 1);
+  L.off_gidx = off; off += align_up((size_t)L.gamma_cap * sizeof(int));
+  L.off_gbuf = off; off += align_up((size_t)L.gamma_cap * 2 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -99,7 +104,7 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
 // Buffers of one level's Newton/CG solve.
 template <class R>
 struct CGBufs {
-  R *kap, *d, *dinv, *r, *z, *x, *p[2], *q;
+  R *kap, *d, *dinv, *r[2], *w[2], *s[2], *p, *x[2];
 };
 
 }  // namespace
@@ -127,15 +132,24 @@ struct tl_sim {
   LevelScalars *sc_c, *sc_f;
   LedgerDev* led;
   double* partials;
-  unsigned* counters;
+  int* gidx;            // padded indices of the coarse interface nodes
+  double* gbuf;         // interface gather/scatter staging
+  int n_gamma;
   // host side
   LevelScalars* h_sc;   // pinned
   LedgerDev* h_led;     // pinned
+  double* h_gbuf;       // pinned, 2 * gamma_cap doubles
   tl_ledger ledger;     // committed ledger
   tl_stats stats;
   long n_macro;
   double theta0;
   int last_cg_f, last_cg_c;
+  // sampled event timing of the fine CG operator kernel (tl_set_profiling)
+  int prof_every;
+  long prof_count;
+  int prof_used;
+  hipEvent_t prof_ev[2 * 64];
+  int prof_k[64];
 };
 
 namespace {
@@ -163,6 +177,10 @@ Region region_all() {
   rg.mode = kAllBottom;
   return rg;
 }
+
+// Padded indices of the coarse interface nodes (on an immersed window face),
+// in box-scan order, uploaded to the device.
+void set_interface(tl_sim* s);
 
 Window make_window(const tl_mesh& me, int I0, int J0) {
   Window w;
@@ -199,6 +217,26 @@ double fine_free_nodes(const Geo& gf, const Window& w) {
   return (double)cnt;
 }
 
+void set_interface(tl_sim* s) {
+  const Window& w = s->win;
+  std::vector<int> idx;
+  for (int k = w.K0; k <= w.K0 + w.wz; ++k)
+    for (int j = w.J0; j <= w.J0 + w.wy; ++j)
+      for (int i = w.I0; i <= w.I0 + w.wx; ++i) {
+        const bool g = ((w.faces & kFx0) && i == w.I0) ||
+                       ((w.faces & kFx1) && i == w.I0 + w.wx) ||
+                       ((w.faces & kFy0) && j == w.J0) ||
+                       ((w.faces & kFy1) && j == w.J0 + w.wy) ||
+                       ((w.faces & kFz0) && k == w.K0);
+        if (g) idx.push_back((k + 1) * s->gc.pxy + (j + 1) * s->gc.px + (i + 1));
+      }
+  s->n_gamma = (int)idx.size();
+  if (!idx.empty())
+    hip_check(hipMemcpy(s->gidx, idx.data(), idx.size() * sizeof(int),
+                        hipMemcpyHostToDevice),
+              "hipMemcpy(interface indices)");
+}
+
 void sync_read_scalars(tl_sim* s, const LevelScalars* dev) {
   hip_check(hipGetLastError(), "kernel launch");
   hip_check(hipMemcpyAsync(s->h_sc, dev, sizeof(LevelScalars),
@@ -207,10 +245,32 @@ void sync_read_scalars(tl_sim* s, const LevelScalars* dev) {
   hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
 }
 
+// Collect the sampled event timings of fine operator launches after a host
+// sync of the CG loop.  Launches of iteration k did work unless the solve has
+// finished with k >= iters (those return at once); only working launches are
+// counted.
+void flush_profile(tl_sim* s, const LevelScalars& sc) {
+  for (int q = 0; q < s->prof_used; ++q) {
+    if (sc.done && s->prof_k[q] >= sc.iters) continue;
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, s->prof_ev[2 * q], s->prof_ev[2 * q + 1]),
+              "hipEventElapsedTime");
+    s->stats.fine_op_timed_ms += ms;
+    s->stats.fine_op_timed += 1;
+  }
+  s->prof_used = 0;
+}
+
 // One backward-Euler step of one level: frozen-kappa Newton with backtracking
-// on |R_free|_2, linear systems by Jacobi-PCG in precision R.  T holds the
+// on |R_free|_2; linear systems by Jacobi-PCG in precision R.  T holds the
 // initial guess with the Dirichlet values in place; on return T (possibly
 // swapped with Tt) holds the solution and Rout the residual there.
+//
+// Each round queues, without host synchronisation: the residual at the trial
+// T - alpha x (alpha = 0 on the first round), the device-side line-search
+// decision with the CG start, and n_launch CG iterations for the next
+// direction (they return at once when the trial is rejected, Newton has
+// converged, or CG has converged).  The host then reads the outcome once.
 template <class R>
 void solve_level(tl_sim* s, bool fine, const Geo& g, const Region& rg,
                  double tau, const double* Told, const double* F,
@@ -223,61 +283,75 @@ void solve_level(tl_sim* s, bool fine, const Geo& g, const Region& rg,
   const double rtol2 = rtol * rtol;
   int64_t& n_newton = fine ? s->stats.newton_fine : s->stats.newton_coarse;
   int64_t& n_cg = fine ? s->stats.cg_fine : s->stats.cg_coarse;
-  const double op_bytes_per_node = 6.0 * sizeof(R);
+  const double op_bytes_per_node = 13.0 * sizeof(R);
+  int xi = 0;  // cg.x[xi]: direction being line-searched; CG writes cg.x[1-xi]
+  int n_launch = std::min(op.cg_max, std::max(3, last_cg + 2));
+  double rn0 = 0.0;
 
-  k_residual<R, R>(s->L, g, rg, s->mat, tau, T, (const R*)nullptr, 0.0, Told,
-                   F, Fext, Tt, Rout, cg.kap, cg.d, cg.dinv, cg.r, cg.z, sc,
-                   s->partials, s->counters);
-  std::swap(T, Tt);
-  sync_read_scalars(s, sc);
-  double rn0 = std::sqrt(s->h_sc->rnorm2);
-  if (!std::isfinite(rn0)) throw NoConv{"non-finite residual"};
-  for (int it = 1; it <= op.newton_max; ++it) {
-    ++n_newton;
-    if (s->h_sc->rz0 == 0.0) return;  // nothing to solve: R_free == 0
-    // Jacobi-PCG, launched in chunks; the kernels stop by themselves once the
-    // device-side convergence flag is set.
-    int k = 0;
-    int chunk = std::max(4, last_cg);
-    for (;;) {
-      for (int c = 0; c < chunk && k < op.cg_max; ++c, ++k) {
-        k_cg_iter<R>(s->L, g, k == 0, cg.z, cg.p[k & 1], cg.p[(k + 1) & 1],
-                     cg.q, cg.d, cg.kap, cg.x, cg.r, cg.z, cg.dinv, rtol2,
-                     op.cg_max, sc, s->partials, s->counters);
-        if (fine) {
-          s->stats.fine_op_bytes += op_bytes_per_node * g.nreal;
-          s->stats.fine_op_applies += 1;
-        }
+  auto round = [&](bool first, double alpha, int h) {
+    k_residual<R, R>(s->L, g, rg, s->mat, tau, T,
+                     first ? (const R*)nullptr : cg.x[xi], alpha, Told, F,
+                     Fext, Tt, Rout, cg.kap, cg.d, cg.dinv, cg.r[0],
+                     s->partials);
+    k_cg_start<R>(s->L, g, first ? 1 : 0, alpha, rn0, tol,
+                  h == kLineSearchMax - 1 ? 1 : 0, cg.r[0], cg.dinv, cg.d,
+                  cg.kap, cg.w[0], sc, s->partials);
+    for (int k = 0; k < n_launch; ++k) {
+      const bool timed = fine && s->prof_every > 0 &&
+                         (s->prof_count++ % s->prof_every) == 0 &&
+                         s->prof_used < kProfPairs;
+      if (timed)
+        hip_check(hipEventRecord(s->prof_ev[2 * s->prof_used], s->stream),
+                  "hipEventRecord");
+      k_cg_iter<R>(s->L, g, k, cg.r, cg.w, cg.s, cg.p, cg.x[1 - xi], cg.d,
+                   cg.kap, cg.dinv, rtol2, sc, s->partials);
+      if (timed) {
+        hip_check(hipEventRecord(s->prof_ev[2 * s->prof_used + 1], s->stream),
+                  "hipEventRecord");
+        s->prof_k[s->prof_used] = k;
+        ++s->prof_used;
       }
-      sync_read_scalars(s, sc);
-      if (s->h_sc->done || k >= op.cg_max) break;
-      chunk = 4;
     }
-    if (s->h_sc->breakdown && s->h_sc->iters == 0)
-      throw NoConv{"CG breakdown (non-positive or non-finite curvature)"};
-    last_cg = s->h_sc->iters;
-    n_cg += s->h_sc->iters;
-    // backtracking line search on |R_free|_2
-    double rn = 0.0, step = 0.0;
-    for (int h = 0; h < kLineSearchMax; ++h) {
-      const double alpha = std::ldexp(1.0, -h);
-      k_residual<R, R>(s->L, g, rg, s->mat, tau, T, cg.x, alpha, Told, F, Fext,
-                       Tt, Rout, cg.kap, cg.d, cg.dinv, cg.r, cg.z, sc,
-                       s->partials, s->counters);
-      sync_read_scalars(s, sc);
-      rn = std::sqrt(s->h_sc->rnorm2);
-      step = s->h_sc->dmax;
-      if (!std::isfinite(rn) || !std::isfinite(step))
-        throw NoConv{"non-finite Newton update"};
-      if (rn <= (1.0 - 1e-4 * alpha) * rn0 || step <= tol) break;
+  };
+
+  round(true, 0.0, 0);
+  int dirs = 0;  // Newton directions computed
+  int h = 0;
+  for (;;) {
+    sync_read_scalars(s, sc);
+    const LevelScalars& o = *s->h_sc;
+    if (fine && s->prof_used > 0) flush_profile(s, o);
+    if (!std::isfinite(o.rnorm2) || !std::isfinite(o.dmax))
+      throw NoConv{"non-finite residual or Newton update"};
+    if (!o.accepted) {
       ++s->stats.line_search_halvings;
+      ++h;
+      round(false, std::ldexp(1.0, -h), h);
+      continue;
     }
     std::swap(T, Tt);
-    rn0 = rn;
-    if (step <= tol) return;
+    rn0 = std::sqrt(o.rnorm2);
+    if (o.converged || o.rz0 == 0.0) return;
+    // the CG of this round produced the next direction
+    if (o.breakdown && o.iters == 0)
+      throw NoConv{"CG breakdown (non-positive or non-finite curvature)"};
+    if (dirs >= op.newton_max)
+      throw NoConv{std::string(fine ? "fine" : "coarse") +
+                   " Newton did not converge within newton_max iterations"};
+    ++dirs;
+    ++n_newton;
+    n_cg += o.iters;
+    if (fine) {
+      s->stats.fine_op_bytes += op_bytes_per_node * g.nreal * o.iters;
+      s->stats.fine_op_applies += o.iters;
+    }
+    const bool cut = !o.done;  // CG stopped by the launch count, not rtol
+    last_cg = cut ? n_launch + 2 : o.iters;
+    n_launch = std::min(op.cg_max, std::max(3, last_cg + 2));
+    xi = 1 - xi;
+    h = 0;
+    round(false, 1.0, 0);
   }
-  throw NoConv{std::string(fine ? "fine" : "coarse") +
-               " Newton did not converge within newton_max iterations"};
 }
 
 void solve_fine(tl_sim* s, double tau, const double* Told, const double* F) {
@@ -324,9 +398,9 @@ SpotSet make_spots(const tl_sim* s, long n, int j0, int j1, double weight) {
 
 void energy_now(tl_sim* s, double* slot) {
   k_energy(s->L, s->gc, region_outside(s), s->mat, s->Tn, slot, 1,
-           s->partials, s->counters);
+           s->partials);
   k_energy(s->L, s->gf, region_window(s), s->mat, s->fstate, slot, 0,
-           s->partials, s->counters);
+           s->partials);
 }
 
 void read_ledger(tl_sim* s) {
@@ -349,12 +423,95 @@ void write_ledger(tl_sim* s) {
   hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
 }
 
-double relaxation(tl_sim* s, int it, double theta) {
-  if (s->opts.dn_theta > 0.0 || it == 1) return theta;
-  const double num = s->h_sc->sum1, den = s->h_sc->sum2;
-  if (den <= 0.0) return theta;
-  return -theta * num / den;
-}
+// Relaxation of the two-level (Dirichlet-Neumann) interface iteration
+// lambda -> G(lambda), G = fine solve with Dirichlet data P lambda followed
+// by the coarse outside solve, read back on the interface nodes.  With a
+// fixed theta: lambda <- lambda + theta (G(lambda) - lambda).  Otherwise the
+// interface quasi-Newton method with inverse least squares (IQN-ILS): the
+// first step is relaxed with theta0; afterwards, with residual r = G(l) - l
+// and the differences of successive residuals (columns of V) and of
+// successive G values (columns of W),
+//   c = argmin |V c + r_k|_2,   lambda_{k+1} = G(lambda_k) + W c.
+// The fixed point -- and so the result -- is the same for every relaxation;
+// only the number of iterations differs.
+struct Interface {
+  std::vector<std::vector<double>> V, W;
+  std::vector<double> r_prev, g_prev;
+  bool has_prev = false;
+  static constexpr int kMaxCols = 24;
+
+  void update(const std::vector<double>& lam, const std::vector<double>& g,
+              double theta0, bool fixed, std::vector<double>& next) {
+    const size_t n = lam.size();
+    std::vector<double> r(n);
+    for (size_t q = 0; q < n; ++q) r[q] = g[q] - lam[q];
+    next.assign(n, 0.0);
+    if (fixed || !has_prev) {
+      for (size_t q = 0; q < n; ++q) next[q] = lam[q] + theta0 * r[q];
+    } else {
+      std::vector<double> dv(n), dw(n);
+      for (size_t q = 0; q < n; ++q) {
+        dv[q] = r[q] - r_prev[q];
+        dw[q] = g[q] - g_prev[q];
+      }
+      V.push_back(dv);
+      W.push_back(dw);
+      if ((int)V.size() > kMaxCols) {
+        V.erase(V.begin());
+        W.erase(W.begin());
+      }
+      // least squares by modified Gram-Schmidt, newest column first; columns
+      // that are (numerically) dependent on newer ones are skipped
+      const int m = (int)V.size();
+      std::vector<std::vector<double>> Q;
+      std::vector<int> cols;
+      std::vector<std::vector<double>> Rm;  // upper triangle, row per kept col
+      for (int c = m - 1; c >= 0; --c) {
+        std::vector<double> v = V[c];
+        double n0 = 0.0;
+        for (double x : v) n0 += x * x;
+        n0 = std::sqrt(n0);
+        std::vector<double> rc(Q.size() + 1, 0.0);
+        for (size_t a = 0; a < Q.size(); ++a) {
+          double d = 0.0;
+          for (size_t q = 0; q < n; ++q) d += Q[a][q] * v[q];
+          rc[a] = d;
+          for (size_t q = 0; q < n; ++q) v[q] -= d * Q[a][q];
+        }
+        double nv = 0.0;
+        for (double x : v) nv += x * x;
+        nv = std::sqrt(nv);
+        if (!(nv > 1e-10 * n0) || n0 == 0.0) continue;
+        for (double& x : v) x /= nv;
+        rc[Q.size()] = nv;
+        Q.push_back(v);
+        Rm.push_back(rc);
+        cols.push_back(c);
+      }
+      const int k = (int)Q.size();
+      // solve R c = -Q^T r (R upper triangular in the kept-column order)
+      std::vector<double> rhs(k), cvec(k, 0.0);
+      for (int a = 0; a < k; ++a) {
+        double d = 0.0;
+        for (size_t q = 0; q < n; ++q) d += Q[a][q] * r[q];
+        rhs[a] = -d;
+      }
+      for (int a = k - 1; a >= 0; --a) {
+        double v = rhs[a];
+        for (int b = a + 1; b < k; ++b) v -= Rm[b][a] * cvec[b];
+        cvec[a] = v / Rm[a][a];
+      }
+      for (size_t q = 0; q < n; ++q) next[q] = g[q];
+      for (int a = 0; a < k; ++a) {
+        const std::vector<double>& wc = W[cols[a]];
+        for (size_t q = 0; q < n; ++q) next[q] += cvec[a] * wc[q];
+      }
+    }
+    r_prev = r;
+    g_prev = g;
+    has_prev = true;
+  }
+};
 
 // One macro step of Algorithm 1.
 void macro_step(tl_sim* s) {
@@ -380,6 +537,8 @@ void macro_step(tl_sim* s) {
     s->win = wn;
     s->gf.x0 = wn.I0 * s->gc.hx;
     s->gf.y0 = wn.J0 * s->gc.hy;
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    set_interface(s);
     k_fill(L, s->ext, 0.0, s->gc.npad);
     energy_now(s, &led->e_tmp1);
     read_ledger(s);
@@ -393,10 +552,9 @@ void macro_step(tl_sim* s) {
 
   // 2. coarse loads averaged over the m micro times; predictor
   SpotSet avg = make_spots(s, n, 1, m, 1.0 / m);
-  k_laser_load(L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr, s->partials,
-               s->counters);
+  k_laser_load(L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr, s->partials);
   k_laser_load(L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy, s->Fout,
-               Dt, &led->absorbed, s->partials, s->counters);
+               Dt, &led->absorbed, s->partials);
   k_copy(L, s->ccur, s->Tn, s->gc.npad);
   solve_coarse(s, region_all(), Dt, s->Fall, nullptr);
   std::swap(s->Tpred, s->ccur);
@@ -409,10 +567,10 @@ void macro_step(tl_sim* s) {
                      (double)j / m, s->fcur);
     SpotSet sp = make_spots(s, n, j, j, 1.0);
     k_laser_load(L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, &led->absorbed,
-                 s->partials, s->counters);
+                 s->partials);
     solve_fine(s, dt, s->fprev, s->fF);
     k_interface_accumulate(L, s->gf, w, s->fR, s->rho, j == 1 ? 1 : 0, -dt,
-                           &led->bottom, s->partials, s->counters);
+                           &led->bottom, s->partials);
     std::swap(s->fprev, s->fcur);
     ++s->stats.micro_steps;
   }
@@ -421,13 +579,14 @@ void macro_step(tl_sim* s) {
   {
     SpotSet sp = make_spots(s, n, m, m, 1.0);
     k_laser_load(L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, &led->absorbed,
-                 s->partials, s->counters);
+                 s->partials);
   }
   k_copy(L, s->lam, s->Tpred, s->gc.npad);
   k_copy(L, s->fcur, s->fprev, s->gf.npad);
   k_copy(L, s->ccur, s->Tpred, s->gc.npad);
   const Region rout = region_outside(s);
-  double theta = s->theta0;
+  Interface iqn;
+  std::vector<double> lam_v, lt_v, next;
   int it = 1;
   for (;; ++it) {
     if (it > op.dn_max) throw NoConv{"two-level iteration did not converge"};
@@ -438,22 +597,37 @@ void macro_step(tl_sim* s) {
                s->ext);
     k_inject(L, s->gf, s->gc, w, s->fcur, s->ccur);
     solve_coarse(s, rout, Dt, s->Fout, s->ext);
-    k_interface_lambda(L, s->gc, w, 0, s->ccur, s->lam, s->dprev, 0.0,
-                       it == 1 ? 1 : 0, s->sc_c);
-    sync_read_scalars(s, s->sc_c);
-    const double diff = s->h_sc->sum0;
+    // interface residual lambda' - lambda on the host
+    const int ng = s->n_gamma;
+    k_gamma_gather(L, s->gidx, ng, s->ccur, s->lam, s->gbuf);
+    if (ng > 0)
+      hip_check(hipMemcpyAsync(s->h_gbuf, s->gbuf, 2 * sizeof(double) * ng,
+                               hipMemcpyDeviceToHost, s->stream),
+                "hipMemcpyAsync(interface)");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    lt_v.resize(ng);
+    lam_v.resize(ng);
+    double diff = 0.0;
+    for (int q = 0; q < ng; ++q) {
+      lt_v[q] = s->h_gbuf[2 * q];
+      lam_v[q] = s->h_gbuf[2 * q + 1];
+      diff = std::max(diff, std::fabs(lt_v[q] - lam_v[q]));
+    }
     if (!std::isfinite(diff)) throw NoConv{"non-finite interface update"};
-    theta = relaxation(s, it, theta);
-    k_interface_lambda(L, s->gc, w, 1, s->ccur, s->lam, s->dprev, theta, 0,
-                       s->sc_c);
     if (diff <= op.dn_tol) break;
+    iqn.update(lam_v, lt_v, s->theta0, op.dn_theta > 0.0, next);
+    for (int q = 0; q < ng; ++q) s->h_gbuf[q] = next[q];
+    hip_check(hipMemcpyAsync(s->gbuf, s->h_gbuf, sizeof(double) * ng,
+                             hipMemcpyHostToDevice, s->stream),
+              "hipMemcpyAsync(interface)");
+    k_gamma_scatter(L, s->gidx, ng, s->gbuf, s->lam);
   }
   s->stats.dn_iters += it;
   ++s->stats.micro_steps;
   // bottom heat flow of the last fine step and of the coarse outside solve
   k_interface_accumulate(L, s->gf, w, s->fR, nullptr, 0, -dt, &led->bottom,
-                         s->partials, s->counters);
-  k_bottom_sum(L, s->gc, s->cR, -Dt, &led->bottom, s->partials, s->counters);
+                         s->partials);
+  k_bottom_sum(L, s->gc, s->cR, -Dt, &led->bottom, s->partials);
   std::swap(s->Tn, s->ccur);
   std::swap(s->fstate, s->fcur);
   energy_now(s, &led->stored);
@@ -618,28 +792,36 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
   s->Tn = C(0); s->Tpred = C(1); s->ccur = C(2); s->ctrial = C(3);
   s->lam = C(4); s->dprev = C(5); s->cR = C(6); s->Fall = C(7);
   s->Fout = C(8); s->ext = C(9);
-  s->ccg.kap = C(10); s->ccg.d = C(11); s->ccg.dinv = C(12); s->ccg.r = C(13);
-  s->ccg.z = C(14); s->ccg.x = C(15); s->ccg.p[0] = C(16); s->ccg.p[1] = C(17);
-  s->ccg.q = C(18);
+  auto cgb64 = [&](auto A) {
+    return CGBufs<double>{(double*)A(0), (double*)A(1), (double*)A(2),
+                          {(double*)A(3), (double*)A(4)},
+                          {(double*)A(5), (double*)A(6)},
+                          {(double*)A(7), (double*)A(8)}, (double*)A(9),
+                          {(double*)A(10), (double*)A(11)}};
+  };
+  s->ccg = cgb64([&](int a) { return (void*)C(10 + a); });
   auto FD = [&](int a) { return (double*)(s->ws + lay.off_fd[a]); };
   s->fstate = FD(0); s->fprev = FD(1); s->fcur = FD(2); s->ftrial = FD(3);
   s->falt = FD(4); s->fR = FD(5); s->fF = FD(6); s->rho = FD(7);
   auto FC = [&](int a) { return (void*)(s->ws + lay.off_fcg[a]); };
-  s->fcg64 = CGBufs<double>{(double*)FC(0), (double*)FC(1), (double*)FC(2),
-                            (double*)FC(3), (double*)FC(4), (double*)FC(5),
-                            {(double*)FC(6), (double*)FC(7)}, (double*)FC(8)};
+  s->fcg64 = cgb64(FC);
   s->fcg32 = CGBufs<float>{(float*)FC(0), (float*)FC(1), (float*)FC(2),
-                           (float*)FC(3), (float*)FC(4), (float*)FC(5),
-                           {(float*)FC(6), (float*)FC(7)}, (float*)FC(8)};
+                           {(float*)FC(3), (float*)FC(4)},
+                           {(float*)FC(5), (float*)FC(6)},
+                           {(float*)FC(7), (float*)FC(8)}, (float*)FC(9),
+                           {(float*)FC(10), (float*)FC(11)}};
   s->sc_c = (LevelScalars*)(s->ws + lay.off_scal);
   s->sc_f = s->sc_c + 1;
   s->led = (LedgerDev*)(s->ws + lay.off_ledger);
   s->partials = (double*)(s->ws + lay.off_partials);
-  s->counters = (unsigned*)(s->ws + lay.off_counters);
+  s->gidx = (int*)(s->ws + lay.off_gidx);
+  s->gbuf = (double*)(s->ws + lay.off_gbuf);
   if (hipHostMalloc((void**)&s->h_sc, sizeof(LevelScalars), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&s->h_led, sizeof(LedgerDev), hipHostMallocDefault) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipHostMalloc((void**)&s->h_gbuf, 2 * sizeof(double) * lay.gamma_cap,
+                    hipHostMallocDefault) != hipSuccess) {
     delete s;
     return fail(TL_EDEVICE, "hipHostMalloc failed");
   }
@@ -663,7 +845,8 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
   s->gf.x0 = I0 * s->gc.hx;
   s->gf.y0 = J0 * s->gc.hy;
   try {
-    st = init_state(s);
+    st = init_state(s);  // zero-fills the whole workspace first
+    if (st == TL_OK) set_interface(s);
   } catch (const DevErr& e) {
     st = fail(TL_EDEVICE, e.msg);
   }
@@ -711,6 +894,7 @@ tl_status tl_step(tl_sim* s, int n_macro) {
       s->falt = alt_saved;
       s->stats = stats_saved;
       try {
+        set_interface(s);
         k_fill(s->L, s->ext, 0.0, s->gc.npad);
         write_ledger(s);
       } catch (const DevErr& e) {
@@ -828,6 +1012,7 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
     s->win = make_window(s->mesh, h.I0, h.J0);
     s->gf.x0 = h.I0 * s->gc.hx;
     s->gf.y0 = h.J0 * s->gc.hy;
+    set_interface(s);
     HIP_OK(hipMemcpyAsync(s->ctrial, p, (size_t)s->gc.nreal * sizeof(double),
                           hipMemcpyHostToDevice, s->stream));
     k_pack(s->L, s->gc, 0, 8, s->ctrial, s->Tn);
@@ -846,12 +1031,27 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
   return TL_OK;
 }
 
+tl_status tl_set_profiling(tl_sim* s, int sample_every) {
+  if (!s) return fail(TL_EINVAL, "null handle");
+  if (sample_every < 0) return fail(TL_EINVAL, "sample_every must be >= 0");
+  if (sample_every > 0 && !s->prof_ev[0]) {
+    for (int q = 0; q < 2 * kProfPairs; ++q)
+      HIP_OK(hipEventCreate(&s->prof_ev[q]));
+  }
+  s->prof_every = sample_every;
+  s->prof_count = 0;
+  return TL_OK;
+}
+
 void tl_destroy(tl_sim* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   else (void)hipDeviceSynchronize();
+  if (s->prof_ev[0])
+    for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(s->prof_ev[q]);
   if (s->h_sc) (void)hipHostFree(s->h_sc);
   if (s->h_led) (void)hipHostFree(s->h_led);
+  if (s->h_gbuf) (void)hipHostFree(s->h_gbuf);
   delete s;
 }
 

@@ -65,6 +65,7 @@ class tl_stats(C.Structure):
                                          "fine_solves", "coarse_solves")] + \
                [("fine_dof_steps", C.c_double), ("step_ms", C.c_double),
                 ("fine_op_bytes", C.c_double), ("fine_op_applies", C.c_int64),
+                ("fine_op_timed", C.c_int64), ("fine_op_timed_ms", C.c_double),
                 ("fine_nodes", C.c_int * 3), ("coarse_nodes", C.c_int * 3)]
 
 
@@ -75,7 +76,8 @@ class tl_grid(C.Structure):
 
 # every symbol declared in include/tl.h and include/tl_ops.h
 SYMBOLS = ["tl_workspace_bytes", "tl_create", "tl_step", "tl_get_temperature", "tl_get_ledger",
-           "tl_get_stats", "tl_get_time", "tl_save", "tl_load", "tl_destroy", "tl_last_error",
+           "tl_get_stats", "tl_get_time", "tl_save", "tl_load", "tl_set_profiling", "tl_destroy",
+           "tl_last_error",
            "tl_op_padded_size", "tl_op_pack", "tl_op_unpack", "tl_op_apply"]
 
 _lib = None
@@ -111,6 +113,8 @@ def load():
     lib.tl_save.argtypes = [vp, vp, sz, C.POINTER(sz)]
     lib.tl_load.restype = C.c_int
     lib.tl_load.argtypes = [vp, vp, sz]
+    lib.tl_set_profiling.restype = C.c_int
+    lib.tl_set_profiling.argtypes = [vp, C.c_int]
     lib.tl_destroy.restype = None
     lib.tl_destroy.argtypes = [vp]
     lib.tl_last_error.restype = C.c_char_p
@@ -231,6 +235,10 @@ def tl_save(h):
 def tl_load(h, data):
     buf = C.create_string_buffer(bytes(data), len(data))
     _check(load().tl_load(h, buf, len(data)))
+
+
+def tl_set_profiling(h, sample_every):
+    _check(load().tl_set_profiling(h, int(sample_every)))
 
 
 def tl_destroy(h):

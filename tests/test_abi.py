@@ -34,11 +34,11 @@ def test_exports_every_declared_symbol():
 def test_workspace_bytes():
     wl = W.config1()
     n = tl.tl_workspace_bytes(wl.mesh, wl.options)
-    # 19 coarse + 8 fine FP64 arrays + 9 fine CG arrays, padded layouts
+    # 22 coarse + 8 fine FP64 arrays + 12 fine CG arrays, padded layouts
     cpad = (50 + 3) * (25 + 3) * (13 + 3)
     fpad = (81 + 2) * (41 + 2) * (25 + 2)
-    assert n >= (19 * cpad + 17 * fpad) * 8
-    assert n < (19 * cpad + 17 * fpad) * 8 + 10 ** 6
+    assert n >= (22 * cpad + 20 * fpad) * 8
+    assert n < (22 * cpad + 20 * fpad) * 8 + 10 ** 6
     mixed = tl.tl_workspace_bytes(wl.mesh, replace(wl.options, precision=W.MIXED))
     assert mixed < n
     assert tl.tl_workspace_bytes(replace(wl.mesh, refine=0), wl.options) == 0

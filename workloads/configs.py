@@ -13,7 +13,7 @@ from dataclasses import replace
 import numpy as np
 
 from .spec import (Mesh, Material, Track, ScanPath, Options, Workload,
-                   FP64, MIXED)
+                   FP64, MIXED, options_for)
 
 UM = 1e-6
 MM = 1e-3
@@ -31,7 +31,7 @@ def config0(precision=FP64):
     50 us macro step, 20 macro steps, track x = 0.1 -> 0.9 mm at y = 0.25 mm."""
     mesh = Mesh(1.0 * MM, 0.5 * MM, 0.25 * MM, 16, 8, 4, 2, 6, 4, 2)
     tr = Track(0.1 * MM, 0.25 * MM, 0.9 * MM, 0.25 * MM, **_laser())
-    opts = Options(dt_coarse=50 * UM, m_time=4, precision=precision)
+    opts = options_for(precision, 50 * UM, 4)
     return Workload("config0", mesh, Material(), ScanPath([tr]), opts, 20)
 
 
@@ -42,7 +42,7 @@ def config1(precision=FP64):
     mid-width."""
     mesh = Mesh(2.0 * MM, 1.0 * MM, 0.5 * MM, 50, 25, 13, 8, 10, 5, 3)
     tr = Track(0.0, 0.5 * MM, 2.0 * MM, 0.5 * MM, **_laser())
-    opts = Options(dt_coarse=25 * UM, m_time=8, precision=precision)
+    opts = options_for(precision, 25 * UM, 8)
     return Workload("config1", mesh, Material(), ScanPath([tr]), opts, 100)
 
 
@@ -59,7 +59,7 @@ def config2(precision=MIXED, seed=0):
         xa, xb = (0.5 * MM, 4.5 * MM) if k % 2 == 0 else (4.5 * MM, 0.5 * MM)
         tracks.append(Track(xa, y, xb, y, **_laser(power=float(powers[k]))))
     mesh = Mesh(5.0 * MM, 5.0 * MM, 1.0 * MM, 100, 100, 20, 8, 10, 6, 3)
-    opts = Options(dt_coarse=50 * UM, m_time=8, precision=precision)
+    opts = options_for(precision, 50 * UM, 8)
     return Workload("config2", mesh, Material(), ScanPath(tracks), opts, 1000)
 
 
@@ -89,7 +89,7 @@ def config3_requests(n=64, seed=0, mean_interarrival=1e-3, precision=MIXED):
         tr = Track(0.0, 0.5 * MM, lx, 0.5 * MM, speed=v, power=p, radius=rad,
                    absorptivity=0.4)
         n_macro = int(math.ceil((lx / v) / dt - 1e-9))
-        opts = Options(dt_coarse=dt, m_time=8, precision=precision)
+        opts = options_for(precision, dt, 8)
         out.append((t, Workload(f"config3_req{q}", mesh, Material(),
                                 ScanPath([tr]), opts, n_macro)))
     return out
@@ -107,7 +107,7 @@ def config4(precision=MIXED):
         p, v = (200.0, 0.8) if k % 2 == 0 else (280.0, 1.2)
         tracks.append(Track(xa, y, xb, y, **_laser(power=p, speed=v)))
     mesh = Mesh(10.0 * MM, 10.0 * MM, 2.0 * MM, 200, 200, 40, 10, 12, 8, 3)
-    opts = Options(dt_coarse=25 * UM, m_time=8, precision=precision)
+    opts = options_for(precision, 25 * UM, 8)
     total = sum(8.0 * MM / t.speed for t in tracks)
     n_macro = int(math.ceil(total / opts.dt_coarse - 1e-9))
     return Workload("config4", mesh, Material(), ScanPath(tracks), opts,

@@ -70,7 +70,11 @@ class ScanPath:
 
 @dataclass
 class Options:
-    """Macro step dt_coarse [s] split into m_time micro steps; arithmetic of
+    """Production defaults: Newton and two-level tolerances 1e-8 K (FP64) --
+    use options_for(MIXED, ...) for the mixed path's 1e-6 K -- and inner CG
+    reduction 1e-3 (the Newton fixed point does not depend on it).
+
+    Macro step dt_coarse [s] split into m_time micro steps; arithmetic of
     the fine linear solves (FP64 or MIXED); Gauss points per face direction
     for the laser load; tolerances (kelvin for Newton and the two-level
     iteration, relative for CG); two-level relaxation theta (<= 0 selects
@@ -79,9 +83,9 @@ class Options:
     m_time: int
     precision: int = FP64
     face_quad: int = 3
-    newton_tol: float = 1e-9
-    cg_rtol: float = 1e-10
-    dn_tol: float = 1e-9
+    newton_tol: float = 1e-8
+    cg_rtol: float = 1e-3
+    dn_tol: float = 1e-8
     dn_theta: float = 0.0
     newton_max: int = 30
     cg_max: int = 500
@@ -97,3 +101,13 @@ class Workload:
     options: Options
     n_macro: int
     meta: dict = field(default_factory=dict)
+
+
+def options_for(precision, dt_coarse, m_time, **kw):
+    """Options with the tolerances suited to the precision: 1e-8 K for the
+    FP64 path, 1e-6 K for the mixed path (whose target is 1e-6 relative)."""
+    tol = 1e-8 if precision == FP64 else 1e-6
+    base = dict(dt_coarse=dt_coarse, m_time=m_time, precision=precision,
+                newton_tol=tol, dn_tol=tol)
+    base.update(kw)
+    return Options(**base)
