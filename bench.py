@@ -43,6 +43,9 @@ def parse():
                     help="time every Nth fine operator launch with HIP events (0: off)")
     ap.add_argument("--k2-sweep", action="store_true",
                     help="also time the bare operator apply at several shapes")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB buffer 3 times (known-size "
+                         "reference for HBM byte counters)")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per launch of the operator kernel")
     return ap.parse_args()
@@ -182,6 +185,15 @@ def main():
                                  - (led["absorbed"] - led["bottom"] + led["remap"]))
                              / max(abs(led["absorbed"]), 1e-300),
     }
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibrate_copy_bytes"] = n * 4
     if args.k2_sweep:
         out["k2_sweep"] = k2_sweep(tl, W, torch)
     if not args.no_cpu_baseline:

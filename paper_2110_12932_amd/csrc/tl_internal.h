@@ -74,12 +74,18 @@ struct LevelScalars {
   int pad;
 };
 
-// Per-workgroup partial sums: regions of kMaxBlocks doubles.
+// Per-workgroup partial sums: regions of kMaxBlocks doubles.  A kernel never
+// writes a region that it (or a still-running workgroup of it) reads: the CG
+// iteration kernels alternate between two pairs of regions by parity, since
+// a grid larger than the resident capacity has workgroups that start only
+// after others have finished.
 enum PartialRegion {
-  kPartCG = 0,     // CG: gamma, delta partials of the last CG kernel (2 regions)
+  kPartCG = 0,     // CG gamma/delta partials, written by CG start and by
+                   // iterations k odd (2 regions)
   kPartRes = 2,    // residual kernel: |R|^2, max|alpha dx|, r.(Dinv r) (3 regions)
   kPartGen = 5,    // generic sums (loads, energy, bottom reactions)
-  kPartRegions = 6
+  kPartCG2 = 6,    // CG gamma/delta partials written by iterations k even
+  kPartRegions = 8
 };
 
 // Energy ledger slots on the device.
@@ -137,10 +143,13 @@ void k_cg_start(Launch L, const Geo& g, int first, double alpha, double rn0,
 //   w' = J u' with u' = Dinv r' formed on the fly at the 27 neighbours,
 //   partials of gamma' = r'.u' and delta' = w'.u'.
 // r, w and s are double-buffered by iteration parity.
+// ev_start/ev_stop (hipEvent_t, may be null): events recorded with the
+// dispatch itself (kernel execution interval) for sampled timing.
 template <class R>
 void k_cg_iter(Launch L, const Geo& g, int k, R* const* rb, R* const* wb,
                R* const* sb, R* p, R* x, const R* d, const R* kap,
-               const R* dinv, double rtol2, LevelScalars* sc, double* partials);
+               const R* dinv, double rtol2, LevelScalars* sc, double* partials,
+               void* ev_start = nullptr, void* ev_stop = nullptr);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,

@@ -12,6 +12,7 @@
 // costs more than the kernel): either the next kernel of the CG iteration
 // re-sums the partials in every workgroup (kernel boundaries make them
 // visible), or a one-workgroup finalize kernel does it.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -385,6 +386,32 @@ struct Tile {
   int tx, ty, tz;   // this thread's node inside the tile
 };
 
+// XCD-aware tile order.  Workgroups are dealt round-robin to the 8 XCDs
+// (blockIdx.x % 8), each with its own L2.  The tiles (x fastest, then y, z)
+// are cut into 8 contiguous chunks and chunk c is processed by the
+// workgroups with blockIdx.x % 8 == c, so tiles that share halo entries sit
+// on the same L2.  The grid is a multiple of 8; workgroup b visits tiles
+// first(b), first(b) + step, ... below last(b).
+constexpr int kXcd = 8;
+struct TileRange {
+  int first, last, step;
+};
+__device__ inline TileRange tile_range(int ntiles) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb / kXcd;                       // workgroups per XCD
+  const int chunk = (ntiles + kXcd - 1) / kXcd;    // tiles per XCD
+  const int c = b % kXcd, slot = b / kXcd;
+  TileRange r;
+  r.first = c * chunk + slot;
+  r.last = min((c + 1) * chunk, ntiles);
+  r.step = per;
+  return r;
+}
+static inline int tiled_grid(int ntiles) {
+  const int per = (ntiles + kXcd - 1) / kXcd;
+  return std::min(per * kXcd, kMaxBlocks);
+}
+
 __device__ inline Tile tile_of(int b, int ntx, int nty) {
   Tile t;
   t.ox = (b % ntx) * TX;
@@ -476,11 +503,15 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
       hd[q] = n >= 0 ? dinv[n] : (R)0;
     }
   };
-  load_halo(tile_of(blockIdx.x, ntx, nty));
-  // 2. gamma_k, delta_k from the previous kernel's partials
+  const TileRange tr = tile_range(ntiles);
+  if (tr.first < tr.last) load_halo(tile_of(tr.first, ntx, nty));
+  // 2. gamma_k, delta_k from the previous kernel's partials (CG start or
+  // iteration k-1), held in the region pair this kernel does not write
+  const int rd = (kit & 1) ? kPartCG2 : kPartCG;
+  const int wr = (kit & 1) ? kPartCG : kPartCG2;
   {
     R v[2] = {(R)0, (R)0};
-    const double* pg = partials + kPartCG * kMaxBlocks;
+    const double* pg = partials + rd * kMaxBlocks;
     for (int b = threadIdx.x; b < nparts; b += kBlock) {
       v[0] += (R)pg[b];
       v[1] += (R)pg[kMaxBlocks + b];
@@ -528,9 +559,9 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
   R acc[2] = {(R)0, (R)0};
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
     const Tile t = tile_of(tile, ntx, nty);
-    if (tile != (int)blockIdx.x) load_halo(t);
+    if (tile != tr.first) load_halo(t);
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     const bool active = i < g.nx && j < g.ny && k < g.nz;
     const int n = active ? pidx(g, i, j, k) : 0;
@@ -575,38 +606,43 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
   }
   block_sum<2>(acc, lds);
   if (threadIdx.x == 0) {
-    partials[kPartCG * kMaxBlocks + blockIdx.x] = (double)acc[0];
-    partials[(kPartCG + 1) * kMaxBlocks + blockIdx.x] = (double)acc[1];
+    partials[wr * kMaxBlocks + blockIdx.x] = (double)acc[0];
+    partials[(wr + 1) * kMaxBlocks + blockIdx.x] = (double)acc[1];
   }
 }
 
 // Tiled matrix-free operator y = d v + K[kap] v (every node).
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-op_apply_tiled_kernel(Geo g, int ntx, int nty, const R* __restrict__ d,
+op_apply_tiled_kernel(Geo g, int ntx, int nty, int ntiles,
+                      const R* __restrict__ d,
                       const R* __restrict__ kap, const R* __restrict__ v,
                       R* __restrict__ y) {
   __shared__ R u_s[HN];
   __shared__ R k_s[EN];
-  const Tile t = tile_of(blockIdx.x, ntx, nty);
+  R wts[8];
 #pragma unroll
-  for (int q = 0; q < HPT; ++q) {
-    const int h = threadIdx.x + q * kBlock;
-    if (h < HN) {
-      const int n = halo_index(g, t, h);
-      u_s[h] = n >= 0 ? v[n] : (R)0;
+  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+  const TileRange tr = tile_range(ntiles);
+  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    const Tile t = tile_of(tile, ntx, nty);
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      if (h < HN) {
+        const int n = halo_index(g, t, h);
+        u_s[h] = n >= 0 ? v[n] : (R)0;
+      }
     }
-  }
-  load_kappa_tile(g, t, kap, k_s);
-  __syncthreads();
-  const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
-  if (i < g.nx && j < g.ny && k < g.nz) {
-    R wts[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-    const int n = pidx(g, i, j, k);
-    const R vc = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-    y[n] = d[n] * vc + stencil_lds(t, u_s, k_s, wts);
+    load_kappa_tile(g, t, kap, k_s);
+    __syncthreads();
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+      const int n = pidx(g, i, j, k);
+      const R vc = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
+      y[n] = d[n] * vc + stencil_lds(t, u_s, k_s, wts);
+    }
+    __syncthreads();  // LDS is reused by the next tile
   }
 }
 
@@ -740,28 +776,37 @@ template <class R>
 void k_cg_iter(Launch L, const Geo& g, int k, R* const* rb, R* const* wb,
                R* const* sb, R* p, R* x, const R* d, const R* kap,
                const R* dinv, double rtol2, LevelScalars* sc,
-               double* partials) {
+               double* partials, void* ev_start, void* ev_stop) {
   const int a = k & 1;
   int ntx, nty, ntz;
   tiles_of(g, ntx, nty, ntz);
   const int ntiles = ntx * nty * ntz;
-  const int nb = std::min(ntiles, kMaxBlocks);
+  const int nb = tiled_grid(ntiles);
   // the previous kernel (CG start or iteration) wrote one partial per
   // workgroup of its own grid
   const int nprev = k == 0 ? grid_for(g.nreal) : nb;
-  hipLaunchKernelGGL(cg_iter_tiled_kernel<R>, dim3(nb), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, g, ntx, nty, ntiles, k, rb[a],
-                     wb[a], sb[1 - a], rb[1 - a], wb[1 - a], sb[a], p, x, d,
-                     kap, dinv, rtol2, nprev, sc, partials);
+  if (ev_start != nullptr)
+    hipExtLaunchKernelGGL(cg_iter_tiled_kernel<R>, dim3(nb), dim3(kBlock), 0,
+                          (hipStream_t)L.stream, (hipEvent_t)ev_start,
+                          (hipEvent_t)ev_stop, 0, g, ntx, nty, ntiles, k,
+                          (const R*)rb[a], (const R*)wb[a], (const R*)sb[1 - a],
+                          rb[1 - a], wb[1 - a], sb[a], p, x, d, kap, dinv,
+                          rtol2, nprev, sc, partials);
+  else
+    hipLaunchKernelGGL(cg_iter_tiled_kernel<R>, dim3(nb), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, g, ntx, nty, ntiles, k, rb[a],
+                       wb[a], sb[1 - a], rb[1 - a], wb[1 - a], sb[a], p, x, d,
+                       kap, dinv, rtol2, nprev, sc, partials);
 }
 template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
                 R* y) {
   int ntx, nty, ntz;
   tiles_of(g, ntx, nty, ntz);
-  hipLaunchKernelGGL(op_apply_tiled_kernel<R>, dim3(ntx * nty * ntz),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, g, ntx, nty, d,
-                     kap, v, y);
+  const int ntiles = ntx * nty * ntz;
+  hipLaunchKernelGGL(op_apply_tiled_kernel<R>, dim3(tiled_grid(ntiles)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, g, ntx, nty,
+                     ntiles, d, kap, v, y);
 }
 template void k_op_apply<float>(Launch, const Geo&, const float*, const float*,
                                 const float*, float*);
@@ -774,7 +819,7 @@ template void k_op_apply<double>(Launch, const Geo&, const double*,
                               LevelScalars*, double*);                        \
   template void k_cg_iter<R>(Launch, const Geo&, int, R* const*, R* const*,   \
                              R* const*, R*, R*, const R*, const R*, const R*, \
-                             double, LevelScalars*, double*);
+                             double, LevelScalars*, double*, void*, void*);
 TL_CG_INST(float)
 TL_CG_INST(double)
 #undef TL_CG_INST

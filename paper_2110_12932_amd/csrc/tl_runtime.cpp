@@ -300,14 +300,11 @@ void solve_level(tl_sim* s, bool fine, const Geo& g, const Region& rg,
       const bool timed = fine && s->prof_every > 0 &&
                          (s->prof_count++ % s->prof_every) == 0 &&
                          s->prof_used < kProfPairs;
-      if (timed)
-        hip_check(hipEventRecord(s->prof_ev[2 * s->prof_used], s->stream),
-                  "hipEventRecord");
       k_cg_iter<R>(s->L, g, k, cg.r, cg.w, cg.s, cg.p, cg.x[1 - xi], cg.d,
-                   cg.kap, cg.dinv, rtol2, sc, s->partials);
+                   cg.kap, cg.dinv, rtol2, sc, s->partials,
+                   timed ? (void*)s->prof_ev[2 * s->prof_used] : nullptr,
+                   timed ? (void*)s->prof_ev[2 * s->prof_used + 1] : nullptr);
       if (timed) {
-        hip_check(hipEventRecord(s->prof_ev[2 * s->prof_used + 1], s->stream),
-                  "hipEventRecord");
         s->prof_k[s->prof_used] = k;
         ++s->prof_used;
       }

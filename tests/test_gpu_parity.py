@@ -27,7 +27,9 @@ def _gpu():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("cells", [(13, 9, 5), (40, 33, 21)])
+# the last shape has more tiles (2508) than workgroups, so every workgroup
+# loops over several tiles
+@pytest.mark.parametrize("cells", [(13, 9, 5), (40, 33, 21), (160, 150, 20)])
 @pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
 def test_op_apply_matches_assembled_operator(cells, prec):
     nx, ny, nz = cells
