@@ -51,6 +51,25 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(path, workload, elem):
+    """HBM bytes per launch of the CG iteration kernel from the calibrated
+    rocprofv3 FETCH_SIZE/WRITE_SIZE record in profiles/, or None when there
+    is no record for this workload and precision or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    kname = "cg_iter_tiled_kernel<%s>" % ("double" if elem == 8 else "float")
+    if path is None:
+        path = os.path.join(root, "profiles", f"cg_iter_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(root, "paper_2110_12932_amd", "csrc", "tl_kernels.hip"), "rb").read()
+    if rec.get("kernel") != kname or rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def cpu_baseline(wl):
     """The oracle on one complete macro step of the same workload, one core."""
     from threadpoolctl import threadpool_limits
@@ -151,9 +170,7 @@ def main():
     if st["fine_op_timed"] > 0:
         avg_s = st["fine_op_timed_ms"] / st["fine_op_timed"] * 1e-3
         achieved = bytes_per_launch / avg_s / 1e9
-        traffic = None
-        if args.traffic and os.path.exists(args.traffic):
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        traffic = measured_traffic(args.traffic, wl.name, elem)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "kernel": "cg_iter_tiled_kernel<%s>" % ("double" if elem == 8 else "float"),
