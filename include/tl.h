@@ -190,6 +190,65 @@ void tl_destroy(tl_sim* sim);
 /* Message of the last failing call on this thread ("" if none). */
 const char* tl_last_error(void);
 
+/* ---- serving: continuous batching of many simulations ------------------- *
+ * A server owns a caller-provided device pool.  Submitted requests wait in
+ * arrival order; each tl_server_tick admits waiting requests while a slot is
+ * free and the request's footprint (tl_workspace_bytes) fits the HBM budget
+ * and the pool, then advances every active request by one macro step --
+ * all their fine and coarse implicit steps as batched launches -- and
+ * retires requests that reached their macro-step count, copying their
+ * temperatures, ledger and counters to host memory and returning their
+ * workspace to the pool.  A request's result does not depend on which other
+ * requests share its ticks. */
+typedef struct tl_server tl_server;
+
+/* Host-clock record of one request (seconds since tl_server_create). */
+typedef struct {
+  double submit_s, admit_s, done_s;  /* -1 when not reached yet */
+  int state;                         /* 0 queued, 1 active, 2 done, 3 failed */
+  int pad;
+  int64_t macro_steps;               /* macro steps run (done requests) */
+} tl_request_info;
+
+/* Device bytes the server keeps for its own tables (part of the pool). */
+size_t tl_server_overhead_bytes(int max_slots);
+
+/* dev_pool: caller-owned device memory of pool_bytes, 256-byte aligned,
+ * outliving the server; hbm_budget caps the summed footprint of active
+ * requests; max_slots caps their number (1..1024).  TL_ENOMEM if the pool
+ * cannot hold the server's tables. */
+tl_status tl_server_create(void* dev_pool, size_t pool_bytes,
+                           size_t hbm_budget, int max_slots, void* hip_stream,
+                           tl_server** out);
+
+/* Queue a request of n_macro macro steps; inputs are copied.  TL_EINVAL as
+ * for tl_create; TL_EBUSY if the request alone exceeds the budget. */
+tl_status tl_server_submit(tl_server* sv, const tl_mesh* mesh,
+                           const tl_material* material,
+                           const tl_scan_path* scan, const tl_options* opts,
+                           int n_macro, uint64_t* id);
+
+/* Admit, advance all active requests by one macro step, retire finished
+ * ones.  Outputs (may be NULL): active and queued counts after the tick,
+ * requests finished (done or failed) during it.  TL_EDEVICE on a HIP
+ * error (the server is then unusable). */
+tl_status tl_server_tick(tl_server* sv, int* n_active, int* n_queued,
+                         int* n_finished);
+
+/* Results of a finished request: temperature of `level` (as
+ * tl_get_temperature; host_out may be NULL), counters, ledger, timing.
+ * TL_EBUSY while queued or active; TL_ENOCONV with the message if it
+ * failed (info is filled in every case). */
+tl_status tl_server_result(tl_server* sv, uint64_t id, int level,
+                           double* host_out, size_t cap, int dims_out[3],
+                           tl_stats* st, tl_ledger* led,
+                           tl_request_info* info);
+
+/* Drop the host-side results of a finished request. */
+tl_status tl_server_release(tl_server* sv, uint64_t id);
+
+void tl_server_destroy(tl_server* sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,7 +40,7 @@ def build(verbose=False):
     _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall",
           "-c", "tl_host.cpp", "-o", o])
     objs.append(o)
-    for src in ("tl_kernels.hip", "tl_runtime.cpp"):
+    for src in ("tl_kernels.hip", "tl_runtime.cpp", "tl_server.cpp"):
         o = os.path.join(bdir, src.split(".")[0] + ".o")
         extra = ["-x", "hip"] if src.endswith(".cpp") else []
         _run([hipcc] + HIP_FLAGS + [f"-I{INCLUDE}"] + extra + ["-c", src, "-o", o])

@@ -113,43 +113,60 @@ void k_copy(Launch L, double* dst, const double* src, long n);
 template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R* y);
 
-// Residual of one implicit step at the trial T' = T - alpha*dx (dx may be
-// null for alpha = 0); writes T', R, the Jacobian coefficients for CG in
-// precision R_cg and the CG initial residual r (zero on Dirichlet rows);
-// per-workgroup partials of |R_free|^2, max|alpha dx| and r.(Dinv r).
-template <class Rcg, class Rdx>
-void k_residual(Launch L, const Geo& g, const Region& rg, const MatDev& m,
-                double tau, const double* T, const Rdx* dx, double alpha,
-                const double* Told, const double* F, const double* Fext,
-                double* Tt, double* Rout, Rcg* kap, Rcg* d, Rcg* dinv, Rcg* r,
-                double* partials);
+// One level solve in a batched Newton/CG launch (device-resident table).
+// CG-precision arrays are untyped; the launch's precision decides.
+struct SolveItem {
+  Geo g;
+  Region rg;
+  MatDev m;
+  double tau;
+  double alpha;      // line-search step of this round's trial
+  double rn0;        // |R_free| at the last accepted temperature
+  double tol;        // Newton tolerance on max |alpha dx| [K]
+  double rtol2;      // CG: stop when r.u <= rtol2 * r0.u0
+  int first;         // first evaluation of this solve (alpha = 0, dx null)
+  int last_try;      // last allowed halving: accept regardless
+  int res_begin, res_nb;    // workgroups of the residual / CG-start kernels
+  int tile_begin, tile_nb;  // workgroups of the CG iteration kernel
+  int ntx, nty, ntiles;     // CG tiles of this item
+  int max_kit;              // CG iterations this item may run in the round
+  const double* T;     // temperature at the last accepted point
+  const double* Told;  // temperature at the previous time level
+  const double* F;     // surface load at the new time level
+  const double* Fext;  // interface load (null if none)
+  double* Tt;          // trial temperature written by the residual kernel
+  double* R;           // residual at the trial
+  const void* dx;      // Newton direction being line-searched (null first)
+  void* kap;           // element conductivity
+  void* d;             // m H'(T) / tau
+  void* dinv;          // Jacobi preconditioner, 0 on Dirichlet rows
+  void* r[2];          // CG residual (double-buffered by parity)
+  void* w[2];          // J u (double-buffered)
+  void* s[2];          // J p (double-buffered)
+  void* p;             // search direction
+  void* x;             // CG solution: the next Newton direction
+  LevelScalars* sc;    // per-item scalars
+  double* partials;    // per-item partial sums, kPartRegions * kMaxBlocks
+};
 
-// Line-search decision and CG start.  From the residual partials every
-// workgroup decides (identically) whether the trial is accepted (first
-// evaluation, sufficient decrease (1 - 1e-4 alpha) rn0, step <= tol, or the
-// last halving) and whether Newton has converged (accepted and step <= tol);
-// workgroup 0 stores the outcome for the host.  If the Newton iteration
-// continues, w0 = J u0 with u0 = Dinv r0 and the partials of gamma0 = r.u
-// and delta0 = w.u are formed; otherwise `done` is set so the CG kernels of
-// this round return at once.
-template <class R>
-void k_cg_start(Launch L, const Geo& g, int first, double alpha, double rn0,
-                double tol, int last_try, const R* r, const R* dinv,
-                const R* d, const R* kap, R* w, LevelScalars* sc,
-                double* partials);
+// Workgroups an item needs in the residual/CG-start kernels and in the CG
+// iteration kernel (both multiples of 8); the latter also returns the tiles.
+int item_residual_blocks(const Geo& g);
+int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles);
 
-// One Chronopoulos-Gear PCG iteration k in a single kernel (one reduction):
-//   p = u + beta p, s = w + beta s_old, x += alpha p, r' = r - alpha s,
-//   w' = J u' with u' = Dinv r' formed on the fly at the 27 neighbours,
-//   partials of gamma' = r'.u' and delta' = w'.u'.
-// r, w and s are double-buffered by iteration parity.
-// ev_start/ev_stop (hipEvent_t, may be null): events recorded with the
-// dispatch itself (kernel execution interval) for sampled timing.
+// Batched launches over a device table of n_items items; total_blocks is the
+// sum of the items' workgroup counts for that kernel.  ev_start/ev_stop
+// (hipEvent_t, may be null) are recorded with the CG dispatch itself.
 template <class R>
-void k_cg_iter(Launch L, const Geo& g, int k, R* const* rb, R* const* wb,
-               R* const* sb, R* p, R* x, const R* d, const R* kap,
-               const R* dinv, double rtol2, LevelScalars* sc, double* partials,
-               void* ev_start = nullptr, void* ev_stop = nullptr);
+void k_residual_batched(Launch L, const SolveItem* items, int n_items,
+                        int total_blocks);
+template <class R>
+void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
+                        int total_blocks);
+template <class R>
+void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
+                       int total_blocks, int kit, void* ev_start,
+                       void* ev_stop);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,

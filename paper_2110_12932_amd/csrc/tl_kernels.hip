@@ -245,127 +245,6 @@ __device__ inline void gather8(const Geo& g, const R* __restrict__ kap, int n,
 }
 
 // ---------------------------------------------------------------------------
-// K4 + K1: nonlinear residual at a trial temperature, Jacobian coefficients,
-// CG initialisation
-// ---------------------------------------------------------------------------
-template <class Rcg, class Rdx>
-__global__ void __launch_bounds__(kBlock)
-residual_kernel(Geo g, Region rg, MatDev m, double tau,
-                const double* __restrict__ T, const Rdx* __restrict__ dx,
-                double alpha, const double* __restrict__ Told,
-                const double* __restrict__ F, const double* __restrict__ Fext,
-                double* __restrict__ Tt, double* __restrict__ Rout,
-                Rcg* __restrict__ kap, Rcg* __restrict__ d,
-                Rcg* __restrict__ dinv, Rcg* __restrict__ r, double* partials) {
-  __shared__ double lds[6 * kBlock / 64];
-  double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
-       t += gridDim.x * blockDim.x) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    const int n = pidx(g, i, j, k);
-    double T27[27];
-    gather27(g, T, n, T27);
-    if (dx != nullptr) {
-#pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-          for (int dxx = -1; dxx <= 1; ++dxx)
-            T27[N27(dxx, dy, dz)] -=
-                alpha * (double)dx[n + dxx + dy * g.px + dz * g.pxy];
-    }
-    double k8[8];
-    double nact = 0.0;
-    double diagK = 0.0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-      double ke = 0.0;
-      if (elem_active(g, rg, i - ex, j - ey, k - ez)) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-          s += T27[N27(cx - ex, cy - ey, cz - ez)];
-        }
-        ke = kappa_of(0.125 * s, m);
-        nact += 1.0;
-      }
-      k8[e] = ke;
-      diagK += ke;
-    }
-    double w[8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) w[p] = g.w[p];
-    const double Tn = T27[13];
-    const double mass = g.vol8 * nact;
-    double Rn = mass * (enthalpy(Tn, m) - enthalpy(Told[n], m)) / tau +
-                stencil_apply(T27, k8, w) - F[n];
-    if (Fext != nullptr) Rn -= Fext[n];
-    Tt[n] = Tn;
-    Rout[n] = Rn;
-    // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
-    const bool dir = node_dirichlet(g, rg, i, j, k);
-    const double dn = mass * enthalpy_slope(Tn, m) / tau;
-    const double diag = dn + diagK * g.w[0];
-    // this node owns the element whose lowest corner it is (k8[0])
-    kap[n] = (Rcg)k8[0];
-    d[n] = (Rcg)dn;
-    const Rcg di = dir ? (Rcg)0 : (Rcg)(1.0 / diag);
-    dinv[n] = di;
-    const Rcg rn = dir ? (Rcg)0 : (Rcg)Rn;
-    const Rcg zn = di * rn;
-    r[n] = rn;
-    if (!dir) {
-      acc[0] += Rn * Rn;
-      if (dx != nullptr) acc[1] = fmax(acc[1], fabs(alpha * (double)dx[n]));
-      acc[2] += (double)(rn * zn);
-    }
-  }
-  // max is taken separately from the two sums
-  double mx = wave_max(acc[1]);
-  double sums[2] = {acc[0], acc[2]};
-  block_sum<2>(sums, lds);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double bm = lds[0];
-    for (int wv = 1; wv < kBlock / 64; ++wv) bm = fmax(bm, lds[wv]);
-    double* part = partials + kPartRes * kMaxBlocks;
-    part[blockIdx.x] = sums[0];
-    part[kMaxBlocks + blockIdx.x] = bm;
-    part[2 * kMaxBlocks + blockIdx.x] = sums[1];
-  }
-}
-
-template <class Rcg, class Rdx>
-void k_residual(Launch L, const Geo& g, const Region& rg, const MatDev& m,
-                double tau, const double* T, const Rdx* dx, double alpha,
-                const double* Told, const double* F, const double* Fext,
-                double* Tt, double* Rout, Rcg* kap, Rcg* d, Rcg* dinv, Rcg* r,
-                double* partials) {
-  hipLaunchKernelGGL((residual_kernel<Rcg, Rdx>), dim3(grid_for(g.nreal)),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, g, rg, m, tau, T,
-                     dx, alpha, Told, F, Fext, Tt, Rout, kap, d, dinv, r,
-                     partials);
-}
-template void k_residual<double, double>(Launch, const Geo&, const Region&,
-                                         const MatDev&, double, const double*,
-                                         const double*, double, const double*,
-                                         const double*, const double*, double*,
-                                         double*, double*, double*, double*,
-                                         double*, double*);
-template void k_residual<float, float>(Launch, const Geo&, const Region&,
-                                       const MatDev&, double, const double*,
-                                       const float*, double, const double*,
-                                       const double*, const double*, double*,
-                                       double*, float*, float*, float*, float*,
-                                       double*);
-
-// ---------------------------------------------------------------------------
 // LDS-tiled CG kernels.  A workgroup owns a TX x TY x TZ tile of nodes (one
 // node per thread).  The halo tile (TX+2)(TY+2)(TZ+2) of the operator input
 // is formed once into LDS from coalesced global loads, together with the
@@ -390,14 +269,14 @@ struct Tile {
 // (blockIdx.x % 8), each with its own L2.  The tiles (x fastest, then y, z)
 // are cut into 8 contiguous chunks and chunk c is processed by the
 // workgroups with blockIdx.x % 8 == c, so tiles that share halo entries sit
-// on the same L2.  The grid is a multiple of 8; workgroup b visits tiles
-// first(b), first(b) + step, ... below last(b).
+// on the same L2.  The workgroup count nb is a multiple of 8 and the first
+// workgroup's index too; local workgroup b visits tiles first(b),
+// first(b) + step, ... below last(b).
 constexpr int kXcd = 8;
 struct TileRange {
   int first, last, step;
 };
-__device__ inline TileRange tile_range(int ntiles) {
-  const int nb = gridDim.x, b = blockIdx.x;
+__device__ inline TileRange tile_range(int b, int nb, int ntiles) {
   const int per = nb / kXcd;                       // workgroups per XCD
   const int chunk = (ntiles + kXcd - 1) / kXcd;    // tiles per XCD
   const int c = b % kXcd, slot = b / kXcd;
@@ -474,21 +353,299 @@ __device__ inline R stencil_lds(const Tile& t, const R* u_s, const R* k_s,
   return stencil_apply(u27, k8, w);
 }
 
+// Tiled matrix-free operator y = d v + K[kap] v (every node).
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
-                     const R* __restrict__ r_in, const R* __restrict__ w_in,
-                     const R* __restrict__ s_old, R* __restrict__ r_out,
-                     R* __restrict__ w_out, R* __restrict__ s_out,
-                     R* __restrict__ p, R* __restrict__ x,
-                     const R* __restrict__ d, const R* __restrict__ kap,
-                     const R* __restrict__ dinv, double rtol2, int nparts,
-                     LevelScalars* sc, double* partials) {
+op_apply_tiled_kernel(Geo g, int ntx, int nty, int ntiles,
+                      const R* __restrict__ d,
+                      const R* __restrict__ kap, const R* __restrict__ v,
+                      R* __restrict__ y) {
+  __shared__ R u_s[HN];
+  __shared__ R k_s[EN];
+  R wts[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+  const TileRange tr = tile_range(blockIdx.x, gridDim.x, ntiles);
+  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    const Tile t = tile_of(tile, ntx, nty);
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      if (h < HN) {
+        const int n = halo_index(g, t, h);
+        u_s[h] = n >= 0 ? v[n] : (R)0;
+      }
+    }
+    load_kappa_tile(g, t, kap, k_s);
+    __syncthreads();
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+      const int n = pidx(g, i, j, k);
+      const R vc = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
+      y[n] = d[n] * vc + stencil_lds(t, u_s, k_s, wts);
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
+  ntx = (g.nx + TX - 1) / TX;
+  nty = (g.ny + TY - 1) / TY;
+  ntz = (g.nz + TZ - 1) / TZ;
+}
+
+// ---------------------------------------------------------------------------
+// Batched Newton/CG kernels.  One launch serves a table of independent level
+// solves ("items": one simulation's fine or coarse step, or many served
+// requests' steps at once).  Item i owns a contiguous range of workgroups
+// starting at a multiple of 8, so the XCD-aware tile order holds inside each
+// item; every item has its own scalars and partial-sum regions.
+// ---------------------------------------------------------------------------
+__device__ inline int item_of_block(const SolveItem* __restrict__ items,
+                                    int n, bool tiled) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int begin = tiled ? items[mid].tile_begin : items[mid].res_begin;
+    if (begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// K4 + K1: nonlinear residual at the trial T - alpha dx, Jacobian
+// coefficients, CG initial residual; partials of |R_free|^2, max|alpha dx|,
+// r.(Dinv r).
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+residual_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
+  __shared__ double lds[6 * kBlock / 64];
+  const SolveItem& it = items[item_of_block(items, n_items, false)];
+  const int blk = blockIdx.x - it.res_begin, nblk = it.res_nb;
+  const Geo& g = it.g;
+  const MatDev& m = it.m;
+  const double* __restrict__ T = it.T;
+  const R* __restrict__ dx = (const R*)it.dx;
+  const double alpha = it.alpha;
+  R* __restrict__ kap = (R*)it.kap;
+  R* __restrict__ d = (R*)it.d;
+  R* __restrict__ dinv = (R*)it.dinv;
+  R* __restrict__ r = (R*)it.r[0];
+  double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
+  for (int t = blk * blockDim.x + threadIdx.x; t < g.nreal;
+       t += nblk * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    double T27[27];
+    gather27(g, T, n, T27);
+    if (dx != nullptr) {
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dxx = -1; dxx <= 1; ++dxx)
+            T27[N27(dxx, dy, dz)] -=
+                alpha * (double)dx[n + dxx + dy * g.px + dz * g.pxy];
+    }
+    double k8[8];
+    double nact = 0.0;
+    double diagK = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+      double ke = 0.0;
+      if (elem_active(g, it.rg, i - ex, j - ey, k - ez)) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          s += T27[N27(cx - ex, cy - ey, cz - ez)];
+        }
+        ke = kappa_of(0.125 * s, m);
+        nact += 1.0;
+      }
+      k8[e] = ke;
+      diagK += ke;
+    }
+    double w[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) w[p] = g.w[p];
+    const double Tn = T27[13];
+    const double mass = g.vol8 * nact;
+    double Rn = mass * (enthalpy(Tn, m) - enthalpy(it.Told[n], m)) / it.tau +
+                stencil_apply(T27, k8, w) - it.F[n];
+    if (it.Fext != nullptr) Rn -= it.Fext[n];
+    it.Tt[n] = Tn;
+    it.R[n] = Rn;
+    // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
+    const bool dir = node_dirichlet(g, it.rg, i, j, k);
+    const double dn = mass * enthalpy_slope(Tn, m) / it.tau;
+    const double diag = dn + diagK * g.w[0];
+    // this node owns the element whose lowest corner it is (k8[0])
+    kap[n] = (R)k8[0];
+    d[n] = (R)dn;
+    const R di = dir ? (R)0 : (R)(1.0 / diag);
+    dinv[n] = di;
+    const R rn = dir ? (R)0 : (R)Rn;
+    const R zn = di * rn;
+    r[n] = rn;
+    if (!dir) {
+      acc[0] += Rn * Rn;
+      if (dx != nullptr) acc[1] = fmax(acc[1], fabs(alpha * (double)dx[n]));
+      acc[2] += (double)(rn * zn);
+    }
+  }
+  // max is taken separately from the two sums
+  double mx = wave_max(acc[1]);
+  double sums[2] = {acc[0], acc[2]};
+  block_sum<2>(sums, lds);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bm = lds[0];
+    for (int wv = 1; wv < kBlock / 64; ++wv) bm = fmax(bm, lds[wv]);
+    double* part = it.partials + kPartRes * kMaxBlocks;
+    part[blk] = sums[0];
+    part[kMaxBlocks + blk] = bm;
+    part[2 * kMaxBlocks + blk] = sums[1];
+  }
+}
+
+// Line-search decision and CG start (see the CG recurrences below).  From
+// the residual partials every workgroup of an item decides, identically,
+// whether its trial is accepted (first evaluation, sufficient decrease
+// (1 - 1e-4 alpha) rn0, step <= tol, or the last halving) and whether Newton
+// has converged (accepted and step <= tol); workgroup 0 stores the outcome.
+// If the iteration continues, w0 = J u0 (u0 = Dinv r0) and the partials of
+// gamma0 = r.u, delta0 = w.u are formed; otherwise `done` is set.
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
+  __shared__ double lds[2 * kBlock / 64];
+  __shared__ double ldm[kBlock / 64];
+  __shared__ double bc[3];
+  __shared__ R ldr[2 * kBlock / 64];
+  const SolveItem& it = items[item_of_block(items, n_items, false)];
+  const int blk = blockIdx.x - it.res_begin, nblk = it.res_nb;
+  const Geo& g = it.g;
+  LevelScalars* sc = it.sc;
+  // 1. residual reductions (every workgroup, same order)
+  {
+    const double* part = it.partials + kPartRes * kMaxBlocks;
+    double v[2] = {0.0, 0.0};
+    double bm = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+      v[0] += part[b];
+      v[1] += part[2 * kMaxBlocks + b];
+      bm = fmax(bm, part[kMaxBlocks + b]);
+    }
+    bm = wave_max(bm);
+    block_sum<2>(v, lds);
+    if ((threadIdx.x & 63) == 0) ldm[threadIdx.x >> 6] = bm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mm = ldm[0];
+      for (int wv = 1; wv < kBlock / 64; ++wv) mm = fmax(mm, ldm[wv]);
+      bc[0] = v[0];
+      bc[1] = mm;
+      bc[2] = v[1];
+    }
+    __syncthreads();
+  }
+  const double rnorm2 = bc[0], dmax = bc[1], rz = bc[2];
+  const double rn = sqrt(rnorm2);
+  const bool finite = isfinite(rnorm2) && isfinite(dmax);
+  bool accepted, converged;
+  if (it.first) {
+    accepted = true;
+    converged = false;
+  } else {
+    accepted = !finite || rn <= (1.0 - 1e-4 * it.alpha) * it.rn0 ||
+               dmax <= it.tol || it.last_try;
+    converged = accepted && finite && dmax <= it.tol;
+  }
+  const bool run = accepted && !converged && finite && rz > 0.0;
+  if (blk == 0 && threadIdx.x == 0) {
+    sc->rnorm2 = rnorm2;
+    sc->dmax = dmax;
+    sc->rz0 = rz;
+    sc->accepted = accepted ? 1 : 0;
+    sc->converged = converged ? 1 : 0;
+    sc->breakdown = finite ? 0 : 3;
+    sc->iters = 0;
+    sc->done = run ? 0 : 1;
+  }
+  if (!run) return;
+  // 2. w0 = J u0, u0 = Dinv r0
+  const R* __restrict__ r = (const R*)it.r[0];
+  const R* __restrict__ dinv = (const R*)it.dinv;
+  const R* __restrict__ d = (const R*)it.d;
+  const R* __restrict__ kap = (const R*)it.kap;
+  R* __restrict__ w = (R*)it.w[0];
+  R wts[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+  R acc[2] = {(R)0, (R)0};
+  for (int t = blk * blockDim.x + threadIdx.x; t < g.nreal;
+       t += nblk * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    R u27[27], k8[8];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int o = n + dx + dy * g.px + dz * g.pxy;
+          u27[N27(dx, dy, dz)] = dinv[o] * r[o];
+        }
+    gather8(g, kap, n, k8);
+    const R un = u27[13];
+    const R wn = d[n] * un + stencil_apply(u27, k8, wts);
+    w[n] = wn;
+    acc[0] += r[n] * un;
+    acc[1] += wn * un;
+  }
+  block_sum<2>(acc, ldr);
+  if (threadIdx.x == 0) {
+    it.partials[kPartCG * kMaxBlocks + blk] = (double)acc[0];
+    it.partials[(kPartCG + 1) * kMaxBlocks + blk] = (double)acc[1];
+  }
+}
+
+// One Chronopoulos-Gear PCG iteration `kit` for every item (LDS-tiled).
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
+                       int kit) {
   __shared__ R u_s[HN];
   __shared__ R k_s[EN];
   __shared__ R lds[2 * kBlock / 64];
   __shared__ R bc[2];
-  if (sc->done) return;
+  const SolveItem& it = items[item_of_block(items, n_items, true)];
+  LevelScalars* sc = it.sc;
+  // past the item's own launch count (other items of the batch may run
+  // more): no work, so the item's result does not depend on the batch
+  if (sc->done || kit >= it.max_kit) return;
+  const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
+  const Geo& g = it.g;
+  const int a = kit & 1;
+  const R* __restrict__ r_in = (const R*)it.r[a];
+  const R* __restrict__ w_in = (const R*)it.w[a];
+  const R* __restrict__ s_old = (const R*)it.s[1 - a];
+  R* __restrict__ r_out = (R*)it.r[1 - a];
+  R* __restrict__ w_out = (R*)it.w[1 - a];
+  R* __restrict__ s_out = (R*)it.s[a];
+  R* __restrict__ p = (R*)it.p;
+  R* __restrict__ x = (R*)it.x;
+  const R* __restrict__ d = (const R*)it.d;
+  const R* __restrict__ kap = (const R*)it.kap;
+  const R* __restrict__ dinv = (const R*)it.dinv;
   // 1. halo loads of the first tile, issued before the reduction so that
   // both latencies overlap
   R hr[HPT], hw[HPT], hs[HPT], hd[HPT];
@@ -503,15 +660,16 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
       hd[q] = n >= 0 ? dinv[n] : (R)0;
     }
   };
-  const TileRange tr = tile_range(ntiles);
-  if (tr.first < tr.last) load_halo(tile_of(tr.first, ntx, nty));
+  const TileRange tr = tile_range(blk, nblk, it.ntiles);
+  if (tr.first < tr.last) load_halo(tile_of(tr.first, it.ntx, it.nty));
   // 2. gamma_k, delta_k from the previous kernel's partials (CG start or
   // iteration k-1), held in the region pair this kernel does not write
   const int rd = (kit & 1) ? kPartCG2 : kPartCG;
   const int wr = (kit & 1) ? kPartCG : kPartCG2;
+  const int nparts = kit == 0 ? it.res_nb : nblk;
   {
     R v[2] = {(R)0, (R)0};
-    const double* pg = partials + rd * kMaxBlocks;
+    const double* pg = it.partials + rd * kMaxBlocks;
     for (int b = threadIdx.x; b < nparts; b += kBlock) {
       v[0] += (R)pg[b];
       v[1] += (R)pg[kMaxBlocks + b];
@@ -531,8 +689,8 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
   } else {
     const R gamma_prev = (R)sc->gbuf[(kit - 1) & 1];
     const R alpha_prev = (R)sc->abuf[(kit - 1) & 1];
-    if ((double)gamma <= rtol2 * sc->rz0 || !isfinite((double)gamma)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if ((double)gamma <= it.rtol2 * sc->rz0 || !isfinite((double)gamma)) {
+      if (blk == 0 && threadIdx.x == 0) {
         sc->done = 1;
         sc->iters = kit;
         if (!isfinite((double)gamma)) sc->breakdown = 2;
@@ -543,14 +701,14 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
     alpha = gamma / (delta - beta * gamma / alpha_prev);
   }
   if (!(alpha > (R)0) || !isfinite((double)alpha)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
       sc->done = 1;
       sc->iters = kit;
       sc->breakdown = 1;
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     sc->gbuf[kit & 1] = (double)gamma;
     sc->abuf[kit & 1] = (double)alpha;
     sc->iters = kit + 1;
@@ -560,7 +718,7 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
   R acc[2] = {(R)0, (R)0};
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
-    const Tile t = tile_of(tile, ntx, nty);
+    const Tile t = tile_of(tile, it.ntx, it.nty);
     if (tile != tr.first) load_halo(t);
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     const bool active = i < g.nx && j < g.ny && k < g.nz;
@@ -606,198 +764,54 @@ cg_iter_tiled_kernel(Geo g, int ntx, int nty, int ntiles, int kit,
   }
   block_sum<2>(acc, lds);
   if (threadIdx.x == 0) {
-    partials[wr * kMaxBlocks + blockIdx.x] = (double)acc[0];
-    partials[(wr + 1) * kMaxBlocks + blockIdx.x] = (double)acc[1];
+    it.partials[wr * kMaxBlocks + blk] = (double)acc[0];
+    it.partials[(wr + 1) * kMaxBlocks + blk] = (double)acc[1];
   }
 }
 
-// Tiled matrix-free operator y = d v + K[kap] v (every node).
-template <class R>
-__global__ void __launch_bounds__(kBlock)
-op_apply_tiled_kernel(Geo g, int ntx, int nty, int ntiles,
-                      const R* __restrict__ d,
-                      const R* __restrict__ kap, const R* __restrict__ v,
-                      R* __restrict__ y) {
-  __shared__ R u_s[HN];
-  __shared__ R k_s[EN];
-  R wts[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-  const TileRange tr = tile_range(ntiles);
-  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
-    const Tile t = tile_of(tile, ntx, nty);
-#pragma unroll
-    for (int q = 0; q < HPT; ++q) {
-      const int h = threadIdx.x + q * kBlock;
-      if (h < HN) {
-        const int n = halo_index(g, t, h);
-        u_s[h] = n >= 0 ? v[n] : (R)0;
-      }
-    }
-    load_kappa_tile(g, t, kap, k_s);
-    __syncthreads();
-    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
-    if (i < g.nx && j < g.ny && k < g.nz) {
-      const int n = pidx(g, i, j, k);
-      const R vc = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-      y[n] = d[n] * vc + stencil_lds(t, u_s, k_s, wts);
-    }
-    __syncthreads();  // LDS is reused by the next tile
-  }
-}
-
-static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
-  ntx = (g.nx + TX - 1) / TX;
-  nty = (g.ny + TY - 1) / TY;
-  ntz = (g.nz + TZ - 1) / TZ;
-}
-
-// ---------------------------------------------------------------------------
-// K1/K3: line-search decision and CG start; K2 + K3: one Chronopoulos-Gear
-// PCG iteration per kernel.
-//
-// CG recurrences (preconditioner M = diag(J)):
-//   u_k = Dinv r_k, w_k = J u_k, gamma_k = r_k.u_k, delta_k = w_k.u_k,
-//   beta_k = gamma_k / gamma_{k-1} (beta_0 = 0),
-//   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}) (alpha_0 =
-//   gamma_0 / delta_0),
-//   p_k = u_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}  (= J p_k),
-//   x_{k+1} = x_k + alpha_k p_k, r_{k+1} = r_k - alpha_k s_k.
-// Kernel k forms gamma_k, delta_k from kernel k-1's per-workgroup partials
-// (identically in every workgroup), updates the node's own p, s, x, r and
-// computes w_{k+1} = J u_{k+1} with u_{k+1} at the 27 neighbours rebuilt from
-// r_k, w_k, s_{k-1} -- so each iteration needs one kernel and one reduction.
-// Workgroup 0 records gamma_k and alpha_k in slot k & 1, which no other
-// workgroup of kernel k reads.  Once `done` is set later kernels return.
-// ---------------------------------------------------------------------------
-template <class R>
-__global__ void __launch_bounds__(kBlock)
-cg_start_kernel(Geo g, int first, double alpha, double rn0, double tol,
-                int last_try, int nparts, const R* __restrict__ r,
-                const R* __restrict__ dinv, const R* __restrict__ d,
-                const R* __restrict__ kap, R* __restrict__ w, LevelScalars* sc,
-                double* partials) {
-  __shared__ double lds[2 * kBlock / 64];
-  __shared__ double ldm[kBlock / 64];
-  __shared__ double bc[3];
-  __shared__ R ldr[2 * kBlock / 64];
-  // 1. residual reductions (every workgroup, same order)
-  {
-    const double* part = partials + kPartRes * kMaxBlocks;
-    double v[2] = {0.0, 0.0};
-    double bm = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
-      v[0] += part[b];
-      v[1] += part[2 * kMaxBlocks + b];
-      bm = fmax(bm, part[kMaxBlocks + b]);
-    }
-    bm = wave_max(bm);
-    block_sum<2>(v, lds);
-    if ((threadIdx.x & 63) == 0) ldm[threadIdx.x >> 6] = bm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double mm = ldm[0];
-      for (int wv = 1; wv < kBlock / 64; ++wv) mm = fmax(mm, ldm[wv]);
-      bc[0] = v[0];
-      bc[1] = mm;
-      bc[2] = v[1];
-    }
-    __syncthreads();
-  }
-  const double rnorm2 = bc[0], dmax = bc[1], rz = bc[2];
-  const double rn = sqrt(rnorm2);
-  const bool finite = isfinite(rnorm2) && isfinite(dmax);
-  bool accepted, converged;
-  if (first) {
-    accepted = true;
-    converged = false;
-  } else {
-    accepted = !finite || rn <= (1.0 - 1e-4 * alpha) * rn0 || dmax <= tol ||
-               last_try;
-    converged = accepted && finite && dmax <= tol;
-  }
-  const bool run = accepted && !converged && finite && rz > 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->rnorm2 = rnorm2;
-    sc->dmax = dmax;
-    sc->rz0 = rz;
-    sc->accepted = accepted ? 1 : 0;
-    sc->converged = converged ? 1 : 0;
-    sc->breakdown = finite ? 0 : 3;
-    sc->iters = 0;
-    sc->done = run ? 0 : 1;
-  }
-  if (!run) return;
-  // 2. w0 = J u0, u0 = Dinv r0
-  R wts[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-  R acc[2] = {(R)0, (R)0};
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
-       t += gridDim.x * blockDim.x) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    const int n = pidx(g, i, j, k);
-    R u27[27], k8[8];
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int o = n + dx + dy * g.px + dz * g.pxy;
-          u27[N27(dx, dy, dz)] = dinv[o] * r[o];
-        }
-    gather8(g, kap, n, k8);
-    const R un = u27[13];
-    const R wn = d[n] * un + stencil_apply(u27, k8, wts);
-    w[n] = wn;
-    acc[0] += r[n] * un;
-    acc[1] += wn * un;
-  }
-  block_sum<2>(acc, ldr);
-  if (threadIdx.x == 0) {
-    partials[kPartCG * kMaxBlocks + blockIdx.x] = (double)acc[0];
-    partials[(kPartCG + 1) * kMaxBlocks + blockIdx.x] = (double)acc[1];
-  }
-}
-
-template <class R>
-void k_cg_start(Launch L, const Geo& g, int first, double alpha, double rn0,
-                double tol, int last_try, const R* r, const R* dinv,
-                const R* d, const R* kap, R* w, LevelScalars* sc,
-                double* partials) {
-  const int nb = grid_for(g.nreal);
-  hipLaunchKernelGGL(cg_start_kernel<R>, dim3(nb), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, g, first, alpha, rn0, tol,
-                     last_try, nb, r, dinv, d, kap, w, sc, partials);
-}
-template <class R>
-void k_cg_iter(Launch L, const Geo& g, int k, R* const* rb, R* const* wb,
-               R* const* sb, R* p, R* x, const R* d, const R* kap,
-               const R* dinv, double rtol2, LevelScalars* sc,
-               double* partials, void* ev_start, void* ev_stop) {
-  const int a = k & 1;
-  int ntx, nty, ntz;
+int item_residual_blocks(const Geo& g) { return (grid_for(g.nreal) + 7) / 8 * 8; }
+int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles) {
+  int ntz;
   tiles_of(g, ntx, nty, ntz);
-  const int ntiles = ntx * nty * ntz;
-  const int nb = tiled_grid(ntiles);
-  // the previous kernel (CG start or iteration) wrote one partial per
-  // workgroup of its own grid
-  const int nprev = k == 0 ? grid_for(g.nreal) : nb;
-  if (ev_start != nullptr)
-    hipExtLaunchKernelGGL(cg_iter_tiled_kernel<R>, dim3(nb), dim3(kBlock), 0,
-                          (hipStream_t)L.stream, (hipEvent_t)ev_start,
-                          (hipEvent_t)ev_stop, 0, g, ntx, nty, ntiles, k,
-                          (const R*)rb[a], (const R*)wb[a], (const R*)sb[1 - a],
-                          rb[1 - a], wb[1 - a], sb[a], p, x, d, kap, dinv,
-                          rtol2, nprev, sc, partials);
-  else
-    hipLaunchKernelGGL(cg_iter_tiled_kernel<R>, dim3(nb), dim3(kBlock), 0,
-                       (hipStream_t)L.stream, g, ntx, nty, ntiles, k, rb[a],
-                       wb[a], sb[1 - a], rb[1 - a], wb[1 - a], sb[a], p, x, d,
-                       kap, dinv, rtol2, nprev, sc, partials);
+  ntiles = ntx * nty * ntz;
+  return tiled_grid(ntiles);
 }
+
+template <class R>
+void k_residual_batched(Launch L, const SolveItem* items, int n_items,
+                        int total_blocks) {
+  hipLaunchKernelGGL(residual_batched_kernel<R>, dim3(total_blocks),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items);
+}
+template <class R>
+void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
+                        int total_blocks) {
+  hipLaunchKernelGGL(cg_start_batched_kernel<R>, dim3(total_blocks),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items);
+}
+template <class R>
+void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
+                       int total_blocks, int kit, void* ev_start,
+                       void* ev_stop) {
+  if (ev_start != nullptr)
+    hipExtLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(total_blocks),
+                          dim3(kBlock), 0, (hipStream_t)L.stream,
+                          (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, items,
+                          n_items, kit);
+  else
+    hipLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(total_blocks),
+                       dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
+                       kit);
+}
+#define TL_BATCH_INST(R)                                                      \
+  template void k_residual_batched<R>(Launch, const SolveItem*, int, int);    \
+  template void k_cg_start_batched<R>(Launch, const SolveItem*, int, int);    \
+  template void k_cg_iter_batched<R>(Launch, const SolveItem*, int, int, int, \
+                                     void*, void*);
+TL_BATCH_INST(float)
+TL_BATCH_INST(double)
+#undef TL_BATCH_INST
+
 template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
                 R* y) {
@@ -812,17 +826,6 @@ template void k_op_apply<float>(Launch, const Geo&, const float*, const float*,
                                 const float*, float*);
 template void k_op_apply<double>(Launch, const Geo&, const double*,
                                  const double*, const double*, double*);
-
-#define TL_CG_INST(R)                                                         \
-  template void k_cg_start<R>(Launch, const Geo&, int, double, double, double, \
-                              int, const R*, const R*, const R*, const R*, R*, \
-                              LevelScalars*, double*);                        \
-  template void k_cg_iter<R>(Launch, const Geo&, int, R* const*, R* const*,   \
-                             R* const*, R*, R*, const R*, const R*, const R*, \
-                             double, LevelScalars*, double*, void*, void*);
-TL_CG_INST(float)
-TL_CG_INST(double)
-#undef TL_CG_INST
 
 // ---------------------------------------------------------------------------
 // K6: surface laser load F_i = sum over top faces of int q phi_i dA (n_q x n_q

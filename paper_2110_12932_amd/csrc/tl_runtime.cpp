@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <utility>
 #include <vector>
@@ -24,6 +25,7 @@
 #include "../../include/tl.h"
 #include "../../include/tl_ops.h"
 #include "tl_internal.h"
+#include "tl_runtime_internal.h"
 
 using namespace tl;
 
@@ -65,7 +67,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   Geo gc, gf;
   size_t off_c[22], off_fd[8], off_fcg[12];
-  size_t off_scal, off_ledger, off_partials, off_gidx, off_gbuf;
+  size_t off_scal, off_items, off_ledger, off_partials, off_gidx, off_gbuf;
   int gamma_cap;
   size_t total;
   int cg_bytes;
@@ -91,6 +93,7 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   for (int a = 0; a < kFineD; ++a) { L.off_fd[a] = off; off += fbytes; }
   for (int a = 0; a < kFineCG; ++a) { L.off_fcg[a] = off; off += fcg; }
   L.off_scal = off; off += align_up(2 * sizeof(LevelScalars));
+  L.off_items = off; off += align_up(2 * sizeof(SolveItem));
   L.off_ledger = off; off += align_up(sizeof(LedgerDev));
   L.off_partials = off;
   off += align_up((size_t)kMaxBlocks * kPartRegions * sizeof(double));
@@ -106,6 +109,216 @@ template <class R>
 struct CGBufs {
   R *kap, *d, *dinv, *r[2], *w[2], *s[2], *p, *x[2];
 };
+
+// Sampled event timing of the fine CG iteration kernel.
+struct Profiler {
+  int every = 0;
+  long count = 0;
+  int used = 0;
+  hipEvent_t ev[2 * kProfPairs] = {};
+  int k[kProfPairs] = {};
+  tl_stats* stats = nullptr;
+};
+
+// Device/pinned tables of one batch context: solve items and scalars.
+struct BatchCtx {
+  SolveItem* d_items = nullptr;
+  SolveItem* h_items = nullptr;
+  LevelScalars* d_sc = nullptr;
+  LevelScalars* h_sc = nullptr;
+  int cap = 0;
+  hipStream_t stream = nullptr;
+  Launch L{nullptr};
+};
+
+// One implicit step of one level inside a batch: the problem (grid, region,
+// step, old field, loads, buffers) and the host-side Newton state.
+template <class R>
+struct Job {
+  Geo g;
+  Region rg;
+  MatDev m;
+  double tau = 0.0;
+  const double* Told = nullptr;
+  const double* F = nullptr;
+  const double* Fext = nullptr;
+  double** T = nullptr;   // accepted temperature (swapped with *Tt)
+  double** Tt = nullptr;  // trial temperature
+  double* Rout = nullptr;
+  CGBufs<R>* cg = nullptr;
+  double* partials = nullptr;
+  int* last_cg = nullptr;   // adaptive CG launch count of this level
+  int64_t* n_newton = nullptr;
+  int64_t* n_cg = nullptr;
+  tl_stats* stats = nullptr;   // line-search count; op bytes if `fine`
+  bool fine = false;
+  double tol = 0.0, rtol2 = 0.0;
+  int newton_max = 0, cg_max = 0;
+  const char* what = "";
+  bool failed = false;
+  std::string err;
+  // Newton state
+  int xi = 0, h = 0, dirs = 0, n_launch = 3;
+  double rn0 = 0.0, alpha = 0.0;
+  bool first = true, finished = false;
+};
+
+void flush_profile(Profiler* pr, int work_limit) {
+  for (int q = 0; q < pr->used; ++q) {
+    if (pr->k[q] >= work_limit) continue;
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, pr->ev[2 * q], pr->ev[2 * q + 1]),
+              "hipEventElapsedTime");
+    pr->stats->fine_op_timed_ms += ms;
+    pr->stats->fine_op_timed += 1;
+  }
+  pr->used = 0;
+}
+
+// Batched implicit steps: frozen-kappa Newton with backtracking on
+// |R_free|_2 for every job, linear systems by Jacobi-PCG in precision R.
+// Each round queues, without host synchronisation and for all unfinished
+// jobs at once: the residual at each job's trial T - alpha x (alpha = 0 on
+// the first round), the device-side line-search decision with the CG start,
+// and CG iterations for the next direction (they return at once for a job
+// whose trial was rejected, whose Newton iteration converged, or whose CG
+// converged).  The host then reads every job's outcome with one copy.  On
+// return each job's *T holds its solution and Rout the residual there.
+template <class R>
+void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
+  const int nj = (int)jobs.size();
+  if (nj > B.cap) throw DevErr{"batch larger than its context"};
+  for (Job<R>* j : jobs) {
+    j->xi = 0; j->h = 0; j->dirs = 0; j->rn0 = 0.0; j->alpha = 0.0;
+    j->first = true; j->finished = false; j->failed = false;
+    j->n_launch = std::min(j->cg_max, std::max(3, *j->last_cg + 2));
+  }
+  std::vector<int> act;
+  for (;;) {
+    act.clear();
+    for (int q = 0; q < nj; ++q)
+      if (!jobs[q]->finished) act.push_back(q);
+    if (act.empty()) return;
+    int rb = 0, tb = 0, n_launch = 0;
+    for (int a = 0; a < (int)act.size(); ++a) {
+      Job<R>& j = *jobs[act[a]];
+      SolveItem& it = B.h_items[a];
+      it.g = j.g;
+      it.rg = j.rg;
+      it.m = j.m;
+      it.tau = j.tau;
+      it.alpha = j.alpha;
+      it.rn0 = j.rn0;
+      it.tol = j.tol;
+      it.rtol2 = j.rtol2;
+      it.first = j.first ? 1 : 0;
+      it.last_try = j.h == kLineSearchMax - 1 ? 1 : 0;
+      it.res_begin = rb;
+      it.res_nb = item_residual_blocks(j.g);
+      rb += it.res_nb;
+      it.tile_begin = tb;
+      it.tile_nb = item_tile_blocks(j.g, it.ntx, it.nty, it.ntiles);
+      tb += it.tile_nb;
+      it.T = *j.T;
+      it.Told = j.Told;
+      it.F = j.F;
+      it.Fext = j.Fext;
+      it.Tt = *j.Tt;
+      it.R = j.Rout;
+      it.dx = j.first ? nullptr : (const void*)j.cg->x[j.xi];
+      it.kap = j.cg->kap;
+      it.d = j.cg->d;
+      it.dinv = j.cg->dinv;
+      it.r[0] = j.cg->r[0];
+      it.r[1] = j.cg->r[1];
+      it.w[0] = j.cg->w[0];
+      it.w[1] = j.cg->w[1];
+      it.s[0] = j.cg->s[0];
+      it.s[1] = j.cg->s[1];
+      it.p = j.cg->p;
+      it.x = j.cg->x[1 - j.xi];
+      it.sc = B.d_sc + act[a];
+      it.max_kit = j.n_launch;
+      it.partials = j.partials;
+      n_launch = std::max(n_launch, j.n_launch);
+    }
+    const int na = (int)act.size();
+    hip_check(hipMemcpyAsync(B.d_items, B.h_items, sizeof(SolveItem) * na,
+                             hipMemcpyHostToDevice, B.stream),
+              "hipMemcpyAsync(items)");
+    k_residual_batched<R>(B.L, B.d_items, na, rb);
+    k_cg_start_batched<R>(B.L, B.d_items, na, rb);
+    for (int k = 0; k < n_launch; ++k) {
+      const bool timed = prof != nullptr && prof->every > 0 &&
+                         (prof->count++ % prof->every) == 0 &&
+                         prof->used < kProfPairs;
+      k_cg_iter_batched<R>(B.L, B.d_items, na, tb, k,
+                           timed ? (void*)prof->ev[2 * prof->used] : nullptr,
+                           timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr);
+      if (timed) prof->k[prof->used++] = k;
+    }
+    hip_check(hipGetLastError(), "kernel launch");
+    hip_check(hipMemcpyAsync(B.h_sc, B.d_sc, sizeof(LevelScalars) * nj,
+                             hipMemcpyDeviceToHost, B.stream),
+              "hipMemcpyAsync(scalars)");
+    hip_check(hipStreamSynchronize(B.stream), "hipStreamSynchronize");
+    int work_limit = 0;  // CG launches below this index did work for some job
+    for (int q : act) {
+      const LevelScalars& o = B.h_sc[q];
+      if (o.accepted && !o.converged && o.rz0 != 0.0)
+        work_limit = std::max(work_limit, o.done ? o.iters : jobs[q]->n_launch);
+    }
+    if (prof != nullptr && prof->used > 0) flush_profile(prof, work_limit);
+    for (int q : act) {
+      Job<R>& j = *jobs[q];
+      const LevelScalars& o = B.h_sc[q];
+      auto job_fail = [&](const std::string& msg) {
+        j.failed = true;
+        j.finished = true;
+        j.err = std::string(j.what) + msg;
+      };
+      if (!std::isfinite(o.rnorm2) || !std::isfinite(o.dmax)) {
+        job_fail(": non-finite residual or Newton update");
+        continue;
+      }
+      if (!o.accepted) {
+        ++j.h;
+        j.alpha = std::ldexp(1.0, -j.h);
+        ++j.stats->line_search_halvings;
+        continue;
+      }
+      std::swap(*j.T, *j.Tt);
+      j.rn0 = std::sqrt(o.rnorm2);
+      j.first = false;
+      if (o.converged || o.rz0 == 0.0) {
+        j.finished = true;
+        continue;
+      }
+      // the CG of this round produced the next direction
+      if (o.breakdown && o.iters == 0) {
+        job_fail(": CG breakdown (non-positive or non-finite curvature)");
+        continue;
+      }
+      if (j.dirs >= j.newton_max) {
+        job_fail(" Newton did not converge within newton_max iterations");
+        continue;
+      }
+      ++j.dirs;
+      ++*j.n_newton;
+      *j.n_cg += o.iters;
+      if (j.fine) {
+        j.stats->fine_op_bytes += 13.0 * sizeof(R) * j.g.nreal * o.iters;
+        j.stats->fine_op_applies += o.iters;
+      }
+      const bool cut = !o.done;  // CG stopped by the launch count, not rtol
+      *j.last_cg = cut ? n_launch + 2 : o.iters;
+      j.n_launch = std::min(j.cg_max, std::max(3, *j.last_cg + 2));
+      j.xi = 1 - j.xi;
+      j.h = 0;
+      j.alpha = 1.0;
+    }
+  }
+}
 
 }  // namespace
 
@@ -144,12 +357,8 @@ struct tl_sim {
   long n_macro;
   double theta0;
   int last_cg_f, last_cg_c;
-  // sampled event timing of the fine CG operator kernel (tl_set_profiling)
-  int prof_every;
-  long prof_count;
-  int prof_used;
-  hipEvent_t prof_ev[2 * 64];
-  int prof_k[64];
+  Profiler prof;   // sampled event timing of the fine CG kernel
+  BatchCtx batch;  // one-item batches for this simulation's solves
 };
 
 namespace {
@@ -237,137 +446,6 @@ void set_interface(tl_sim* s) {
               "hipMemcpy(interface indices)");
 }
 
-void sync_read_scalars(tl_sim* s, const LevelScalars* dev) {
-  hip_check(hipGetLastError(), "kernel launch");
-  hip_check(hipMemcpyAsync(s->h_sc, dev, sizeof(LevelScalars),
-                           hipMemcpyDeviceToHost, s->stream),
-            "hipMemcpyAsync(scalars)");
-  hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-}
-
-// Collect the sampled event timings of fine operator launches after a host
-// sync of the CG loop.  Launches of iteration k did work unless the solve has
-// finished with k >= iters (those return at once); only working launches are
-// counted.
-void flush_profile(tl_sim* s, const LevelScalars& sc) {
-  for (int q = 0; q < s->prof_used; ++q) {
-    if (sc.done && s->prof_k[q] >= sc.iters) continue;
-    float ms = 0.0f;
-    hip_check(hipEventElapsedTime(&ms, s->prof_ev[2 * q], s->prof_ev[2 * q + 1]),
-              "hipEventElapsedTime");
-    s->stats.fine_op_timed_ms += ms;
-    s->stats.fine_op_timed += 1;
-  }
-  s->prof_used = 0;
-}
-
-// One backward-Euler step of one level: frozen-kappa Newton with backtracking
-// on |R_free|_2; linear systems by Jacobi-PCG in precision R.  T holds the
-// initial guess with the Dirichlet values in place; on return T (possibly
-// swapped with Tt) holds the solution and Rout the residual there.
-//
-// Each round queues, without host synchronisation: the residual at the trial
-// T - alpha x (alpha = 0 on the first round), the device-side line-search
-// decision with the CG start, and n_launch CG iterations for the next
-// direction (they return at once when the trial is rejected, Newton has
-// converged, or CG has converged).  The host then reads the outcome once.
-template <class R>
-void solve_level(tl_sim* s, bool fine, const Geo& g, const Region& rg,
-                 double tau, const double* Told, const double* F,
-                 const double* Fext, double*& T, double*& Tt, double* Rout,
-                 CGBufs<R>& cg, LevelScalars* sc, int& last_cg) {
-  const tl_options& op = s->opts;
-  const double tol = op.newton_tol;
-  double rtol = op.cg_rtol;
-  if (sizeof(R) == 4) rtol = std::max(rtol, 1e-5);
-  const double rtol2 = rtol * rtol;
-  int64_t& n_newton = fine ? s->stats.newton_fine : s->stats.newton_coarse;
-  int64_t& n_cg = fine ? s->stats.cg_fine : s->stats.cg_coarse;
-  const double op_bytes_per_node = 13.0 * sizeof(R);
-  int xi = 0;  // cg.x[xi]: direction being line-searched; CG writes cg.x[1-xi]
-  int n_launch = std::min(op.cg_max, std::max(3, last_cg + 2));
-  double rn0 = 0.0;
-
-  auto round = [&](bool first, double alpha, int h) {
-    k_residual<R, R>(s->L, g, rg, s->mat, tau, T,
-                     first ? (const R*)nullptr : cg.x[xi], alpha, Told, F,
-                     Fext, Tt, Rout, cg.kap, cg.d, cg.dinv, cg.r[0],
-                     s->partials);
-    k_cg_start<R>(s->L, g, first ? 1 : 0, alpha, rn0, tol,
-                  h == kLineSearchMax - 1 ? 1 : 0, cg.r[0], cg.dinv, cg.d,
-                  cg.kap, cg.w[0], sc, s->partials);
-    for (int k = 0; k < n_launch; ++k) {
-      const bool timed = fine && s->prof_every > 0 &&
-                         (s->prof_count++ % s->prof_every) == 0 &&
-                         s->prof_used < kProfPairs;
-      k_cg_iter<R>(s->L, g, k, cg.r, cg.w, cg.s, cg.p, cg.x[1 - xi], cg.d,
-                   cg.kap, cg.dinv, rtol2, sc, s->partials,
-                   timed ? (void*)s->prof_ev[2 * s->prof_used] : nullptr,
-                   timed ? (void*)s->prof_ev[2 * s->prof_used + 1] : nullptr);
-      if (timed) {
-        s->prof_k[s->prof_used] = k;
-        ++s->prof_used;
-      }
-    }
-  };
-
-  round(true, 0.0, 0);
-  int dirs = 0;  // Newton directions computed
-  int h = 0;
-  for (;;) {
-    sync_read_scalars(s, sc);
-    const LevelScalars& o = *s->h_sc;
-    if (fine && s->prof_used > 0) flush_profile(s, o);
-    if (!std::isfinite(o.rnorm2) || !std::isfinite(o.dmax))
-      throw NoConv{"non-finite residual or Newton update"};
-    if (!o.accepted) {
-      ++s->stats.line_search_halvings;
-      ++h;
-      round(false, std::ldexp(1.0, -h), h);
-      continue;
-    }
-    std::swap(T, Tt);
-    rn0 = std::sqrt(o.rnorm2);
-    if (o.converged || o.rz0 == 0.0) return;
-    // the CG of this round produced the next direction
-    if (o.breakdown && o.iters == 0)
-      throw NoConv{"CG breakdown (non-positive or non-finite curvature)"};
-    if (dirs >= op.newton_max)
-      throw NoConv{std::string(fine ? "fine" : "coarse") +
-                   " Newton did not converge within newton_max iterations"};
-    ++dirs;
-    ++n_newton;
-    n_cg += o.iters;
-    if (fine) {
-      s->stats.fine_op_bytes += op_bytes_per_node * g.nreal * o.iters;
-      s->stats.fine_op_applies += o.iters;
-    }
-    const bool cut = !o.done;  // CG stopped by the launch count, not rtol
-    last_cg = cut ? n_launch + 2 : o.iters;
-    n_launch = std::min(op.cg_max, std::max(3, last_cg + 2));
-    xi = 1 - xi;
-    h = 0;
-    round(false, 1.0, 0);
-  }
-}
-
-void solve_fine(tl_sim* s, double tau, const double* Told, const double* F) {
-  const Region rg = region_window(s);
-  if (s->opts.precision == TL_MIXED)
-    solve_level<float>(s, true, s->gf, rg, tau, Told, F, nullptr, s->fcur,
-                       s->ftrial, s->fR, s->fcg32, s->sc_f, s->last_cg_f);
-  else
-    solve_level<double>(s, true, s->gf, rg, tau, Told, F, nullptr, s->fcur,
-                        s->ftrial, s->fR, s->fcg64, s->sc_f, s->last_cg_f);
-  ++s->stats.fine_solves;
-}
-
-void solve_coarse(tl_sim* s, const Region& rg, double tau, const double* F,
-                  const double* Fext) {
-  solve_level<double>(s, false, s->gc, rg, tau, s->Tn, F, Fext, s->ccur,
-                      s->ctrial, s->cR, s->ccg, s->sc_c, s->last_cg_c);
-  ++s->stats.coarse_solves;
-}
 
 SpotSet make_spots(const tl_sim* s, long n, int j0, int j1, double weight) {
   SpotSet sp;
@@ -510,125 +588,353 @@ struct Interface {
   }
 };
 
-// One macro step of Algorithm 1.
-void macro_step(tl_sim* s) {
-  const tl_options& op = s->opts;
-  const int m = op.m_time;
-  const double Dt = op.dt_coarse, dt = Dt / m;
-  const long n = s->n_macro;
-  const Launch L = s->L;
-  LedgerDev* led = s->led;
-
-  // 1. window placement for the beam at t_{n+1}
-  int I0, J0;
-  window_origin(s->tracks.data(), (int)s->tracks.size(), s->t_start,
-                micro_time(s->t_start, Dt, m, n + 1, 0), s->gc.hx, s->gc.hy,
-                s->mesh.nx, s->mesh.ny, s->mesh.win_nx, s->mesh.win_ny, 1,
-                s->win.I0, s->win.J0, &I0, &J0);
-  if (I0 != s->win.I0 || J0 != s->win.J0) {
-    energy_now(s, &led->e_tmp0);
-    const Window wo = s->win;
-    const Window wn = make_window(s->mesh, I0, J0);
-    k_window_shift(L, s->gf, s->gc, wn, wo, s->fstate, s->Tn, s->falt);
-    std::swap(s->fstate, s->falt);
-    s->win = wn;
-    s->gf.x0 = wn.I0 * s->gc.hx;
-    s->gf.y0 = wn.J0 * s->gc.hy;
-    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    set_interface(s);
-    k_fill(L, s->ext, 0.0, s->gc.npad);
-    energy_now(s, &led->e_tmp1);
-    read_ledger(s);
-    s->h_led->remap += s->h_led->e_tmp1 - s->h_led->e_tmp0;
-    hip_check(hipMemcpyAsync(&led->remap, &s->h_led->remap, sizeof(double),
-                             hipMemcpyHostToDevice, s->stream),
-              "hipMemcpyAsync(remap)");
-    ++s->stats.window_moves;
-  }
-  const Window& w = s->win;
-
-  // 2. coarse loads averaged over the m micro times; predictor
-  SpotSet avg = make_spots(s, n, 1, m, 1.0 / m);
-  k_laser_load(L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr, s->partials);
-  k_laser_load(L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy, s->Fout,
-               Dt, &led->absorbed, s->partials);
-  k_copy(L, s->ccur, s->Tn, s->gc.npad);
-  solve_coarse(s, region_all(), Dt, s->Fall, nullptr);
-  std::swap(s->Tpred, s->ccur);
-
-  // 3. micro steps j = 1..m-1 with blended Dirichlet data
-  k_copy(L, s->fprev, s->fstate, s->gf.npad);
-  for (int j = 1; j < m; ++j) {
-    k_copy(L, s->fcur, s->fprev, s->gf.npad);
-    k_fine_dirichlet(L, s->gf, s->gc, w, s->mat_in.T_bottom, s->Tn, s->Tpred,
-                     (double)j / m, s->fcur);
-    SpotSet sp = make_spots(s, n, j, j, 1.0);
-    k_laser_load(L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, &led->absorbed,
-                 s->partials);
-    solve_fine(s, dt, s->fprev, s->fF);
-    k_interface_accumulate(L, s->gf, w, s->fR, s->rho, j == 1 ? 1 : 0, -dt,
-                           &led->bottom, s->partials);
-    std::swap(s->fprev, s->fcur);
-    ++s->stats.micro_steps;
-  }
-
-  // 4. two-level correction at t_{n+1}
-  {
-    SpotSet sp = make_spots(s, n, m, m, 1.0);
-    k_laser_load(L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, &led->absorbed,
-                 s->partials);
-  }
-  k_copy(L, s->lam, s->Tpred, s->gc.npad);
-  k_copy(L, s->fcur, s->fprev, s->gf.npad);
-  k_copy(L, s->ccur, s->Tpred, s->gc.npad);
-  const Region rout = region_outside(s);
+// Per-simulation state of one macro step run in lockstep with others.
+struct StepState {
+  tl_sim* s = nullptr;
+  bool failed = false;
+  std::string err;
+  int m = 1;
+  double Dt = 0.0, dt = 0.0;
+  long n = 0;
+  bool dn_done = false;
+  int it = 0;
   Interface iqn;
   std::vector<double> lam_v, lt_v, next;
-  int it = 1;
-  for (;; ++it) {
-    if (it > op.dn_max) throw NoConv{"two-level iteration did not converge"};
-    k_fine_dirichlet(L, s->gf, s->gc, w, s->mat_in.T_bottom, s->lam, nullptr,
-                     0.0, s->fcur);
-    solve_fine(s, dt, s->fprev, s->fF);
-    k_restrict(L, s->gf, s->gc, w, m > 1 ? s->rho : nullptr, s->fR, -1.0 / m,
-               s->ext);
-    k_inject(L, s->gf, s->gc, w, s->fcur, s->ccur);
-    solve_coarse(s, rout, Dt, s->Fout, s->ext);
-    // interface residual lambda' - lambda on the host
-    const int ng = s->n_gamma;
-    k_gamma_gather(L, s->gidx, ng, s->ccur, s->lam, s->gbuf);
-    if (ng > 0)
-      hip_check(hipMemcpyAsync(s->h_gbuf, s->gbuf, 2 * sizeof(double) * ng,
-                               hipMemcpyDeviceToHost, s->stream),
-                "hipMemcpyAsync(interface)");
-    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    lt_v.resize(ng);
-    lam_v.resize(ng);
-    double diff = 0.0;
-    for (int q = 0; q < ng; ++q) {
-      lt_v[q] = s->h_gbuf[2 * q];
-      lam_v[q] = s->h_gbuf[2 * q + 1];
-      diff = std::max(diff, std::fabs(lt_v[q] - lam_v[q]));
-    }
-    if (!std::isfinite(diff)) throw NoConv{"non-finite interface update"};
-    if (diff <= op.dn_tol) break;
-    iqn.update(lam_v, lt_v, s->theta0, op.dn_theta > 0.0, next);
-    for (int q = 0; q < ng; ++q) s->h_gbuf[q] = next[q];
-    hip_check(hipMemcpyAsync(s->gbuf, s->h_gbuf, sizeof(double) * ng,
-                             hipMemcpyHostToDevice, s->stream),
-              "hipMemcpyAsync(interface)");
-    k_gamma_scatter(L, s->gidx, ng, s->gbuf, s->lam);
+};
+
+void fail_step(StepState& st, const std::string& msg) {
+  if (!st.failed) {
+    st.failed = true;
+    st.err = "macro step " + std::to_string(st.n) + ": " + msg;
   }
-  s->stats.dn_iters += it;
-  ++s->stats.micro_steps;
-  // bottom heat flow of the last fine step and of the coarse outside solve
-  k_interface_accumulate(L, s->gf, w, s->fR, nullptr, 0, -dt, &led->bottom,
-                         s->partials);
-  k_bottom_sum(L, s->gc, s->cR, -Dt, &led->bottom, s->partials);
-  std::swap(s->Tn, s->ccur);
-  std::swap(s->fstate, s->fcur);
-  energy_now(s, &led->stored);
-  s->stats.fine_dof_steps += fine_free_nodes(s->gf, w) * m;
+}
+
+template <class R>
+Job<R> make_job(tl_sim* s, bool fine, const Region& rg, double tau,
+                const double* Told, const double* F, const double* Fext) {
+  Job<R> j;
+  j.g = fine ? s->gf : s->gc;
+  j.rg = rg;
+  j.m = s->mat;
+  j.tau = tau;
+  j.Told = Told;
+  j.F = F;
+  j.Fext = Fext;
+  j.T = fine ? &s->fcur : &s->ccur;
+  j.Tt = fine ? &s->ftrial : &s->ctrial;
+  j.Rout = fine ? s->fR : s->cR;
+  j.partials = s->partials;
+  j.last_cg = fine ? &s->last_cg_f : &s->last_cg_c;
+  j.n_newton = fine ? &s->stats.newton_fine : &s->stats.newton_coarse;
+  j.n_cg = fine ? &s->stats.cg_fine : &s->stats.cg_coarse;
+  j.stats = &s->stats;
+  j.fine = fine;
+  j.tol = s->opts.newton_tol;
+  const double rtol =
+      sizeof(R) == 4 ? std::max(s->opts.cg_rtol, 1e-5) : s->opts.cg_rtol;
+  j.rtol2 = rtol * rtol;
+  j.newton_max = s->opts.newton_max;
+  j.cg_max = s->opts.cg_max;
+  j.what = fine ? "fine" : "coarse";
+  return j;
+}
+
+template <class R>
+CGBufs<R>& cg_of(tl_sim* s, bool fine);
+template <>
+CGBufs<double>& cg_of<double>(tl_sim* s, bool fine) {
+  return fine ? s->fcg64 : s->ccg;
+}
+template <>
+CGBufs<float>& cg_of<float>(tl_sim* s, bool fine) {
+  (void)fine;
+  return s->fcg32;
+}
+
+// Solve one fine (fine = true) or coarse step for every listed simulation
+// in batched launches; `setup` supplies region, step, old field, loads.
+// Simulations whose solve fails are marked failed.
+template <class R>
+void batch_solve(BatchCtx& B, std::vector<StepState*>& list, bool fine,
+                 const std::function<Job<R>(StepState&)>& setup,
+                 Profiler* prof) {
+  std::vector<Job<R>> jobs;
+  jobs.reserve(list.size());
+  for (StepState* st : list) {
+    jobs.push_back(setup(*st));
+    jobs.back().cg = &cg_of<R>(st->s, fine);
+  }
+  std::vector<Job<R>*> ptrs;
+  for (Job<R>& j : jobs) ptrs.push_back(&j);
+  if (!ptrs.empty()) solve_batch<R>(B, ptrs, prof);
+  for (size_t q = 0; q < list.size(); ++q) {
+    tl_sim* s = list[q]->s;
+    if (jobs[q].failed) fail_step(*list[q], jobs[q].err);
+    if (fine)
+      ++s->stats.fine_solves;
+    else
+      ++s->stats.coarse_solves;
+  }
+}
+
+// Fine solves of the listed simulations, grouped by the precision of their
+// linear solves.
+void batch_fine(BatchCtx& B, std::vector<StepState*>& list,
+                const std::function<void(StepState&, Region&, double&,
+                                         const double*&)>& told,
+                Profiler* prof) {
+  std::vector<StepState*> f64, f32;
+  for (StepState* st : list)
+    (st->s->opts.precision == TL_MIXED ? f32 : f64).push_back(st);
+  auto mk64 = [&](StepState& st) {
+    Region rg;
+    double tau;
+    const double* Told;
+    told(st, rg, tau, Told);
+    return make_job<double>(st.s, true, rg, tau, Told, st.s->fF, nullptr);
+  };
+  auto mk32 = [&](StepState& st) {
+    Region rg;
+    double tau;
+    const double* Told;
+    told(st, rg, tau, Told);
+    return make_job<float>(st.s, true, rg, tau, Told, st.s->fF, nullptr);
+  };
+  batch_solve<double>(B, f64, true, mk64, prof);
+  batch_solve<float>(B, f32, true, mk32, prof);
+}
+
+std::vector<StepState*> live(std::vector<StepState>& steps) {
+  std::vector<StepState*> out;
+  for (StepState& st : steps)
+    if (!st.failed) out.push_back(&st);
+  return out;
+}
+
+// One macro step of Algorithm 1 for several simulations in lockstep: the
+// per-simulation work (window, loads, Dirichlet data, transfers, ledger) is
+// queued simulation by simulation, and every fine or coarse implicit step of
+// a phase is one batched Newton/CG solve over all simulations.  The
+// two-level iteration drops each simulation once its interface has
+// converged.  A simulation that fails is marked and left out of the rest of
+// the step; the caller restores its state.
+void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
+                      Profiler* prof) {
+  for (StepState& st : steps) {
+    tl_sim* s = st.s;
+    st.m = s->opts.m_time;
+    st.Dt = s->opts.dt_coarse;
+    st.dt = st.Dt / st.m;
+    st.n = s->n_macro;
+    st.dn_done = false;
+    st.it = 0;
+  }
+  // 1. window placement for the beam at t_{n+1}; 2. coarse loads
+  for (StepState& st : steps) {
+    tl_sim* s = st.s;
+    const Launch L = s->L;
+    LedgerDev* led = s->led;
+    int I0, J0;
+    window_origin(s->tracks.data(), (int)s->tracks.size(), s->t_start,
+                  micro_time(s->t_start, st.Dt, st.m, st.n + 1, 0), s->gc.hx,
+                  s->gc.hy, s->mesh.nx, s->mesh.ny, s->mesh.win_nx,
+                  s->mesh.win_ny, 1, s->win.I0, s->win.J0, &I0, &J0);
+    if (I0 != s->win.I0 || J0 != s->win.J0) {
+      energy_now(s, &led->e_tmp0);
+      const Window wo = s->win;
+      const Window wn = make_window(s->mesh, I0, J0);
+      k_window_shift(L, s->gf, s->gc, wn, wo, s->fstate, s->Tn, s->falt);
+      std::swap(s->fstate, s->falt);
+      s->win = wn;
+      s->gf.x0 = wn.I0 * s->gc.hx;
+      s->gf.y0 = wn.J0 * s->gc.hy;
+      hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+      set_interface(s);
+      k_fill(L, s->ext, 0.0, s->gc.npad);
+      energy_now(s, &led->e_tmp1);
+      read_ledger(s);
+      s->h_led->remap += s->h_led->e_tmp1 - s->h_led->e_tmp0;
+      hip_check(hipMemcpyAsync(&led->remap, &s->h_led->remap, sizeof(double),
+                               hipMemcpyHostToDevice, s->stream),
+                "hipMemcpyAsync(remap)");
+      ++s->stats.window_moves;
+    }
+    const Window& w = s->win;
+    SpotSet avg = make_spots(s, st.n, 1, st.m, 1.0 / st.m);
+    k_laser_load(L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr, s->partials);
+    k_laser_load(L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy, s->Fout,
+                 st.Dt, &led->absorbed, s->partials);
+    k_copy(L, s->ccur, s->Tn, s->gc.npad);
+  }
+  // coarse predictor over the whole plate
+  {
+    std::vector<StepState*> list = live(steps);
+    batch_solve<double>(
+        B, list, false,
+        [](StepState& st) {
+          return make_job<double>(st.s, false, region_all(), st.Dt, st.s->Tn,
+                                  st.s->Fall, nullptr);
+        },
+        nullptr);
+  }
+  for (StepState* st : live(steps)) {
+    tl_sim* s = st->s;
+    std::swap(s->Tpred, s->ccur);
+    k_copy(s->L, s->fprev, s->fstate, s->gf.npad);
+  }
+  // 3. micro steps j = 1..m-1 with blended Dirichlet data
+  int mmax = 1;
+  for (StepState& st : steps) mmax = std::max(mmax, st.m);
+  for (int j = 1; j < mmax; ++j) {
+    std::vector<StepState*> list;
+    for (StepState* st : live(steps))
+      if (j < st->m) list.push_back(st);
+    for (StepState* st : list) {
+      tl_sim* s = st->s;
+      k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
+      k_fine_dirichlet(s->L, s->gf, s->gc, s->win, s->mat_in.T_bottom, s->Tn,
+                       s->Tpred, (double)j / st->m, s->fcur);
+      SpotSet sp = make_spots(s, st->n, j, j, 1.0);
+      k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, st->dt,
+                   &s->led->absorbed, s->partials);
+    }
+    batch_fine(
+        B, list,
+        [](StepState& st, Region& rg, double& tau, const double*& Told) {
+          rg = region_window(st.s);
+          tau = st.dt;
+          Told = st.s->fprev;
+        },
+        prof);
+    for (StepState* st : list) {
+      if (st->failed) continue;
+      tl_sim* s = st->s;
+      k_interface_accumulate(s->L, s->gf, s->win, s->fR, s->rho, j == 1 ? 1 : 0,
+                             -st->dt, &s->led->bottom, s->partials);
+      std::swap(s->fprev, s->fcur);
+      ++s->stats.micro_steps;
+    }
+  }
+  // 4. two-level correction at t_{n+1}
+  for (StepState* st : live(steps)) {
+    tl_sim* s = st->s;
+    SpotSet sp = make_spots(s, st->n, st->m, st->m, 1.0);
+    k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, st->dt, &s->led->absorbed,
+                 s->partials);
+    k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
+    k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
+    k_copy(s->L, s->ccur, s->Tpred, s->gc.npad);
+  }
+  for (;;) {
+    std::vector<StepState*> list;
+    for (StepState* st : live(steps))
+      if (!st->dn_done) list.push_back(st);
+    if (list.empty()) break;
+    for (StepState* st : list) {
+      tl_sim* s = st->s;
+      if (++st->it > s->opts.dn_max) {
+        fail_step(*st, "two-level iteration did not converge");
+        continue;
+      }
+      k_fine_dirichlet(s->L, s->gf, s->gc, s->win, s->mat_in.T_bottom, s->lam,
+                       nullptr, 0.0, s->fcur);
+    }
+    list.clear();
+    for (StepState* st : live(steps))
+      if (!st->dn_done) list.push_back(st);
+    batch_fine(
+        B, list,
+        [](StepState& st, Region& rg, double& tau, const double*& Told) {
+          rg = region_window(st.s);
+          tau = st.dt;
+          Told = st.s->fprev;
+        },
+        prof);
+    std::vector<StepState*> clist;
+    for (StepState* st : list) {
+      if (st->failed) continue;
+      tl_sim* s = st->s;
+      k_restrict(s->L, s->gf, s->gc, s->win, st->m > 1 ? s->rho : nullptr, s->fR,
+                 -1.0 / st->m, s->ext);
+      k_inject(s->L, s->gf, s->gc, s->win, s->fcur, s->ccur);
+      clist.push_back(st);
+    }
+    batch_solve<double>(
+        B, clist, false,
+        [](StepState& st) {
+          return make_job<double>(st.s, false, region_outside(st.s), st.Dt,
+                                  st.s->Tn, st.s->Fout, st.s->ext);
+        },
+        nullptr);
+    // interface residuals lambda' - lambda, read back for all at once
+    std::vector<StepState*> glist;
+    for (StepState* st : clist) {
+      if (st->failed) continue;
+      tl_sim* s = st->s;
+      const int ng = s->n_gamma;
+      k_gamma_gather(s->L, s->gidx, ng, s->ccur, s->lam, s->gbuf);
+      if (ng > 0)
+        hip_check(hipMemcpyAsync(s->h_gbuf, s->gbuf, 2 * sizeof(double) * ng,
+                                 hipMemcpyDeviceToHost, s->stream),
+                  "hipMemcpyAsync(interface)");
+      glist.push_back(st);
+    }
+    for (StepState* st : glist)
+      hip_check(hipStreamSynchronize(st->s->stream), "hipStreamSynchronize");
+    for (StepState* st : glist) {
+      tl_sim* s = st->s;
+      const int ng = s->n_gamma;
+      st->lt_v.resize(ng);
+      st->lam_v.resize(ng);
+      double diff = 0.0;
+      for (int q = 0; q < ng; ++q) {
+        st->lt_v[q] = s->h_gbuf[2 * q];
+        st->lam_v[q] = s->h_gbuf[2 * q + 1];
+        diff = std::max(diff, std::fabs(st->lt_v[q] - st->lam_v[q]));
+      }
+      if (!std::isfinite(diff)) {
+        fail_step(*st, "non-finite interface update");
+        continue;
+      }
+      if (diff <= s->opts.dn_tol) {
+        st->dn_done = true;
+        continue;
+      }
+      st->iqn.update(st->lam_v, st->lt_v, s->theta0, s->opts.dn_theta > 0.0,
+                     st->next);
+      for (int q = 0; q < ng; ++q) s->h_gbuf[q] = st->next[q];
+      hip_check(hipMemcpyAsync(s->gbuf, s->h_gbuf, sizeof(double) * ng,
+                               hipMemcpyHostToDevice, s->stream),
+                "hipMemcpyAsync(interface)");
+      k_gamma_scatter(s->L, s->gidx, ng, s->gbuf, s->lam);
+    }
+  }
+  // 5. ledger and commit of the new state
+  for (StepState* st : live(steps)) {
+    tl_sim* s = st->s;
+    const Launch L = s->L;
+    s->stats.dn_iters += st->it;
+    ++s->stats.micro_steps;
+    // bottom heat flow of the last fine step and of the coarse outside solve
+    k_interface_accumulate(L, s->gf, s->win, s->fR, nullptr, 0, -st->dt,
+                           &s->led->bottom, s->partials);
+    k_bottom_sum(L, s->gc, s->cR, -st->Dt, &s->led->bottom, s->partials);
+    std::swap(s->Tn, s->ccur);
+    std::swap(s->fstate, s->fcur);
+    energy_now(s, &s->led->stored);
+    s->stats.fine_dof_steps += fine_free_nodes(s->gf, s->win) * st->m;
+  }
+}
+
+// After a successful macro step: read the device ledger, count the step.
+void commit_step(tl_sim* s) {
+  read_ledger(s);
+  s->ledger.stored = s->h_led->stored;
+  s->ledger.absorbed = s->h_led->absorbed;
+  s->ledger.bottom = s->h_led->bottom;
+  s->ledger.remap = s->h_led->remap;
+  ++s->n_macro;
+  ++s->stats.macro_steps;
 }
 
 bool finite_all(std::initializer_list<double> v) {
@@ -693,6 +999,84 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
 }  // namespace
 
 // ===========================================================================
+// Internal interface for the serving loop
+// ===========================================================================
+namespace tl {
+
+struct BatchImpl {
+  BatchCtx ctx;
+};
+
+size_t batch_tables_bytes(int max_slots) {
+  return align_up(sizeof(SolveItem) * (size_t)max_slots) +
+         align_up(sizeof(LevelScalars) * (size_t)max_slots);
+}
+
+tl_status batch_tables_init(BatchTables* bt, void* dev_area, int max_slots,
+                            void* hip_stream) {
+  BatchImpl* b = new BatchImpl();
+  char* p = (char*)dev_area;
+  b->ctx.d_items = (SolveItem*)p;
+  b->ctx.d_sc = (LevelScalars*)(p + align_up(sizeof(SolveItem) * (size_t)max_slots));
+  b->ctx.cap = max_slots;
+  b->ctx.stream = (hipStream_t)hip_stream;
+  b->ctx.L.stream = hip_stream;
+  if (hipHostMalloc((void**)&b->ctx.h_items, sizeof(SolveItem) * max_slots,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->ctx.h_sc, sizeof(LevelScalars) * max_slots,
+                    hipHostMallocDefault) != hipSuccess) {
+    batch_tables_free(&(bt->impl = b, *bt));
+    return fail(TL_EDEVICE, "hipHostMalloc failed");
+  }
+  bt->impl = b;
+  return TL_OK;
+}
+
+void batch_tables_free(BatchTables* bt) {
+  BatchImpl* b = (BatchImpl*)bt->impl;
+  if (!b) return;
+  if (b->ctx.h_items) (void)hipHostFree(b->ctx.h_items);
+  if (b->ctx.h_sc) (void)hipHostFree(b->ctx.h_sc);
+  delete b;
+  bt->impl = nullptr;
+}
+
+tl_status step_many(const std::vector<tl_sim*>& sims, BatchTables* bt,
+                    std::vector<std::string>& errs) {
+  BatchImpl* b = (BatchImpl*)bt->impl;
+  errs.assign(sims.size(), std::string());
+  std::vector<StepState> steps(sims.size());
+  for (size_t q = 0; q < sims.size(); ++q) steps[q].s = sims[q];
+  try {
+    macro_step_batch(steps, b->ctx, nullptr);
+    for (size_t q = 0; q < sims.size(); ++q) {
+      if (steps[q].failed)
+        errs[q] = steps[q].err;
+      else
+        commit_step(sims[q]);
+    }
+  } catch (const NoConv& e) {
+    return fail(TL_ENOCONV, e.msg);
+  } catch (const DevErr& e) {
+    return fail(TL_EDEVICE, e.msg);
+  }
+  return TL_OK;
+}
+
+tl_status validate_request(const tl_mesh* mesh, const tl_material* material,
+                           const tl_scan_path* scan, const tl_options* opts) {
+  return validate(mesh, material, scan, opts);
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+size_t tl_sim_nodes(tl_sim* s, int level) {
+  return (size_t)(level == 0 ? s->gc.nreal : s->gf.nreal);
+}
+
+}  // namespace tl
+
+// ===========================================================================
 // C interface
 // ===========================================================================
 extern "C" {
@@ -740,12 +1124,25 @@ static tl_status init_state(tl_sim* s) {
   return TL_OK;
 }
 
+static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
+                            const tl_scan_path* scan, const tl_options* opts,
+                            void* dev_workspace, size_t ws_bytes,
+                            void* hip_stream, tl_sim** out);
+
 tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
                     const tl_scan_path* scan, const tl_options* opts,
                     void* dev_workspace, size_t ws_bytes, void* hip_stream,
                     tl_sim** out) {
   if (!out) return fail(TL_EINVAL, "out is null");
   *out = nullptr;
+  return create_sim(mesh, material, scan, opts, dev_workspace, ws_bytes,
+                    hip_stream, out);
+}
+
+static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
+                            const tl_scan_path* scan, const tl_options* opts,
+                            void* dev_workspace, size_t ws_bytes,
+                            void* hip_stream, tl_sim** out) {
   tl_status st = validate(mesh, material, scan, opts);
   if (st != TL_OK) return st;
   Layout lay = make_layout(*mesh, *opts);
@@ -813,7 +1210,10 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
   s->partials = (double*)(s->ws + lay.off_partials);
   s->gidx = (int*)(s->ws + lay.off_gidx);
   s->gbuf = (double*)(s->ws + lay.off_gbuf);
-  if (hipHostMalloc((void**)&s->h_sc, sizeof(LevelScalars), hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&s->h_sc, 2 * sizeof(LevelScalars), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&s->batch.h_items, 2 * sizeof(SolveItem),
+                    hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&s->h_led, sizeof(LedgerDev), hipHostMallocDefault) !=
           hipSuccess ||
@@ -822,7 +1222,14 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
     delete s;
     return fail(TL_EDEVICE, "hipHostMalloc failed");
   }
+  s->batch.d_items = (SolveItem*)(s->ws + lay.off_items);
+  s->batch.d_sc = s->sc_c;
+  s->batch.h_sc = s->h_sc;
+  s->batch.cap = 2;
+  s->batch.stream = s->stream;
+  s->batch.L = s->L;
   std::memset(&s->stats, 0, sizeof(s->stats));
+  s->prof.stats = &s->stats;
   s->stats.fine_nodes[0] = s->gf.nx;
   s->stats.fine_nodes[1] = s->gf.ny;
   s->stats.fine_nodes[2] = s->gf.nz;
@@ -867,16 +1274,13 @@ tl_status tl_step(tl_sim* s, int n_macro) {
     double* alt_saved = s->falt;
     const tl_stats stats_saved = s->stats;
     try {
-      macro_step(s);
-      read_ledger(s);
-      s->ledger.stored = s->h_led->stored;
-      s->ledger.absorbed = s->h_led->absorbed;
-      s->ledger.bottom = s->h_led->bottom;
-      s->ledger.remap = s->h_led->remap;
-      ++s->n_macro;
-      ++s->stats.macro_steps;
+      std::vector<StepState> steps(1);
+      steps[0].s = s;
+      macro_step_batch(steps, s->batch, &s->prof);
+      if (steps[0].failed) throw NoConv{steps[0].err};
+      commit_step(s);
     } catch (const NoConv& e) {
-      st = fail(TL_ENOCONV, "macro step " + std::to_string(s->n_macro) + ": " + e.msg);
+      st = fail(TL_ENOCONV, e.msg);
     } catch (const DevErr& e) {
       st = fail(TL_EDEVICE, e.msg);
     }
@@ -1031,12 +1435,12 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
 tl_status tl_set_profiling(tl_sim* s, int sample_every) {
   if (!s) return fail(TL_EINVAL, "null handle");
   if (sample_every < 0) return fail(TL_EINVAL, "sample_every must be >= 0");
-  if (sample_every > 0 && !s->prof_ev[0]) {
+  if (sample_every > 0 && !s->prof.ev[0]) {
     for (int q = 0; q < 2 * kProfPairs; ++q)
-      HIP_OK(hipEventCreate(&s->prof_ev[q]));
+      HIP_OK(hipEventCreate(&s->prof.ev[q]));
   }
-  s->prof_every = sample_every;
-  s->prof_count = 0;
+  s->prof.every = sample_every;
+  s->prof.count = 0;
   return TL_OK;
 }
 
@@ -1044,8 +1448,9 @@ void tl_destroy(tl_sim* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   else (void)hipDeviceSynchronize();
-  if (s->prof_ev[0])
-    for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(s->prof_ev[q]);
+  if (s->prof.ev[0])
+    for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(s->prof.ev[q]);
+  if (s->batch.h_items) (void)hipHostFree(s->batch.h_items);
   if (s->h_sc) (void)hipHostFree(s->h_sc);
   if (s->h_led) (void)hipHostFree(s->h_led);
   if (s->h_gbuf) (void)hipHostFree(s->h_gbuf);

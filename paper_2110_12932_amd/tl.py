@@ -69,6 +69,11 @@ class tl_stats(C.Structure):
                 ("fine_nodes", C.c_int * 3), ("coarse_nodes", C.c_int * 3)]
 
 
+class tl_request_info(C.Structure):
+    _fields_ = [("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("state", C.c_int), ("pad", C.c_int), ("macro_steps", C.c_int64)]
+
+
 class tl_grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double)]
@@ -78,6 +83,8 @@ class tl_grid(C.Structure):
 SYMBOLS = ["tl_workspace_bytes", "tl_create", "tl_step", "tl_get_temperature", "tl_get_ledger",
            "tl_get_stats", "tl_get_time", "tl_save", "tl_load", "tl_set_profiling", "tl_destroy",
            "tl_last_error",
+           "tl_server_overhead_bytes", "tl_server_create", "tl_server_submit",
+           "tl_server_tick", "tl_server_result", "tl_server_release", "tl_server_destroy",
            "tl_op_padded_size", "tl_op_pack", "tl_op_unpack", "tl_op_apply"]
 
 _lib = None
@@ -119,6 +126,25 @@ def load():
     lib.tl_destroy.argtypes = [vp]
     lib.tl_last_error.restype = C.c_char_p
     lib.tl_last_error.argtypes = []
+    lib.tl_server_overhead_bytes.restype = sz
+    lib.tl_server_overhead_bytes.argtypes = [C.c_int]
+    lib.tl_server_create.restype = C.c_int
+    lib.tl_server_create.argtypes = [vp, sz, sz, C.c_int, vp, C.POINTER(vp)]
+    lib.tl_server_submit.restype = C.c_int
+    lib.tl_server_submit.argtypes = [vp, C.POINTER(tl_mesh), C.POINTER(tl_material),
+                                     C.POINTER(tl_scan_path), C.POINTER(tl_options), C.c_int,
+                                     C.POINTER(C.c_uint64)]
+    lib.tl_server_tick.restype = C.c_int
+    lib.tl_server_tick.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int)]
+    lib.tl_server_result.restype = C.c_int
+    lib.tl_server_result.argtypes = [vp, C.c_uint64, C.c_int, C.POINTER(C.c_double), sz,
+                                     C.POINTER(C.c_int), C.POINTER(tl_stats),
+                                     C.POINTER(tl_ledger), C.POINTER(tl_request_info)]
+    lib.tl_server_release.restype = C.c_int
+    lib.tl_server_release.argtypes = [vp, C.c_uint64]
+    lib.tl_server_destroy.restype = None
+    lib.tl_server_destroy.argtypes = [vp]
     lib.tl_op_padded_size.restype = sz
     lib.tl_op_padded_size.argtypes = [C.POINTER(tl_grid)]
     for f in (lib.tl_op_pack, lib.tl_op_unpack):
@@ -308,6 +334,113 @@ class Sim:
     def close(self):
         if self.h:
             tl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving (tl.h, tl_server_*) ------------------------------------------------
+def tl_server_overhead_bytes(max_slots):
+    return int(load().tl_server_overhead_bytes(int(max_slots)))
+
+
+def tl_server_create(pool, hbm_budget, max_slots, stream=None):
+    """pool: a torch uint8 CUDA tensor holding the server's device memory."""
+    h = C.c_void_p()
+    _check(load().tl_server_create(C.c_void_p(pool.data_ptr()), pool.numel(), int(hbm_budget),
+                                   int(max_slots), C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+    return h
+
+
+def tl_server_submit(sv, mesh, material, scan, opts, n_macro):
+    rid = C.c_uint64()
+    sp = to_scan(scan)
+    _check(load().tl_server_submit(sv, C.byref(to_mesh(mesh)), C.byref(to_material(material)),
+                                   C.byref(sp), C.byref(to_options(opts)), int(n_macro),
+                                   C.byref(rid)))
+    return rid.value
+
+
+def tl_server_tick(sv):
+    a, q, f = C.c_int(), C.c_int(), C.c_int()
+    _check(load().tl_server_tick(sv, C.byref(a), C.byref(q), C.byref(f)))
+    return a.value, q.value, f.value
+
+
+def _info_dict(info):
+    return {n: getattr(info, n) for n, _ in tl_request_info._fields_ if n != "pad"}
+
+
+def tl_server_info(sv, rid):
+    """Timing/state record of a request (any state)."""
+    info = tl_request_info()
+    st = load().tl_server_result(sv, rid, 0, None, 0, None, None, None, C.byref(info))
+    if st not in (TL_OK, TL_EBUSY, TL_ENOCONV):
+        _check(st)
+    return _info_dict(info)
+
+
+def tl_server_result(sv, rid):
+    """(coarse T, fine T, stats, ledger, info) of a finished request."""
+    lib = load()
+    out = []
+    stats, led, info = tl_stats(), tl_ledger(), tl_request_info()
+    for level in (0, 1):
+        n = 1
+        _check(lib.tl_server_result(sv, rid, level, None, 0, None, C.byref(stats), C.byref(led),
+                                    C.byref(info)))
+        dims = stats.fine_nodes if level == 1 else stats.coarse_nodes
+        n = dims[0] * dims[1] * dims[2]
+        buf = np.empty(n, dtype=np.float64)
+        d = (C.c_int * 3)()
+        _check(lib.tl_server_result(sv, rid, level, buf.ctypes.data_as(C.POINTER(C.c_double)),
+                                    n, d, None, None, None))
+        out.append(buf.reshape(d[2], d[1], d[0]))
+    st = {n: (tuple(getattr(stats, n)) if n.endswith("_nodes") else getattr(stats, n))
+          for n, _ in tl_stats._fields_}
+    lg = {n: getattr(led, n) for n, _ in tl_ledger._fields_}
+    return out[0], out[1], st, lg, _info_dict(info)
+
+
+def tl_server_release(sv, rid):
+    _check(load().tl_server_release(sv, rid))
+
+
+def tl_server_destroy(sv):
+    if sv:
+        load().tl_server_destroy(sv)
+
+
+class Server:
+    """Serving loop on cuda:0 with a torch-allocated device pool."""
+
+    def __init__(self, pool_bytes, hbm_budget=None, max_slots=64, device="cuda", stream=None):
+        import torch
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
+        budget = int(pool_bytes) if hbm_budget is None else int(hbm_budget)
+        self.h = tl_server_create(self.pool, budget, max_slots, stream)
+
+    def submit(self, workload, n_macro=None):
+        return tl_server_submit(self.h, workload.mesh, workload.material, workload.scan,
+                                workload.options,
+                                workload.n_macro if n_macro is None else n_macro)
+
+    def tick(self):
+        return tl_server_tick(self.h)
+
+    def result(self, rid):
+        return tl_server_result(self.h, rid)
+
+    def info(self, rid):
+        return tl_server_info(self.h, rid)
+
+    def close(self):
+        if self.h:
+            tl_server_destroy(self.h)
             self.h = None
 
     def __del__(self):
