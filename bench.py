@@ -26,6 +26,7 @@ import json
 import os
 import sys
 import time
+from dataclasses import replace
 
 HBM_PEAK_GBS = 8000.0
 
@@ -36,7 +37,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=100, help="timed macro steps")
     ap.add_argument("--warmup", type=int, default=2, help="untimed macro steps (separate run)")
     ap.add_argument("--workload", default="config1", choices=["config1", "config0", "config2",
-                                                              "config4"])
+                                                              "config3", "config4"])
+    ap.add_argument("--requests", type=int, default=64, help="config3: requests in the stream")
+    ap.add_argument("--slots", type=int, default=64, help="config3: server slots")
+    ap.add_argument("--budget-mb", type=float, default=0.0,
+                    help="config3: HBM budget for active requests (0: room for every slot)")
+    ap.add_argument("--load", type=float, default=1.5,
+                    help="config3: arrival rate as a multiple of the measured batched capacity")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=8,
@@ -122,8 +129,112 @@ def k2_sweep(tl, W, torch):
     return out
 
 
+def serve_stream(tl, W, torch, reqs, slots, budget, arrivals=None, profile_every=0):
+    """Run a request stream through a server.  arrivals: seconds after the
+    start at which each request is submitted (None: all at once).  Returns
+    (wall seconds, per-request latencies, per-request stats, profile)."""
+    pool = sum(tl.tl_workspace_bytes(w.mesh, w.options) + 4096 for w in reqs)
+    pool += tl.tl_server_overhead_bytes(slots) + (1 << 20)
+    sv = tl.Server(pool, hbm_budget=budget if budget else pool, max_slots=slots)
+    if profile_every:
+        tl.tl_server_set_profiling(sv.h, profile_every)
+    arr = [0.0] * len(reqs) if arrivals is None else list(arrivals)
+    order = sorted(range(len(reqs)), key=lambda q: arr[q])
+    ids, done_t = {}, {}
+    nxt = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while len(done_t) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(order) and arr[order[nxt]] <= now:
+            q = order[nxt]
+            ids[sv.submit(reqs[q])] = q
+            nxt += 1
+        active, queued, finished = sv.tick()
+        if finished:
+            t = time.perf_counter() - t0
+            for rid, q in ids.items():
+                if q not in done_t and sv.info(rid)["state"] >= 2:
+                    done_t[q] = t
+        if active == 0 and queued == 0 and nxt < len(order):
+            time.sleep(max(0.0, arr[order[nxt]] - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    stats = []
+    for rid, q in ids.items():
+        _, _, st, _, info = sv.result(rid)
+        if info["state"] != 2:
+            raise RuntimeError(f"request {q} failed")
+        stats.append(st)
+    lat = [done_t[q] - arr[q] for q in range(len(reqs))]
+    prof = tl.tl_server_get_profile(sv.h) if profile_every else (0, 0.0)
+    sv.close()
+    return wall, lat, stats, prof
+
+
+def main_serving(args):
+    """config 3: a seeded stream of single-track requests through the
+    continuous-batching server.  A closed-loop run (all requests at t = 0)
+    measures the batched capacity; the stream then arrives as a Poisson
+    process at `--load` times that capacity, and throughput (fine
+    DOF-timesteps/s over the stream's wall time) and p50/p99 latency come
+    from that run."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2110_12932_amd import tl
+    tl.load()
+    stream = W.config3_requests(args.requests, seed=0, mean_interarrival=1.0)
+    reqs = [w for _, w in stream]
+    unit_gaps = np.diff([0.0] + [a for a, _ in stream])   # Exp(1) draws, in order
+    budget = int(args.budget_mb * 2 ** 20) if args.budget_mb else 0
+    # warm-up: two short requests
+    serve_stream(tl, W, torch, [replace(reqs[0], n_macro=2), replace(reqs[1], n_macro=2)],
+                 2, 0)
+    wall_c, _, _, _ = serve_stream(tl, W, torch, reqs, args.slots, budget)
+    capacity = len(reqs) / wall_c                      # requests per second
+    mean_gap = 1.0 / (args.load * capacity)
+    arrivals = np.cumsum(unit_gaps * mean_gap)
+    wall, lat, stats, prof = serve_stream(tl, W, torch, reqs, args.slots, budget,
+                                          arrivals, args.profile_every)
+    dof = sum(st["fine_dof_steps"] for st in stats)
+    fine_bytes = sum(st["fine_op_bytes"] for st in stats)
+    roofline = None
+    if prof[0] > 0:
+        # fused CG iteration: 13 arrays of FP32 per fine node and iteration
+        fine_iters = sum(st["fine_op_applies"] for st in stats)
+        launches_work = prof[0] * max(1, args.profile_every)
+        achieved = fine_bytes / (prof[1] * 1e-3 * max(1, args.profile_every)) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "cg_iter_batched_kernel<float> (all requests of a tick)",
+                    "avg_launch_us": prof[1] * 1e3 / prof[0],
+                    "bytes_per_launch": fine_bytes / max(1.0, launches_work),
+                    "launches_timed": prof[0], "fine_cg_item_iterations": fine_iters}
+    lat = np.array(lat)
+    out = {
+        "metric": "fine DOF-timesteps/s", "value": dof / wall, "unit": "fine DOF-timesteps/s",
+        "n_gpus": 1, "steps": int(sum(st["macro_steps"] for st in stats)), "warmup": 1,
+        "ms_per_step": wall * 1e3 / max(1, int(sum(st["macro_steps"] for st in stats))),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "config3", "requests": len(reqs), "slots": args.slots,
+                   "hbm_budget_bytes": budget or "unbounded",
+                   "fine_nodes_per_request": list(stats[0]["fine_nodes"]),
+                   "arrivals": f"Poisson, {args.load}x the closed-loop capacity "
+                               f"({capacity:.2f} req/s), mean gap {mean_gap * 1e3:.1f} ms"},
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "closed_loop": {"wall_s": wall_c, "fine_dof_steps_per_s": dof / wall_c},
+        "roofline": roofline,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "config3" and args.gpus == 1:
+        main_serving(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

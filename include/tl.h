@@ -244,6 +244,12 @@ tl_status tl_server_result(tl_server* sv, uint64_t id, int level,
                            tl_stats* st, tl_ledger* led,
                            tl_request_info* info);
 
+/* Time every sample_every-th launch of the batched fine CG kernel with HIP
+ * events attached to the dispatch (0: off); tl_server_get_profile returns
+ * the number of timed launches that did work and their summed duration. */
+tl_status tl_server_set_profiling(tl_server* sv, int sample_every);
+tl_status tl_server_get_profile(tl_server* sv, int64_t* launches, double* ms);
+
 /* Drop the host-side results of a finished request. */
 tl_status tl_server_release(tl_server* sv, uint64_t id);
 

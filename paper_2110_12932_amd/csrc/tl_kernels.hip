@@ -124,6 +124,17 @@ __device__ inline double enthalpy_slope(double T, const MatDev& m) {
   return m.rho * (heatcap_of(T, m) + m.latent * 0.5 * m.S * (1.0 - th * th));
 }
 
+// Trial temperature of one node for the Newton step `step` (= alpha dx):
+// T - step, except that a step crossing the centre T_m of the melting
+// sigmoid lands on T_m.  Plain Newton on the enthalpy form cycles across the
+// sharp latent-heat peak of H' (the tangent on one side overshoots to the
+// other); from T_m the next step no longer crosses.  The converged solution
+// R(T) = 0 is unchanged.
+__device__ inline double trial_T(double T, double step, const MatDev& m) {
+  const double t1 = T - step;
+  return ((T - m.Tm) * (t1 - m.Tm) < 0.0) ? m.Tm : t1;
+}
+
 // ---------------------------------------------------------------------------
 // region rules (which elements are active, which nodes are Dirichlet)
 // ---------------------------------------------------------------------------
@@ -439,15 +450,18 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
     const int n = pidx(g, i, j, k);
     double T27[27];
     gather27(g, T, n, T27);
+    const double Tc0 = T27[13];
     if (dx != nullptr) {
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-          for (int dxx = -1; dxx <= 1; ++dxx)
-            T27[N27(dxx, dy, dz)] -=
-                alpha * (double)dx[n + dxx + dy * g.px + dz * g.pxy];
+          for (int dxx = -1; dxx <= 1; ++dxx) {
+            const double t0 = T27[N27(dxx, dy, dz)];
+            T27[N27(dxx, dy, dz)] = trial_T(
+                t0, alpha * (double)dx[n + dxx + dy * g.px + dz * g.pxy], m);
+          }
     }
     double k8[8];
     double nact = 0.0;
@@ -493,7 +507,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
     r[n] = rn;
     if (!dir) {
       acc[0] += Rn * Rn;
-      if (dx != nullptr) acc[1] = fmax(acc[1], fabs(alpha * (double)dx[n]));
+      acc[1] = fmax(acc[1], fabs(Tn - Tc0));
       acc[2] += (double)(rn * zn);
     }
   }

@@ -1005,6 +1005,8 @@ namespace tl {
 
 struct BatchImpl {
   BatchCtx ctx;
+  Profiler prof;
+  tl_stats pstats{};  // only the timing and op-byte fields are used
 };
 
 size_t batch_tables_bytes(int max_slots) {
@@ -1015,6 +1017,7 @@ size_t batch_tables_bytes(int max_slots) {
 tl_status batch_tables_init(BatchTables* bt, void* dev_area, int max_slots,
                             void* hip_stream) {
   BatchImpl* b = new BatchImpl();
+  b->prof.stats = &b->pstats;
   char* p = (char*)dev_area;
   b->ctx.d_items = (SolveItem*)p;
   b->ctx.d_sc = (LevelScalars*)(p + align_up(sizeof(SolveItem) * (size_t)max_slots));
@@ -1037,6 +1040,8 @@ void batch_tables_free(BatchTables* bt) {
   if (!b) return;
   if (b->ctx.h_items) (void)hipHostFree(b->ctx.h_items);
   if (b->ctx.h_sc) (void)hipHostFree(b->ctx.h_sc);
+  if (b->prof.ev[0])
+    for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(b->prof.ev[q]);
   delete b;
   bt->impl = nullptr;
 }
@@ -1048,7 +1053,7 @@ tl_status step_many(const std::vector<tl_sim*>& sims, BatchTables* bt,
   std::vector<StepState> steps(sims.size());
   for (size_t q = 0; q < sims.size(); ++q) steps[q].s = sims[q];
   try {
-    macro_step_batch(steps, b->ctx, nullptr);
+    macro_step_batch(steps, b->ctx, b->prof.every > 0 ? &b->prof : nullptr);
     for (size_t q = 0; q < sims.size(); ++q) {
       if (steps[q].failed)
         errs[q] = steps[q].err;
@@ -1066,6 +1071,26 @@ tl_status step_many(const std::vector<tl_sim*>& sims, BatchTables* bt,
 tl_status validate_request(const tl_mesh* mesh, const tl_material* material,
                            const tl_scan_path* scan, const tl_options* opts) {
   return validate(mesh, material, scan, opts);
+}
+
+tl_status batch_set_profiling(BatchTables* bt, int sample_every) {
+  BatchImpl* b = (BatchImpl*)bt->impl;
+  if (sample_every < 0) return fail(TL_EINVAL, "sample_every must be >= 0");
+  if (sample_every > 0 && !b->prof.ev[0]) {
+    for (int q = 0; q < 2 * kProfPairs; ++q)
+      HIP_OK(hipEventCreate(&b->prof.ev[q]));
+  }
+  b->prof.every = sample_every;
+  b->prof.count = 0;
+  return TL_OK;
+}
+
+void batch_get_profile(BatchTables* bt, int64_t* launches, double* ms,
+                       double* bytes) {
+  BatchImpl* b = (BatchImpl*)bt->impl;
+  if (launches) *launches = b->pstats.fine_op_timed;
+  if (ms) *ms = b->pstats.fine_op_timed_ms;
+  if (bytes) *bytes = b->pstats.fine_op_bytes;
 }
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }

@@ -27,6 +27,11 @@ void batch_tables_free(BatchTables* bt);
 tl_status step_many(const std::vector<tl_sim*>& sims, BatchTables* bt,
                     std::vector<std::string>& errs);
 
+// Sampled event timing of the batched fine CG kernel of a server.
+tl_status batch_set_profiling(BatchTables* bt, int sample_every);
+void batch_get_profile(BatchTables* bt, int64_t* launches, double* ms,
+                       double* bytes);
+
 tl_status validate_request(const tl_mesh* mesh, const tl_material* material,
                            const tl_scan_path* scan, const tl_options* opts);
 void set_last_error(const std::string& msg);

@@ -333,6 +333,17 @@ tl_status tl_server_release(tl_server* sv, uint64_t id) {
   return TL_OK;
 }
 
+tl_status tl_server_set_profiling(tl_server* sv, int sample_every) {
+  if (!sv) return sfail(TL_EINVAL, "null server");
+  return batch_set_profiling(&sv->tables, sample_every);
+}
+
+tl_status tl_server_get_profile(tl_server* sv, int64_t* launches, double* ms) {
+  if (!sv) return sfail(TL_EINVAL, "null server");
+  batch_get_profile(&sv->tables, launches, ms, nullptr);
+  return TL_OK;
+}
+
 void tl_server_destroy(tl_server* sv) {
   if (!sv) return;
   (void)hipStreamSynchronize(sv->stream);

@@ -85,6 +85,7 @@ SYMBOLS = ["tl_workspace_bytes", "tl_create", "tl_step", "tl_get_temperature", "
            "tl_last_error",
            "tl_server_overhead_bytes", "tl_server_create", "tl_server_submit",
            "tl_server_tick", "tl_server_result", "tl_server_release", "tl_server_destroy",
+           "tl_server_set_profiling", "tl_server_get_profile",
            "tl_op_padded_size", "tl_op_pack", "tl_op_unpack", "tl_op_apply"]
 
 _lib = None
@@ -143,6 +144,10 @@ def load():
                                      C.POINTER(tl_ledger), C.POINTER(tl_request_info)]
     lib.tl_server_release.restype = C.c_int
     lib.tl_server_release.argtypes = [vp, C.c_uint64]
+    lib.tl_server_set_profiling.restype = C.c_int
+    lib.tl_server_set_profiling.argtypes = [vp, C.c_int]
+    lib.tl_server_get_profile.restype = C.c_int
+    lib.tl_server_get_profile.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     lib.tl_server_destroy.restype = None
     lib.tl_server_destroy.argtypes = [vp]
     lib.tl_op_padded_size.restype = sz
@@ -408,6 +413,17 @@ def tl_server_result(sv, rid):
 
 def tl_server_release(sv, rid):
     _check(load().tl_server_release(sv, rid))
+
+
+def tl_server_set_profiling(sv, sample_every):
+    _check(load().tl_server_set_profiling(sv, int(sample_every)))
+
+
+def tl_server_get_profile(sv):
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(load().tl_server_get_profile(sv, C.byref(n), C.byref(ms)))
+    return n.value, ms.value
 
 
 def tl_server_destroy(sv):

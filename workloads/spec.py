@@ -87,7 +87,7 @@ class Options:
     cg_rtol: float = 1e-3
     dn_tol: float = 1e-8
     dn_theta: float = 0.0
-    newton_max: int = 30
+    newton_max: int = 60
     cg_max: int = 500
     dn_max: int = 60
 
