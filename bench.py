@@ -65,7 +65,7 @@ def measured_traffic(path, workload, elem):
     changed since the counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    kname = "cg_iter_tiled_kernel<%s>" % ("double" if elem == 8 else "float")
+    kname = "cg_iter_batched_kernel<%s>" % ("double" if elem == 8 else "float")
     if path is None:
         path = os.path.join(root, "profiles", f"cg_iter_{workload}_traffic.json")
     if not os.path.exists(path):
@@ -284,7 +284,7 @@ def main():
         traffic = measured_traffic(args.traffic, wl.name, elem)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": "cg_iter_tiled_kernel<%s>" % ("double" if elem == 8 else "float"),
+                    "kernel": "cg_iter_batched_kernel<%s>" % ("double" if elem == 8 else "float"),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                     "launches_timed": st["fine_op_timed"]}
     out = {

@@ -660,10 +660,18 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   const R* __restrict__ d = (const R*)it.d;
   const R* __restrict__ kap = (const R*)it.kap;
   const R* __restrict__ dinv = (const R*)it.dinv;
-  // 1. halo loads of the first tile, issued before the reduction so that
-  // both latencies overlap
-  R hr[HPT], hw[HPT], hs[HPT], hd[HPT];
-  auto load_halo = [&](const Tile& t) {
+  // Every global input of a tile is loaded into registers in one batch:
+  // the halo of r, w, s_{k-1}, Dinv (for u_{k+1}), the element
+  // conductivities, and the node's own d, p, x, s_{k-1}.  The first tile's
+  // batch is issued before the scalar reduction, each later tile's while the
+  // previous tile's stencil is computed, so a workgroup waits on memory
+  // about once per tile.
+  R hr[HPT], hw[HPT], hs[HPT], hd[HPT], kr[EPT];
+  R o_r = (R)0, o_w = (R)0, o_di = (R)0, o_d = (R)0, o_s = (R)0, o_p = (R)0,
+    o_x = (R)0;
+  int o_n = 0;
+  bool o_act = false;
+  auto load_tile = [&](const Tile& t) {
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
@@ -673,10 +681,30 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
       hs[q] = (n >= 0 && kit > 0) ? s_old[n] : (R)0;
       hd[q] = n >= 0 ? dinv[n] : (R)0;
     }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      const int n = e < EN ? elem_index(g, t, e) : -1;
+      kr[q] = n >= 0 ? kap[n] : (R)0;
+    }
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    o_act = i < g.nx && j < g.ny && k < g.nz;
+    o_n = o_act ? pidx(g, i, j, k) : 0;
+    if (o_act) {
+      o_r = r_in[o_n];
+      o_w = w_in[o_n];
+      o_di = dinv[o_n];
+      o_d = d[o_n];
+      if (kit > 0) {
+        o_s = s_old[o_n];
+        o_p = p[o_n];
+        o_x = x[o_n];
+      }
+    }
   };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
-  if (tr.first < tr.last) load_halo(tile_of(tr.first, it.ntx, it.nty));
-  // 2. gamma_k, delta_k from the previous kernel's partials (CG start or
+  if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
+  // gamma_k, delta_k from the previous kernel's partials (CG start or
   // iteration k-1), held in the region pair this kernel does not write
   const int rd = (kit & 1) ? kPartCG2 : kPartCG;
   const int wr = (kit & 1) ? kPartCG : kPartCG2;
@@ -733,32 +761,25 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   R acc[2] = {(R)0, (R)0};
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
     const Tile t = tile_of(tile, it.ntx, it.nty);
-    if (tile != tr.first) load_halo(t);
-    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
-    const bool active = i < g.nx && j < g.ny && k < g.nz;
-    const int n = active ? pidx(g, i, j, k) : 0;
-    R r_own = (R)0, w_own = (R)0, s_prev = (R)0, di_own = (R)0,
-      p_own = (R)0, x_own = (R)0, d_own = (R)0;
-    if (active) {
-      r_own = r_in[n];
-      w_own = w_in[n];
-      di_own = dinv[n];
-      d_own = d[n];
-      if (kit > 0) {
-        s_prev = s_old[n];
-        p_own = p[n];
-        x_own = x[n];
-      }
-    }
-    load_kappa_tile(g, t, kap, k_s);
-    // 3. u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
+    // u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
       if (h < HN) u_s[h] = hd[q] * (hr[q] - alpha * (hw[q] + beta * hs[q]));
     }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      if (e < EN) k_s[e] = kr[q];
+    }
     __syncthreads();
-    // 4. the node's own recurrences and w_{k+1} = J u_{k+1}
+    const bool active = o_act;
+    const int n = o_n;
+    const R r_own = o_r, w_own = o_w, di_own = o_di, d_own = o_d,
+            s_prev = o_s, p_own = o_p, x_own = o_x;
+    if (tile + tr.step < tr.last)
+      load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
+    // the node's own recurrences and w_{k+1} = J u_{k+1}
     if (active) {
       const R s_k = w_own + beta * s_prev;
       const R u_k = di_own * r_own;
