@@ -58,20 +58,53 @@ struct SpotSet {
   Spot s[kMaxSpots];
 };
 
-// Device-resident scalars of one level.  Written only by single-workgroup
-// finalize kernels or by workgroup 0 of a CG kernel into a slot no other
-// workgroup of that kernel reads, so no grid-wide synchronisation is needed.
-struct LevelScalars {
-  double rnorm2;     // |R_free|^2 at the last evaluated temperature
-  double dmax;       // max |alpha delta| over free nodes of the last trial
-  double rz0;        // r.z at the start of the current CG solve
-  double gbuf[2];    // CG: gamma_k = r_k.u_k in gbuf[k & 1]
-  double abuf[2];    // CG: alpha_k in abuf[k & 1]
-  double sum0, sum1, sum2;   // generic reduction results
-  int iters, done, breakdown;
-  int accepted;      // line-search outcome of the last trial
-  int converged;     // Newton converged at the last trial
+// Newton state of one implicit solve, kept on the device so that the host
+// can queue several Newton rounds between synchronisations.  Round r reads
+// ns[r & 1]; only workgroup 0 of round r's CG-start kernel writes, into
+// ns[(r + 1) & 1], which no kernel of round r reads before that.
+constexpr int kLineSearchMax = 12;  // halvings tried before a step is taken anyway
+enum NewtonStatus {
+  kRunning = 0,
+  kConverged = 1,
+  kFailNonFinite = 2,   // non-finite residual or update
+  kFailBreakdown = 3,   // CG broke down before its first iteration
+  kFailNewtonMax = 4    // no convergence within newton_max directions
+};
+struct NewtonState {
+  double alpha;       // step of the trial evaluated in this round
+  double rn0;         // |R_free| at the accepted temperature
+  double dmax_last;   // max |alpha dx| of the last accepted step
+  double dmax_prev;   // the same for the accepted step before it
+  int cur;            // Tb[cur] holds the accepted temperature
+  int xi;             // xb[xi] holds the direction being line-searched
+  int h;              // halvings of the current direction
+  int first;          // no accepted evaluation yet (trial = T, no direction)
+  int pending;        // the direction was produced by the previous round's CG
+  int status;         // NewtonStatus
+  int budget;         // CG iterations a round may run (fixed per solve, so
+                      // that a solve does not depend on the others of its
+                      // batch)
+  int cg_need;        // most CG iterations a direction took (+2 if cut)
+  int n_newton;       // directions taken
+  int n_cg;           // CG iterations summed over the solve
+  int n_halvings;     // line-search halvings summed over the solve
   int pad;
+};
+// CG scalars of one round, double-buffered by round parity: round r's CG
+// kernels use cg[r & 1] and the next round's CG-start reads its outcome.
+struct CGScalars {
+  double rz0;        // r.z at the start of the CG solve
+  double gbuf[2];    // gamma_k = r_k.u_k in gbuf[k & 1]
+  double abuf[2];    // alpha_k in abuf[k & 1]
+  int iters, done, breakdown, pad;
+};
+constexpr int kRoundLog = 32;   // rounds whose CG iteration counts are kept
+struct LevelScalars {
+  NewtonState ns[2];
+  CGScalars cg[2];
+  double rnorm2;     // |R_free|^2 at the last evaluated trial
+  double dmax;       // max |alpha dx| of the last evaluated trial
+  int cg_log[kRoundLog];   // CG iterations of round r at [r % kRoundLog]
 };
 
 // Per-workgroup partial sums: regions of kMaxBlocks doubles.  A kernel never
@@ -120,23 +153,19 @@ struct SolveItem {
   Region rg;
   MatDev m;
   double tau;
-  double alpha;      // line-search step of this round's trial
-  double rn0;        // |R_free| at the last accepted temperature
   double tol;        // Newton tolerance on max |alpha dx| [K]
   double rtol2;      // CG: stop when r.u <= rtol2 * r0.u0
-  int first;         // first evaluation of this solve (alpha = 0, dx null)
-  int last_try;      // last allowed halving: accept regardless
-  int res_begin, res_nb;    // workgroups of the residual / CG-start kernels
-  int tile_begin, tile_nb;  // workgroups of the CG iteration kernel
-  int ntx, nty, ntiles;     // CG tiles of this item
-  int max_kit;              // CG iterations this item may run in the round
-  const double* T;     // temperature at the last accepted point
+  int newton_max;    // Newton directions allowed
+  int cg_max;        // CG iterations allowed per direction
+  int tile_begin, tile_nb;  // workgroups of the item in every batched kernel
+  int ntx, nty, ntiles;     // tiles of this item
+  double* Tb[2];       // the accepted and the trial temperature (see ns.cur)
   const double* Told;  // temperature at the previous time level
   const double* F;     // surface load at the new time level
   const double* Fext;  // interface load (null if none)
-  double* Tt;          // trial temperature written by the residual kernel
   double* R;           // residual at the trial
-  const void* dx;      // Newton direction being line-searched (null first)
+  void* xb[2];         // CG solutions: the direction being line-searched
+                       // and the next one (see ns.xi)
   void* kap;           // element conductivity
   void* d;             // m H'(T) / tau
   void* dinv;          // Jacobi preconditioner, 0 on Dirichlet rows
@@ -144,28 +173,27 @@ struct SolveItem {
   void* w[2];          // J u (double-buffered)
   void* s[2];          // J p (double-buffered)
   void* p;             // search direction
-  void* x;             // CG solution: the next Newton direction
   LevelScalars* sc;    // per-item scalars
   double* partials;    // per-item partial sums, kPartRegions * kMaxBlocks
 };
 
-// Workgroups an item needs in the residual/CG-start kernels and in the CG
-// iteration kernel (both multiples of 8); the latter also returns the tiles.
-int item_residual_blocks(const Geo& g);
+// Workgroups an item needs in the batched kernels (a multiple of 8) and its
+// tiles.
 int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles);
 
-// Batched launches over a device table of n_items items; total_blocks is the
-// sum of the items' workgroup counts for that kernel.  ev_start/ev_stop
-// (hipEvent_t, may be null) are recorded with the CG dispatch itself.
+// Batched launches of Newton round `round` over a device table of n_items
+// items; total_blocks is the sum of the items' workgroup counts for that
+// kernel.  ev_start/ev_stop (hipEvent_t, may be null) are recorded with the
+// CG dispatch itself.
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks);
+                        int total_blocks, int round);
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks);
+                        int total_blocks, int round);
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int total_blocks, int kit, void* ev_start,
+                       int total_blocks, int round, int kit, void* ev_start,
                        void* ev_stop);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,

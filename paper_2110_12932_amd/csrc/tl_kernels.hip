@@ -413,103 +413,148 @@ static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
 // item; every item has its own scalars and partial-sum regions.
 // ---------------------------------------------------------------------------
 __device__ inline int item_of_block(const SolveItem* __restrict__ items,
-                                    int n, bool tiled) {
+                                    int n) {
   const int b = blockIdx.x;
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int begin = tiled ? items[mid].tile_begin : items[mid].res_begin;
-    if (begin <= b) lo = mid; else hi = mid - 1;
+    if (items[mid].tile_begin <= b) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
 // K4 + K1: nonlinear residual at the trial T - alpha dx, Jacobian
 // coefficients, CG initial residual; partials of |R_free|^2, max|alpha dx|,
-// r.(Dinv r).
+// r.(Dinv r).  LDS-tiled like the CG kernels: the trial temperature is
+// formed once per halo node and each element's conductivity once per tile.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-residual_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
+residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
+                        int round) {
+  __shared__ double t_s[HN];
+  __shared__ double k_s[EN];
   __shared__ double lds[6 * kBlock / 64];
-  const SolveItem& it = items[item_of_block(items, n_items, false)];
-  const int blk = blockIdx.x - it.res_begin, nblk = it.res_nb;
+  const SolveItem& it = items[item_of_block(items, n_items)];
+  const NewtonState& st = it.sc->ns[round & 1];
+  if (st.status != kRunning) return;
+  if (st.pending) {
+    // the CG that should have produced the direction broke down at once:
+    // the CG-start kernel of this round records the failure
+    const CGScalars& cgp = it.sc->cg[(round + 1) & 1];
+    if (cgp.breakdown && cgp.iters == 0) return;
+  }
+  const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
   const Geo& g = it.g;
   const MatDev& m = it.m;
-  const double* __restrict__ T = it.T;
-  const R* __restrict__ dx = (const R*)it.dx;
-  const double alpha = it.alpha;
+  const double* __restrict__ T = it.Tb[st.cur];
+  double* __restrict__ Tt = it.Tb[1 - st.cur];
+  const R* __restrict__ dx = st.first ? nullptr : (const R*)it.xb[st.xi];
+  const double alpha = st.alpha;
   R* __restrict__ kap = (R*)it.kap;
   R* __restrict__ d = (R*)it.d;
   R* __restrict__ dinv = (R*)it.dinv;
   R* __restrict__ r = (R*)it.r[0];
+  double w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) w[q] = g.w[q];
   double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
-  for (int t = blk * blockDim.x + threadIdx.x; t < g.nreal;
-       t += nblk * blockDim.x) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    const int n = pidx(g, i, j, k);
-    double T27[27];
-    gather27(g, T, n, T27);
-    const double Tc0 = T27[13];
-    if (dx != nullptr) {
+  const TileRange tr = tile_range(blk, nblk, it.ntiles);
+  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    const Tile t = tile_of(tile, it.ntx, it.nty);
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    const bool active = i < g.nx && j < g.ny && k < g.nz;
+    const int n = active ? pidx(g, i, j, k) : 0;
+    double Tc0 = 0.0, Told_n = 0.0, F_n = 0.0, Fx_n = 0.0;
+    if (active) {
+      Tc0 = T[n];
+      Told_n = it.Told[n];
+      F_n = it.F[n];
+      if (it.Fext != nullptr) Fx_n = it.Fext[n];
+    }
+    // trial temperature on the halo tile
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      if (h < HN) {
+        const int hn = halo_index(g, t, h);
+        double v = 0.0;
+        if (hn >= 0) {
+          v = T[hn];
+          if (dx != nullptr) v = trial_T(v, alpha * (double)dx[hn], m);
+        }
+        t_s[h] = v;
+      }
+    }
+    __syncthreads();
+    // conductivity of each element of the tile at its mean trial temperature
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      if (e < EN) {
+        const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
+        double ke = 0.0;
+        if (elem_active(g, it.rg, t.ox + ex - 1, t.oy + ey - 1, t.oz + ez - 1)) {
+          double sm = 0.0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+            sm += t_s[(ez + cz) * (HX * HY) + (ey + cy) * HX + (ex + cx)];
+          }
+          ke = kappa_of(0.125 * sm, m);
+        }
+        k_s[e] = ke;
+      }
+    }
+    __syncthreads();
+    if (active) {
+      double T27[27];
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-          for (int dxx = -1; dxx <= 1; ++dxx) {
-            const double t0 = T27[N27(dxx, dy, dz)];
-            T27[N27(dxx, dy, dz)] = trial_T(
-                t0, alpha * (double)dx[n + dxx + dy * g.px + dz * g.pxy], m);
-          }
-    }
-    double k8[8];
-    double nact = 0.0;
-    double diagK = 0.0;
+          for (int dxx = -1; dxx <= 1; ++dxx)
+            T27[N27(dxx, dy, dz)] =
+                t_s[(t.tz + 1 + dz) * (HX * HY) + (t.ty + 1 + dy) * HX +
+                    (t.tx + 1 + dxx)];
+      double k8[8];
+      double nact = 0.0;
+      double diagK = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-      double ke = 0.0;
-      if (elem_active(g, it.rg, i - ex, j - ey, k - ez)) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-          s += T27[N27(cx - ex, cy - ey, cz - ez)];
-        }
-        ke = kappa_of(0.125 * s, m);
-        nact += 1.0;
+      for (int e = 0; e < 8; ++e) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+        const double ke = k_s[(t.tz + 1 - ez) * (EX * EY) +
+                              (t.ty + 1 - ey) * EX + (t.tx + 1 - ex)];
+        if (elem_active(g, it.rg, i - ex, j - ey, k - ez)) nact += 1.0;
+        k8[e] = ke;
+        diagK += ke;
       }
-      k8[e] = ke;
-      diagK += ke;
+      const double Tn = T27[13];
+      const double mass = g.vol8 * nact;
+      double Rn = mass * (enthalpy(Tn, m) - enthalpy(Told_n, m)) / it.tau +
+                  stencil_apply(T27, k8, w) - F_n;
+      if (it.Fext != nullptr) Rn -= Fx_n;
+      Tt[n] = Tn;
+      it.R[n] = Rn;
+      // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
+      const bool dir = node_dirichlet(g, it.rg, i, j, k);
+      const double dn = mass * enthalpy_slope(Tn, m) / it.tau;
+      const double diag = dn + diagK * g.w[0];
+      // this node owns the element whose lowest corner it is (k8[0])
+      kap[n] = (R)k8[0];
+      d[n] = (R)dn;
+      const R di = dir ? (R)0 : (R)(1.0 / diag);
+      dinv[n] = di;
+      const R rn = dir ? (R)0 : (R)Rn;
+      const R zn = di * rn;
+      r[n] = rn;
+      if (!dir) {
+        acc[0] += Rn * Rn;
+        acc[1] = fmax(acc[1], fabs(Tn - Tc0));
+        acc[2] += (double)(rn * zn);
+      }
     }
-    double w[8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) w[p] = g.w[p];
-    const double Tn = T27[13];
-    const double mass = g.vol8 * nact;
-    double Rn = mass * (enthalpy(Tn, m) - enthalpy(it.Told[n], m)) / it.tau +
-                stencil_apply(T27, k8, w) - it.F[n];
-    if (it.Fext != nullptr) Rn -= it.Fext[n];
-    it.Tt[n] = Tn;
-    it.R[n] = Rn;
-    // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
-    const bool dir = node_dirichlet(g, it.rg, i, j, k);
-    const double dn = mass * enthalpy_slope(Tn, m) / it.tau;
-    const double diag = dn + diagK * g.w[0];
-    // this node owns the element whose lowest corner it is (k8[0])
-    kap[n] = (R)k8[0];
-    d[n] = (R)dn;
-    const R di = dir ? (R)0 : (R)(1.0 / diag);
-    dinv[n] = di;
-    const R rn = dir ? (R)0 : (R)Rn;
-    const R zn = di * rn;
-    r[n] = rn;
-    if (!dir) {
-      acc[0] += Rn * Rn;
-      acc[1] = fmax(acc[1], fabs(Tn - Tc0));
-      acc[2] += (double)(rn * zn);
-    }
+    __syncthreads();  // LDS is reused by the next tile
   }
   // max is taken separately from the two sums
   double mx = wave_max(acc[1]);
@@ -528,26 +573,87 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
   }
 }
 
-// Line-search decision and CG start (see the CG recurrences below).  From
-// the residual partials every workgroup of an item decides, identically,
-// whether its trial is accepted (first evaluation, sufficient decrease
-// (1 - 1e-4 alpha) rn0, step <= tol, or the last halving) and whether Newton
-// has converged (accepted and step <= tol); workgroup 0 stores the outcome.
-// If the iteration continues, w0 = J u0 (u0 = Dinv r0) and the partials of
-// gamma0 = r.u, delta0 = w.u are formed; otherwise `done` is set.
+// Newton state machine and CG start of round `round` (see the CG
+// recurrences below).  Every workgroup of an item computes the same next
+// state from the round's input state, the previous round's CG outcome and
+// the residual partials; workgroup 0 stores it.
+//  * A direction produced by the previous round's CG is accounted for
+//    (Newton and CG counts, the most CG iterations a direction needed, 2
+//    more when the budget cut the CG), or the solve fails when that CG broke
+//    down at once.
+//  * The trial is accepted on the first evaluation, on sufficient decrease
+//    |R| <= (1 - 1e-4 alpha) rn0, when its step is within tol, or on the last
+//    halving; Newton has converged when an accepted step is within tol.
+//  * Rejected: the step is halved for the next round.  Accepted and not
+//    converged: the trial becomes the accepted temperature and this round's
+//    CG computes the next direction; w0 = J u0 (u0 = Dinv r0) and the
+//    partials of gamma0 = r.u, delta0 = w.u are formed here.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
+cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items,
+                        int round) {
+  __shared__ R u_s[HN];
+  __shared__ R k_s[EN];
   __shared__ double lds[2 * kBlock / 64];
   __shared__ double ldm[kBlock / 64];
   __shared__ double bc[3];
   __shared__ R ldr[2 * kBlock / 64];
-  const SolveItem& it = items[item_of_block(items, n_items, false)];
-  const int blk = blockIdx.x - it.res_begin, nblk = it.res_nb;
+  const SolveItem& it = items[item_of_block(items, n_items)];
+  const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
   const Geo& g = it.g;
   LevelScalars* sc = it.sc;
-  // 1. residual reductions (every workgroup, same order)
-  {
+  const NewtonState st = sc->ns[round & 1];
+  const CGScalars& cgp = sc->cg[(round + 1) & 1];  // previous round's CG
+  NewtonState nx = st;
+  const int prev_iters = round > 0 ? cgp.iters : 0;
+  if (st.status == kRunning && st.pending) {
+    nx.pending = 0;
+    if (cgp.breakdown && cgp.iters == 0) {
+      nx.status = kFailBreakdown;
+    } else {
+      nx.n_newton += 1;
+      nx.n_cg += cgp.iters;
+      nx.cg_need = max(nx.cg_need, cgp.done ? cgp.iters : cgp.iters + 2);
+    }
+  }
+  // inputs of w0 = J u0 for a tile, loaded into registers in one batch
+  const R* __restrict__ r = (const R*)it.r[0];
+  const R* __restrict__ dinv = (const R*)it.dinv;
+  const R* __restrict__ d = (const R*)it.d;
+  const R* __restrict__ kap = (const R*)it.kap;
+  R hr[HPT], hd[HPT], kr[EPT];
+  R o_r = (R)0, o_d = (R)0;
+  int o_n = 0;
+  bool o_act = false;
+  auto load_tile = [&](const Tile& t) {
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      const int n = h < HN ? halo_index(g, t, h) : -1;
+      hr[q] = n >= 0 ? r[n] : (R)0;
+      hd[q] = n >= 0 ? dinv[n] : (R)0;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      const int n = e < EN ? elem_index(g, t, e) : -1;
+      kr[q] = n >= 0 ? kap[n] : (R)0;
+    }
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    o_act = i < g.nx && j < g.ny && k < g.nz;
+    o_n = o_act ? pidx(g, i, j, k) : 0;
+    if (o_act) {
+      o_r = r[o_n];
+      o_d = d[o_n];
+    }
+  };
+  const TileRange tr = tile_range(blk, nblk, it.ntiles);
+  double rnorm2 = 0.0, dmax = 0.0, rz = 0.0;
+  bool run = false;
+  if (nx.status == kRunning) {
+    // the first tile's inputs are in flight during the reduction
+    if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
+    // residual reductions (every workgroup, same order)
     const double* part = it.partials + kPartRes * kMaxBlocks;
     double v[2] = {0.0, 0.0};
     double bm = 0.0;
@@ -568,62 +674,89 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
       bc[2] = v[1];
     }
     __syncthreads();
+    rnorm2 = bc[0];
+    dmax = bc[1];
+    rz = bc[2];
+    const double rn = sqrt(rnorm2);
+    const bool finite = isfinite(rnorm2) && isfinite(dmax);
+    const bool accepted =
+        st.first || !finite || rn <= (1.0 - 1e-4 * st.alpha) * st.rn0 ||
+        dmax <= it.tol || st.h == kLineSearchMax - 1;
+    const bool converged = !st.first && accepted && finite && dmax <= it.tol;
+    if (!finite) {
+      nx.status = kFailNonFinite;
+    } else if (!accepted) {
+      nx.h = st.h + 1;
+      nx.alpha = ldexp(1.0, -nx.h);
+      nx.n_halvings += 1;
+    } else {
+      nx.cur = 1 - st.cur;
+      nx.rn0 = rn;
+      nx.first = 0;
+      if (!st.first) {
+        nx.dmax_prev = st.dmax_last;
+        nx.dmax_last = dmax;
+      }
+      if (converged || rz == 0.0) {
+        nx.status = kConverged;
+      } else if (nx.n_newton >= it.newton_max) {
+        nx.status = kFailNewtonMax;
+      } else {
+        nx.xi = 1 - st.xi;
+        nx.h = 0;
+        nx.alpha = 1.0;
+        nx.pending = 1;
+        run = rz > 0.0;
+        if (!run) nx.status = kFailBreakdown;
+      }
+    }
   }
-  const double rnorm2 = bc[0], dmax = bc[1], rz = bc[2];
-  const double rn = sqrt(rnorm2);
-  const bool finite = isfinite(rnorm2) && isfinite(dmax);
-  bool accepted, converged;
-  if (it.first) {
-    accepted = true;
-    converged = false;
-  } else {
-    accepted = !finite || rn <= (1.0 - 1e-4 * it.alpha) * it.rn0 ||
-               dmax <= it.tol || it.last_try;
-    converged = accepted && finite && dmax <= it.tol;
-  }
-  const bool run = accepted && !converged && finite && rz > 0.0;
   if (blk == 0 && threadIdx.x == 0) {
-    sc->rnorm2 = rnorm2;
-    sc->dmax = dmax;
-    sc->rz0 = rz;
-    sc->accepted = accepted ? 1 : 0;
-    sc->converged = converged ? 1 : 0;
-    sc->breakdown = finite ? 0 : 3;
-    sc->iters = 0;
-    sc->done = run ? 0 : 1;
+    sc->ns[(round + 1) & 1] = nx;
+    CGScalars& cg = sc->cg[round & 1];
+    cg.rz0 = rz;
+    cg.iters = 0;
+    cg.done = run ? 0 : 1;
+    cg.breakdown = 0;
+    if (st.status == kRunning && nx.status == kRunning) {
+      sc->rnorm2 = rnorm2;
+      sc->dmax = dmax;
+    }
+    if (round > 0) sc->cg_log[(round - 1) % kRoundLog] = prev_iters;
   }
   if (!run) return;
-  // 2. w0 = J u0, u0 = Dinv r0
-  const R* __restrict__ r = (const R*)it.r[0];
-  const R* __restrict__ dinv = (const R*)it.dinv;
-  const R* __restrict__ d = (const R*)it.d;
-  const R* __restrict__ kap = (const R*)it.kap;
+  // w0 = J u0, u0 = Dinv r0, on the tiles
   R* __restrict__ w = (R*)it.w[0];
   R wts[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
   R acc[2] = {(R)0, (R)0};
-  for (int t = blk * blockDim.x + threadIdx.x; t < g.nreal;
-       t += nblk * blockDim.x) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    const int n = pidx(g, i, j, k);
-    R u27[27], k8[8];
+  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    const Tile t = tile_of(tile, it.ntx, it.nty);
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      if (h < HN) u_s[h] = hd[q] * hr[q];
+    }
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int o = n + dx + dy * g.px + dz * g.pxy;
-          u27[N27(dx, dy, dz)] = dinv[o] * r[o];
-        }
-    gather8(g, kap, n, k8);
-    const R un = u27[13];
-    const R wn = d[n] * un + stencil_apply(u27, k8, wts);
-    w[n] = wn;
-    acc[0] += r[n] * un;
-    acc[1] += wn * un;
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      if (e < EN) k_s[e] = kr[q];
+    }
+    __syncthreads();
+    const bool active = o_act;
+    const int n = o_n;
+    const R r_own = o_r, d_own = o_d;
+    if (tile + tr.step < tr.last)
+      load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
+    if (active) {
+      const R un = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
+      const R wn = d_own * un + stencil_lds(t, u_s, k_s, wts);
+      w[n] = wn;
+      acc[0] += r_own * un;
+      acc[1] += wn * un;
+    }
+    __syncthreads();  // LDS is reused by the next tile
   }
   block_sum<2>(acc, ldr);
   if (threadIdx.x == 0) {
@@ -636,16 +769,18 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items) {
 template <class R>
 __global__ void __launch_bounds__(kBlock)
 cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
-                       int kit) {
+                       int round, int kit) {
   __shared__ R u_s[HN];
   __shared__ R k_s[EN];
   __shared__ R lds[2 * kBlock / 64];
   __shared__ R bc[2];
-  const SolveItem& it = items[item_of_block(items, n_items, true)];
-  LevelScalars* sc = it.sc;
-  // past the item's own launch count (other items of the batch may run
-  // more): no work, so the item's result does not depend on the batch
-  if (sc->done || kit >= it.max_kit) return;
+  const SolveItem& it = items[item_of_block(items, n_items)];
+  // the state written by this round's CG-start kernel
+  const NewtonState& nst = it.sc->ns[(round + 1) & 1];
+  CGScalars* sc = &it.sc->cg[round & 1];
+  // past the item's own budget (other items of the batch may run more): no
+  // work, so the item's result does not depend on the batch
+  if (sc->done || kit >= nst.budget) return;
   const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
   const Geo& g = it.g;
   const int a = kit & 1;
@@ -656,7 +791,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   R* __restrict__ w_out = (R*)it.w[1 - a];
   R* __restrict__ s_out = (R*)it.s[a];
   R* __restrict__ p = (R*)it.p;
-  R* __restrict__ x = (R*)it.x;
+  R* __restrict__ x = (R*)it.xb[nst.xi];
   const R* __restrict__ d = (const R*)it.d;
   const R* __restrict__ kap = (const R*)it.kap;
   const R* __restrict__ dinv = (const R*)it.dinv;
@@ -708,11 +843,10 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   // iteration k-1), held in the region pair this kernel does not write
   const int rd = (kit & 1) ? kPartCG2 : kPartCG;
   const int wr = (kit & 1) ? kPartCG : kPartCG2;
-  const int nparts = kit == 0 ? it.res_nb : nblk;
   {
     R v[2] = {(R)0, (R)0};
     const double* pg = it.partials + rd * kMaxBlocks;
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
       v[0] += (R)pg[b];
       v[1] += (R)pg[kMaxBlocks + b];
     }
@@ -804,7 +938,6 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   }
 }
 
-int item_residual_blocks(const Geo& g) { return (grid_for(g.nreal) + 7) / 8 * 8; }
 int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles) {
   int ntz;
   tiles_of(g, ntx, nty, ntz);
@@ -814,35 +947,39 @@ int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles) {
 
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks) {
+                        int total_blocks, int round) {
   hipLaunchKernelGGL(residual_batched_kernel<R>, dim3(total_blocks),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items);
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
+                     round);
 }
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks) {
+                        int total_blocks, int round) {
   hipLaunchKernelGGL(cg_start_batched_kernel<R>, dim3(total_blocks),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items);
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
+                     round);
 }
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int total_blocks, int kit, void* ev_start,
+                       int total_blocks, int round, int kit, void* ev_start,
                        void* ev_stop) {
   if (ev_start != nullptr)
     hipExtLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(total_blocks),
                           dim3(kBlock), 0, (hipStream_t)L.stream,
                           (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, items,
-                          n_items, kit);
+                          n_items, round, kit);
   else
     hipLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(total_blocks),
                        dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
-                       kit);
+                       round, kit);
 }
-#define TL_BATCH_INST(R)                                                      \
-  template void k_residual_batched<R>(Launch, const SolveItem*, int, int);    \
-  template void k_cg_start_batched<R>(Launch, const SolveItem*, int, int);    \
+#define TL_BATCH_INST(R)                                                     \
+  template void k_residual_batched<R>(Launch, const SolveItem*, int, int,    \
+                                      int);                                  \
+  template void k_cg_start_batched<R>(Launch, const SolveItem*, int, int,    \
+                                      int);                                  \
   template void k_cg_iter_batched<R>(Launch, const SolveItem*, int, int, int, \
-                                     void*, void*);
+                                     int, void*, void*);
 TL_BATCH_INST(float)
 TL_BATCH_INST(double)
 #undef TL_BATCH_INST

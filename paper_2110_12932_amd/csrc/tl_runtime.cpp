@@ -57,8 +57,8 @@ inline void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw DevErr{std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-constexpr int kLineSearchMax = 12;  // halvings tried before a step is taken anyway
 constexpr int kProfPairs = 64;      // event pairs held between host syncs
+constexpr int kMaxRoundsPerSync = 8;  // Newton rounds queued between syncs
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -110,13 +110,16 @@ struct CGBufs {
   R *kap, *d, *dinv, *r[2], *w[2], *s[2], *p, *x[2];
 };
 
-// Sampled event timing of the fine CG iteration kernel.
+// Sampled event timing of the fine CG iteration kernel.  Each timed launch
+// keeps its round and iteration index; after the host synchronises, only
+// launches that did work for some item are counted.
 struct Profiler {
   int every = 0;
   long count = 0;
   int used = 0;
   hipEvent_t ev[2 * kProfPairs] = {};
   int k[kProfPairs] = {};
+  int round[kProfPairs] = {};
   tl_stats* stats = nullptr;
 };
 
@@ -132,7 +135,7 @@ struct BatchCtx {
 };
 
 // One implicit step of one level inside a batch: the problem (grid, region,
-// step, old field, loads, buffers) and the host-side Newton state.
+// step, old field, loads, buffers); the Newton state lives on the device.
 template <class R>
 struct Job {
   Geo g;
@@ -147,7 +150,7 @@ struct Job {
   double* Rout = nullptr;
   CGBufs<R>* cg = nullptr;
   double* partials = nullptr;
-  int* last_cg = nullptr;   // adaptive CG launch count of this level
+  int* last_cg = nullptr;   // most CG iterations the level's last solve needed
   int64_t* n_newton = nullptr;
   int64_t* n_cg = nullptr;
   tl_stats* stats = nullptr;   // line-search count; op bytes if `fine`
@@ -156,16 +159,17 @@ struct Job {
   int newton_max = 0, cg_max = 0;
   const char* what = "";
   bool failed = false;
+  bool finished = false;
   std::string err;
-  // Newton state
-  int xi = 0, h = 0, dirs = 0, n_launch = 3;
-  double rn0 = 0.0, alpha = 0.0;
-  bool first = true, finished = false;
+  int rounds_hint = 2;   // rounds to queue before the next host sync
 };
 
-void flush_profile(Profiler* pr, int work_limit) {
+// Count the timed launches that did work: round r's launch k worked when
+// some item ran more than k CG iterations in that round.
+void flush_profile(Profiler* pr, int r0, const std::vector<int>& iters) {
   for (int q = 0; q < pr->used; ++q) {
-    if (pr->k[q] >= work_limit) continue;
+    const int r = pr->round[q] - r0;
+    if (r < 0 || r >= (int)iters.size() || pr->k[q] >= iters[r]) continue;
     float ms = 0.0f;
     hip_check(hipEventElapsedTime(&ms, pr->ev[2 * q], pr->ev[2 * q + 1]),
               "hipEventElapsedTime");
@@ -175,147 +179,176 @@ void flush_profile(Profiler* pr, int work_limit) {
   pr->used = 0;
 }
 
+// Rounds a running solve is expected to need: two while the Newton steps
+// are irregular (start, line search), else the count at which the observed
+// linear rate of the accepted steps brings them within tol.
+int predict_rounds(const NewtonState& st, double tol) {
+  if (st.first || st.n_newton < 2 || st.h > 0 || st.dmax_prev <= 0.0 ||
+      st.dmax_last <= tol)
+    return 2;
+  const double rate = st.dmax_last / st.dmax_prev;
+  if (!(rate > 0.0) || rate >= 0.5) return 2;
+  const double q = std::ceil(std::log(tol / st.dmax_last) / std::log(rate));
+  return std::max(1, std::min(kMaxRoundsPerSync, (int)q));
+}
+
 // Batched implicit steps: frozen-kappa Newton with backtracking on
 // |R_free|_2 for every job, linear systems by Jacobi-PCG in precision R.
-// Each round queues, without host synchronisation and for all unfinished
-// jobs at once: the residual at each job's trial T - alpha x (alpha = 0 on
-// the first round), the device-side line-search decision with the CG start,
-// and CG iterations for the next direction (they return at once for a job
-// whose trial was rejected, whose Newton iteration converged, or whose CG
-// converged).  The host then reads every job's outcome with one copy.  On
+// A Newton round is three kinds of launch over all unfinished jobs at once:
+// the residual at each job's trial, the device-side Newton state machine
+// with the CG start, and the CG iterations for the next direction (they
+// return at once for a job whose trial was rejected, whose Newton iteration
+// converged or failed, or whose CG converged or used its budget).  The host
+// queues several rounds without synchronising -- as many as the slowest job
+// is predicted to need -- then reads every job's state with one copy.  On
 // return each job's *T holds its solution and Rout the residual there.
 template <class R>
 void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
   const int nj = (int)jobs.size();
   if (nj > B.cap) throw DevErr{"batch larger than its context"};
-  for (Job<R>* j : jobs) {
-    j->xi = 0; j->h = 0; j->dirs = 0; j->rn0 = 0.0; j->alpha = 0.0;
-    j->first = true; j->finished = false; j->failed = false;
-    j->n_launch = std::min(j->cg_max, std::max(3, *j->last_cg + 2));
+  if (nj == 0) return;
+  for (int q = 0; q < nj; ++q) {
+    Job<R>& j = *jobs[q];
+    j.finished = false;
+    j.failed = false;
+    j.rounds_hint = 2;
+    LevelScalars& h = B.h_sc[q];
+    std::memset(&h, 0, sizeof(LevelScalars));
+    NewtonState& st = h.ns[0];
+    st.first = 1;
+    st.status = kRunning;
+    // CG budget: 1 more than the most the level's last solve needed
+    st.budget = std::min(j.cg_max, std::max(3, *j.last_cg + 1));
   }
-  std::vector<int> act;
+  hip_check(hipMemcpyAsync(B.d_sc, B.h_sc, sizeof(LevelScalars) * nj,
+                           hipMemcpyHostToDevice, B.stream),
+            "hipMemcpyAsync(scalars)");
+  std::vector<int> act, built, round_iters;
+  int round = 0, tb = 0;
   for (;;) {
     act.clear();
     for (int q = 0; q < nj; ++q)
       if (!jobs[q]->finished) act.push_back(q);
     if (act.empty()) return;
-    int rb = 0, tb = 0, n_launch = 0;
-    for (int a = 0; a < (int)act.size(); ++a) {
-      Job<R>& j = *jobs[act[a]];
-      SolveItem& it = B.h_items[a];
-      it.g = j.g;
-      it.rg = j.rg;
-      it.m = j.m;
-      it.tau = j.tau;
-      it.alpha = j.alpha;
-      it.rn0 = j.rn0;
-      it.tol = j.tol;
-      it.rtol2 = j.rtol2;
-      it.first = j.first ? 1 : 0;
-      it.last_try = j.h == kLineSearchMax - 1 ? 1 : 0;
-      it.res_begin = rb;
-      it.res_nb = item_residual_blocks(j.g);
-      rb += it.res_nb;
-      it.tile_begin = tb;
-      it.tile_nb = item_tile_blocks(j.g, it.ntx, it.nty, it.ntiles);
-      tb += it.tile_nb;
-      it.T = *j.T;
-      it.Told = j.Told;
-      it.F = j.F;
-      it.Fext = j.Fext;
-      it.Tt = *j.Tt;
-      it.R = j.Rout;
-      it.dx = j.first ? nullptr : (const void*)j.cg->x[j.xi];
-      it.kap = j.cg->kap;
-      it.d = j.cg->d;
-      it.dinv = j.cg->dinv;
-      it.r[0] = j.cg->r[0];
-      it.r[1] = j.cg->r[1];
-      it.w[0] = j.cg->w[0];
-      it.w[1] = j.cg->w[1];
-      it.s[0] = j.cg->s[0];
-      it.s[1] = j.cg->s[1];
-      it.p = j.cg->p;
-      it.x = j.cg->x[1 - j.xi];
-      it.sc = B.d_sc + act[a];
-      it.max_kit = j.n_launch;
-      it.partials = j.partials;
-      n_launch = std::max(n_launch, j.n_launch);
+    if (act != built) {
+      tb = 0;
+      for (int a = 0; a < (int)act.size(); ++a) {
+        Job<R>& j = *jobs[act[a]];
+        SolveItem& it = B.h_items[a];
+        it.g = j.g;
+        it.rg = j.rg;
+        it.m = j.m;
+        it.tau = j.tau;
+        it.tol = j.tol;
+        it.rtol2 = j.rtol2;
+        it.newton_max = j.newton_max;
+        it.cg_max = j.cg_max;
+        it.tile_begin = tb;
+        it.tile_nb = item_tile_blocks(j.g, it.ntx, it.nty, it.ntiles);
+        tb += it.tile_nb;
+        it.Tb[0] = *j.T;
+        it.Tb[1] = *j.Tt;
+        it.Told = j.Told;
+        it.F = j.F;
+        it.Fext = j.Fext;
+        it.R = j.Rout;
+        it.xb[0] = j.cg->x[0];
+        it.xb[1] = j.cg->x[1];
+        it.kap = j.cg->kap;
+        it.d = j.cg->d;
+        it.dinv = j.cg->dinv;
+        it.r[0] = j.cg->r[0];
+        it.r[1] = j.cg->r[1];
+        it.w[0] = j.cg->w[0];
+        it.w[1] = j.cg->w[1];
+        it.s[0] = j.cg->s[0];
+        it.s[1] = j.cg->s[1];
+        it.p = j.cg->p;
+        it.sc = B.d_sc + act[a];
+        it.partials = j.partials;
+      }
+      hip_check(hipMemcpyAsync(B.d_items, B.h_items,
+                               sizeof(SolveItem) * act.size(),
+                               hipMemcpyHostToDevice, B.stream),
+                "hipMemcpyAsync(items)");
+      built = act;
+    }
+    // CG launches per round: the largest budget
+    int n_launch = 0, n_rounds = 1;
+    for (int q : act) {
+      n_launch = std::max(n_launch, B.h_sc[q].ns[round & 1].budget);
+      n_rounds = std::max(n_rounds, jobs[q]->rounds_hint);
     }
     const int na = (int)act.size();
-    hip_check(hipMemcpyAsync(B.d_items, B.h_items, sizeof(SolveItem) * na,
-                             hipMemcpyHostToDevice, B.stream),
-              "hipMemcpyAsync(items)");
-    k_residual_batched<R>(B.L, B.d_items, na, rb);
-    k_cg_start_batched<R>(B.L, B.d_items, na, rb);
-    for (int k = 0; k < n_launch; ++k) {
-      const bool timed = prof != nullptr && prof->every > 0 &&
-                         (prof->count++ % prof->every) == 0 &&
-                         prof->used < kProfPairs;
-      k_cg_iter_batched<R>(B.L, B.d_items, na, tb, k,
-                           timed ? (void*)prof->ev[2 * prof->used] : nullptr,
-                           timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr);
-      if (timed) prof->k[prof->used++] = k;
+    const int r0 = round;
+    for (int rr = 0; rr < n_rounds; ++rr, ++round) {
+      k_residual_batched<R>(B.L, B.d_items, na, tb, round);
+      k_cg_start_batched<R>(B.L, B.d_items, na, tb, round);
+      for (int k = 0; k < n_launch; ++k) {
+        const bool timed = prof != nullptr && prof->every > 0 &&
+                           (prof->count++ % prof->every) == 0 &&
+                           prof->used < kProfPairs;
+        k_cg_iter_batched<R>(
+            B.L, B.d_items, na, tb, round, k,
+            timed ? (void*)prof->ev[2 * prof->used] : nullptr,
+            timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr);
+        if (timed) {
+          prof->k[prof->used] = k;
+          prof->round[prof->used] = round;
+          ++prof->used;
+        }
+      }
     }
     hip_check(hipGetLastError(), "kernel launch");
     hip_check(hipMemcpyAsync(B.h_sc, B.d_sc, sizeof(LevelScalars) * nj,
                              hipMemcpyDeviceToHost, B.stream),
               "hipMemcpyAsync(scalars)");
     hip_check(hipStreamSynchronize(B.stream), "hipStreamSynchronize");
-    int work_limit = 0;  // CG launches below this index did work for some job
-    for (int q : act) {
-      const LevelScalars& o = B.h_sc[q];
-      if (o.accepted && !o.converged && o.rz0 != 0.0)
-        work_limit = std::max(work_limit, o.done ? o.iters : jobs[q]->n_launch);
+    if (prof != nullptr && prof->used > 0) {
+      // CG iterations per queued round, most over the jobs: rounds before
+      // the last from the log, the last from its CG scalars
+      round_iters.assign(n_rounds, 0);
+      for (int q : act) {
+        const LevelScalars& h = B.h_sc[q];
+        for (int rr = 0; rr < n_rounds; ++rr) {
+          const int r = r0 + rr;
+          const int n = r + 1 < round ? h.cg_log[r % kRoundLog]
+                                      : h.cg[r & 1].iters;
+          round_iters[rr] = std::max(round_iters[rr], n);
+        }
+      }
+      flush_profile(prof, r0, round_iters);
     }
-    if (prof != nullptr && prof->used > 0) flush_profile(prof, work_limit);
     for (int q : act) {
       Job<R>& j = *jobs[q];
-      const LevelScalars& o = B.h_sc[q];
-      auto job_fail = [&](const std::string& msg) {
-        j.failed = true;
-        j.finished = true;
-        j.err = std::string(j.what) + msg;
-      };
-      if (!std::isfinite(o.rnorm2) || !std::isfinite(o.dmax)) {
-        job_fail(": non-finite residual or Newton update");
+      const NewtonState& st = B.h_sc[q].ns[round & 1];
+      if (st.status == kRunning) {
+        j.rounds_hint = predict_rounds(st, j.tol);
         continue;
       }
-      if (!o.accepted) {
-        ++j.h;
-        j.alpha = std::ldexp(1.0, -j.h);
-        ++j.stats->line_search_halvings;
-        continue;
-      }
-      std::swap(*j.T, *j.Tt);
-      j.rn0 = std::sqrt(o.rnorm2);
-      j.first = false;
-      if (o.converged || o.rz0 == 0.0) {
-        j.finished = true;
-        continue;
-      }
-      // the CG of this round produced the next direction
-      if (o.breakdown && o.iters == 0) {
-        job_fail(": CG breakdown (non-positive or non-finite curvature)");
-        continue;
-      }
-      if (j.dirs >= j.newton_max) {
-        job_fail(" Newton did not converge within newton_max iterations");
-        continue;
-      }
-      ++j.dirs;
-      ++*j.n_newton;
-      *j.n_cg += o.iters;
+      j.finished = true;
+      *j.n_newton += st.n_newton;
+      *j.n_cg += st.n_cg;
+      j.stats->line_search_halvings += st.n_halvings;
       if (j.fine) {
-        j.stats->fine_op_bytes += 13.0 * sizeof(R) * j.g.nreal * o.iters;
-        j.stats->fine_op_applies += o.iters;
+        j.stats->fine_op_bytes += 13.0 * sizeof(R) * j.g.nreal * st.n_cg;
+        j.stats->fine_op_applies += st.n_cg;
       }
-      const bool cut = !o.done;  // CG stopped by the launch count, not rtol
-      *j.last_cg = cut ? n_launch + 2 : o.iters;
-      j.n_launch = std::min(j.cg_max, std::max(3, *j.last_cg + 2));
-      j.xi = 1 - j.xi;
-      j.h = 0;
-      j.alpha = 1.0;
+      if (st.cg_need > 0) *j.last_cg = st.cg_need;
+      if (st.cur == 1) std::swap(*j.T, *j.Tt);
+      if (st.status == kConverged) continue;
+      j.failed = true;
+      j.err = std::string(j.what);
+      switch (st.status) {
+        case kFailNonFinite:
+          j.err += ": non-finite residual or Newton update";
+          break;
+        case kFailBreakdown:
+          j.err += ": CG breakdown (non-positive or non-finite curvature)";
+          break;
+        default:
+          j.err += " Newton did not converge within newton_max iterations";
+      }
     }
   }
 }
