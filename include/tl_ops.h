@@ -6,8 +6,10 @@
  *
  * Device layout ("padded"): a grid of nx x ny x nz Q1 cells has
  * (nx+1) x (ny+1) x (nz+1) nodes stored with one ghost layer on every side,
- * node (i,j,k) at ((k+1)*(ny+3) + (j+1))*(nx+3) + (i+1); ghost entries are
- * zero.  A per-element quantity of element (i,j,k) is stored at the padded
+ * node (i,j,k) at ((k+1)*(ny+3) + (j+1))*px + (i+1), where the row pitch px
+ * is nx+3 rounded up to a multiple of 32 (so every row starts on a 128-byte
+ * boundary of a 256-byte aligned buffer); ghost and pitch-padding entries
+ * are zero.  A per-element quantity of element (i,j,k) is stored at the padded
  * index of its lowest corner node (i,j,k); all other entries are zero.
  */
 #ifndef TL_OPS_H

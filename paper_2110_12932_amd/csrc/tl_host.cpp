@@ -125,7 +125,7 @@ Geo make_geo(int ncx, int ncy, int ncz, double hx, double hy, double hz,
   g.nx = ncx + 1;
   g.ny = ncy + 1;
   g.nz = ncz + 1;
-  g.px = g.nx + 2;
+  g.px = (g.nx + 2 + 31) / 32 * 32;
   g.pxy = g.px * (g.ny + 2);
   g.nreal = g.nx * g.ny * g.nz;
   g.npad = (long)g.pxy * (g.nz + 2);

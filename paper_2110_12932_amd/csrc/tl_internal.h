@@ -16,9 +16,11 @@ constexpr int kMaxSpots = 32;    // laser positions averaged by one load call
 // (i,j,k) is stored at that node's index.
 struct Geo {
   int nx, ny, nz;        // nodes per axis
-  int px, pxy;           // padded strides (nx+2, (nx+2)*(ny+2))
+  int px, pxy;           // padded strides: px = nx+2 rounded up to a
+                         // multiple of 32 (rows start on 128-byte lines),
+                         // pxy = px*(ny+2)
   int nreal;             // nx*ny*nz
-  long npad;             // (nx+2)*(ny+2)*(nz+2)
+  long npad;             // pxy*(nz+2)
   double hx, hy, hz;     // spacing
   double x0, y0;         // coordinates of node (0,0,*)
   double vol8;           // element volume / 8

@@ -399,6 +399,212 @@ op_apply_tiled_kernel(Geo g, int ntx, int nty, int ntiles,
   }
 }
 
+// ---------------------------------------------------------------------------
+// z-marching operator for grids too large for the caches.  A workgroup owns
+// a ZX x ZY column of nodes (one wave per row of ZX = 64 nodes, so every row
+// is one contiguous 512-byte (FP64) or 256-byte (FP32) segment) over a run
+// of z planes and walks up the column.  Each thread keeps the 3 x 3 x 3
+// values of v around its node and the 2 x 2 x 2 element conductivities in
+// registers as a sliding window, so a step reads from LDS only the nine
+// values of the next node plane and the four of the next element layer;
+// LDS holds two node planes and two element layers (with x-y halo).  Global
+// loads run two planes ahead of the stencil, so each input value is read
+// from memory once (its x-y halo copies hit the L2 of neighbouring columns
+// on the same XCD) and one barrier per plane suffices.
+// ---------------------------------------------------------------------------
+constexpr int ZX = 64, ZY = kBlock / ZX;
+constexpr int ZHX = ZX + 2, ZHY = ZY + 2, ZHN = ZHX * ZHY;   // node plane
+constexpr int ZEX = ZX + 1, ZEY = ZY + 1, ZEN = ZEX * ZEY;   // element layer
+constexpr int ZHPT = (ZHN + kBlock - 1) / kBlock;
+constexpr int ZEPT = (ZEN + kBlock - 1) / kBlock;
+
+// Column tiles and z runs of the z-marching kernels.  Work units (x column
+// fastest, then y column, then run) are cut into 8 contiguous chunks, one
+// per XCD as in tile_range, so that columns sharing halo rows share an L2.
+struct ZPlan {
+  int ncx, ncy, nrun, run;   // columns per axis, runs per column, run length
+};
+static inline ZPlan zplan_of(const Geo& g) {
+  ZPlan z;
+  z.ncx = (g.nx + 1 + ZX - 1) / ZX;   // columns start at i = -1 (see below)
+  z.ncy = (g.ny + ZY - 1) / ZY;
+  const int cols = z.ncx * z.ncy;
+  // about 8 work units per workgroup of a full grid (kMaxBlocks), so the
+  // grid-stride loop balances, and runs of at least 16 planes, so the two
+  // halo planes of a run add at most an eighth to its reads
+  const int nrun = std::max(1, std::min(8 * kMaxBlocks / cols, g.nz / 16));
+  z.run = (g.nz + nrun - 1) / nrun;
+  z.nrun = (g.nz + z.run - 1) / z.run;
+  return z;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
+                       const R* __restrict__ kap, const R* __restrict__ v,
+                       R* __restrict__ y) {
+  __shared__ R v_s[2][ZHN];
+  __shared__ R k_s[2][ZEN];
+  const int nunits = zp.ncx * zp.ncy * zp.nrun;
+  const TileRange tr = tile_range(blockIdx.x, gridDim.x, nunits);
+  R wts[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
+  const int tx = threadIdx.x % ZX, ty = threadIdx.x / ZX;
+  for (int u = tr.first; u < tr.last; u += tr.step) {
+    const int cx = u % zp.ncx, cy = (u / zp.ncx) % zp.ncy,
+              run = u / (zp.ncx * zp.ncy);
+    // column cx covers i = 64 cx - 1 ... 64 cx + 62: with the row pitch a
+    // multiple of 32, its own row is then a whole number of 128-byte lines
+    const int ox = cx * ZX - 1, oy = cy * ZY;
+    const int k0 = run * zp.run, k1 = min(g.nz, k0 + zp.run);
+    const int i = ox + tx, j = oy + ty;
+    const bool col_active = i >= 0 && i < g.nx && j < g.ny;
+    // padded offset within a plane of this thread's halo entries, or -1
+    // past the ghost layer
+    int voff[ZHPT], koff[ZEPT];
+#pragma unroll
+    for (int q = 0; q < ZHPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      const int ii = ox + h % ZHX - 1, jj = oy + h / ZHX - 1;
+      voff[q] = (h >= ZHN || ii < -1 || ii > g.nx || jj > g.ny)
+                    ? -1 : (jj + 1) * g.px + (ii + 1);
+    }
+#pragma unroll
+    for (int q = 0; q < ZEPT; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      const int ii = ox + e % ZEX - 1, jj = oy + e / ZEX - 1;
+      koff[q] = (e >= ZEN || ii < -1 || ii > g.nx || jj > g.ny)
+                    ? -1 : (jj + 1) * g.px + (ii + 1);
+    }
+    // node plane / element layer p (-1 <= p <= nz) at padded z offset
+    // (p + 1) * pxy
+    auto load_plane = [&](int p, R (&rv)[ZHPT]) {
+#pragma unroll
+      for (int q = 0; q < ZHPT; ++q)
+        rv[q] = (voff[q] >= 0 && p >= -1 && p <= g.nz)
+                    ? v[(long)(p + 1) * g.pxy + voff[q]] : (R)0;
+    };
+    auto load_layer = [&](int l, R (&rk)[ZEPT]) {
+#pragma unroll
+      for (int q = 0; q < ZEPT; ++q)
+        rk[q] = (koff[q] >= 0 && l >= -1 && l <= g.nz)
+                    ? kap[(long)(l + 1) * g.pxy + koff[q]] : (R)0;
+    };
+    auto put_plane = [&](int p, const R (&rv)[ZHPT]) {
+#pragma unroll
+      for (int q = 0; q < ZHPT; ++q) {
+        const int h = threadIdx.x + q * kBlock;
+        if (h < ZHN) v_s[(p + 2) & 1][h] = rv[q];
+      }
+    };
+    auto put_layer = [&](int l, const R (&rk)[ZEPT]) {
+#pragma unroll
+      for (int q = 0; q < ZEPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e < ZEN) k_s[(l + 2) & 1][e] = rk[q];
+      }
+    };
+    // the 9 values of plane p around the node, the 4 conductivities of
+    // layer l around it (element (ex, ey) at offset (-ex, -ey))
+    auto get_plane = [&](int p, R (&w9)[9]) {
+      const R* pl = v_s[(p + 2) & 1];
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          w9[(dx + 1) + 3 * (dy + 1)] = pl[(ty + 1 + dy) * ZHX + (tx + 1 + dx)];
+    };
+    auto get_layer = [&](int l, R (&w4)[4]) {
+      const R* la = k_s[(l + 2) & 1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w4[e] = la[(ty + 1 - (e >> 1)) * ZEX + (tx + 1 - (e & 1))];
+    };
+    auto load_d = [&](int k) {
+      return (col_active && k < k1)
+                 ? d[(long)(k + 1) * g.pxy + (j + 1) * g.px + (i + 1)] : (R)0;
+    };
+    R vm[9], v0[9], vp[9], km[4], k0v[4];
+    R av[ZHPT], ak[ZEPT];
+    R d0, d1;   // the node's own d at planes k and k+1
+    // prologue: planes k0-1, k0 and layer k0-1 into the window; plane k0+1
+    // and layer k0 into LDS; plane k0+2, layer k0+1 and d at k0, k0+1 into
+    // registers
+    {
+      R a[ZHPT], b[ZHPT], c[ZHPT], ka[ZEPT], kb[ZEPT];
+      load_plane(k0 - 1, a);
+      load_plane(k0, b);
+      load_layer(k0 - 1, ka);
+      load_plane(k0 + 1, c);
+      load_layer(k0, kb);
+      d0 = load_d(k0);
+      d1 = load_d(k0 + 1);
+      load_plane(k0 + 2, av);
+      load_layer(k0 + 1, ak);
+      put_plane(k0 - 1, a);
+      put_plane(k0, b);
+      put_layer(k0 - 1, ka);
+      __syncthreads();
+      get_plane(k0 - 1, vm);
+      get_plane(k0, v0);
+      get_layer(k0 - 1, km);
+      __syncthreads();
+      put_plane(k0 + 1, c);
+      put_layer(k0, kb);
+      __syncthreads();
+    }
+    for (int k = k0; k < k1; ++k) {
+      // every global input runs two planes ahead of the stencil: d of plane
+      // k+2, node plane k+3 and element layer k+2 are loaded now, while
+      // plane k is computed from values loaded in earlier steps (memory
+      // counters complete in issue order, so nothing loaded in this step is
+      // waited for before the next one)
+      const R d2 = load_d(k + 2);
+      R bv[ZHPT], bk[ZEPT];
+      load_plane(k + 3, bv);
+      load_layer(k + 2, bk);
+      get_plane(k + 1, vp);
+      get_layer(k, k0v);
+      if (col_active) {
+        R u27[27], k8[8];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          u27[q] = vm[q];
+          u27[9 + q] = v0[q];
+          u27[18 + q] = vp[q];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          k8[e] = k0v[e];
+          k8[4 + e] = km[e];
+        }
+        const long n = (long)(k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+        y[n] = d0 * u27[13] + stencil_apply(u27, k8, wts);
+      }
+      // plane k+2 replaces plane k, layer k+1 replaces layer k-1: both were
+      // last read before the previous barrier
+      put_plane(k + 2, av);
+      put_layer(k + 1, ak);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        vm[q] = v0[q];
+        v0[q] = vp[q];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) km[e] = k0v[e];
+#pragma unroll
+      for (int q = 0; q < ZHPT; ++q) av[q] = bv[q];
+#pragma unroll
+      for (int q = 0; q < ZEPT; ++q) ak[q] = bk[q];
+      d0 = d1;
+      d1 = d2;
+    }
+    __syncthreads();  // LDS is reused by the next work unit
+  }
+}
+
 static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
   ntx = (g.nx + TX - 1) / TX;
   nty = (g.ny + TY - 1) / TY;
@@ -984,9 +1190,21 @@ TL_BATCH_INST(float)
 TL_BATCH_INST(double)
 #undef TL_BATCH_INST
 
+// Grids of more than kZmarchNodes nodes take the z-marching kernel; smaller
+// ones, cache-resident and latency-bound, the 3D-tiled kernel.
+constexpr long kZmarchNodes = 4l << 20;
+
 template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
                 R* y) {
+  if ((long)g.nreal > kZmarchNodes && g.nz >= 8) {
+    const ZPlan zp = zplan_of(g);
+    const int units = zp.ncx * zp.ncy * zp.nrun;
+    hipLaunchKernelGGL(op_apply_zmarch_kernel<R>, dim3(tiled_grid(units)),
+                       dim3(kBlock), 0, (hipStream_t)L.stream, g, zp, d, kap,
+                       v, y);
+    return;
+  }
   int ntx, nty, ntz;
   tiles_of(g, ntx, nty, ntz);
   const int ntiles = ntx * nty * ntz;

@@ -988,9 +988,9 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
   if (me->win_nx < 1 || me->win_ny < 1 || me->win_nz < 1 ||
       me->win_nx > me->nx || me->win_ny > me->ny || me->win_nz > me->nz)
     return fail(TL_EINVAL, "window must fit inside the plate");
-  const double nf = (double)(me->refine * me->win_nx + 1) *
-                    (me->refine * me->win_ny + 1) * (me->refine * me->win_nz + 1);
-  const double nc = (double)(me->nx + 3) * (me->ny + 3) * (me->nz + 3);
+  const double nf = (double)((me->refine * me->win_nx + 3 + 31) / 32 * 32) *
+                    (me->refine * me->win_ny + 3) * (me->refine * me->win_nz + 3);
+  const double nc = (double)((me->nx + 3 + 31) / 32 * 32) * (me->ny + 3) * (me->nz + 3);
   if (nf > 2.0e8 || nc > 2.0e8) return fail(TL_EINVAL, "grid too large");
   if (!finite_all({ma->rho, ma->T_lo, ma->T_hi, ma->c_lo, ma->c_hi, ma->k_lo,
                    ma->k_hi, ma->latent, ma->T_sol, ma->T_liq, ma->sharpness,
@@ -1526,7 +1526,7 @@ static tl_status check_grid(const tl_grid* g) {
   if (!(g->hx > 0) || !(g->hy > 0) || !(g->hz > 0) || !std::isfinite(g->hx) ||
       !std::isfinite(g->hy) || !std::isfinite(g->hz))
     return fail(TL_EINVAL, "spacings must be positive and finite");
-  if ((double)(g->nx + 3) * (g->ny + 3) * (g->nz + 3) > 2.0e9)
+  if ((double)((g->nx + 3 + 31) / 32 * 32) * (g->ny + 3) * (g->nz + 3) > 2.0e9)
     return fail(TL_EINVAL, "grid too large");
   return TL_OK;
 }

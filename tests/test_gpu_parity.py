@@ -59,6 +59,72 @@ def test_op_apply_matches_assembled_operator(cells, prec):
     assert err.max() < tol, err.max()
 
 
+def _op_rows(g, Ke, d, kap, v, nodes):
+    """y_i = d_i v_i + sum over the elements e around node i of
+    kap_e (K_e v_e)_i, one sampled node at a time (plain loops)."""
+    out, scale = [], []
+    for (i, j, k) in nodes:
+        y = d[g.node(i, j, k)] * v[g.node(i, j, k)]
+        s = abs(y)
+        for ez in (0, 1):
+            for ey in (0, 1):
+                for ex in (0, 1):
+                    ei, ej, ek = i - ex, j - ey, k - ez
+                    if not (0 <= ei < g.nx and 0 <= ej < g.ny and 0 <= ek < g.nz):
+                        continue
+                    ke = kap[ei + g.nx * (ej + g.ny * ek)]
+                    a = ex + 2 * ey + 4 * ez   # the node's corner in element e
+                    for c in range(8):
+                        cx, cy, cz = c & 1, (c >> 1) & 1, c >> 2
+                        vc = v[g.node(ei + cx, ej + cy, ek + cz)]
+                        y += ke * Ke[a, c] * vc
+                        s += abs(ke * Ke[a, c] * vc)
+        out.append(y)
+        scale.append(s)
+    return np.array(out), np.array(scale)
+
+
+# more than 4M nodes: the z-marching kernel, with ragged column tiles in x
+# (301 = 4 x 64 + 45) and y (121 = 30 x 4 + 1) and a short last z run
+@pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
+def test_op_apply_large_grid_sampled(prec):
+    nx, ny, nz = 300, 120, 118
+    say("op_apply large", (nx, ny, nz), prec)
+    h = (5.3e-6, 4.1e-6, 6.7e-6)
+    g = G.Grid(nx, ny, nz, *h)
+    assert g.n_nodes > 4 * 2**20
+    rng = np.random.default_rng(11)
+    d = rng.uniform(1e-4, 1e-3, g.n_nodes)
+    kap = rng.uniform(10.0, 30.0, g.n_elems)
+    v = rng.normal(300.0, 50.0, g.n_nodes)
+    dt = torch.float64 if prec == W.FP64 else torch.float32
+    grid = tl.to_grid(nx, ny, nz, *h)
+    npad = tl.tl_op_padded_size(grid)
+    dev = lambda a: torch.tensor(a, dtype=dt, device="cuda")
+    pads = [torch.empty(npad, dtype=dt, device="cuda") for _ in range(4)]
+    tl.tl_op_pack(grid, 0, dev(d), pads[0])
+    tl.tl_op_pack(grid, 1, dev(kap), pads[1])
+    tl.tl_op_pack(grid, 0, dev(v), pads[2])
+    tl.tl_op_apply(grid, prec, pads[0], pads[1], pads[2], pads[3])
+    y = torch.empty(g.n_nodes, dtype=dt, device="cuda")
+    tl.tl_op_unpack(grid, 0, pads[3], y)
+    y = y.cpu().numpy().astype(np.float64)
+    if prec != W.FP64:   # the reference takes the inputs the kernel saw
+        d, kap, v = (a.astype(np.float32).astype(np.float64) for a in (d, kap, v))
+    # every corner and edge class of the domain and of the tiles, plus random
+    xs = sorted({0, 1, 63, 64, 65, 127, 128, 255, 256, 299, 300})
+    ys = sorted({0, 1, 3, 4, 5, 59, 60, 116, 119, 120})
+    zs = sorted({0, 1, 8, 9, 17, 18, 116, 117, 118})
+    nodes = [(i, j, k) for i in xs for j in ys for k in zs]
+    nodes += [tuple(int(t) for t in rng.integers(0, (nx + 1, ny + 1, nz + 1)))
+              for _ in range(300)]
+    ref, scale = _op_rows(g, G.element_stiffness(*h), d, kap, v, nodes)
+    got = np.array([y[g.node(*n)] for n in nodes])
+    err = np.abs(got - ref) / scale
+    tol = 1e-12 if prec == W.FP64 else 2e-6
+    assert err.max() < tol, err.max()
+
+
 def _run_pair(wl, n_macro):
     say("case", wl.name, "precision", wl.options.precision, "macro steps", n_macro)
     sim = tl.Sim(wl)
