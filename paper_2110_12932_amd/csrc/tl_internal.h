@@ -109,18 +109,22 @@ struct LevelScalars {
   int cg_log[kRoundLog];   // CG iterations of round r at [r % kRoundLog]
 };
 
-// Per-workgroup partial sums: regions of kMaxBlocks doubles.  A kernel never
-// writes a region that it (or a still-running workgroup of it) reads: the CG
-// iteration kernels alternate between two pairs of regions by parity, since
-// a grid larger than the resident capacity has workgroups that start only
-// after others have finished.
-enum PartialRegion {
-  kPartCG = 0,     // CG gamma/delta partials, written by CG start and by
-                   // iterations k odd (2 regions)
-  kPartRes = 2,    // residual kernel: |R|^2, max|alpha dx|, r.(Dinv r) (3 regions)
-  kPartGen = 5,    // generic sums (loads, energy, bottom reactions)
-  kPartCG2 = 6,    // CG gamma/delta partials written by iterations k even
-  kPartRegions = 8
+// Per-workgroup partial sums of the generic reductions (loads, energy,
+// bottom reactions): kMaxBlocks doubles, summed by a one-workgroup kernel.
+enum PartialRegion { kPartGen = 0, kPartRegions = 1 };
+
+// Per-tile partial sums of the batched Newton/CG kernels: regions of
+// `tstride` doubles indexed by tile.  A consumer sums an item's tiles in
+// tile order, so the result does not depend on how many workgroups shared
+// the tiles.  The CG iteration kernels alternate between two region pairs
+// by parity, since a kernel never writes a region it reads (a grid larger
+// than the resident capacity has workgroups that start only after others
+// have finished).
+enum TilePartial {
+  kTRes = 0,    // residual kernel: |R_free|^2, max |alpha dx|, r.(Dinv r)
+  kTCG = 3,     // CG gamma/delta, written by CG start and odd iterations
+  kTCG2 = 5,    // CG gamma/delta, written by even iterations
+  kTileRegions = 7
 };
 
 // Energy ledger slots on the device.
@@ -159,10 +163,11 @@ struct SolveItem {
   double rtol2;      // CG: stop when r.u <= rtol2 * r0.u0
   int newton_max;    // Newton directions allowed
   int cg_max;        // CG iterations allowed per direction
-  int tile_begin, tile_nb;  // workgroups of the item in every batched kernel
   int ntx, nty, ntiles;     // tiles of this item
+  int tstride;              // entries per region of tpart (>= ntiles)
   double* Tb[2];       // the accepted and the trial temperature (see ns.cur)
   const double* Told;  // temperature at the previous time level
+  double* Hold;        // H(Told): written in a solve's first round, then read
   const double* F;     // surface load at the new time level
   const double* Fext;  // interface load (null if none)
   double* R;           // residual at the trial
@@ -176,26 +181,30 @@ struct SolveItem {
   void* s[2];          // J p (double-buffered)
   void* p;             // search direction
   LevelScalars* sc;    // per-item scalars
-  double* partials;    // per-item partial sums, kPartRegions * kMaxBlocks
+  double* tpart;       // per-tile partial sums, kTileRegions * tstride
 };
 
-// Workgroups an item needs in the batched kernels (a multiple of 8) and its
-// tiles.
-int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles);
+// Tiles of a grid in the batched kernels.
+int grid_tiles(const Geo& g, int& ntx, int& nty);
+// Workgroups every item of a batched launch gets (a multiple of 8), for a
+// largest item of ntiles tiles: one per tile up to kMaxBlocks when alone,
+// fewer in larger batches so that a launch stays near kMaxBlocks workgroups
+// (each then walks several tiles; an item with fewer tiles leaves some
+// workgroups without work).
+int item_tile_blocks(int ntiles, int n_items);
 
 // Batched launches of Newton round `round` over a device table of n_items
-// items; total_blocks is the sum of the items' workgroup counts for that
-// kernel.  ev_start/ev_stop (hipEvent_t, may be null) are recorded with the
-// CG dispatch itself.
+// items, per_item workgroups each.  ev_start/ev_stop (hipEvent_t, may be
+// null) are recorded with the CG dispatch itself.
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks, int round);
+                        int per_item, int round);
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks, int round);
+                        int per_item, int round);
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int total_blocks, int round, int kit, void* ev_start,
+                       int per_item, int round, int kit, void* ev_start,
                        void* ev_stop);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,

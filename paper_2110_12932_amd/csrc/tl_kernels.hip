@@ -105,23 +105,34 @@ __device__ inline double kappa_of(double T, const MatDev& m) {
 __device__ inline double heatcap_of(double T, const MatDev& m) {
   return m.c_lo + m.cslope * (clampT(T, m) - m.T_lo);
 }
-// H(T) = rho int_{T_lo}^T c + rho chi f_pc(T)
-__device__ inline double enthalpy(double T, const MatDev& m) {
-  double sens;
-  if (T < m.T_lo) {
-    sens = m.c_lo * (T - m.T_lo);
-  } else if (T > m.T_hi) {
-    sens = m.sens_full + m.c_hi * (T - m.T_hi);
-  } else {
-    double u = T - m.T_lo;
-    sens = m.c_lo * u + 0.5 * m.cslope * u * u;
-  }
-  double f = 0.5 * (1.0 + tanh(m.S * (T - m.Tm)));
-  return m.rho * (sens + m.latent * f);
+// tanh for the phase-change sigmoid, from expm1: t = -em / (2 + em) with
+// em = expm1(-2|x|), sign restored.  For |x| > 20, tanh(x) rounds to +-1 in
+// double precision (1 - tanh(20) < 1e-17), so the exponential is skipped --
+// the case of every node more than 20/S from the melting centre.
+__device__ inline double sigmoid_tanh(double x) {
+  const double ax = fabs(x);
+  if (ax > 20.0) return copysign(1.0, x);
+  const double em = expm1(-2.0 * ax);
+  return copysign(-em / (2.0 + em), x);
 }
-__device__ inline double enthalpy_slope(double T, const MatDev& m) {
-  double th = tanh(m.S * (T - m.Tm));
-  return m.rho * (heatcap_of(T, m) + m.latent * 0.5 * m.S * (1.0 - th * th));
+// rho int_{T_lo}^T c (sensible part of the enthalpy)
+__device__ inline double sensible(double T, const MatDev& m) {
+  if (T < m.T_lo) return m.c_lo * (T - m.T_lo);
+  if (T > m.T_hi) return m.sens_full + m.c_hi * (T - m.T_hi);
+  const double u = T - m.T_lo;
+  return m.c_lo * u + 0.5 * m.cslope * u * u;
+}
+// H(T) = rho int_{T_lo}^T c + rho chi f_pc(T), f_pc = (1 + tanh(S(T - Tm)))/2
+__device__ inline double enthalpy(double T, const MatDev& m) {
+  const double th = sigmoid_tanh(m.S * (T - m.Tm));
+  return m.rho * (sensible(T, m) + m.latent * 0.5 * (1.0 + th));
+}
+// H(T) and H'(T) sharing one tanh
+__device__ inline void enthalpy_and_slope(double T, const MatDev& m, double& H,
+                                          double& dH) {
+  const double th = sigmoid_tanh(m.S * (T - m.Tm));
+  H = m.rho * (sensible(T, m) + m.latent * 0.5 * (1.0 + th));
+  dH = m.rho * (heatcap_of(T, m) + m.latent * 0.5 * m.S * (1.0 - th * th));
 }
 
 // Trial temperature of one node for the Newton step `step` (= alpha dx):
@@ -211,13 +222,72 @@ void k_copy(Launch L, double* dst, const double* src, long n) {
 // Neighbour offset table: n27(dx,dy,dz) = (dx+1) + 3(dy+1) + 9(dz+1).
 #define N27(dx, dy, dz) (((dx) + 1) + 3 * ((dy) + 1) + 9 * ((dz) + 1))
 
-// y = d*v_c + sum over the 8 elements around the node of
-// kap_e * sum_corners W[pattern] v_corner, with v27 the 27 values around the
-// node and k8[e] the conductivity of element e (node is its corner e, i.e.
-// the element sits at offset (-ex, -ey, -ez)).
+// K v at a node, with v27 the 27 values around the node and k8[e] the
+// conductivity of element e = ex + 2 ey + 4 ez (the element at offset
+// (-ex, -ey, -ez), of which the node is corner e).  The element sums
+// sum_e k8[e] sum_c W[e ^ c] v_c are regrouped by neighbour: the elements
+// holding both the node and its neighbour at offset d are those with
+// e_a = (d_a < 0) on every axis where d_a != 0 (either value where d_a = 0),
+// and for all of them the pattern e ^ c is (|dx|, |dy|, |dz|).  So
+//   K v = sum_d W[|dx| + 2|dy| + 4|dz|] Ksum(d) v_d,
+// with Ksum(d) the sum of those elements' conductivities: partial sums of
+// k8 along one axis (edges), two axes (faces) and all three (centre).  This
+// takes 19 additions and 35 multiply-adds per node instead of 72, and uses
+// each neighbour value once.
 template <class R>
 __device__ inline R stencil_apply(const R (&v27)[27], const R (&k8)[8],
                                   const R (&w)[8]) {
+  auto V = [&](int dx, int dy, int dz) { return v27[N27(dx, dy, dz)]; };
+  auto I = [](int dd) { return dd < 0 ? 1 : 0; };
+  R kz[2][2], ky[2][2], kx[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      kz[a][b] = k8[a + 2 * b] + k8[a + 2 * b + 4];   // (ex, ey), both ez
+      ky[a][b] = k8[a + 4 * b] + k8[a + 2 + 4 * b];   // (ex, ez), both ey
+      kx[a][b] = k8[2 * a + 4 * b] + k8[1 + 2 * a + 4 * b];  // (ey, ez)
+    }
+  const R fx0 = kz[0][0] + kz[0][1], fx1 = kz[1][0] + kz[1][1];
+  const R fy0 = kz[0][0] + kz[1][0], fy1 = kz[0][1] + kz[1][1];
+  const R fz0 = ky[0][0] + ky[1][0], fz1 = ky[0][1] + ky[1][1];
+  const R tot = fx0 + fx1;
+  R s1 = fx0 * V(1, 0, 0);
+  s1 += fx1 * V(-1, 0, 0);
+  R s2 = fy0 * V(0, 1, 0);
+  s2 += fy1 * V(0, -1, 0);
+  R s4 = fz0 * V(0, 0, 1);
+  s4 += fz1 * V(0, 0, -1);
+  R s3 = (R)0, s5 = (R)0, s6 = (R)0, s7 = (R)0;
+#pragma unroll
+  for (int a = -1; a <= 1; a += 2)
+#pragma unroll
+    for (int b = -1; b <= 1; b += 2) {
+      s3 += kz[I(a)][I(b)] * V(a, b, 0);
+      s5 += ky[I(a)][I(b)] * V(a, 0, b);
+      s6 += kx[I(a)][I(b)] * V(0, a, b);
+#pragma unroll
+      for (int c = -1; c <= 1; c += 2)
+        s7 += k8[I(a) + 2 * I(b) + 4 * I(c)] * V(a, b, c);
+    }
+  R acc = w[0] * (tot * V(0, 0, 0));
+  acc += w[1] * s1;
+  acc += w[2] * s2;
+  acc += w[3] * s3;
+  acc += w[4] * s4;
+  acc += w[5] * s5;
+  acc += w[6] * s6;
+  acc += w[7] * s7;
+  return acc;
+}
+
+// The same K v summed element by element (8 x 8 multiply-adds): more
+// arithmetic, but fewer values live at once, which keeps the FP64 z-march
+// kernel at a higher occupancy.
+template <class R>
+__device__ inline R stencil_apply_elementwise(const R (&v27)[27],
+                                              const R (&k8)[8],
+                                              const R (&w)[8]) {
   R acc = (R)0;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -361,7 +431,10 @@ __device__ inline R stencil_lds(const Tile& t, const R* u_s, const R* k_s,
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
     k8[e] = k_s[(t.tz + 1 - ez) * (EX * EY) + (t.ty + 1 - ey) * EX + (t.tx + 1 - ex)];
   }
-  return stencil_apply(u27, k8, w);
+  if constexpr (sizeof(R) == 8)
+    return stencil_apply_elementwise(u27, k8, w);   // fewer live registers
+  else
+    return stencil_apply(u27, k8, w);
 }
 
 // Tiled matrix-free operator y = d v + K[kap] v (every node).
@@ -580,7 +653,10 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
           k8[4 + e] = km[e];
         }
         const long n = (long)(k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
-        y[n] = d0 * u27[13] + stencil_apply(u27, k8, wts);
+        if constexpr (sizeof(R) == 8)
+          y[n] = d0 * u27[13] + stencil_apply_elementwise(u27, k8, wts);
+        else
+          y[n] = d0 * u27[13] + stencil_apply(u27, k8, wts);
       }
       // plane k+2 replaces plane k, layer k+1 replaces layer k-1: both were
       // last read before the previous barrier
@@ -618,16 +694,10 @@ static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
 // starting at a multiple of 8, so the XCD-aware tile order holds inside each
 // item; every item has its own scalars and partial-sum regions.
 // ---------------------------------------------------------------------------
-__device__ inline int item_of_block(const SolveItem* __restrict__ items,
-                                    int n) {
-  const int b = blockIdx.x;
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].tile_begin <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
+// Every item of a batched launch has the same number of workgroups
+// (`per_item`), so a workgroup finds its item and its rank within the item
+// without reading the table.
+__device__ inline int item_of_block(int per_item) { return blockIdx.x / per_item; }
 
 // K4 + K1: nonlinear residual at the trial T - alpha dx, Jacobian
 // coefficients, CG initial residual; partials of |R_free|^2, max|alpha dx|,
@@ -635,12 +705,12 @@ __device__ inline int item_of_block(const SolveItem* __restrict__ items,
 // formed once per halo node and each element's conductivity once per tile.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
+residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                         int round) {
   __shared__ double t_s[HN];
   __shared__ double k_s[EN];
   __shared__ double lds[6 * kBlock / 64];
-  const SolveItem& it = items[item_of_block(items, n_items)];
+  const SolveItem& it = items[item_of_block(per_item)];
   const NewtonState& st = it.sc->ns[round & 1];
   if (st.status != kRunning) return;
   if (st.pending) {
@@ -649,7 +719,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
     const CGScalars& cgp = it.sc->cg[(round + 1) & 1];
     if (cgp.breakdown && cgp.iters == 0) return;
   }
-  const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
+  const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
   const MatDev& m = it.m;
   const double* __restrict__ T = it.Tb[st.cur];
@@ -663,35 +733,52 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   double w[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) w[q] = g.w[q];
-  double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
+  double* __restrict__ tp = it.tpart;
+  const int ts = it.tstride;
+  // a tile's global inputs, loaded into registers in one batch: the next
+  // tile's while this tile's elements and nodes are computed
+  double hT[HPT];
+  R hd[HPT];
+  // o_H: T_old in the first round (H(T_old) is formed and kept), H(T_old)
+  // in later rounds
+  double o_T = 0.0, o_H = 0.0, o_F = 0.0, o_Fx = 0.0;
+  const bool first = st.first != 0;
+  auto load_tile = [&](const Tile& t) {
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int h = threadIdx.x + q * kBlock;
+      const int hn = h < HN ? halo_index(g, t, h) : -1;
+      hT[q] = hn >= 0 ? T[hn] : 0.0;
+      hd[q] = (hn >= 0 && dx != nullptr) ? dx[hn] : (R)0;
+    }
+    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+      const int n = pidx(g, i, j, k);
+      o_T = T[n];
+      o_H = first ? it.Told[n] : it.Hold[n];
+      o_F = it.F[n];
+      if (it.Fext != nullptr) o_Fx = it.Fext[n];
+    }
+  };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
+  if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
     const Tile t = tile_of(tile, it.ntx, it.nty);
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     const bool active = i < g.nx && j < g.ny && k < g.nz;
     const int n = active ? pidx(g, i, j, k) : 0;
-    double Tc0 = 0.0, Told_n = 0.0, F_n = 0.0, Fx_n = 0.0;
-    if (active) {
-      Tc0 = T[n];
-      Told_n = it.Told[n];
-      F_n = it.F[n];
-      if (it.Fext != nullptr) Fx_n = it.Fext[n];
-    }
-    // trial temperature on the halo tile
+    const double Tc0 = o_T, H_old = o_H, F_n = o_F, Fx_n = o_Fx;
+    // trial temperature on the halo tile (entries past the grid are 0)
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      if (h < HN) {
-        const int hn = halo_index(g, t, h);
-        double v = 0.0;
-        if (hn >= 0) {
-          v = T[hn];
-          if (dx != nullptr) v = trial_T(v, alpha * (double)dx[hn], m);
-        }
-        t_s[h] = v;
-      }
+      if (h < HN)
+        t_s[h] = dx != nullptr ? trial_T(hT[q], alpha * (double)hd[q], m) : hT[q];
     }
     __syncthreads();
+    if (tile + tr.step < tr.last)
+      load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
     // conductivity of each element of the tile at its mean trial temperature
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -737,14 +824,20 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
       }
       const double Tn = T27[13];
       const double mass = g.vol8 * nact;
-      double Rn = mass * (enthalpy(Tn, m) - enthalpy(Told_n, m)) / it.tau +
-                  stencil_apply(T27, k8, w) - F_n;
+      double Hn, dHn;
+      enthalpy_and_slope(Tn, m, Hn, dHn);
+      double Ho = H_old;
+      if (first) {
+        Ho = enthalpy(H_old, m);   // H_old holds T_old here
+        it.Hold[n] = Ho;
+      }
+      double Rn = mass * (Hn - Ho) / it.tau + stencil_apply(T27, k8, w) - F_n;
       if (it.Fext != nullptr) Rn -= Fx_n;
       Tt[n] = Tn;
       it.R[n] = Rn;
       // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
       const bool dir = node_dirichlet(g, it.rg, i, j, k);
-      const double dn = mass * enthalpy_slope(Tn, m) / it.tau;
+      const double dn = mass * dHn / it.tau;
       const double diag = dn + diagK * g.w[0];
       // this node owns the element whose lowest corner it is (k8[0])
       kap[n] = (R)k8[0];
@@ -760,22 +853,21 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
         acc[2] += (double)(rn * zn);
       }
     }
+    // the tile's partials; the max is taken separately from the two sums
+    const double mx = wave_max(acc[1]);
+    double sums[2] = {acc[0], acc[2]};
+    block_sum<2>(sums, lds);
+    if ((threadIdx.x & 63) == 0) lds[2 * kBlock / 64 + (threadIdx.x >> 6)] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double bm = lds[2 * kBlock / 64];
+      for (int wv = 1; wv < kBlock / 64; ++wv)
+        bm = fmax(bm, lds[2 * kBlock / 64 + wv]);
+      tp[kTRes * ts + tile] = sums[0];
+      tp[(kTRes + 1) * ts + tile] = bm;
+      tp[(kTRes + 2) * ts + tile] = sums[1];
+    }
     __syncthreads();  // LDS is reused by the next tile
-  }
-  // max is taken separately from the two sums
-  double mx = wave_max(acc[1]);
-  double sums[2] = {acc[0], acc[2]};
-  block_sum<2>(sums, lds);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double bm = lds[0];
-    for (int wv = 1; wv < kBlock / 64; ++wv) bm = fmax(bm, lds[wv]);
-    double* part = it.partials + kPartRes * kMaxBlocks;
-    part[blk] = sums[0];
-    part[kMaxBlocks + blk] = bm;
-    part[2 * kMaxBlocks + blk] = sums[1];
   }
 }
 
@@ -796,7 +888,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int n_items,
 //    partials of gamma0 = r.u, delta0 = w.u are formed here.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items,
+cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                         int round) {
   __shared__ R u_s[HN];
   __shared__ R k_s[EN];
@@ -804,8 +896,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   __shared__ double ldm[kBlock / 64];
   __shared__ double bc[3];
   __shared__ R ldr[2 * kBlock / 64];
-  const SolveItem& it = items[item_of_block(items, n_items)];
-  const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
+  const SolveItem& it = items[item_of_block(per_item)];
+  const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
   LevelScalars* sc = it.sc;
   const NewtonState st = sc->ns[round & 1];
@@ -859,14 +951,15 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   if (nx.status == kRunning) {
     // the first tile's inputs are in flight during the reduction
     if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
-    // residual reductions (every workgroup, same order)
-    const double* part = it.partials + kPartRes * kMaxBlocks;
+    // residual reductions over the item's tiles (every workgroup, same
+    // order)
+    const double* part = it.tpart + kTRes * it.tstride;
     double v[2] = {0.0, 0.0};
     double bm = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    for (int b = threadIdx.x; b < it.ntiles; b += kBlock) {
       v[0] += part[b];
-      v[1] += part[2 * kMaxBlocks + b];
-      bm = fmax(bm, part[kMaxBlocks + b]);
+      v[1] += part[2 * it.tstride + b];
+      bm = fmax(bm, part[it.tstride + b]);
     }
     bm = wave_max(bm);
     block_sum<2>(v, lds);
@@ -936,8 +1029,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   R wts[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-  R acc[2] = {(R)0, (R)0};
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    R acc[2] = {(R)0, (R)0};
     const Tile t = tile_of(tile, it.ntx, it.nty);
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
@@ -962,32 +1055,32 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int n_items,
       acc[0] += r_own * un;
       acc[1] += wn * un;
     }
+    block_sum<2>(acc, ldr);
+    if (threadIdx.x == 0) {
+      it.tpart[kTCG * it.tstride + tile] = (double)acc[0];
+      it.tpart[(kTCG + 1) * it.tstride + tile] = (double)acc[1];
+    }
     __syncthreads();  // LDS is reused by the next tile
-  }
-  block_sum<2>(acc, ldr);
-  if (threadIdx.x == 0) {
-    it.partials[kPartCG * kMaxBlocks + blk] = (double)acc[0];
-    it.partials[(kPartCG + 1) * kMaxBlocks + blk] = (double)acc[1];
   }
 }
 
 // One Chronopoulos-Gear PCG iteration `kit` for every item (LDS-tiled).
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
+cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                        int round, int kit) {
   __shared__ R u_s[HN];
   __shared__ R k_s[EN];
   __shared__ R lds[2 * kBlock / 64];
   __shared__ R bc[2];
-  const SolveItem& it = items[item_of_block(items, n_items)];
+  const SolveItem& it = items[item_of_block(per_item)];
   // the state written by this round's CG-start kernel
   const NewtonState& nst = it.sc->ns[(round + 1) & 1];
   CGScalars* sc = &it.sc->cg[round & 1];
   // past the item's own budget (other items of the batch may run more): no
   // work, so the item's result does not depend on the batch
   if (sc->done || kit >= nst.budget) return;
-  const int blk = blockIdx.x - it.tile_begin, nblk = it.tile_nb;
+  const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
   const int a = kit & 1;
   const R* __restrict__ r_in = (const R*)it.r[a];
@@ -1047,14 +1140,15 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
   // gamma_k, delta_k from the previous kernel's partials (CG start or
   // iteration k-1), held in the region pair this kernel does not write
-  const int rd = (kit & 1) ? kPartCG2 : kPartCG;
-  const int wr = (kit & 1) ? kPartCG : kPartCG2;
+  const int rd = (kit & 1) ? kTCG2 : kTCG;
+  const int wr = (kit & 1) ? kTCG : kTCG2;
+  const int ts = it.tstride;
   {
     R v[2] = {(R)0, (R)0};
-    const double* pg = it.partials + rd * kMaxBlocks;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    const double* pg = it.tpart + rd * ts;
+    for (int b = threadIdx.x; b < it.ntiles; b += kBlock) {
       v[0] += (R)pg[b];
-      v[1] += (R)pg[kMaxBlocks + b];
+      v[1] += (R)pg[ts + b];
     }
     block_sum<2>(v, lds);
     if (threadIdx.x == 0) {
@@ -1098,8 +1192,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
   R wts[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-  R acc[2] = {(R)0, (R)0};
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
+    R acc[2] = {(R)0, (R)0};
     const Tile t = tile_of(tile, it.ntx, it.nty);
     // u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
 #pragma unroll
@@ -1135,48 +1229,51 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int n_items,
       acc[0] += r1 * u1;
       acc[1] += w1 * u1;
     }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+      it.tpart[wr * ts + tile] = (double)acc[0];
+      it.tpart[(wr + 1) * ts + tile] = (double)acc[1];
+    }
     __syncthreads();  // LDS is reused by the next tile
-  }
-  block_sum<2>(acc, lds);
-  if (threadIdx.x == 0) {
-    it.partials[wr * kMaxBlocks + blk] = (double)acc[0];
-    it.partials[(wr + 1) * kMaxBlocks + blk] = (double)acc[1];
   }
 }
 
-int item_tile_blocks(const Geo& g, int& ntx, int& nty, int& ntiles) {
+int grid_tiles(const Geo& g, int& ntx, int& nty) {
   int ntz;
   tiles_of(g, ntx, nty, ntz);
-  ntiles = ntx * nty * ntz;
-  return tiled_grid(ntiles);
+  return ntx * nty * ntz;
+}
+int item_tile_blocks(int ntiles, int n_items) {
+  const int share = std::max(64, kMaxBlocks / std::max(1, n_items)) / kXcd * kXcd;
+  return std::min(tiled_grid(ntiles), share);
 }
 
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks, int round) {
-  hipLaunchKernelGGL(residual_batched_kernel<R>, dim3(total_blocks),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
+                        int per_item, int round) {
+  hipLaunchKernelGGL(residual_batched_kernel<R>, dim3(n_items * per_item),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item,
                      round);
 }
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int total_blocks, int round) {
-  hipLaunchKernelGGL(cg_start_batched_kernel<R>, dim3(total_blocks),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
+                        int per_item, int round) {
+  hipLaunchKernelGGL(cg_start_batched_kernel<R>, dim3(n_items * per_item),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item,
                      round);
 }
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int total_blocks, int round, int kit, void* ev_start,
+                       int per_item, int round, int kit, void* ev_start,
                        void* ev_stop) {
   if (ev_start != nullptr)
-    hipExtLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(total_blocks),
+    hipExtLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(n_items * per_item),
                           dim3(kBlock), 0, (hipStream_t)L.stream,
                           (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, items,
-                          n_items, round, kit);
+                          per_item, round, kit);
   else
-    hipLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(total_blocks),
-                       dim3(kBlock), 0, (hipStream_t)L.stream, items, n_items,
+    hipLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(n_items * per_item),
+                       dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item,
                        round, kit);
 }
 #define TL_BATCH_INST(R)                                                     \

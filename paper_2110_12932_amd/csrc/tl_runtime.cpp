@@ -66,15 +66,17 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Sizes of everything carved out of the caller's workspace.
 struct Layout {
   Geo gc, gf;
-  size_t off_c[22], off_fd[8], off_fcg[12];
-  size_t off_scal, off_items, off_ledger, off_partials, off_gidx, off_gbuf;
+  size_t off_c[23], off_fd[9], off_fcg[12];
+  size_t off_scal, off_items, off_ledger, off_partials, off_tpart, off_gidx,
+      off_gbuf;
+  int tstride;   // per-tile partial slots per region (both levels)
   int gamma_cap;
   size_t total;
   int cg_bytes;
 };
 
-constexpr int kCoarseArrays = 22;  // Tn Tpred cur trial lam dprev R Fall Fout ext | 12 CG arrays
-constexpr int kFineD = 8;          // state prev cur trial alt R F rho
+constexpr int kCoarseArrays = 23;  // Tn Tpred cur trial lam dprev R Fall Fout ext | 12 CG arrays | Hold
+constexpr int kFineD = 9;          // state prev cur trial alt R F rho Hold
 constexpr int kFineCG = 12;        // kap d dinv r0 r1 w0 w1 s0 s1 p x0 x1
 
 Layout make_layout(const tl_mesh& me, const tl_options& op) {
@@ -97,6 +99,11 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   L.off_ledger = off; off += align_up(sizeof(LedgerDev));
   L.off_partials = off;
   off += align_up((size_t)kMaxBlocks * kPartRegions * sizeof(double));
+  int ntx, nty;
+  const int nt = std::max(grid_tiles(L.gc, ntx, nty), grid_tiles(L.gf, ntx, nty));
+  L.tstride = (nt + 63) / 64 * 64;
+  L.off_tpart = off;
+  off += align_up((size_t)L.tstride * kTileRegions * sizeof(double));
   L.gamma_cap = (me.win_nx + 1) * (me.win_ny + 1) * (me.win_nz + 1);
   L.off_gidx = off; off += align_up((size_t)L.gamma_cap * sizeof(int));
   L.off_gbuf = off; off += align_up((size_t)L.gamma_cap * 2 * sizeof(double));
@@ -149,7 +156,10 @@ struct Job {
   double** Tt = nullptr;  // trial temperature
   double* Rout = nullptr;
   CGBufs<R>* cg = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;   // generic per-workgroup partials
+  double* tpart = nullptr;      // per-tile partials of the Newton/CG kernels
+  double* Hold = nullptr;       // H(T_old), formed in the first round
+  int tstride = 0;
   int* last_cg = nullptr;   // most CG iterations the level's last solve needed
   int64_t* n_newton = nullptr;
   int64_t* n_cg = nullptr;
@@ -224,14 +234,19 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
                            hipMemcpyHostToDevice, B.stream),
             "hipMemcpyAsync(scalars)");
   std::vector<int> act, built, round_iters;
-  int round = 0, tb = 0;
+  int round = 0, per_item = 0;
   for (;;) {
     act.clear();
     for (int q = 0; q < nj; ++q)
       if (!jobs[q]->finished) act.push_back(q);
     if (act.empty()) return;
     if (act != built) {
-      tb = 0;
+      int most = 1;
+      for (int q : act) {
+        int ntx, nty;
+        most = std::max(most, grid_tiles(jobs[q]->g, ntx, nty));
+      }
+      per_item = item_tile_blocks(most, (int)act.size());
       for (int a = 0; a < (int)act.size(); ++a) {
         Job<R>& j = *jobs[act[a]];
         SolveItem& it = B.h_items[a];
@@ -243,12 +258,12 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
         it.rtol2 = j.rtol2;
         it.newton_max = j.newton_max;
         it.cg_max = j.cg_max;
-        it.tile_begin = tb;
-        it.tile_nb = item_tile_blocks(j.g, it.ntx, it.nty, it.ntiles);
-        tb += it.tile_nb;
+        it.ntiles = grid_tiles(j.g, it.ntx, it.nty);
+        it.tstride = j.tstride;
         it.Tb[0] = *j.T;
         it.Tb[1] = *j.Tt;
         it.Told = j.Told;
+        it.Hold = j.Hold;
         it.F = j.F;
         it.Fext = j.Fext;
         it.R = j.Rout;
@@ -265,7 +280,7 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
         it.s[1] = j.cg->s[1];
         it.p = j.cg->p;
         it.sc = B.d_sc + act[a];
-        it.partials = j.partials;
+        it.tpart = j.tpart;
       }
       hip_check(hipMemcpyAsync(B.d_items, B.h_items,
                                sizeof(SolveItem) * act.size(),
@@ -282,14 +297,14 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
     const int na = (int)act.size();
     const int r0 = round;
     for (int rr = 0; rr < n_rounds; ++rr, ++round) {
-      k_residual_batched<R>(B.L, B.d_items, na, tb, round);
-      k_cg_start_batched<R>(B.L, B.d_items, na, tb, round);
+      k_residual_batched<R>(B.L, B.d_items, na, per_item, round);
+      k_cg_start_batched<R>(B.L, B.d_items, na, per_item, round);
       for (int k = 0; k < n_launch; ++k) {
         const bool timed = prof != nullptr && prof->every > 0 &&
                            (prof->count++ % prof->every) == 0 &&
                            prof->used < kProfPairs;
         k_cg_iter_batched<R>(
-            B.L, B.d_items, na, tb, round, k,
+            B.L, B.d_items, na, per_item, round, k,
             timed ? (void*)prof->ev[2 * prof->used] : nullptr,
             timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr);
         if (timed) {
@@ -373,11 +388,13 @@ struct tl_sim {
   CGBufs<double> ccg;
   // fine fields
   double *fstate, *fprev, *fcur, *ftrial, *falt, *fR, *fF, *rho;
+  double *cHold, *fHold;   // H(T_old) of the level's current solve
   CGBufs<double> fcg64;
   CGBufs<float> fcg32;
   LevelScalars *sc_c, *sc_f;
   LedgerDev* led;
   double* partials;
+  double* tpart;
   int* gidx;            // padded indices of the coarse interface nodes
   double* gbuf;         // interface gather/scatter staging
   int n_gamma;
@@ -657,6 +674,9 @@ Job<R> make_job(tl_sim* s, bool fine, const Region& rg, double tau,
   j.Tt = fine ? &s->ftrial : &s->ctrial;
   j.Rout = fine ? s->fR : s->cR;
   j.partials = s->partials;
+  j.tpart = s->tpart;
+  j.Hold = fine ? s->fHold : s->cHold;
+  j.tstride = s->lay.tstride;
   j.last_cg = fine ? &s->last_cg_f : &s->last_cg_c;
   j.n_newton = fine ? &s->stats.newton_fine : &s->stats.newton_coarse;
   j.n_cg = fine ? &s->stats.cg_fine : &s->stats.cg_coarse;
@@ -1252,9 +1272,11 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
                           {(double*)A(10), (double*)A(11)}};
   };
   s->ccg = cgb64([&](int a) { return (void*)C(10 + a); });
+  s->cHold = C(22);
   auto FD = [&](int a) { return (double*)(s->ws + lay.off_fd[a]); };
   s->fstate = FD(0); s->fprev = FD(1); s->fcur = FD(2); s->ftrial = FD(3);
   s->falt = FD(4); s->fR = FD(5); s->fF = FD(6); s->rho = FD(7);
+  s->fHold = FD(8);
   auto FC = [&](int a) { return (void*)(s->ws + lay.off_fcg[a]); };
   s->fcg64 = cgb64(FC);
   s->fcg32 = CGBufs<float>{(float*)FC(0), (float*)FC(1), (float*)FC(2),
@@ -1266,6 +1288,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->sc_f = s->sc_c + 1;
   s->led = (LedgerDev*)(s->ws + lay.off_ledger);
   s->partials = (double*)(s->ws + lay.off_partials);
+  s->tpart = (double*)(s->ws + lay.off_tpart);
   s->gidx = (int*)(s->ws + lay.off_gidx);
   s->gbuf = (double*)(s->ws + lay.off_gbuf);
   if (hipHostMalloc((void**)&s->h_sc, 2 * sizeof(LevelScalars), hipHostMallocDefault) !=
