@@ -234,10 +234,9 @@ void k_copy(Launch L, double* dst, const double* src, long n) {
 // k8 along one axis (edges), two axes (faces) and all three (centre).  This
 // takes 19 additions and 35 multiply-adds per node instead of 72, and uses
 // each neighbour value once.
-template <class R>
-__device__ inline R stencil_apply(const R (&v27)[27], const R (&k8)[8],
-                                  const R (&w)[8]) {
-  auto V = [&](int dx, int dy, int dz) { return v27[N27(dx, dy, dz)]; };
+// V(dx, dy, dz) supplies the neighbour values.
+template <class R, class VF>
+__device__ inline R stencil_grouped(VF V, const R (&k8)[8], const R (&w)[8]) {
   auto I = [](int dd) { return dd < 0 ? 1 : 0; };
   R kz[2][2], ky[2][2], kx[2][2];
 #pragma unroll
@@ -280,14 +279,19 @@ __device__ inline R stencil_apply(const R (&v27)[27], const R (&k8)[8],
   acc += w[7] * s7;
   return acc;
 }
+template <class R>
+__device__ inline R stencil_apply(const R (&v27)[27], const R (&k8)[8],
+                                  const R (&w)[8]) {
+  return stencil_grouped(
+      [&](int dx, int dy, int dz) { return v27[N27(dx, dy, dz)]; }, k8, w);
+}
 
 // The same K v summed element by element (8 x 8 multiply-adds): more
 // arithmetic, but fewer values live at once, which keeps the FP64 z-march
 // kernel at a higher occupancy.
-template <class R>
-__device__ inline R stencil_apply_elementwise(const R (&v27)[27],
-                                              const R (&k8)[8],
-                                              const R (&w)[8]) {
+template <class R, class VF>
+__device__ inline R stencil_elementwise(VF V, const R (&k8)[8],
+                                        const R (&w)[8]) {
   R acc = (R)0;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -296,11 +300,18 @@ __device__ inline R stencil_apply_elementwise(const R (&v27)[27],
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-      s += w[e ^ c] * v27[N27(cx - ex, cy - ey, cz - ez)];
+      s += w[e ^ c] * V(cx - ex, cy - ey, cz - ez);
     }
     acc += k8[e] * s;
   }
   return acc;
+}
+template <class R>
+__device__ inline R stencil_apply_elementwise(const R (&v27)[27],
+                                              const R (&k8)[8],
+                                              const R (&w)[8]) {
+  return stencil_elementwise(
+      [&](int dx, int dy, int dz) { return v27[N27(dx, dy, dz)]; }, k8, w);
 }
 
 template <class R>
@@ -516,8 +527,10 @@ __global__ void __launch_bounds__(kBlock)
 op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
                        const R* __restrict__ kap, const R* __restrict__ v,
                        R* __restrict__ y) {
-  __shared__ R v_s[2][ZHN];
-  __shared__ R k_s[2][ZEN];
+  // LDS planes padded to whole rounds of the workgroup, so that every
+  // thread stores unconditionally
+  __shared__ R v_s[2][ZHPT * kBlock];
+  __shared__ R k_s[2][ZEPT * kBlock];
   const int nunits = zp.ncx * zp.ncy * zp.nrun;
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, nunits);
   R wts[8];
@@ -533,50 +546,57 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
     const int k0 = run * zp.run, k1 = min(g.nz, k0 + zp.run);
     const int i = ox + tx, j = oy + ty;
     const bool col_active = i >= 0 && i < g.nx && j < g.ny;
-    // padded offset within a plane of this thread's halo entries, or -1
-    // past the ghost layer
+    // padded offset within a plane of this thread's halo entries; entries
+    // past the ghost layer (and the padding threads) read offset 0, the
+    // plane's corner ghost, which is zero -- so every load is unconditional
     int voff[ZHPT], koff[ZEPT];
 #pragma unroll
     for (int q = 0; q < ZHPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
       const int ii = ox + h % ZHX - 1, jj = oy + h / ZHX - 1;
       voff[q] = (h >= ZHN || ii < -1 || ii > g.nx || jj > g.ny)
-                    ? -1 : (jj + 1) * g.px + (ii + 1);
+                    ? 0 : (jj + 1) * g.px + (ii + 1);
     }
 #pragma unroll
     for (int q = 0; q < ZEPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
       const int ii = ox + e % ZEX - 1, jj = oy + e / ZEX - 1;
       koff[q] = (e >= ZEN || ii < -1 || ii > g.nx || jj > g.ny)
-                    ? -1 : (jj + 1) * g.px + (ii + 1);
+                    ? 0 : (jj + 1) * g.px + (ii + 1);
     }
+    const int doff = col_active ? (j + 1) * g.px + (i + 1) : 0;
     // node plane / element layer p (-1 <= p <= nz) at padded z offset
-    // (p + 1) * pxy
+    // (p + 1) * pxy; planes past the grid are zero without a load
     auto load_plane = [&](int p, R (&rv)[ZHPT]) {
+      if (p <= g.nz) {
+        const R* __restrict__ pl = v + (long)(p + 1) * g.pxy;
 #pragma unroll
-      for (int q = 0; q < ZHPT; ++q)
-        rv[q] = (voff[q] >= 0 && p >= -1 && p <= g.nz)
-                    ? v[(long)(p + 1) * g.pxy + voff[q]] : (R)0;
+        for (int q = 0; q < ZHPT; ++q) rv[q] = pl[voff[q]];
+      } else {
+#pragma unroll
+        for (int q = 0; q < ZHPT; ++q) rv[q] = (R)0;
+      }
     };
     auto load_layer = [&](int l, R (&rk)[ZEPT]) {
+      if (l <= g.nz) {
+        const R* __restrict__ la = kap + (long)(l + 1) * g.pxy;
 #pragma unroll
-      for (int q = 0; q < ZEPT; ++q)
-        rk[q] = (koff[q] >= 0 && l >= -1 && l <= g.nz)
-                    ? kap[(long)(l + 1) * g.pxy + koff[q]] : (R)0;
+        for (int q = 0; q < ZEPT; ++q) rk[q] = la[koff[q]];
+      } else {
+#pragma unroll
+        for (int q = 0; q < ZEPT; ++q) rk[q] = (R)0;
+      }
+    };
+    auto load_d = [&](int k) {
+      return k < k1 ? d[(long)(k + 1) * g.pxy + doff] : (R)0;
     };
     auto put_plane = [&](int p, const R (&rv)[ZHPT]) {
 #pragma unroll
-      for (int q = 0; q < ZHPT; ++q) {
-        const int h = threadIdx.x + q * kBlock;
-        if (h < ZHN) v_s[(p + 2) & 1][h] = rv[q];
-      }
+      for (int q = 0; q < ZHPT; ++q) v_s[(p + 2) & 1][threadIdx.x + q * kBlock] = rv[q];
     };
     auto put_layer = [&](int l, const R (&rk)[ZEPT]) {
 #pragma unroll
-      for (int q = 0; q < ZEPT; ++q) {
-        const int e = threadIdx.x + q * kBlock;
-        if (e < ZEN) k_s[(l + 2) & 1][e] = rk[q];
-      }
+      for (int q = 0; q < ZEPT; ++q) k_s[(l + 2) & 1][threadIdx.x + q * kBlock] = rk[q];
     };
     // the 9 values of plane p around the node, the 4 conductivities of
     // layer l around it (element (ex, ey) at offset (-ex, -ey))
@@ -594,16 +614,13 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
       for (int e = 0; e < 4; ++e)
         w4[e] = la[(ty + 1 - (e >> 1)) * ZEX + (tx + 1 - (e & 1))];
     };
-    auto load_d = [&](int k) {
-      return (col_active && k < k1)
-                 ? d[(long)(k + 1) * g.pxy + (j + 1) * g.px + (i + 1)] : (R)0;
-    };
-    R vm[9], v0[9], vp[9], km[4], k0v[4];
-    R av[ZHPT], ak[ZEPT];
-    R d0, d1;   // the node's own d at planes k and k+1
-    // prologue: planes k0-1, k0 and layer k0-1 into the window; plane k0+1
-    // and layer k0 into LDS; plane k0+2, layer k0+1 and d at k0, k0+1 into
-    // registers
+    // Register window: planes k-1, k, k+1 (VM, V0, VP) and element layers
+    // k-1, k (KM, K0).  Global loads run two planes ahead: queue slots QA
+    // (node plane k+2, element layer k+1, loaded one step earlier) and QB
+    // (plane k+3, layer k+2, loaded now); the node's own d at k, k+1.
+    R V1[9], V2[9], V3[9], K1[4], K2[4];
+    R Q1[ZHPT], Q1k[ZEPT], Q2[ZHPT], Q2k[ZEPT];
+    R dq0, dq1;
     {
       R a[ZHPT], b[ZHPT], c[ZHPT], ka[ZEPT], kb[ZEPT];
       load_plane(k0 - 1, a);
@@ -611,71 +628,84 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
       load_layer(k0 - 1, ka);
       load_plane(k0 + 1, c);
       load_layer(k0, kb);
-      d0 = load_d(k0);
-      d1 = load_d(k0 + 1);
-      load_plane(k0 + 2, av);
-      load_layer(k0 + 1, ak);
+      dq0 = load_d(k0);
+      dq1 = load_d(k0 + 1);
+      load_plane(k0 + 2, Q1);
+      load_layer(k0 + 1, Q1k);
       put_plane(k0 - 1, a);
       put_plane(k0, b);
       put_layer(k0 - 1, ka);
       __syncthreads();
-      get_plane(k0 - 1, vm);
-      get_plane(k0, v0);
-      get_layer(k0 - 1, km);
+      get_plane(k0 - 1, V1);
+      get_plane(k0, V2);
+      get_layer(k0 - 1, K1);
       __syncthreads();
       put_plane(k0 + 1, c);
       put_layer(k0, kb);
       __syncthreads();
     }
-    for (int k = k0; k < k1; ++k) {
-      // every global input runs two planes ahead of the stencil: d of plane
-      // k+2, node plane k+3 and element layer k+2 are loaded now, while
-      // plane k is computed from values loaded in earlier steps (memory
-      // counters complete in issue order, so nothing loaded in this step is
-      // waited for before the next one)
-      const R d2 = load_d(k + 2);
-      R bv[ZHPT], bk[ZEPT];
-      load_plane(k + 3, bv);
-      load_layer(k + 2, bk);
-      get_plane(k + 1, vp);
-      get_layer(k, k0v);
+    // One plane.  The register roles rotate between calls instead of being
+    // copied: the window by three (VM, V0, VP -> V0, VP, VM), the element
+    // layers and the load queue by two.
+    auto step = [&](int k, R (&VM)[9], R (&V0)[9], R (&VP)[9], R (&KM)[4],
+                    R (&K0)[4], R (&QA)[ZHPT], R (&QAk)[ZEPT], R (&QB)[ZHPT],
+                    R (&QBk)[ZEPT]) {
+      // steps are not interleaved by the scheduler (that would only raise
+      // the register count); nothing loaded here is waited for before the
+      // next step (memory counters complete in issue order)
+      __builtin_amdgcn_sched_barrier(0);
+      const R dn = load_d(k + 2);
+      load_plane(k + 3, QB);
+      load_layer(k + 2, QBk);
+      get_plane(k + 1, VP);
+      get_layer(k, K0);
       if (col_active) {
-        R u27[27], k8[8];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          u27[q] = vm[q];
-          u27[9 + q] = v0[q];
-          u27[18 + q] = vp[q];
-        }
+        R k8[8];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          k8[e] = k0v[e];
-          k8[4 + e] = km[e];
+          k8[e] = K0[e];
+          k8[4 + e] = KM[e];
         }
-        const long n = (long)(k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+        auto V = [&](int dx, int dy, int dz) {
+          const int q = (dx + 1) + 3 * (dy + 1);
+          return dz < 0 ? VM[q] : (dz == 0 ? V0[q] : VP[q]);
+        };
+        R yn;
         if constexpr (sizeof(R) == 8)
-          y[n] = d0 * u27[13] + stencil_apply_elementwise(u27, k8, wts);
+          yn = dq0 * V0[4] + stencil_elementwise(V, k8, wts);
         else
-          y[n] = d0 * u27[13] + stencil_apply(u27, k8, wts);
+          yn = dq0 * V0[4] + stencil_grouped(V, k8, wts);
+        y[(long)(k + 1) * g.pxy + doff] = yn;
       }
       // plane k+2 replaces plane k, layer k+1 replaces layer k-1: both were
       // last read before the previous barrier
-      put_plane(k + 2, av);
-      put_layer(k + 1, ak);
+      put_plane(k + 2, QA);
+      put_layer(k + 1, QAk);
       __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        vm[q] = v0[q];
-        v0[q] = vp[q];
+      dq0 = dq1;
+      dq1 = dn;
+    };
+    int k = k0;
+    for (; k + 6 <= k1; k += 6) {
+      step(k, V1, V2, V3, K1, K2, Q1, Q1k, Q2, Q2k);
+      step(k + 1, V2, V3, V1, K2, K1, Q2, Q2k, Q1, Q1k);
+      step(k + 2, V3, V1, V2, K1, K2, Q1, Q1k, Q2, Q2k);
+      step(k + 3, V1, V2, V3, K2, K1, Q2, Q2k, Q1, Q1k);
+      step(k + 4, V2, V3, V1, K1, K2, Q1, Q1k, Q2, Q2k);
+      step(k + 5, V3, V1, V2, K2, K1, Q2, Q2k, Q1, Q1k);
+    }
+    if (k < k1) {
+      step(k, V1, V2, V3, K1, K2, Q1, Q1k, Q2, Q2k);
+      if (k + 1 < k1) {
+        step(k + 1, V2, V3, V1, K2, K1, Q2, Q2k, Q1, Q1k);
+        if (k + 2 < k1) {
+          step(k + 2, V3, V1, V2, K1, K2, Q1, Q1k, Q2, Q2k);
+          if (k + 3 < k1) {
+            step(k + 3, V1, V2, V3, K2, K1, Q2, Q2k, Q1, Q1k);
+            if (k + 4 < k1) step(k + 4, V2, V3, V1, K1, K2, Q1, Q1k, Q2, Q2k);
+          }
+        }
       }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) km[e] = k0v[e];
-#pragma unroll
-      for (int q = 0; q < ZHPT; ++q) av[q] = bv[q];
-#pragma unroll
-      for (int q = 0; q < ZEPT; ++q) ak[q] = bk[q];
-      d0 = d1;
-      d1 = d2;
     }
     __syncthreads();  // LDS is reused by the next work unit
   }
