@@ -153,7 +153,9 @@ def _check(gpu, ref, tol):
     rhs = led["absorbed"] - led["bottom"] + led["remap"]
     assert abs(lhs - rhs) <= 1e-8 * abs(led["absorbed"])
     assert led["absorbed"] == pytest.approx(orc.ledger["absorbed"], rel=1e-12)
-    assert led["stored"] == pytest.approx(orc.ledger["stored"], rel=1e-9)
+    # the stored energy is a mass-weighted sum of H(T), so it carries the
+    # temperature bar of the path
+    assert led["stored"] == pytest.approx(orc.ledger["stored"], rel=max(tol, 1e-9))
     assert st["window_moves"] == orc.stats["moves"]
 
 
