@@ -173,9 +173,13 @@ tl_status tl_get_stats(tl_sim* sim, tl_stats* out);
 tl_status tl_get_time(tl_sim* sim, double* t, int64_t* n_macro);
 
 /* Checkpoint: serialise the committed state (coarse and fine temperatures,
- * window origin, step counter, ledger, stats) into host memory; *used receives
- * the byte count (call with host = NULL to query).  tl_load restores a buffer
- * written by tl_save for a handle created with the same mesh and options. */
+ * window origin, step counter, ledger, stats) and the solver history later
+ * steps depend on (two-level quasi-Newton secant pairs, CG budgets) into
+ * host memory, so that a restored run continues exactly as the saved one;
+ * *used receives the byte count (call with host = NULL to query; the count
+ * changes as the history grows).  tl_load restores a buffer written by
+ * tl_save for a handle created with the same mesh and options; a buffer of
+ * another format or grid returns TL_EINVAL. */
 tl_status tl_save(tl_sim* sim, void* host, size_t cap, size_t* used);
 tl_status tl_load(tl_sim* sim, const void* host, size_t n);
 

@@ -368,6 +368,106 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
   }
 }
 
+// Interface quasi-Newton (IQN-ILS) for the two-level iteration: lambda is
+// the coarse interface trace, g(lambda) the coarse solution there after the
+// fine and outside solves, r = g - lambda.  Secant pairs (differences of r
+// and of g between iterations) approximate the inverse Jacobian of r by
+// least squares.  The pairs are kept across macro steps while the interface
+// keeps its nodes (the problem changes little from one step to the next),
+// so a step's first update is already a quasi-Newton one; the oldest pairs
+// drop out beyond kMaxCols, and a window move or a restored state clears
+// them.
+struct Interface {
+  std::vector<std::vector<double>> V, W;
+  std::vector<double> r_prev, g_prev;
+  bool has_prev = false;
+  static constexpr int kMaxCols = 24;
+
+  void clear() {
+    V.clear();
+    W.clear();
+    has_prev = false;
+  }
+  // a new macro step: the last iterate of the previous step is no partner
+  // for a new secant pair
+  void begin_step() { has_prev = false; }
+
+  void update(const std::vector<double>& lam, const std::vector<double>& g,
+              double theta0, bool fixed, std::vector<double>& next) {
+    const size_t n = lam.size();
+    std::vector<double> r(n);
+    for (size_t q = 0; q < n; ++q) r[q] = g[q] - lam[q];
+    next.assign(n, 0.0);
+    if (!fixed && has_prev) {
+      std::vector<double> dv(n), dw(n);
+      for (size_t q = 0; q < n; ++q) {
+        dv[q] = r[q] - r_prev[q];
+        dw[q] = g[q] - g_prev[q];
+      }
+      V.push_back(dv);
+      W.push_back(dw);
+      if ((int)V.size() > kMaxCols) {
+        V.erase(V.begin());
+        W.erase(W.begin());
+      }
+    }
+    if (fixed || V.empty() || (V[0].size() != n)) {
+      if (!V.empty() && V[0].size() != n) clear();
+      for (size_t q = 0; q < n; ++q) next[q] = lam[q] + theta0 * r[q];
+    } else {
+      // least squares by modified Gram-Schmidt, newest column first; columns
+      // that are (numerically) dependent on newer ones are skipped
+      const int m = (int)V.size();
+      std::vector<std::vector<double>> Q;
+      std::vector<int> cols;
+      std::vector<std::vector<double>> Rm;  // upper triangle, row per kept col
+      for (int c = m - 1; c >= 0; --c) {
+        std::vector<double> v = V[c];
+        double n0 = 0.0;
+        for (double x : v) n0 += x * x;
+        n0 = std::sqrt(n0);
+        std::vector<double> rc(Q.size() + 1, 0.0);
+        for (size_t a = 0; a < Q.size(); ++a) {
+          double d = 0.0;
+          for (size_t q = 0; q < n; ++q) d += Q[a][q] * v[q];
+          rc[a] = d;
+          for (size_t q = 0; q < n; ++q) v[q] -= d * Q[a][q];
+        }
+        double nv = 0.0;
+        for (double x : v) nv += x * x;
+        nv = std::sqrt(nv);
+        if (!(nv > 1e-10 * n0) || n0 == 0.0) continue;
+        for (double& x : v) x /= nv;
+        rc[Q.size()] = nv;
+        Q.push_back(v);
+        Rm.push_back(rc);
+        cols.push_back(c);
+      }
+      const int k = (int)Q.size();
+      // solve R c = -Q^T r (R upper triangular in the kept-column order)
+      std::vector<double> rhs(k), cvec(k, 0.0);
+      for (int a = 0; a < k; ++a) {
+        double d = 0.0;
+        for (size_t q = 0; q < n; ++q) d += Q[a][q] * r[q];
+        rhs[a] = -d;
+      }
+      for (int a = k - 1; a >= 0; --a) {
+        double v = rhs[a];
+        for (int b = a + 1; b < k; ++b) v -= Rm[b][a] * cvec[b];
+        cvec[a] = v / Rm[a][a];
+      }
+      for (size_t q = 0; q < n; ++q) next[q] = g[q];
+      for (int a = 0; a < k; ++a) {
+        const std::vector<double>& wc = W[cols[a]];
+        for (size_t q = 0; q < n; ++q) next[q] += cvec[a] * wc[q];
+      }
+    }
+    r_prev = r;
+    g_prev = g;
+    has_prev = true;
+  }
+};
+
 }  // namespace
 
 struct tl_sim {
@@ -377,6 +477,7 @@ struct tl_sim {
   MatDev mat;
   std::vector<TrackH> tracks;
   double t_start;
+  Interface iqn;   // two-level secant pairs, kept across macro steps
   Layout lay;
   Geo gc, gf;
   Window win;
@@ -478,6 +579,7 @@ double fine_free_nodes(const Geo& gf, const Window& w) {
 
 void set_interface(tl_sim* s) {
   const Window& w = s->win;
+  s->iqn.clear();   // secant pairs belong to the previous interface
   std::vector<int> idx;
   for (int k = w.K0; k <= w.K0 + w.wz; ++k)
     for (int j = w.J0; j <= w.J0 + w.wy; ++j)
@@ -559,84 +661,6 @@ void write_ledger(tl_sim* s) {
 //   c = argmin |V c + r_k|_2,   lambda_{k+1} = G(lambda_k) + W c.
 // The fixed point -- and so the result -- is the same for every relaxation;
 // only the number of iterations differs.
-struct Interface {
-  std::vector<std::vector<double>> V, W;
-  std::vector<double> r_prev, g_prev;
-  bool has_prev = false;
-  static constexpr int kMaxCols = 24;
-
-  void update(const std::vector<double>& lam, const std::vector<double>& g,
-              double theta0, bool fixed, std::vector<double>& next) {
-    const size_t n = lam.size();
-    std::vector<double> r(n);
-    for (size_t q = 0; q < n; ++q) r[q] = g[q] - lam[q];
-    next.assign(n, 0.0);
-    if (fixed || !has_prev) {
-      for (size_t q = 0; q < n; ++q) next[q] = lam[q] + theta0 * r[q];
-    } else {
-      std::vector<double> dv(n), dw(n);
-      for (size_t q = 0; q < n; ++q) {
-        dv[q] = r[q] - r_prev[q];
-        dw[q] = g[q] - g_prev[q];
-      }
-      V.push_back(dv);
-      W.push_back(dw);
-      if ((int)V.size() > kMaxCols) {
-        V.erase(V.begin());
-        W.erase(W.begin());
-      }
-      // least squares by modified Gram-Schmidt, newest column first; columns
-      // that are (numerically) dependent on newer ones are skipped
-      const int m = (int)V.size();
-      std::vector<std::vector<double>> Q;
-      std::vector<int> cols;
-      std::vector<std::vector<double>> Rm;  // upper triangle, row per kept col
-      for (int c = m - 1; c >= 0; --c) {
-        std::vector<double> v = V[c];
-        double n0 = 0.0;
-        for (double x : v) n0 += x * x;
-        n0 = std::sqrt(n0);
-        std::vector<double> rc(Q.size() + 1, 0.0);
-        for (size_t a = 0; a < Q.size(); ++a) {
-          double d = 0.0;
-          for (size_t q = 0; q < n; ++q) d += Q[a][q] * v[q];
-          rc[a] = d;
-          for (size_t q = 0; q < n; ++q) v[q] -= d * Q[a][q];
-        }
-        double nv = 0.0;
-        for (double x : v) nv += x * x;
-        nv = std::sqrt(nv);
-        if (!(nv > 1e-10 * n0) || n0 == 0.0) continue;
-        for (double& x : v) x /= nv;
-        rc[Q.size()] = nv;
-        Q.push_back(v);
-        Rm.push_back(rc);
-        cols.push_back(c);
-      }
-      const int k = (int)Q.size();
-      // solve R c = -Q^T r (R upper triangular in the kept-column order)
-      std::vector<double> rhs(k), cvec(k, 0.0);
-      for (int a = 0; a < k; ++a) {
-        double d = 0.0;
-        for (size_t q = 0; q < n; ++q) d += Q[a][q] * r[q];
-        rhs[a] = -d;
-      }
-      for (int a = k - 1; a >= 0; --a) {
-        double v = rhs[a];
-        for (int b = a + 1; b < k; ++b) v -= Rm[b][a] * cvec[b];
-        cvec[a] = v / Rm[a][a];
-      }
-      for (size_t q = 0; q < n; ++q) next[q] = g[q];
-      for (int a = 0; a < k; ++a) {
-        const std::vector<double>& wc = W[cols[a]];
-        for (size_t q = 0; q < n; ++q) next[q] += cvec[a] * wc[q];
-      }
-    }
-    r_prev = r;
-    g_prev = g;
-    has_prev = true;
-  }
-};
 
 // Per-simulation state of one macro step run in lockstep with others.
 struct StepState {
@@ -648,7 +672,6 @@ struct StepState {
   long n = 0;
   bool dn_done = false;
   int it = 0;
-  Interface iqn;
   std::vector<double> lam_v, lt_v, next;
 };
 
@@ -780,6 +803,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     st.dt = st.Dt / st.m;
     st.n = s->n_macro;
     st.dn_done = false;
+    s->iqn.begin_step();
     st.it = 0;
   }
   // 1. window placement for the beam at t_{n+1}; 2. coarse loads
@@ -953,7 +977,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
         st->dn_done = true;
         continue;
       }
-      st->iqn.update(st->lam_v, st->lt_v, s->theta0, s->opts.dn_theta > 0.0,
+      s->iqn.update(st->lam_v, st->lt_v, s->theta0, s->opts.dn_theta > 0.0,
                      st->next);
       for (int q = 0; q < ng; ++q) s->h_gbuf[q] = st->next[q];
       hip_check(hipMemcpyAsync(s->gbuf, s->h_gbuf, sizeof(double) * ng,
@@ -1434,32 +1458,47 @@ tl_status tl_get_time(tl_sim* s, double* t, int64_t* n) {
 }
 
 namespace {
+// Checkpoint: header, coarse and fine fields (plain layout), then the
+// solver history that later steps depend on -- the two-level secant pairs
+// (ncols columns of V, then of W, n_gamma values each) -- so that a restored
+// run continues exactly as the saved one would have.
 struct CkptHeader {
   char magic[8];
   int32_t version;
   int32_t I0, J0;
   int32_t gc_n, gf_n;
+  int32_t n_gamma, ncols;
+  int32_t last_cg_f, last_cg_c;
   int64_t n_macro;
   tl_ledger ledger;
   tl_stats stats;
 };
+size_t ckpt_bytes(const tl_sim* s) {
+  const size_t ng = s->iqn.V.empty() ? 0 : s->iqn.V[0].size();
+  return sizeof(CkptHeader) +
+         ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double) +
+         2 * s->iqn.V.size() * ng * sizeof(double);
+}
 }  // namespace
 
 tl_status tl_save(tl_sim* s, void* host, size_t cap, size_t* used) {
   if (!s || !used) return fail(TL_EINVAL, "null argument");
-  const size_t need = sizeof(CkptHeader) +
-                      ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double);
+  const size_t need = ckpt_bytes(s);
   *used = need;
   if (!host) return TL_OK;
   if (cap < need) return fail(TL_ENOMEM, "checkpoint buffer too small");
   CkptHeader h;
   std::memset(&h, 0, sizeof(h));
-  std::memcpy(h.magic, "TLCKPT1", 8);
-  h.version = 1;
+  std::memcpy(h.magic, "TLCKPT2", 8);
+  h.version = 2;
   h.I0 = s->win.I0;
   h.J0 = s->win.J0;
   h.gc_n = s->gc.nreal;
   h.gf_n = s->gf.nreal;
+  h.ncols = (int32_t)s->iqn.V.size();
+  h.n_gamma = h.ncols ? (int32_t)s->iqn.V[0].size() : 0;
+  h.last_cg_f = s->last_cg_f;
+  h.last_cg_c = s->last_cg_c;
   h.n_macro = s->n_macro;
   h.ledger = s->ledger;
   h.stats = s->stats;
@@ -1469,9 +1508,15 @@ tl_status tl_save(tl_sim* s, void* host, size_t cap, size_t* used) {
   tl_status st = tl_get_temperature(s, 0, (double*)(p + sizeof(h)),
                                     (size_t)s->gc.nreal, dims, nullptr);
   if (st != TL_OK) return st;
-  return tl_get_temperature(
+  st = tl_get_temperature(
       s, 1, (double*)(p + sizeof(h) + (size_t)s->gc.nreal * sizeof(double)),
       (size_t)s->gf.nreal, dims, nullptr);
+  if (st != TL_OK) return st;
+  char* q = p + sizeof(h) + ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double);
+  const size_t col = (size_t)h.n_gamma * sizeof(double);
+  for (const auto& v : s->iqn.V) { std::memcpy(q, v.data(), col); q += col; }
+  for (const auto& w : s->iqn.W) { std::memcpy(q, w.data(), col); q += col; }
+  return TL_OK;
 }
 
 tl_status tl_load(tl_sim* s, const void* host, size_t n) {
@@ -1479,12 +1524,16 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
   if (n < sizeof(CkptHeader)) return fail(TL_EINVAL, "checkpoint too short");
   CkptHeader h;
   std::memcpy(&h, host, sizeof(h));
-  if (std::memcmp(h.magic, "TLCKPT1", 8) != 0 || h.version != 1)
+  if (std::memcmp(h.magic, "TLCKPT2", 8) != 0 || h.version != 2)
     return fail(TL_EINVAL, "not a checkpoint of this library");
   if (h.gc_n != s->gc.nreal || h.gf_n != s->gf.nreal)
     return fail(TL_EINVAL, "checkpoint grid sizes differ from this handle");
+  if (h.ncols < 0 || h.ncols > Interface::kMaxCols || h.n_gamma < 0 ||
+      (h.ncols > 0 && h.n_gamma == 0))
+    return fail(TL_EINVAL, "checkpoint interface history is malformed");
   const size_t need = sizeof(CkptHeader) +
-                      ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double);
+                      ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double) +
+                      2 * (size_t)h.ncols * h.n_gamma * sizeof(double);
   if (n < need) return fail(TL_EINVAL, "checkpoint truncated");
   if (h.I0 < 0 || h.J0 < 0 || h.I0 + s->mesh.win_nx > s->mesh.nx ||
       h.J0 + s->mesh.win_ny > s->mesh.ny)
@@ -1506,6 +1555,14 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
     s->n_macro = h.n_macro;
     s->ledger = h.ledger;
     s->stats = h.stats;
+    s->last_cg_f = h.last_cg_f;
+    s->last_cg_c = h.last_cg_c;
+    // the secant pairs (set_interface above cleared the old ones)
+    const double* q = (const double*)(p + ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double));
+    for (int c = 0; c < h.ncols; ++c, q += h.n_gamma)
+      s->iqn.V.emplace_back(q, q + h.n_gamma);
+    for (int c = 0; c < h.ncols; ++c, q += h.n_gamma)
+      s->iqn.W.emplace_back(q, q + h.n_gamma);
     write_ledger(s);
   } catch (const DevErr& e) {
     return fail(TL_EDEVICE, e.msg);
