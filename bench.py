@@ -126,6 +126,25 @@ def k2_sweep(tl, W, torch):
                         "us_per_launch": round(us, 3), "GB/s": round(gbs, 1),
                         "frac": round(gbs / HBM_PEAK_GBS, 4)})
             del d, kap, v, y
+    # the practical HBM ceiling for reference: a device-to-device copy of
+    # 1 GiB (read + write bytes over the time) and a read-only reduction
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").uniform_(generator=g)
+    dst = torch.empty_like(src)
+    for kind in ("copy", "sum"):
+        for _ in range(2):
+            dst.copy_(src) if kind == "copy" else src.sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src) if kind == "copy" else src.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 10
+        nbytes = (2 if kind == "copy" else 1) * src.numel() * 4
+        out.append({"shape": f"torch {kind}, 1 GiB fp32", "dtype": "f32",
+                    "us_per_launch": round(us, 3), "GB/s": round(nbytes / (us * 1e-6) / 1e9, 1),
+                    "frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
+    del src, dst
     return out
 
 
