@@ -38,10 +38,12 @@ class NoConvergence(RuntimeError):
 LINE_SEARCH_MAX = 12
 
 
-def residual(grid, mat, T, T_old, tau, load, elem_mask, mass):
+def residual(grid, mat, T, T_old, tau, load, elem_mask, mass, surface=None):
     kap = M.conductivity(G.element_mean(grid, T), mat) * elem_mask
     K = G.stiffness(grid, kap)
     R = mass * (M.enthalpy(T, mat) - M.enthalpy(T_old, mat)) / tau + K @ T - load
+    if surface is not None and surface.active:
+        R = R + surface.term(T)
     return R, K
 
 
@@ -63,10 +65,11 @@ def solve_spd(A, b):
 
 def implicit_step(grid, mat, T_old, tau, load, elem_mask=None,
                   dirichlet=None, dirichlet_values=None, T_guess=None,
-                  tol=1e-10, maxit=30):
+                  tol=1e-10, maxit=30, surface=None):
     """Backward-Euler step of one level.  Returns (T, R, iterations) with R
     the residual at the converged T (reactions on Dirichlet rows, ~0 on free
-    rows)."""
+    rows).  `surface` (oracle.surface.Surface) adds the top-surface heat
+    loss A q(T) to the residual and A q'(T) to the Jacobian diagonal."""
     if elem_mask is None:
         elem_mask = np.ones(grid.n_elems)
     elem_mask = np.asarray(elem_mask, dtype=np.float64)
@@ -77,9 +80,12 @@ def implicit_step(grid, mat, T_old, tau, load, elem_mask=None,
     if dirichlet_values is not None:
         T[dirichlet] = np.asarray(dirichlet_values)[dirichlet]
     free = np.flatnonzero(~dirichlet)
-    R, K = residual(grid, mat, T, T_old, tau, load, elem_mask, mass)
+    R, K = residual(grid, mat, T, T_old, tau, load, elem_mask, mass, surface)
     for it in range(1, maxit + 1):
-        J = K + sp.diags(mass * M.enthalpy_slope(T, mat) / tau)
+        diag = mass * M.enthalpy_slope(T, mat) / tau
+        if surface is not None and surface.active:
+            diag = diag + surface.slope(T)
+        J = K + sp.diags(diag)
         Jff = J[free][:, free]
         delta = solve_spd(Jff.tocsr(), R[free])
         if not np.all(np.isfinite(delta)):
@@ -91,7 +97,8 @@ def implicit_step(grid, mat, T_old, tau, load, elem_mask=None,
             alpha = 0.5 ** h
             T_try = T.copy()
             T_try[free] -= alpha * delta
-            R_try, K_try = residual(grid, mat, T_try, T_old, tau, load, elem_mask, mass)
+            R_try, K_try = residual(grid, mat, T_try, T_old, tau, load, elem_mask, mass,
+                                    surface)
             if (np.linalg.norm(R_try[free]) <= (1.0 - 1e-4 * alpha) * r0
                     or alpha * dmax <= tol):
                 break

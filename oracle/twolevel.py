@@ -45,6 +45,11 @@ Readings adopted where the paper is silent, ambiguous or garbled:
     plate; kept in place while the beam is off.
   * Coarse load: the time average of the surface loads at the m micro times
     (the intent of the paper's smeared global source, Section 5.2).
+  * Top-surface heat loss (Section 2): convection and radiation on the fine
+    level's top faces, convection only on the coarse level's (the window's
+    faces excluded in the outside solve); lumped over the faces' corners
+    (oracle.surface).  The ledger then reads
+    E_{n+1} - E_n = absorbed - bottom - surface + remap.
 """
 import math
 
@@ -54,6 +59,7 @@ import scipy.sparse as sp
 from . import grid as G
 from . import laser as L
 from . import material as M
+from . import surface as S
 from .level import implicit_step, NoConvergence
 
 
@@ -105,6 +111,10 @@ class Window:
                               & (fj2 >= J0) & (fj2 < J0 + self.wy))
         self.mass_out = G.lumped_mass(c, self.outside_e)
         self.mass_f = G.lumped_mass(f)
+        # lumped top-surface areas: every fine top face; coarse top faces
+        # outside the window
+        self.area_f = S.top_area(f)
+        self.area_out = S.top_area(c, self.outside_face)
         # injection: coarse window-interior node -> fine node at its position
         idx = np.flatnonzero(self.interior_c)
         self.inject_c = idx
@@ -201,8 +211,9 @@ class TwoLevel:
         self.win = Window(c, mesh, *origin)
         self.Tf = np.full(self.win.fine.n_nodes, mat.T_init)
         self.Tf[self.win.bottom_f] = mat.T_bottom
+        self.area_c = S.top_area(c)
         self.ledger = dict(stored=self.energy(), absorbed=0.0, bottom=0.0, remap=0.0,
-                           stored0=0.0)
+                           surface=0.0, stored0=0.0)
         self.ledger["stored0"] = self.ledger["stored"]
         self.stats = dict(newton_fine=0, newton_coarse=0, dn_iters=0, moves=0,
                           fine_solves=0, coarse_solves=0)
@@ -245,12 +256,22 @@ class TwoLevel:
             return theta
         return -theta * float(d_prev @ dd) / den
 
+    # -- top-surface loss of each level --------------------------------------
+    def surf_fine(self):
+        m = self.mat
+        return S.Surface(self.win.area_f, m.h_conv, m.emissivity, m.T_amb)
+
+    def surf_coarse(self, area):
+        m = self.mat
+        return S.Surface(area, m.h_conv, 0.0, m.T_amb)
+
     # -- one macro step (Algorithm 1) ----------------------------------------
     def fine_step(self, T_prev, tau, load, g, guess=None):
         w = self.win
         vals = np.where(w.bottom_f, self.mat.T_bottom, g)
         T, R, it = implicit_step(w.fine, self.mat, T_prev, tau, load, None, w.dir_f, vals,
-                                 T_guess=guess, tol=self.newton_tol, maxit=self.opts.newton_max)
+                                 T_guess=guess, tol=self.newton_tol, maxit=self.opts.newton_max,
+                                 surface=self.surf_fine())
         self.stats["newton_fine"] += it
         self.stats["fine_solves"] += 1
         return T, R
@@ -274,7 +295,7 @@ class TwoLevel:
         # predictor over the whole plate
         Tpred, _, it = implicit_step(c, mat, self.Tc, Dt, Fc_all, None, self.bottom_c,
                                      np.full(c.n_nodes, mat.T_bottom), tol=self.newton_tol,
-                                     maxit=opts.newton_max)
+                                     maxit=opts.newton_max, surface=self.surf_coarse(self.area_c))
         self.stats["newton_coarse"] += it
         self.stats["coarse_solves"] += 1
         PTn = w.P @ self.Tc
@@ -283,6 +304,8 @@ class TwoLevel:
         rho_sum = np.zeros(w.fine.n_nodes)
         absorbed = 0.0
         bottom = 0.0
+        surface = 0.0
+        sf = self.surf_fine()
         for j in range(1, m):
             g = (1.0 - j / m) * PTn + (j / m) * PTp
             Ff = L.top_load(w.fine, spots[j - 1], opts.face_quad)
@@ -290,6 +313,7 @@ class TwoLevel:
             rho_sum[w.gamma_f] += R[w.gamma_f]
             bottom -= dt * R[w.bottom_f].sum()
             absorbed += dt * Ff.sum()
+            surface += dt * sf.loss(T_prev)
         # two-level correction at t_{n+1}
         Ff = L.top_load(w.fine, spots[m - 1], opts.face_quad)
         lam = Tpred.copy()
@@ -304,7 +328,8 @@ class TwoLevel:
             vals[w.inject_c] = Tf_m[w.inject_f]
             Tc_new, Rc, itc = implicit_step(c, mat, self.Tc, Dt, Fc_out + ext, w.outside_e,
                                             dir_c, vals, T_guess=guess_c, tol=self.newton_tol,
-                                            maxit=opts.newton_max)
+                                            maxit=opts.newton_max,
+                                            surface=self.surf_coarse(w.area_out))
             self.stats["newton_coarse"] += itc
             self.stats["coarse_solves"] += 1
             d = np.where(w.gamma_c, Tc_new - lam, 0.0)
@@ -320,8 +345,10 @@ class TwoLevel:
         self.stats["dn_iters"] += it
         bottom -= dt * R_m[w.bottom_f].sum()
         absorbed += dt * Ff.sum()
+        surface += dt * sf.loss(Tf_m)
         bottom -= Dt * Rc[self.bottom_c].sum()
         absorbed += Dt * Fc_out.sum()
+        surface += Dt * self.surf_coarse(w.area_out).loss(Tc_new)
         self.Tc = Tc_new
         self.Tf = Tf_m
         self.n += 1
@@ -329,8 +356,10 @@ class TwoLevel:
         self.ledger["stored"] = E_end
         self.ledger["absorbed"] += absorbed
         self.ledger["bottom"] += bottom
+        self.ledger["surface"] += surface
         self.history.append(dict(n=self.n, E_start=E_start, E_end=E_end, absorbed=absorbed,
-                                 bottom=bottom, dn_iters=it, origin=(w.I0, w.J0)))
+                                 bottom=bottom, surface=surface, dn_iters=it,
+                                 origin=(w.I0, w.J0)))
 
     def run(self, n_macro):
         for _ in range(n_macro):
@@ -348,10 +377,14 @@ def run(wl, n_macro=None, **kw):
     return sim
 
 
-def single_level_run(grid, mat, scan, dt, n_steps, t_start=None, nq=3, tol=1e-10, T0=None):
+def single_level_run(grid, mat, scan, dt, n_steps, t_start=None, nq=3, tol=1e-10, T0=None,
+                     radiation=False):
     """Plain backward-Euler run of one level over all elements with Dirichlet
-    T_bottom at z = z0 and the surface load at each new time level.  Returns
-    the list of nodal fields after every step."""
+    T_bottom at z = z0 and the surface load at each new time level; the top
+    surface loses heat by convection (and radiation when `radiation`) as the
+    material says.  Returns the list of nodal fields after every step."""
+    surf = S.Surface(S.top_area(grid), mat.h_conv, mat.emissivity if radiation else 0.0,
+                     mat.T_amb)
     _, _, k = grid.node_ijk()
     bottom = k == 0
     T = np.full(grid.n_nodes, mat.T_init) if T0 is None else np.array(T0, dtype=np.float64)
@@ -361,6 +394,6 @@ def single_level_run(grid, mat, scan, dt, n_steps, t_start=None, nq=3, tol=1e-10
     for s in range(1, n_steps + 1):
         F = L.top_load(grid, L.laser_at(scan, t0 + s * dt), nq)
         T, _, _ = implicit_step(grid, mat, T, dt, F, None, bottom,
-                                np.full(grid.n_nodes, mat.T_bottom), tol=tol)
+                                np.full(grid.n_nodes, mat.T_bottom), tol=tol, surface=surf)
         out.append(T.copy())
     return out

@@ -25,7 +25,7 @@ def _ledger_errors(sim):
     out = []
     for h in sim.history:
         lhs = h["E_end"] - h["E_start"]
-        rhs = h["absorbed"] - h["bottom"]
+        rhs = h["absorbed"] - h["bottom"] - h["surface"]
         out.append(abs(lhs - rhs) / h["absorbed"])
     return out
 

@@ -27,7 +27,10 @@ class Mesh:
 class Material:
     """rho [kg/m3]; c(T) and kappa(T) linear on [T_lo, T_hi], constant
     outside; latent heat [J/kg] released by a tanh sigmoid of the given
-    sharpness [1/K] centred between T_sol and T_liq; temperatures in K."""
+    sharpness [1/K] centred between T_sol and T_liq; temperatures in K.
+    Top-surface heat loss: convection h_conv [W/m2/K] to T_amb on both
+    levels, radiation of emissivity `emissivity` on the fine level only (the
+    paper's boundary conditions); zero (adiabatic top) by default."""
     rho: float = 8000.0
     T_lo: float = 300.0
     T_hi: float = 1563.0
@@ -42,6 +45,9 @@ class Material:
     pc_kind: int = 0
     T_init: float = 300.0
     T_bottom: float = 300.0
+    h_conv: float = 0.0
+    emissivity: float = 0.0
+    T_amb: float = 300.0
 
 
 def default_material(**kw):
