@@ -329,7 +329,7 @@ def main():
                                         "cg_coarse", "dn_iters", "window_moves", "fine_solves",
                                         "coarse_solves", "line_search_halvings")},
         "ledger_rel_defect": abs((led["stored"] - led["stored0"])
-                                 - (led["absorbed"] - led["bottom"] + led["remap"]))
+                                 - (led["absorbed"] - led["bottom"] - led["surface"] + led["remap"]))
                              / max(abs(led["absorbed"]), 1e-300),
     }
     if args.calibrate_copy > 0:

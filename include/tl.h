@@ -58,12 +58,19 @@ typedef struct {
  * k_hi) and constant outside; latent heat `latent` [J/kg] released by the
  * sigmoid f_pc = (1 + tanh(sharpness (T - (T_sol + T_liq)/2))) / 2.
  * pc_kind must be 0 (the sigmoid).  T_init is the initial temperature of the
- * plate, T_bottom the fixed temperature of its bottom face. */
+ * plate, T_bottom the fixed temperature of its bottom face.
+ * Top-surface heat loss (paper Section 2, boundary conditions): the flux
+ * h_conv (T - T_amb) [W/m^2] leaves through the top faces of both levels and
+ * sigma emissivity (T^4 - T_amb^4) through the fine window's top faces
+ * (sigma = 5.670374419e-8); both are lumped onto the faces' corner nodes.
+ * h_conv >= 0, 0 <= emissivity <= 1, T_amb > 0; zero h_conv and emissivity
+ * give an adiabatic top. */
 typedef struct {
   double rho, T_lo, T_hi, c_lo, c_hi, k_lo, k_hi;
   double latent, T_sol, T_liq, sharpness;
   int pc_kind;
   double T_init, T_bottom;
+  double h_conv, emissivity, T_amb;
 } tl_material;
 
 /* One straight laser pass from (x0,y0) to (x1,y1) on the top surface at
@@ -103,10 +110,11 @@ typedef struct {
 /* Energy ledger in J (FP64).  stored = sum over coarse nodes of the outside
  * lumped mass times H(T+) plus the same over fine nodes; absorbed = laser
  * energy taken in; bottom = heat that left through the bottom face; remap =
- * energy change caused by window moves.  Identity (to solver tolerance):
- * stored - stored0 = absorbed - bottom + remap. */
+ * energy change caused by window moves; surface = heat that left through
+ * the top surface.  Identity (to solver tolerance):
+ * stored - stored0 = absorbed - bottom - surface + remap. */
 typedef struct {
-  double stored, stored0, absorbed, bottom, remap;
+  double stored, stored0, absorbed, bottom, remap, surface;
 } tl_ledger;
 
 /* Counters and timings accumulated over the handle's life. */

@@ -49,6 +49,13 @@ struct MatDev {
   double cslope, kslope, sens_full;  // derived on the host
 };
 
+// Top-surface heat loss of one level: q(T) = h (T - T_amb) + es (T^4 -
+// T_amb^4), es = sigma * emissivity (0 on the coarse level).
+struct SurfDev {
+  double h, es, T_amb;
+};
+constexpr double kSigmaSB = 5.670374419e-8;   // W / (m^2 K^4)
+
 // One laser position with its flux parameters q0 = 3 eta P / (pi R^2) and
 // a3 = 3 / R^2, and the weight of this position in a time average.
 struct Spot { double xc, yc, q0, a3, weight; };
@@ -129,7 +136,7 @@ enum TilePartial {
 
 // Energy ledger slots on the device.
 struct LedgerDev {
-  double stored, stored0, absorbed, bottom, remap;
+  double stored, stored0, absorbed, bottom, remap, surface;
   double e_tmp0, e_tmp1;
 };
 
@@ -158,6 +165,7 @@ struct SolveItem {
   Geo g;
   Region rg;
   MatDev m;
+  SurfDev sf;        // top-surface loss of this level
   double tau;
   double tol;        // Newton tolerance on max |alpha dx| [K]
   double rtol2;      // CG: stop when r.u <= rtol2 * r0.u0
@@ -238,6 +246,13 @@ void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
 // Sum over nodes with k = 0 of R (scaled, added into slot).
 void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,
                   double* slot, double* partials);
+
+// Heat flow out of the top surface, sum over top nodes of A_i q(T_i) with
+// A_i the lumped area of the top faces the region keeps (scaled, added into
+// slot).  Nothing is launched when the level has no loss.
+void k_surface_sum(Launch L, const Geo& g, const Region& rg, const SurfDev& sf,
+                   const double* T, double scale, double* slot,
+                   double* partials);
 
 // Interface values: out[2q] = T[idx[q]], out[2q+1] = lam[idx[q]] for the
 // n coarse interface nodes listed in idx (padded indices); and the inverse

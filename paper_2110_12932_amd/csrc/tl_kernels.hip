@@ -183,6 +183,31 @@ __device__ inline bool node_dirichlet(const Geo& g, const Region& rg, int i,
   return on_immersed_face(rg, i, j, k, 0, g.nx - 1, 0, g.ny - 1, 0);
 }
 
+// Top-surface loss (paper Section 2): lumped area of the top faces around
+// top node (i, j) -- a quarter of each face -- counting only faces the
+// region keeps (the coarse outside solve drops the window's faces).
+__device__ inline double top_area(const Geo& g, const Region& rg, int i, int j) {
+  int n = 0;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int fi = i - a, fj = j - b;
+      bool keep = fi >= 0 && fj >= 0 && fi <= g.nx - 2 && fj <= g.ny - 2;
+      if (keep && rg.mode == kOutside)
+        keep = !(fi >= rg.I0 && fi < rg.I1 && fj >= rg.J0 && fj < rg.J1);
+      n += keep ? 1 : 0;
+    }
+  return 0.25 * g.hx * g.hy * n;
+}
+__device__ inline double surface_flux(double T, const SurfDev& sf) {
+  const double T2 = T * T, a2 = sf.T_amb * sf.T_amb;
+  return sf.h * (T - sf.T_amb) + sf.es * (T2 * T2 - a2 * a2);
+}
+__device__ inline double surface_slope(double T, const SurfDev& sf) {
+  return sf.h + 4.0 * sf.es * T * T * T;
+}
+
 // ---------------------------------------------------------------------------
 // utilities
 // ---------------------------------------------------------------------------
@@ -863,11 +888,18 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       }
       double Rn = mass * (Hn - Ho) / it.tau + stencil_apply(T27, k8, w) - F_n;
       if (it.Fext != nullptr) Rn -= Fx_n;
+      // heat loss through the top surface and its (exact) slope
+      double sd = 0.0;
+      if (k == g.nz - 1 && (it.sf.h != 0.0 || it.sf.es != 0.0)) {
+        const double A = top_area(g, it.rg, i, j);
+        Rn += A * surface_flux(Tn, it.sf);
+        sd = A * surface_slope(Tn, it.sf);
+      }
       Tt[n] = Tn;
       it.R[n] = Rn;
       // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
       const bool dir = node_dirichlet(g, it.rg, i, j, k);
-      const double dn = mass * dHn / it.tau;
+      const double dn = mass * dHn / it.tau + sd;
       const double diag = dn + diagK * g.w[0];
       // this node owns the element whose lowest corner it is (k8[0])
       kap[n] = (R)k8[0];
@@ -1671,6 +1703,32 @@ void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,
   const int nb = grid_for((long)g.nx * g.ny);
   hipLaunchKernelGGL(bottom_sum_kernel, dim3(nb), dim3(kBlock), 0,
                      (hipStream_t)L.stream, g, R, partials);
+  finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, scale, slot, 0);
+}
+
+__global__ void __launch_bounds__(kBlock)
+surface_sum_kernel(Geo g, Region rg, SurfDev sf, const double* __restrict__ T,
+                   double* partials) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  const int ntop = g.nx * g.ny;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntop;
+       t += gridDim.x * blockDim.x) {
+    const int i = t % g.nx, j = t / g.nx;
+    const double A = top_area(g, rg, i, j);
+    if (A > 0.0) acc[0] += A * surface_flux(T[pidx(g, i, j, g.nz - 1)], sf);
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
+}
+
+void k_surface_sum(Launch L, const Geo& g, const Region& rg, const SurfDev& sf,
+                   const double* T, double scale, double* slot,
+                   double* partials) {
+  if (sf.h == 0.0 && sf.es == 0.0) return;
+  const int nb = grid_for((long)g.nx * g.ny);
+  hipLaunchKernelGGL(surface_sum_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, rg, sf, T, partials);
   finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, scale, slot, 0);
 }
 

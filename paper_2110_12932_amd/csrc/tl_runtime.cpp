@@ -148,6 +148,7 @@ struct Job {
   Geo g;
   Region rg;
   MatDev m;
+  SurfDev sf{};
   double tau = 0.0;
   const double* Told = nullptr;
   const double* F = nullptr;
@@ -253,6 +254,7 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
         it.g = j.g;
         it.rg = j.rg;
         it.m = j.m;
+        it.sf = j.sf;
         it.tau = j.tau;
         it.tol = j.tol;
         it.rtol2 = j.rtol2;
@@ -537,6 +539,15 @@ Region region_all() {
   rg.mode = kAllBottom;
   return rg;
 }
+// top-surface loss: convection and radiation on the fine level, convection
+// only on the coarse one (paper Section 2)
+SurfDev surf_fine(const tl_sim* s) {
+  return SurfDev{s->mat_in.h_conv, kSigmaSB * s->mat_in.emissivity,
+                 s->mat_in.T_amb};
+}
+SurfDev surf_coarse(const tl_sim* s) {
+  return SurfDev{s->mat_in.h_conv, 0.0, s->mat_in.T_amb};
+}
 
 // Padded indices of the coarse interface nodes (on an immersed window face),
 // in box-scan order, uploaded to the device.
@@ -644,6 +655,7 @@ void write_ledger(tl_sim* s) {
   s->h_led->absorbed = s->ledger.absorbed;
   s->h_led->bottom = s->ledger.bottom;
   s->h_led->remap = s->ledger.remap;
+  s->h_led->surface = s->ledger.surface;
   hip_check(hipMemcpyAsync(s->led, s->h_led, sizeof(LedgerDev),
                            hipMemcpyHostToDevice, s->stream),
             "hipMemcpyAsync(ledger)");
@@ -689,6 +701,7 @@ Job<R> make_job(tl_sim* s, bool fine, const Region& rg, double tau,
   j.g = fine ? s->gf : s->gc;
   j.rg = rg;
   j.m = s->mat;
+  j.sf = fine ? surf_fine(s) : surf_coarse(s);
   j.tau = tau;
   j.Told = Told;
   j.F = F;
@@ -888,6 +901,8 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
       tl_sim* s = st->s;
       k_interface_accumulate(s->L, s->gf, s->win, s->fR, s->rho, j == 1 ? 1 : 0,
                              -st->dt, &s->led->bottom, s->partials);
+      k_surface_sum(s->L, s->gf, region_window(s), surf_fine(s), s->fcur,
+                    st->dt, &s->led->surface, s->partials);
       std::swap(s->fprev, s->fcur);
       ++s->stats.micro_steps;
     }
@@ -996,6 +1011,11 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     k_interface_accumulate(L, s->gf, s->win, s->fR, nullptr, 0, -st->dt,
                            &s->led->bottom, s->partials);
     k_bottom_sum(L, s->gc, s->cR, -st->Dt, &s->led->bottom, s->partials);
+    // heat lost through the top by the last fine step and the outside solve
+    k_surface_sum(L, s->gf, region_window(s), surf_fine(s), s->fcur, st->dt,
+                  &s->led->surface, s->partials);
+    k_surface_sum(L, s->gc, region_outside(s), surf_coarse(s), s->ccur, st->Dt,
+                  &s->led->surface, s->partials);
     std::swap(s->Tn, s->ccur);
     std::swap(s->fstate, s->fcur);
     energy_now(s, &s->led->stored);
@@ -1010,6 +1030,7 @@ void commit_step(tl_sim* s) {
   s->ledger.absorbed = s->h_led->absorbed;
   s->ledger.bottom = s->h_led->bottom;
   s->ledger.remap = s->h_led->remap;
+  s->ledger.surface = s->h_led->surface;
   ++s->n_macro;
   ++s->stats.macro_steps;
 }
@@ -1038,8 +1059,13 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
   if (nf > 2.0e8 || nc > 2.0e8) return fail(TL_EINVAL, "grid too large");
   if (!finite_all({ma->rho, ma->T_lo, ma->T_hi, ma->c_lo, ma->c_hi, ma->k_lo,
                    ma->k_hi, ma->latent, ma->T_sol, ma->T_liq, ma->sharpness,
-                   ma->T_init, ma->T_bottom}))
+                   ma->T_init, ma->T_bottom, ma->h_conv, ma->emissivity,
+                   ma->T_amb}))
     return fail(TL_EINVAL, "non-finite material parameter");
+  if (ma->h_conv < 0 || ma->emissivity < 0 || ma->emissivity > 1 ||
+      ma->T_amb <= 0)
+    return fail(TL_EINVAL,
+                "surface loss needs h_conv >= 0, 0 <= emissivity <= 1, T_amb > 0");
   if (ma->rho <= 0 || ma->c_lo <= 0 || ma->c_hi <= 0 || ma->k_lo <= 0 ||
       ma->k_hi <= 0 || ma->latent < 0 || ma->sharpness <= 0)
     return fail(TL_EINVAL, "non-physical material parameter");

@@ -65,6 +65,9 @@ class _FakeWorkspace:
     (lambda wl: replace(wl, material=replace(wl.material, T_sol=1700.0)), "T_sol"),
     (lambda wl: replace(wl, material=replace(wl.material, rho=float("nan"))), "non-finite"),
     (lambda wl: replace(wl, material=replace(wl.material, pc_kind=1)), "pc_kind"),
+    (lambda wl: replace(wl, material=replace(wl.material, h_conv=-1.0)), "surface"),
+    (lambda wl: replace(wl, material=replace(wl.material, emissivity=1.5)), "surface"),
+    (lambda wl: replace(wl, material=replace(wl.material, T_amb=0.0)), "surface"),
     (lambda wl: replace(wl, scan=W.ScanPath([])), "track"),
     (lambda wl: replace(wl, options=replace(wl.options, m_time=0)), "m_time"),
     (lambda wl: replace(wl, options=replace(wl.options, face_quad=7)), "face_quad"),

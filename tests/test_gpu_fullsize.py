@@ -53,7 +53,7 @@ def _golden(name):
 
 def _ledger_closes(led):
     lhs = led["stored"] - led["stored0"]
-    rhs = led["absorbed"] - led["bottom"] + led["remap"]
+    rhs = led["absorbed"] - led["bottom"] - led["surface"] + led["remap"]
     return abs(lhs - rhs) <= 1e-8 * abs(led["absorbed"])
 
 

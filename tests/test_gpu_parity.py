@@ -150,7 +150,7 @@ def _check(gpu, ref, tol):
     assert ec <= tol and ef <= tol
     # ledger identity on the device and agreement with the oracle's ledger
     lhs = led["stored"] - led["stored0"]
-    rhs = led["absorbed"] - led["bottom"] + led["remap"]
+    rhs = led["absorbed"] - led["bottom"] - led["surface"] + led["remap"]
     assert abs(lhs - rhs) <= 1e-8 * abs(led["absorbed"])
     assert led["absorbed"] == pytest.approx(orc.ledger["absorbed"], rel=1e-12)
     # the stored energy is a mass-weighted sum of H(T), so it carries the
@@ -174,6 +174,19 @@ def test_small_cases_fp64(name):
 def test_config0_mixed():
     gpu, ref = _run_pair(W.config0(W.MIXED), 20)
     _check(gpu, ref, 1e-6)
+
+
+# Top-surface loss (convection on both levels, radiation on the fine one),
+# strong enough to move the field well beyond the parity bar
+@pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
+def test_config0_surface_loss(prec, tol):
+    wl = W.config0(prec)
+    wl = replace(wl, material=replace(wl.material, h_conv=2.0e4, emissivity=0.8, T_amb=300.0))
+    gpu, ref = _run_pair(wl, 12)
+    _check(gpu, ref, tol)
+    led, orc = gpu[3], ref[3]
+    assert led["surface"] > 0.0
+    assert led["surface"] == pytest.approx(orc.ledger["surface"], rel=max(tol, 1e-9))
 
 
 def test_checkpoint_roundtrip_bitwise():

@@ -100,7 +100,7 @@ def test_served_results_match_oracle():
         tol = 1e-9 if w.options.precision == W.FP64 else 1e-6
         say("  ", k, "rel err", ec, ef)
         assert ec <= tol and ef <= tol
-        assert abs((led["stored"] - led["stored0"]) - (led["absorbed"] - led["bottom"] + led["remap"])) \
+        assert abs((led["stored"] - led["stored0"]) - (led["absorbed"] - led["bottom"] - led["surface"] + led["remap"])) \
             <= 1e-8 * led["absorbed"]
     sv.close()
 

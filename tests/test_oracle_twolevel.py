@@ -37,7 +37,7 @@ def test_energy_ledger_identity(name):
     assert max(_ledger_errors(sim)) < 1e-9
     led = sim.ledger
     total = led["stored"] - led["stored0"]
-    assert total == pytest.approx(led["absorbed"] - led["bottom"] + led["remap"],
+    assert total == pytest.approx(led["absorbed"] - led["bottom"] - led["surface"] + led["remap"],
                                   rel=1e-9)
 
 
