@@ -60,7 +60,7 @@ from . import grid as G
 from . import laser as L
 from . import material as M
 from . import surface as S
-from .level import implicit_step, NoConvergence
+from .level import implicit_step, residual, solve_spd, NoConvergence, LINE_SEARCH_MAX
 
 
 class Window:
@@ -316,6 +316,11 @@ class TwoLevel:
             surface += dt * sf.loss(T_prev)
         # two-level correction at t_{n+1}
         Ff = L.top_load(w.fine, spots[m - 1], opts.face_quad)
+        if getattr(opts, "coupling", 0) == 1:
+            Tf_m, R_m, Tc_new, Rc, it = self.composite_correction(
+                T_prev, dt, Ff, rho_sum, Fc_out, T_prev, Tpred)
+            return self._finish(Tf_m, R_m, Tc_new, Rc, it, Ff, Fc_out, absorbed,
+                                bottom, surface, E_start)
         lam = Tpred.copy()
         dir_c = self.bottom_c | w.interior_c
         guess_f, guess_c = T_prev, Tpred
@@ -342,6 +347,108 @@ class TwoLevel:
                 break
         else:
             raise NoConvergence("two-level iteration did not converge")
+        self._finish(Tf_m, R_m, Tc_new, Rc, it, Ff, Fc_out, absorbed, bottom, surface,
+                     E_start)
+
+    def composite_correction(self, T_prev, dt, Ff, rho_sum, Fc_out, guess_f, guess_c):
+        """The two-level correction at t_{n+1} as one nonlinear solve on the
+        composite grid -- the coarse nodes outside the window's interior
+        (interface nodes included) together with the free fine nodes, the
+        fine interface values slaved to the coarse ones, T-_gamma = P T+_Gamma.
+        Its equations are those that the Dirichlet-Neumann iteration holds at
+        its fixed point: R-(T-) = 0 on the free fine rows, and on the free
+        coarse rows the outside residual plus the reactions of all m micro
+        steps restricted by P^T and averaged, (1/m) sum_j P^T rho_j = 0 --
+        so the solution is the same, without the outer iteration.
+
+        With the fine rows scaled by 1/m and z the composite unknowns, the
+        residual is G(z) = (1/m) Q^T R-(Q z) + C^T R+(C z) (+ the fixed
+        reactions of steps 1..m-1), Q and C the maps from z to the fine and
+        coarse fields, and the frozen-kappa Jacobian (1/m) Q^T J- Q + C^T J+ C
+        is symmetric positive definite.  Newton with the backtracking of
+        oracle.level, stopped when the step taken is within tol.  Returns
+        (T-, R-, T+, R+, iterations); T+ holds the injected fine values at the
+        window-interior nodes, R- the fine residual with the reactions, R+ the
+        coarse outside residual with the restricted reactions (the bottom rows
+        of both give the heat leaving through the plate bottom)."""
+        w, c, mat, opts = self.win, self.coarse, self.mat, self.opts
+        m, Dt = opts.m_time, opts.dt_coarse
+        f = w.fine
+        free_f = np.flatnonzero(~w.dir_f)
+        free_c = np.flatnonzero(~(self.bottom_c | w.interior_c))
+        nf, nc = free_f.size, free_c.size
+        Pg = w.P[np.flatnonzero(w.gamma_f)]          # fine interface rows
+        gam = np.flatnonzero(w.gamma_f)
+        # z -> fine field (free rows: identity, interface rows: P), z -> coarse
+        Pz = Pg[:, free_c]
+        Q = (sp.csr_matrix((np.ones(nf), (free_f, np.arange(nf))), shape=(f.n_nodes, nf + nc))
+             + sp.csr_matrix((Pz.data, (gam[np.repeat(np.arange(Pz.shape[0]),
+                                                        np.diff(Pz.indptr))],
+                                        Pz.indices + nf)), shape=(f.n_nodes, nf + nc)))
+        C = sp.csr_matrix((np.ones(nc), (free_c, nf + np.arange(nc))), shape=(c.n_nodes, nf + nc))
+        base_c = np.where(self.bottom_c, mat.T_bottom, 0.0)
+        # fixed part of the fields: T_bottom on the bottom rows, and its share
+        # in the interface values of a window that reaches the bottom
+        base_f = np.where(w.bottom_f, mat.T_bottom, 0.0)
+        base_f[gam] = Pg @ base_c
+        ones_f = np.ones(f.n_elems)
+        mass_f, mass_c = w.mass_f, w.mass_out
+        sf, sc = self.surf_fine(), self.surf_coarse(w.area_out)
+        fixed = (w.P.T @ np.where(w.gamma_f, rho_sum, 0.0)) / m
+
+        def fields(z):
+            return base_f + Q @ z, base_c + C @ z
+
+        def evaluate(z):
+            Tf, Tc = fields(z)
+            Rf, Kf = residual(f, mat, Tf, T_prev, dt, Ff, ones_f, mass_f, sf)
+            Rc, Kc = residual(c, mat, Tc, self.Tc, Dt, Fc_out, w.outside_e, mass_c, sc)
+            # coarse rows with the restricted reactions of all m micro steps
+            Rc = Rc + fixed + (w.P.T @ np.where(w.gamma_f, Rf, 0.0)) / m
+            G = (Q.T @ np.where(w.gamma_f, 0.0, Rf)) / m + C.T @ Rc
+            return G, Tf, Tc, Rf, Rc, Kf, Kc
+
+        z = np.concatenate([guess_f[free_f], guess_c[free_c]])
+        G, Tf, Tc, Rf, Rc, Kf, Kc = evaluate(z)
+        for it in range(1, opts.newton_max + 1):
+            df = mass_f * M.enthalpy_slope(Tf, mat) / dt
+            dc = mass_c * M.enthalpy_slope(Tc, mat) / Dt
+            if sf.active:
+                df = df + sf.slope(Tf)
+            if sc.active:
+                dc = dc + sc.slope(Tc)
+            A = (Q.T @ (Kf + sp.diags(df)) @ Q) / m + C.T @ (Kc + sp.diags(dc)) @ C
+            delta = solve_spd(A.tocsr(), G)
+            if not np.all(np.isfinite(delta)):
+                raise NoConvergence("non-finite composite Newton update")
+            g0 = np.linalg.norm(G)
+            dmax = np.max(np.abs(delta)) if delta.size else 0.0
+            for h in range(LINE_SEARCH_MAX):
+                alpha = 0.5 ** h
+                z_try = z - alpha * delta
+                trial = evaluate(z_try)
+                if np.linalg.norm(trial[0]) <= (1.0 - 1e-4 * alpha) * g0 or alpha * dmax <= self.newton_tol:
+                    break
+            z = z_try
+            G, Tf, Tc, Rf, Rc, Kf, Kc = trial
+            if alpha * dmax <= self.newton_tol:
+                break
+        else:
+            raise NoConvergence("composite Newton did not converge")
+        self.stats["newton_fine"] += it
+        self.stats["fine_solves"] += 1
+        Tc = Tc.copy()
+        Tc[w.inject_c] = Tf[w.inject_f]
+        return Tf, Rf, Tc, Rc, 1
+
+    def _finish(self, Tf_m, R_m, Tc_new, Rc, it, Ff, Fc_out, absorbed, bottom, surface,
+                E_start):
+        """Ledger terms of the last fine step and the coarse outside step,
+        and the commit of the new state."""
+        w, opts = self.win, self.opts
+        m, Dt = opts.m_time, opts.dt_coarse
+        dt = Dt / m
+        sf = self.surf_fine()
         self.stats["dn_iters"] += it
         bottom -= dt * R_m[w.bottom_f].sum()
         absorbed += dt * Ff.sum()

@@ -5,6 +5,9 @@ from typing import List
 FP64 = 0
 MIXED = 1
 
+DN = 0
+COMPOSITE = 1
+
 
 @dataclass
 class Mesh:
@@ -86,7 +89,10 @@ class Options:
     the fine linear solves (FP64 or MIXED); Gauss points per face direction
     for the laser load; tolerances (kelvin for Newton and the two-level
     iteration, relative for CG); two-level relaxation theta (<= 0 selects
-    refine/(refine+1)); iteration caps."""
+    refine/(refine+1)); iteration caps; how the two-level correction is
+    solved: DN (0), the Dirichlet-Neumann iteration, or COMPOSITE (1), one
+    Newton solve on the composite grid with the fine interface values slaved
+    to the coarse ones (the same discrete solution)."""
     dt_coarse: float
     m_time: int
     precision: int = FP64
@@ -98,6 +104,7 @@ class Options:
     newton_max: int = 60
     cg_max: int = 500
     dn_max: int = 60
+    coupling: int = 0
 
 
 @dataclass
