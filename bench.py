@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--load", type=float, default=1.5,
                     help="config3: arrival rate as a multiple of the measured batched capacity")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--coupling", default=None, choices=[None, "dn", "composite"],
+                    help="two-level correction: Dirichlet-Neumann iteration or one "
+                         "composite-grid solve (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time every Nth fine operator launch with HIP events (0: off)")
@@ -65,7 +68,7 @@ def measured_traffic(path, workload, elem):
     changed since the counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    kname = "cg_iter_batched_kernel<%s>" % ("double" if elem == 8 else "float")
+    kname = "cg_iter_batched_kernel<%s, 0>" % ("double" if elem == 8 else "float")
     if path is None:
         path = os.path.join(root, "profiles", f"cg_iter_{workload}_traffic.json")
     if not os.path.exists(path):
@@ -225,7 +228,7 @@ def main_serving(args):
         achieved = fine_bytes / (prof[1] * 1e-3 * max(1, args.profile_every)) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "cg_iter_batched_kernel<float> (all requests of a tick)",
+                    "kernel": "cg_iter_batched_kernel<float, 0> (all requests of a tick)",
                     "avg_launch_us": prof[1] * 1e3 / prof[0],
                     "bytes_per_launch": fine_bytes / max(1.0, launches_work),
                     "launches_timed": prof[0], "fine_cg_item_iterations": fine_iters}
@@ -268,6 +271,10 @@ def main():
     if args.precision:
         kw["precision"] = W.FP64 if args.precision == "fp64" else W.MIXED
     wl = W.by_name(args.workload, **kw)
+    if args.coupling:
+        from dataclasses import replace
+        wl = replace(wl, options=replace(
+            wl.options, coupling=W.COMPOSITE if args.coupling == "composite" else W.DN))
     steps = min(args.steps, wl.n_macro)
     tl.load()
 
@@ -303,7 +310,7 @@ def main():
         traffic = measured_traffic(args.traffic, wl.name, elem)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": "cg_iter_batched_kernel<%s>" % ("double" if elem == 8 else "float"),
+                    "kernel": "cg_iter_batched_kernel<%s, 0>" % ("double" if elem == 8 else "float"),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                     "launches_timed": st["fine_op_timed"]}
     out = {
@@ -323,6 +330,7 @@ def main():
                    "coarse_nodes": list(st["coarse_nodes"]), "m_time": wl.options.m_time,
                    "dt_coarse": wl.options.dt_coarse,
                    "precision": "fp64" if wl.options.precision == W.FP64 else "mixed",
+                   "coupling": "composite" if wl.options.coupling == W.COMPOSITE else "dn",
                    "macro_steps_timed": steps},
         "roofline": roofline,
         "counters": {k: st[k] for k in ("micro_steps", "newton_fine", "newton_coarse", "cg_fine",

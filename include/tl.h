@@ -89,6 +89,17 @@ typedef struct {
   double t_start;
 } tl_scan_path;
 
+/* How the two-level correction at the end of a macro step is solved (paper
+ * Section 3).  TL_COUPLE_DN: the Dirichlet-Neumann iteration -- fine solve
+ * with the coarse interface trace, coarse solve outside the window loaded by
+ * the restricted fine reactions -- relaxed until the trace settles.
+ * TL_COUPLE_COMPOSITE: one Newton solve of the equations that iteration
+ * holds at its fixed point, over the free fine nodes and the coarse nodes
+ * outside the window interior, the fine interface values slaved to the
+ * coarse ones by the trilinear prolongation.  Both give the same discrete
+ * solution (to the tolerances). */
+typedef enum { TL_COUPLE_DN = 0, TL_COUPLE_COMPOSITE = 1 } tl_coupling;
+
 /* dt_coarse: macro step; m_time: micro steps per macro step (1..32);
  * face_quad: Gauss points per direction for the surface load (1..4);
  * newton_tol [K]: stop when the applied Newton step has max-norm <= tol;
@@ -97,7 +108,8 @@ typedef struct {
  * update has max-norm <= dn_tol; dn_theta: fixed relaxation when > 0, else
  * interface quasi-Newton (IQN-ILS) acceleration whose first step is relaxed
  * by refine/(refine+1); *_max: iteration caps.  Any relaxation converges to
- * the same fixed point. */
+ * the same fixed point.  coupling: a tl_coupling value (dn_tol, dn_theta and
+ * dn_max apply to TL_COUPLE_DN only). */
 typedef struct {
   double dt_coarse;
   int m_time;
@@ -105,6 +117,7 @@ typedef struct {
   int face_quad;
   double newton_tol, cg_rtol, dn_tol, dn_theta;
   int newton_max, cg_max, dn_max;
+  int coupling;
 } tl_options;
 
 /* Energy ledger in J (FP64).  stored = sum over coarse nodes of the outside
@@ -136,6 +149,9 @@ typedef struct {
   double fine_op_timed_ms;
   int fine_nodes[3];        /* fine grid nodes per axis                      */
   int coarse_nodes[3];
+  int64_t newton_corr, cg_corr;   /* the part of newton_fine / cg_fine spent in
+                                     the two-level correction (its fine solves,
+                                     or its composite solves)                */
 } tl_stats;
 
 typedef struct tl_sim tl_sim;

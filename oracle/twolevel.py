@@ -189,8 +189,13 @@ def micro_time(scan, opts, n, j):
 class TwoLevel:
     """State and macro step of the spatiotemporal two-level method."""
 
-    def __init__(self, wl, newton_tol=None, dn_tol=None):
+    def __init__(self, wl, newton_tol=None, dn_tol=None, composite=False):
+        """The correction runs the Dirichlet-Neumann iteration of Section 3
+        unless `composite` asks for the composite-grid solve of the same
+        equations (composite_correction); the workload's own choice of
+        solver for the GPU path does not change the oracle."""
         self.wl = wl
+        self.composite = bool(composite)
         mesh, mat, opts = wl.mesh, wl.material, wl.options
         if mesh.win_nx > mesh.nx or mesh.win_ny > mesh.ny or mesh.win_nz > mesh.nz:
             raise ValueError("window larger than the plate")
@@ -316,7 +321,7 @@ class TwoLevel:
             surface += dt * sf.loss(T_prev)
         # two-level correction at t_{n+1}
         Ff = L.top_load(w.fine, spots[m - 1], opts.face_quad)
-        if getattr(opts, "coupling", 0) == 1:
+        if self.composite:
             Tf_m, R_m, Tc_new, Rc, it = self.composite_correction(
                 T_prev, dt, Ff, rho_sum, Fc_out, T_prev, Tpred)
             return self._finish(Tf_m, R_m, Tc_new, Rc, it, Ff, Fc_out, absorbed,

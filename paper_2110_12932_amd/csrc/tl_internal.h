@@ -159,6 +159,47 @@ void k_copy(Launch L, double* dst, const double* src, long n);
 template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R* y);
 
+// Composite-grid coupling: the two-level correction solved as one system
+// over the free fine nodes and the coarse nodes outside the window interior,
+// with the fine interface values slaved to the coarse ones (T-_gamma =
+// P T+_Gamma) and the fine rows scaled by 1/m so that the frozen-kappa
+// Jacobian is symmetric.  The pair is a fine item and a coarse item that
+// share one Newton/CG state; every launch of a round runs the fine side, a
+// gather kernel (P^T of the fine interface rows onto the coarse interface
+// nodes), then the coarse side.  The fine side forms its interface values
+// from the coarse arrays; the coarse side adds the gathered rows on its
+// interface nodes.  Both sides sum the pair's tile partials in the same
+// order (fine tiles, then coarse tiles), so they take the same decisions.
+enum CoupleSide { kAlone = 0, kFineSide = 1, kCoarseSide = 2 };
+struct Couple {
+  Window w;              // window placement
+  Geo go;                // the other level's grid
+  double rscale;         // scale of this side's rows (1/m fine, 1 coarse)
+  // fine side: the coarse arrays its interface values come from
+  const double* oT[2];   // temperatures (Tb)
+  const void* ox[2];     // Newton directions (xb)
+  const void* odinv;     // Jacobi preconditioner
+  const void* orr[2];    // CG residuals
+  const void* ow[2];     // J u
+  const void* os[2];     // J p
+  // coarse side: the fine arrays the gather kernel restricts, and where
+  // the gathered rows go (coarse-indexed, read on interface nodes only)
+  const double* fR;      // fine residual (rows scaled by 1/m)
+  const void* fdiag;     // fine Jacobian diagonal on interface rows (the
+                         // fine preconditioner array holds it there)
+  const void* fw[2];     // fine J u
+  double* gR;            // gathered residual rows
+  void* gDW;             // gathered diagonal (double, residual phase), then
+                         // gathered J u rows (CG precision, CG phases)
+  const int* gidx;       // padded indices of the coarse interface nodes
+  int ngamma;
+  // the pair's per-tile partials: fine tiles (A), then coarse tiles (B);
+  // an item alone has only A (its own)
+  int ntA, ntB, tsA, tsB;
+  const double* tpA;
+  const double* tpB;
+};
+
 // One level solve in a batched Newton/CG launch (device-resident table).
 // CG-precision arrays are untyped; the launch's precision decides.
 struct SolveItem {
@@ -188,8 +229,9 @@ struct SolveItem {
   void* w[2];          // J u (double-buffered)
   void* s[2];          // J p (double-buffered)
   void* p;             // search direction
-  LevelScalars* sc;    // per-item scalars
+  LevelScalars* sc;    // per-item scalars (shared by a composite pair)
   double* tpart;       // per-tile partial sums, kTileRegions * tstride
+  Couple cp;           // composite-grid coupling (cp side kAlone: none)
 };
 
 // Tiles of a grid in the batched kernels.
@@ -214,6 +256,23 @@ template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
                        int per_item, int round, int kit, void* ev_start,
                        void* ev_stop);
+// The same launches for the two sides of composite pairs (side =
+// kFineSide or kCoarseSide), and the gather between them over the coarse
+// sides' table: phase 0 after the residual, 1 after the CG start, 2 after
+// CG iteration kit.
+template <class R>
+void k_residual_pair(Launch L, const SolveItem* items, int n_items,
+                     int per_item, int round, int side);
+template <class R>
+void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
+                     int per_item, int round, int side);
+template <class R>
+void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
+                    int per_item, int round, int kit, int side,
+                    void* ev_start, void* ev_stop);
+template <class R>
+void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
+                     int max_gamma, int round, int phase, int kit);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,

@@ -749,6 +749,71 @@ static inline void tiles_of(const Geo& g, int& ntx, int& nty, int& ntz) {
 // starting at a multiple of 8, so the XCD-aware tile order holds inside each
 // item; every item has its own scalars and partial-sum regions.
 // ---------------------------------------------------------------------------
+// ---- composite-grid coupling helpers --------------------------------------
+// Fine node (i, j, k) of the window lies on an immersed face (and not on the
+// plate bottom): its value is slaved to the coarse interface nodes.
+__device__ inline bool fine_gamma(const Geo& gf, const Window& w, int i, int j,
+                                  int k);
+// Coarse node (I, J, K) is an interface node: on an immersed face of the
+// closed window box.
+__device__ inline bool coarse_gamma(const Window& w, int I, int J, int K) {
+  if (I < w.I0 || I > w.I0 + w.wx || J < w.J0 || J > w.J0 + w.wy || K < w.K0)
+    return false;
+  return ((w.faces & kFx0) && I == w.I0) ||
+         ((w.faces & kFx1) && I == w.I0 + w.wx) ||
+         ((w.faces & kFy0) && J == w.J0) ||
+         ((w.faces & kFy1) && J == w.J0 + w.wy) ||
+         ((w.faces & kFz0) && K == w.K0);
+}
+// Trilinear prolongation weight between fine node offset (di, dj, dk) (fine
+// cells from the coarse node, |d| < r) -- the same formula in both
+// directions, so P and P^T agree.
+__device__ inline double pweight(int di, int dj, int dk, int r) {
+  return (double)((r - abs(di)) * (r - abs(dj)) * (r - abs(dk))) /
+         (double)(r * r * r);
+}
+// f(padded coarse index, weight) for the coarse nodes with a nonzero
+// weight at window-local fine node (i, j, k).
+template <class F>
+__device__ inline void prolong_each(const Geo& gc, const Window& w, int i,
+                                    int j, int k, F f) {
+  const int r = w.r;
+  const int ci = i / r, cj = j / r, ck = k / r;
+  const int ri = i - ci * r, rj = j - cj * r, rk = k - ck * r;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int a = c & 1, b = (c >> 1) & 1, e = c >> 2;
+    if ((a && ri == 0) || (b && rj == 0) || (e && rk == 0)) continue;
+    const double wt = pweight(a ? r - ri : ri, b ? r - rj : rj,
+                              e ? r - rk : rk, r);
+    f(pidx(gc, w.I0 + ci + a, w.J0 + cj + b, w.K0 + ck + e), wt);
+  }
+}
+// Fine coordinates of halo entry h, and whether it is a slaved interface
+// node of a composite pair's fine side.
+__device__ inline bool halo_gamma(const Geo& g, const Window& w, const Tile& t,
+                                  int h, int& i, int& j, int& k) {
+  i = t.ox + h % HX - 1;
+  j = t.oy + (h / HX) % HY - 1;
+  k = t.oz + h / (HX * HY) - 1;
+  if (i < 0 || j < 0 || k < 0 || i >= g.nx || j >= g.ny || k >= g.nz)
+    return false;
+  return fine_gamma(g, w, i, j, k);
+}
+// Sums of nv consecutive tile-partial regions starting at `reg` over an
+// item's tiles -- for a composite pair, the fine tiles and then the coarse
+// tiles, the same order on both sides.  Per-thread sums; the caller reduces
+// over the workgroup.
+template <int NV, class T>
+__device__ inline void pair_partials(const Couple& cp, int reg, T (&v)[NV]) {
+  for (int b = threadIdx.x; b < cp.ntA; b += kBlock)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += (T)cp.tpA[(reg + q) * cp.tsA + b];
+  for (int b = threadIdx.x; b < cp.ntB; b += kBlock)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += (T)cp.tpB[(reg + q) * cp.tsB + b];
+}
+
 // Every item of a batched launch has the same number of workgroups
 // (`per_item`), so a workgroup finds its item and its rank within the item
 // without reading the table.
@@ -758,7 +823,13 @@ __device__ inline int item_of_block(int per_item) { return blockIdx.x / per_item
 // coefficients, CG initial residual; partials of |R_free|^2, max|alpha dx|,
 // r.(Dinv r).  LDS-tiled like the CG kernels: the trial temperature is
 // formed once per halo node and each element's conductivity once per tile.
-template <class R>
+//
+// Composite pairs (CP = kFineSide / kCoarseSide): the fine side takes the
+// trial values of its interface nodes from the coarse trial (prolonged),
+// scales its rows by 1/m and keeps its Jacobian diagonal on the interface
+// rows (in place of the preconditioner, which is the coarse row's there);
+// the coarse side adds the gathered fine rows on its interface nodes.
+template <class R, int CP>
 __global__ void __launch_bounds__(kBlock)
 residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                         int round) {
@@ -803,8 +874,23 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
       const int hn = h < HN ? halo_index(g, t, h) : -1;
-      hT[q] = hn >= 0 ? T[hn] : 0.0;
-      hd[q] = (hn >= 0 && dx != nullptr) ? dx[hn] : (R)0;
+      int fi, fj, fk;
+      if (CP == kFineSide && hn >= 0 &&
+          halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
+        // interface node: P of the coarse trial, no step of its own
+        const double* Tc = it.cp.oT[st.cur];
+        const R* dxc = st.first ? nullptr : (const R*)it.cp.ox[st.xi];
+        double v = 0.0;
+        prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
+          v += wt * (dxc != nullptr ? trial_T(Tc[cn], alpha * (double)dxc[cn], m)
+                                    : Tc[cn]);
+        });
+        hT[q] = v;
+        hd[q] = (R)0;
+      } else {
+        hT[q] = hn >= 0 ? T[hn] : 0.0;
+        hd[q] = (hn >= 0 && dx != nullptr) ? dx[hn] : (R)0;
+      }
     }
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     if (i < g.nx && j < g.ny && k < g.nz) {
@@ -895,17 +981,33 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         Rn += A * surface_flux(Tn, it.sf);
         sd = A * surface_slope(Tn, it.sf);
       }
-      Tt[n] = Tn;
-      it.R[n] = Rn;
       // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
       const bool dir = node_dirichlet(g, it.rg, i, j, k);
-      const double dn = mass * dHn / it.tau + sd;
-      const double diag = dn + diagK * g.w[0];
+      double dn = mass * dHn / it.tau + sd;
+      double diag = dn + diagK * g.w[0];
+      double kown = k8[0];
+      bool keep_diag = false;
+      if constexpr (CP == kFineSide) {
+        const double sc = it.cp.rscale;
+        Rn *= sc;
+        dn *= sc;
+        diag *= sc;
+        kown *= sc;
+        keep_diag = fine_gamma(g, it.cp.w, i, j, k);
+      }
+      if constexpr (CP == kCoarseSide) {
+        if (coarse_gamma(it.cp.w, i, j, k)) {
+          Rn += it.cp.gR[n];
+          diag += ((const double*)it.cp.gDW)[n];
+        }
+      }
+      Tt[n] = Tn;
+      it.R[n] = Rn;
       // this node owns the element whose lowest corner it is (k8[0])
-      kap[n] = (R)k8[0];
+      kap[n] = (R)kown;
       d[n] = (R)dn;
       const R di = dir ? (R)0 : (R)(1.0 / diag);
-      dinv[n] = di;
+      dinv[n] = keep_diag ? (R)diag : di;
       const R rn = dir ? (R)0 : (R)Rn;
       const R zn = di * rn;
       r[n] = rn;
@@ -948,7 +1050,12 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 //    converged: the trial becomes the accepted temperature and this round's
 //    CG computes the next direction; w0 = J u0 (u0 = Dinv r0) and the
 //    partials of gamma0 = r.u, delta0 = w.u are formed here.
-template <class R>
+//
+// Composite pairs: both sides take the same decisions from the pair's
+// partials; the fine side forms u0 on its interface nodes from the coarse
+// u0 (prolonged) and leaves those rows out of its dot products, the coarse
+// side adds the gathered fine rows of w0 on its interface nodes.
+template <class R, int CP>
 __global__ void __launch_bounds__(kBlock)
 cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                         int round) {
@@ -984,14 +1091,28 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   R hr[HPT], hd[HPT], kr[EPT];
   R o_r = (R)0, o_d = (R)0;
   int o_n = 0;
-  bool o_act = false;
+  bool o_act = false, o_gam = false;
   auto load_tile = [&](const Tile& t) {
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
       const int n = h < HN ? halo_index(g, t, h) : -1;
-      hr[q] = n >= 0 ? r[n] : (R)0;
-      hd[q] = n >= 0 ? dinv[n] : (R)0;
+      int fi, fj, fk;
+      if (CP == kFineSide && n >= 0 &&
+          halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
+        // interface node: u0 = P (Dinv r0) of the coarse side
+        const R* rc = (const R*)it.cp.orr[0];
+        const R* dc = (const R*)it.cp.odinv;
+        double v = 0.0;
+        prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
+          v += wt * (double)(dc[cn] * rc[cn]);
+        });
+        hr[q] = (R)v;
+        hd[q] = (R)1;
+      } else {
+        hr[q] = n >= 0 ? r[n] : (R)0;
+        hd[q] = n >= 0 ? dinv[n] : (R)0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -1002,6 +1123,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     o_act = i < g.nx && j < g.ny && k < g.nz;
     o_n = o_act ? pidx(g, i, j, k) : 0;
+    if (CP == kFineSide) o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
+    if (CP == kCoarseSide) o_gam = o_act && coarse_gamma(it.cp.w, i, j, k);
     if (o_act) {
       o_r = r[o_n];
       o_d = d[o_n];
@@ -1015,13 +1138,18 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
     // residual reductions over the item's tiles (every workgroup, same
     // order)
-    const double* part = it.tpart + kTRes * it.tstride;
+    const Couple& cp = it.cp;
     double v[2] = {0.0, 0.0};
     double bm = 0.0;
-    for (int b = threadIdx.x; b < it.ntiles; b += kBlock) {
-      v[0] += part[b];
-      v[1] += part[2 * it.tstride + b];
-      bm = fmax(bm, part[it.tstride + b]);
+    for (int b = threadIdx.x; b < cp.ntA; b += kBlock) {
+      v[0] += cp.tpA[kTRes * cp.tsA + b];
+      v[1] += cp.tpA[(kTRes + 2) * cp.tsA + b];
+      bm = fmax(bm, cp.tpA[(kTRes + 1) * cp.tsA + b]);
+    }
+    for (int b = threadIdx.x; b < cp.ntB; b += kBlock) {
+      v[0] += cp.tpB[kTRes * cp.tsB + b];
+      v[1] += cp.tpB[(kTRes + 2) * cp.tsB + b];
+      bm = fmax(bm, cp.tpB[(kTRes + 1) * cp.tsB + b]);
     }
     bm = wave_max(bm);
     block_sum<2>(v, lds);
@@ -1105,17 +1233,20 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       if (e < EN) k_s[e] = kr[q];
     }
     __syncthreads();
-    const bool active = o_act;
+    const bool active = o_act, gam = o_gam;
     const int n = o_n;
     const R r_own = o_r, d_own = o_d;
     if (tile + tr.step < tr.last)
       load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
     if (active) {
       const R un = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-      const R wn = d_own * un + stencil_lds(t, u_s, k_s, wts);
+      R wn = d_own * un + stencil_lds(t, u_s, k_s, wts);
+      if (CP == kCoarseSide && gam) wn += ((const R*)it.cp.gDW)[n];
       w[n] = wn;
-      acc[0] += r_own * un;
-      acc[1] += wn * un;
+      if (CP != kFineSide || !gam) {
+        acc[0] += r_own * un;
+        acc[1] += wn * un;
+      }
     }
     block_sum<2>(acc, ldr);
     if (threadIdx.x == 0) {
@@ -1127,7 +1258,11 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 }
 
 // One Chronopoulos-Gear PCG iteration `kit` for every item (LDS-tiled).
-template <class R>
+// Composite pairs: the fine side forms u_{k+1} on its interface nodes from
+// the coarse vectors (prolonged; the coarse side of iteration k-1 wrote
+// them) and leaves those rows out of its dot products; the coarse side adds
+// the gathered fine rows of w_{k+1} on its interface nodes.
+template <class R, int CP>
 __global__ void __launch_bounds__(kBlock)
 cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                        int round, int kit) {
@@ -1166,16 +1301,39 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   R o_r = (R)0, o_w = (R)0, o_di = (R)0, o_d = (R)0, o_s = (R)0, o_p = (R)0,
     o_x = (R)0;
   int o_n = 0;
-  bool o_act = false;
+  bool o_act = false, o_gam = false;
   auto load_tile = [&](const Tile& t) {
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
       const int n = h < HN ? halo_index(g, t, h) : -1;
-      hr[q] = n >= 0 ? r_in[n] : (R)0;
-      hw[q] = n >= 0 ? w_in[n] : (R)0;
-      hs[q] = (n >= 0 && kit > 0) ? s_old[n] : (R)0;
-      hd[q] = n >= 0 ? dinv[n] : (R)0;
+      int fi, fj, fk;
+      if (CP == kFineSide && n >= 0 &&
+          halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
+        // interface node: P (Dinv r), P (Dinv w), P (Dinv s) of the coarse
+        // side with a unit preconditioner, so that the recurrence below
+        // gives u_{k+1} = P (Dinv (r - alpha (w + beta s))) there
+        const R* rc = (const R*)it.cp.orr[a];
+        const R* wc = (const R*)it.cp.ow[a];
+        const R* sc_ = (const R*)it.cp.os[1 - a];
+        const R* dc = (const R*)it.cp.odinv;
+        double vr = 0.0, vw = 0.0, vs = 0.0;
+        prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
+          const R dv = dc[cn];
+          vr += wt * (double)(dv * rc[cn]);
+          vw += wt * (double)(dv * wc[cn]);
+          if (kit > 0) vs += wt * (double)(dv * sc_[cn]);
+        });
+        hr[q] = (R)vr;
+        hw[q] = (R)vw;
+        hs[q] = (R)vs;
+        hd[q] = (R)1;
+      } else {
+        hr[q] = n >= 0 ? r_in[n] : (R)0;
+        hw[q] = n >= 0 ? w_in[n] : (R)0;
+        hs[q] = (n >= 0 && kit > 0) ? s_old[n] : (R)0;
+        hd[q] = n >= 0 ? dinv[n] : (R)0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -1186,6 +1344,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     o_act = i < g.nx && j < g.ny && k < g.nz;
     o_n = o_act ? pidx(g, i, j, k) : 0;
+    if (CP == kFineSide) o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
+    if (CP == kCoarseSide) o_gam = o_act && coarse_gamma(it.cp.w, i, j, k);
     if (o_act) {
       o_r = r_in[o_n];
       o_w = w_in[o_n];
@@ -1207,11 +1367,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   const int ts = it.tstride;
   {
     R v[2] = {(R)0, (R)0};
-    const double* pg = it.tpart + rd * ts;
-    for (int b = threadIdx.x; b < it.ntiles; b += kBlock) {
-      v[0] += (R)pg[b];
-      v[1] += (R)pg[ts + b];
-    }
+    pair_partials<2>(it.cp, rd, v);
     block_sum<2>(v, lds);
     if (threadIdx.x == 0) {
       bc[0] = v[0];
@@ -1269,7 +1425,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       if (e < EN) k_s[e] = kr[q];
     }
     __syncthreads();
-    const bool active = o_act;
+    const bool active = o_act, gam = o_gam;
     const int n = o_n;
     const R r_own = o_r, w_own = o_w, di_own = o_di, d_own = o_d,
             s_prev = o_s, p_own = o_p, x_own = o_x;
@@ -1277,19 +1433,25 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
     // the node's own recurrences and w_{k+1} = J u_{k+1}
     if (active) {
-      const R s_k = w_own + beta * s_prev;
+      // (a slaved interface node of a fine side keeps zero recurrences: its
+      // values come from the coarse side)
+      const bool slave = CP == kFineSide && gam;
+      const R s_k = slave ? (R)0 : w_own + beta * s_prev;
       const R u_k = di_own * r_own;
-      const R pn = u_k + beta * p_own;
+      const R pn = slave ? (R)0 : u_k + beta * p_own;
       p[n] = pn;
       s_out[n] = s_k;
       x[n] = x_own + alpha * pn;
-      const R r1 = r_own - alpha * s_k;
+      const R r1 = slave ? (R)0 : r_own - alpha * s_k;
       r_out[n] = r1;
       const R u1 = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-      const R w1 = d_own * u1 + stencil_lds(t, u_s, k_s, wts);
+      R w1 = d_own * u1 + stencil_lds(t, u_s, k_s, wts);
+      if (CP == kCoarseSide && gam) w1 += ((const R*)it.cp.gDW)[n];
       w_out[n] = w1;
-      acc[0] += r1 * u1;
-      acc[1] += w1 * u1;
+      if (CP != kFineSide || !gam) {
+        acc[0] += r1 * u1;
+        acc[1] += w1 * u1;
+      }
     }
     block_sum<2>(acc, lds);
     if (threadIdx.x == 0) {
@@ -1297,6 +1459,98 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       it.tpart[(wr + 1) * ts + tile] = (double)acc[1];
     }
     __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+// Gather of composite pairs (over the coarse sides' table): for every
+// coarse interface node J, sum_k P_kJ v_k over the fine interface nodes k
+// in its support (fewer than r fine cells away on every axis) -- phase 0:
+// the fine residual rows, and sum_k P_kJ^2 of the fine Jacobian diagonal as
+// the preconditioner's share; phases 1 and 2: the fine rows of w = J u of
+// the CG start or of iteration kit.  One wave per interface node.  The
+// support's interface nodes lie on the immersed faces through J; the lanes
+// walk each face's (2r-1)^2 patch, and a node on two faces is taken on the
+// first, so every fine node enters once.  Runs under the same conditions as
+// the coarse side it feeds.
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
+                     int round, int phase, int kit) {
+  const SolveItem& it = items[blockIdx.x / per_item];
+  const Couple& cp = it.cp;
+  const LevelScalars* sc = it.sc;
+  if (phase == 0) {
+    const NewtonState& st = sc->ns[round & 1];
+    if (st.status != kRunning) return;
+    if (st.pending) {
+      const CGScalars& cgp = sc->cg[(round + 1) & 1];
+      if (cgp.breakdown && cgp.iters == 0) return;
+    }
+  } else {
+    const NewtonState& nx = sc->ns[(round + 1) & 1];
+    if (nx.status != kRunning || !nx.pending) return;
+    if (phase == 2) {
+      const CGScalars& c = sc->cg[round & 1];
+      if (c.done || kit >= nx.budget) return;
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const int q = (blockIdx.x % per_item) * (kBlock / 64) + (threadIdx.x >> 6);
+  if (q >= cp.ngamma) return;   // the whole wave; no barrier follows
+  const Geo& gc = it.g;
+  const Geo& gf = cp.go;
+  const Window& w = cp.w;
+  const int n = cp.gidx[q];
+  const int I = n % gc.px - 1, J = (n / gc.px) % (gc.ny + 2) - 1,
+            K = n / gc.pxy - 1;
+  const int r = w.r, span = 2 * r - 1;
+  // fine coordinates of the coarse node
+  const int ci = r * (I - w.I0), cj = r * (J - w.J0), ck = r * (K - w.K0);
+  const R* fw = (const R*)cp.fw[phase == 2 ? 1 - (kit & 1) : 0];
+  const R* fdg = (const R*)cp.fdiag;
+  double a0 = 0.0, a1 = 0.0;
+  for (int face = 0; face < 5; ++face) {
+    const bool on =
+        face == 0 ? ((w.faces & kFx0) && ci == 0)
+      : face == 1 ? ((w.faces & kFx1) && ci == gf.nx - 1)
+      : face == 2 ? ((w.faces & kFy0) && cj == 0)
+      : face == 3 ? ((w.faces & kFy1) && cj == gf.ny - 1)
+                  : ((w.faces & kFz0) && ck == 0);
+    if (!on) continue;
+    for (int t = lane; t < span * span; t += 64) {
+      const int u = t % span - (r - 1), v = t / span - (r - 1);
+      const int fi = face < 2 ? ci : ci + u;
+      const int fj = face < 2 ? cj + u : (face < 4 ? cj : cj + v);
+      const int fk = face < 4 ? ck + v : ck;
+      if (fi < 0 || fj < 0 || fk < 0 || fi >= gf.nx || fj >= gf.ny ||
+          fk >= gf.nz)
+        continue;
+      if (w.bottom && fk == 0) continue;   // plate bottom: fixed, not slaved
+      // a node also on an earlier immersed face was taken there
+      if ((face > 0 && (w.faces & kFx0) && fi == 0) ||
+          (face > 1 && (w.faces & kFx1) && fi == gf.nx - 1) ||
+          (face > 2 && (w.faces & kFy0) && fj == 0) ||
+          (face > 3 && (w.faces & kFy1) && fj == gf.ny - 1))
+        continue;
+      const double wt = pweight(fi - ci, fj - cj, fk - ck, r);
+      const int fn = pidx(gf, fi, fj, fk);
+      if (phase == 0) {
+        a0 += wt * cp.fR[fn];
+        a1 += wt * wt * (double)fdg[fn];
+      } else {
+        a0 += wt * (double)fw[fn];
+      }
+    }
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  if (lane == 0) {
+    if (phase == 0) {
+      cp.gR[n] = a0;
+      ((double*)cp.gDW)[n] = a1;
+    } else {
+      ((R*)cp.gDW)[n] = (R)a0;
+    }
   }
 }
 
@@ -1310,33 +1564,85 @@ int item_tile_blocks(int ntiles, int n_items) {
   return std::min(tiled_grid(ntiles), share);
 }
 
+template <class R, int CP>
+static void launch_residual(Launch L, const SolveItem* items, int n_items,
+                            int per_item, int round) {
+  hipLaunchKernelGGL((residual_batched_kernel<R, CP>),
+                     dim3(n_items * per_item), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, items, per_item, round);
+}
+template <class R, int CP>
+static void launch_cg_start(Launch L, const SolveItem* items, int n_items,
+                            int per_item, int round) {
+  hipLaunchKernelGGL((cg_start_batched_kernel<R, CP>),
+                     dim3(n_items * per_item), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, items, per_item, round);
+}
+template <class R, int CP>
+static void launch_cg_iter(Launch L, const SolveItem* items, int n_items,
+                           int per_item, int round, int kit, void* ev_start,
+                           void* ev_stop) {
+  if (ev_start != nullptr)
+    hipExtLaunchKernelGGL((cg_iter_batched_kernel<R, CP>),
+                          dim3(n_items * per_item), dim3(kBlock), 0,
+                          (hipStream_t)L.stream, (hipEvent_t)ev_start,
+                          (hipEvent_t)ev_stop, 0, items, per_item, round, kit);
+  else
+    hipLaunchKernelGGL((cg_iter_batched_kernel<R, CP>),
+                       dim3(n_items * per_item), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, items, per_item, round, kit);
+}
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
                         int per_item, int round) {
-  hipLaunchKernelGGL(residual_batched_kernel<R>, dim3(n_items * per_item),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item,
-                     round);
+  launch_residual<R, kAlone>(L, items, n_items, per_item, round);
 }
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
                         int per_item, int round) {
-  hipLaunchKernelGGL(cg_start_batched_kernel<R>, dim3(n_items * per_item),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item,
-                     round);
+  launch_cg_start<R, kAlone>(L, items, n_items, per_item, round);
 }
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
                        int per_item, int round, int kit, void* ev_start,
                        void* ev_stop) {
-  if (ev_start != nullptr)
-    hipExtLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(n_items * per_item),
-                          dim3(kBlock), 0, (hipStream_t)L.stream,
-                          (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, items,
-                          per_item, round, kit);
+  launch_cg_iter<R, kAlone>(L, items, n_items, per_item, round, kit, ev_start,
+                            ev_stop);
+}
+template <class R>
+void k_residual_pair(Launch L, const SolveItem* items, int n_items,
+                     int per_item, int round, int side) {
+  if (side == kFineSide)
+    launch_residual<R, kFineSide>(L, items, n_items, per_item, round);
   else
-    hipLaunchKernelGGL(cg_iter_batched_kernel<R>, dim3(n_items * per_item),
-                       dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item,
-                       round, kit);
+    launch_residual<R, kCoarseSide>(L, items, n_items, per_item, round);
+}
+template <class R>
+void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
+                     int per_item, int round, int side) {
+  if (side == kFineSide)
+    launch_cg_start<R, kFineSide>(L, items, n_items, per_item, round);
+  else
+    launch_cg_start<R, kCoarseSide>(L, items, n_items, per_item, round);
+}
+template <class R>
+void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
+                    int per_item, int round, int kit, int side,
+                    void* ev_start, void* ev_stop) {
+  if (side == kFineSide)
+    launch_cg_iter<R, kFineSide>(L, items, n_items, per_item, round, kit,
+                                 ev_start, ev_stop);
+  else
+    launch_cg_iter<R, kCoarseSide>(L, items, n_items, per_item, round, kit,
+                                   ev_start, ev_stop);
+}
+template <class R>
+void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
+                     int max_gamma, int round, int phase, int kit) {
+  const int per = std::max(1, (max_gamma + kBlock / 64 - 1) / (kBlock / 64));
+  hipLaunchKernelGGL(couple_gather_kernel<R>, dim3(n_items * per),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, coarse_items, per,
+                     round, phase, kit);
 }
 #define TL_BATCH_INST(R)                                                     \
   template void k_residual_batched<R>(Launch, const SolveItem*, int, int,    \
@@ -1344,7 +1650,15 @@ void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
   template void k_cg_start_batched<R>(Launch, const SolveItem*, int, int,    \
                                       int);                                  \
   template void k_cg_iter_batched<R>(Launch, const SolveItem*, int, int, int, \
-                                     int, void*, void*);
+                                     int, void*, void*);                     \
+  template void k_residual_pair<R>(Launch, const SolveItem*, int, int, int,  \
+                                   int);                                     \
+  template void k_cg_start_pair<R>(Launch, const SolveItem*, int, int, int,  \
+                                   int);                                     \
+  template void k_cg_iter_pair<R>(Launch, const SolveItem*, int, int, int,   \
+                                  int, int, void*, void*);                   \
+  template void k_couple_gather<R>(Launch, const SolveItem*, int, int, int,  \
+                                   int, int);
 TL_BATCH_INST(float)
 TL_BATCH_INST(double)
 #undef TL_BATCH_INST
@@ -1545,7 +1859,8 @@ void k_interface_accumulate(Launch L, const Geo& gf, const Window& w,
 // ---------------------------------------------------------------------------
 // K9 (part 2): restriction of the interface reactions onto the coarse
 // interface nodes with the transpose of the trilinear prolongation:
-//   ext_J = scale * sum_k P_kJ (rho_acc_k + Rm_k)   over fine interface nodes k.
+//   ext_J = scale * sum_k P_kJ (rho_acc_k + Rm_k)   over fine interface nodes k
+// (either array may be null).
 // One workgroup per coarse node of the closed window box; nodes of the box
 // that are not interface nodes get 0.
 // ---------------------------------------------------------------------------
@@ -1580,7 +1895,8 @@ restrict_kernel(Geo gf, Geo gc, Window w, const double* __restrict__ rho,
                         ((double)(r - abs(dj)) / (double)r) *
                         ((double)(r - abs(dk)) / (double)r);
       const int n = pidx(gf, fi, fj, fk);
-      acc[0] += wt * (rho != nullptr ? rho[n] + Rm[n] : Rm[n]);
+      acc[0] += wt * ((rho != nullptr ? rho[n] : 0.0) +
+                      (Rm != nullptr ? Rm[n] : 0.0));
     }
   }
   block_sum<1>(acc, lds);

@@ -67,15 +67,17 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   Geo gc, gf;
   size_t off_c[23], off_fd[9], off_fcg[12];
-  size_t off_scal, off_items, off_ledger, off_partials, off_tpart, off_gidx,
-      off_gbuf;
+  size_t off_ccg32[12];   // FP32 coarse CG arrays (mixed composite solves)
+  bool ccg32 = false;
+  size_t off_scal, off_items, off_ledger, off_partials, off_tpart,
+      off_tpart2, off_gidx, off_gbuf;
   int tstride;   // per-tile partial slots per region (both levels)
   int gamma_cap;
   size_t total;
   int cg_bytes;
 };
 
-constexpr int kCoarseArrays = 23;  // Tn Tpred cur trial lam dprev R Fall Fout ext | 12 CG arrays | Hold
+constexpr int kCoarseArrays = 23;  // Tn Tpred cur trial lam gdw R Fall Fout ext | 12 CG arrays | Hold
 constexpr int kFineD = 9;          // state prev cur trial alt R F rho Hold
 constexpr int kFineCG = 12;        // kap d dinv r0 r1 w0 w1 s0 s1 p x0 x1
 
@@ -94,6 +96,14 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   for (int a = 0; a < kCoarseArrays; ++a) { L.off_c[a] = off; off += cbytes; }
   for (int a = 0; a < kFineD; ++a) { L.off_fd[a] = off; off += fbytes; }
   for (int a = 0; a < kFineCG; ++a) { L.off_fcg[a] = off; off += fcg; }
+  // A mixed-precision composite solve runs its coarse side in FP32 too; it
+  // gets arrays of its own, since the stencils rely on zero ghost entries
+  // that an FP32 view of the FP64 arrays would not keep.
+  L.ccg32 = op.precision == TL_MIXED && op.coupling == TL_COUPLE_COMPOSITE;
+  for (int a = 0; a < kFineCG; ++a) {
+    L.off_ccg32[a] = off;
+    if (L.ccg32) off += align_up((size_t)L.gc.npad * 4);
+  }
   L.off_scal = off; off += align_up(2 * sizeof(LevelScalars));
   L.off_items = off; off += align_up(2 * sizeof(SolveItem));
   L.off_ledger = off; off += align_up(sizeof(LedgerDev));
@@ -103,6 +113,9 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   const int nt = std::max(grid_tiles(L.gc, ntx, nty), grid_tiles(L.gf, ntx, nty));
   L.tstride = (nt + 63) / 64 * 64;
   L.off_tpart = off;
+  off += align_up((size_t)L.tstride * kTileRegions * sizeof(double));
+  // the coarse side of a composite pair keeps its own tile partials
+  L.off_tpart2 = off;
   off += align_up((size_t)L.tstride * kTileRegions * sizeof(double));
   L.gamma_cap = (me.win_nx + 1) * (me.win_ny + 1) * (me.win_nz + 1);
   L.off_gidx = off; off += align_up((size_t)L.gamma_cap * sizeof(int));
@@ -136,7 +149,8 @@ struct BatchCtx {
   SolveItem* h_items = nullptr;
   LevelScalars* d_sc = nullptr;
   LevelScalars* h_sc = nullptr;
-  int cap = 0;
+  int cap = 0;        // solves (scalar sets)
+  int item_cap = 0;   // items (a composite pair takes two)
   hipStream_t stream = nullptr;
   Launch L{nullptr};
 };
@@ -164,6 +178,8 @@ struct Job {
   int* last_cg = nullptr;   // most CG iterations the level's last solve needed
   int64_t* n_newton = nullptr;
   int64_t* n_cg = nullptr;
+  int64_t* n_newton_x = nullptr;   // also counted here when set
+  int64_t* n_cg_x = nullptr;
   tl_stats* stats = nullptr;   // line-search count; op bytes if `fine`
   bool fine = false;
   double tol = 0.0, rtol2 = 0.0;
@@ -173,6 +189,10 @@ struct Job {
   bool finished = false;
   std::string err;
   int rounds_hint = 2;   // rounds to queue before the next host sync
+  // composite pairs: the caller's part of the coupling (window, row scale;
+  // on the coarse side the gather targets and interface list); the solver
+  // fills in the partner's arrays
+  Couple cpl{};
 };
 
 // Count the timed launches that did work: round r's launch k worked when
@@ -213,17 +233,100 @@ int predict_rounds(const NewtonState& st, double tol) {
 // queues several rounds without synchronising -- as many as the slowest job
 // is predicted to need -- then reads every job's state with one copy.  On
 // return each job's *T holds its solution and Rout the residual there.
+//
+// With `paired`, jobs come as (fine, coarse) composite pairs (jobs[2u],
+// jobs[2u+1]) that share one Newton/CG state: every launch of a round runs
+// over the fine sides, then the gather of the fine interface rows, then the
+// coarse sides (see Couple).  Counts and the CG budget go to the fine job.
 template <class R>
-void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
+void fill_item(SolveItem& it, const Job<R>& j) {
+  it.g = j.g;
+  it.rg = j.rg;
+  it.m = j.m;
+  it.sf = j.sf;
+  it.tau = j.tau;
+  it.tol = j.tol;
+  it.rtol2 = j.rtol2;
+  it.newton_max = j.newton_max;
+  it.cg_max = j.cg_max;
+  it.ntiles = grid_tiles(j.g, it.ntx, it.nty);
+  it.tstride = j.tstride;
+  it.Tb[0] = *j.T;
+  it.Tb[1] = *j.Tt;
+  it.Told = j.Told;
+  it.Hold = j.Hold;
+  it.F = j.F;
+  it.Fext = j.Fext;
+  it.R = j.Rout;
+  it.xb[0] = j.cg->x[0];
+  it.xb[1] = j.cg->x[1];
+  it.kap = j.cg->kap;
+  it.d = j.cg->d;
+  it.dinv = j.cg->dinv;
+  it.r[0] = j.cg->r[0];
+  it.r[1] = j.cg->r[1];
+  it.w[0] = j.cg->w[0];
+  it.w[1] = j.cg->w[1];
+  it.s[0] = j.cg->s[0];
+  it.s[1] = j.cg->s[1];
+  it.p = j.cg->p;
+  it.tpart = j.tpart;
+  it.cp = j.cpl;
+  it.cp.ntA = it.ntiles;
+  it.cp.tsA = j.tstride;
+  it.cp.tpA = j.tpart;
+  it.cp.ntB = 0;
+  it.cp.tsB = 0;
+  it.cp.tpB = nullptr;
+}
+
+// The pair's cross references: the fine side reads the coarse arrays, the
+// coarse side gathers from the fine ones; both sum fine then coarse tiles.
+template <class R>
+void link_pair(SolveItem& f, SolveItem& c, const Job<R>& fj, const Job<R>& cj) {
+  f.cp.go = cj.g;
+  f.cp.oT[0] = *cj.T;
+  f.cp.oT[1] = *cj.Tt;
+  f.cp.ox[0] = cj.cg->x[0];
+  f.cp.ox[1] = cj.cg->x[1];
+  f.cp.odinv = cj.cg->dinv;
+  for (int b = 0; b < 2; ++b) {
+    f.cp.orr[b] = cj.cg->r[b];
+    f.cp.ow[b] = cj.cg->w[b];
+    f.cp.os[b] = cj.cg->s[b];
+  }
+  c.cp.go = fj.g;
+  c.cp.fR = fj.Rout;
+  c.cp.fdiag = fj.cg->dinv;
+  c.cp.fw[0] = fj.cg->w[0];
+  c.cp.fw[1] = fj.cg->w[1];
+  f.cp.ntB = c.cp.ntA;
+  f.cp.tsB = c.cp.tsA;
+  f.cp.tpB = c.cp.tpA;
+  c.cp.ntB = c.cp.ntA;
+  c.cp.tsB = c.cp.tsA;
+  c.cp.tpB = c.cp.tpA;
+  c.cp.ntA = f.cp.ntA;
+  c.cp.tsA = f.cp.tsA;
+  c.cp.tpA = f.cp.tpA;
+}
+
+template <class R>
+void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
+                 bool paired = false) {
   const int nj = (int)jobs.size();
-  if (nj > B.cap) throw DevErr{"batch larger than its context"};
+  const int nu = paired ? nj / 2 : nj;   // solves: jobs, or pairs
+  if (nu > B.cap || nj > B.item_cap)
+    throw DevErr{"batch larger than its context"};
   if (nj == 0) return;
   for (int q = 0; q < nj; ++q) {
-    Job<R>& j = *jobs[q];
-    j.finished = false;
-    j.failed = false;
-    j.rounds_hint = 2;
-    LevelScalars& h = B.h_sc[q];
+    jobs[q]->finished = false;
+    jobs[q]->failed = false;
+    jobs[q]->rounds_hint = 2;
+  }
+  for (int u = 0; u < nu; ++u) {
+    Job<R>& j = *jobs[paired ? 2 * u : u];
+    LevelScalars& h = B.h_sc[u];
     std::memset(&h, 0, sizeof(LevelScalars));
     NewtonState& st = h.ns[0];
     st.first = 1;
@@ -231,84 +334,87 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
     // CG budget: 1 more than the most the level's last solve needed
     st.budget = std::min(j.cg_max, std::max(3, *j.last_cg + 1));
   }
-  hip_check(hipMemcpyAsync(B.d_sc, B.h_sc, sizeof(LevelScalars) * nj,
+  hip_check(hipMemcpyAsync(B.d_sc, B.h_sc, sizeof(LevelScalars) * nu,
                            hipMemcpyHostToDevice, B.stream),
             "hipMemcpyAsync(scalars)");
   std::vector<int> act, built, round_iters;
-  int round = 0, per_item = 0;
+  int round = 0, per_a = 0, per_c = 0, max_gamma = 0;
   for (;;) {
     act.clear();
-    for (int q = 0; q < nj; ++q)
-      if (!jobs[q]->finished) act.push_back(q);
+    for (int u = 0; u < nu; ++u)
+      if (!jobs[paired ? 2 * u : u]->finished) act.push_back(u);
     if (act.empty()) return;
+    const int na = (int)act.size();
     if (act != built) {
-      int most = 1;
-      for (int q : act) {
+      int most = 1, most_c = 1;
+      max_gamma = 0;
+      for (int u : act) {
         int ntx, nty;
-        most = std::max(most, grid_tiles(jobs[q]->g, ntx, nty));
+        most = std::max(most, grid_tiles(jobs[paired ? 2 * u : u]->g, ntx, nty));
+        if (paired) {
+          most_c = std::max(most_c, grid_tiles(jobs[2 * u + 1]->g, ntx, nty));
+          max_gamma = std::max(max_gamma, jobs[2 * u + 1]->cpl.ngamma);
+        }
       }
-      per_item = item_tile_blocks(most, (int)act.size());
-      for (int a = 0; a < (int)act.size(); ++a) {
-        Job<R>& j = *jobs[act[a]];
-        SolveItem& it = B.h_items[a];
-        it.g = j.g;
-        it.rg = j.rg;
-        it.m = j.m;
-        it.sf = j.sf;
-        it.tau = j.tau;
-        it.tol = j.tol;
-        it.rtol2 = j.rtol2;
-        it.newton_max = j.newton_max;
-        it.cg_max = j.cg_max;
-        it.ntiles = grid_tiles(j.g, it.ntx, it.nty);
-        it.tstride = j.tstride;
-        it.Tb[0] = *j.T;
-        it.Tb[1] = *j.Tt;
-        it.Told = j.Told;
-        it.Hold = j.Hold;
-        it.F = j.F;
-        it.Fext = j.Fext;
-        it.R = j.Rout;
-        it.xb[0] = j.cg->x[0];
-        it.xb[1] = j.cg->x[1];
-        it.kap = j.cg->kap;
-        it.d = j.cg->d;
-        it.dinv = j.cg->dinv;
-        it.r[0] = j.cg->r[0];
-        it.r[1] = j.cg->r[1];
-        it.w[0] = j.cg->w[0];
-        it.w[1] = j.cg->w[1];
-        it.s[0] = j.cg->s[0];
-        it.s[1] = j.cg->s[1];
-        it.p = j.cg->p;
-        it.sc = B.d_sc + act[a];
-        it.tpart = j.tpart;
+      per_a = item_tile_blocks(most, na);
+      per_c = item_tile_blocks(most_c, na);
+      for (int a = 0; a < na; ++a) {
+        const int u = act[a];
+        if (!paired) {
+          fill_item(B.h_items[a], *jobs[u]);
+          B.h_items[a].sc = B.d_sc + u;
+        } else {
+          SolveItem& f = B.h_items[a];
+          SolveItem& c = B.h_items[na + a];
+          fill_item(f, *jobs[2 * u]);
+          fill_item(c, *jobs[2 * u + 1]);
+          link_pair(f, c, *jobs[2 * u], *jobs[2 * u + 1]);
+          f.sc = c.sc = B.d_sc + u;
+        }
       }
       hip_check(hipMemcpyAsync(B.d_items, B.h_items,
-                               sizeof(SolveItem) * act.size(),
+                               sizeof(SolveItem) * na * (paired ? 2 : 1),
                                hipMemcpyHostToDevice, B.stream),
                 "hipMemcpyAsync(items)");
       built = act;
     }
     // CG launches per round: the largest budget
     int n_launch = 0, n_rounds = 1;
-    for (int q : act) {
-      n_launch = std::max(n_launch, B.h_sc[q].ns[round & 1].budget);
-      n_rounds = std::max(n_rounds, jobs[q]->rounds_hint);
+    for (int u : act) {
+      n_launch = std::max(n_launch, B.h_sc[u].ns[round & 1].budget);
+      n_rounds = std::max(n_rounds, jobs[paired ? 2 * u : u]->rounds_hint);
     }
-    const int na = (int)act.size();
     const int r0 = round;
+    const SolveItem* fi = B.d_items;
+    const SolveItem* ci = B.d_items + na;
     for (int rr = 0; rr < n_rounds; ++rr, ++round) {
-      k_residual_batched<R>(B.L, B.d_items, na, per_item, round);
-      k_cg_start_batched<R>(B.L, B.d_items, na, per_item, round);
+      if (!paired) {
+        k_residual_batched<R>(B.L, fi, na, per_a, round);
+        k_cg_start_batched<R>(B.L, fi, na, per_a, round);
+      } else {
+        k_residual_pair<R>(B.L, fi, na, per_a, round, kFineSide);
+        k_couple_gather<R>(B.L, ci, na, max_gamma, round, 0, 0);
+        k_residual_pair<R>(B.L, ci, na, per_c, round, kCoarseSide);
+        k_cg_start_pair<R>(B.L, fi, na, per_a, round, kFineSide);
+        k_couple_gather<R>(B.L, ci, na, max_gamma, round, 1, 0);
+        k_cg_start_pair<R>(B.L, ci, na, per_c, round, kCoarseSide);
+      }
       for (int k = 0; k < n_launch; ++k) {
-        const bool timed = prof != nullptr && prof->every > 0 &&
+        // sampled event timing covers the plain CG kernel (not the pairs')
+        const bool timed = !paired && prof != nullptr && prof->every > 0 &&
                            (prof->count++ % prof->every) == 0 &&
                            prof->used < kProfPairs;
-        k_cg_iter_batched<R>(
-            B.L, B.d_items, na, per_item, round, k,
-            timed ? (void*)prof->ev[2 * prof->used] : nullptr,
-            timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr);
+        void* e0 = timed ? (void*)prof->ev[2 * prof->used] : nullptr;
+        void* e1 = timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr;
+        if (!paired) {
+          k_cg_iter_batched<R>(B.L, fi, na, per_a, round, k, e0, e1);
+        } else {
+          k_cg_iter_pair<R>(B.L, fi, na, per_a, round, k, kFineSide, nullptr,
+                            nullptr);
+          k_couple_gather<R>(B.L, ci, na, max_gamma, round, 2, k);
+          k_cg_iter_pair<R>(B.L, ci, na, per_c, round, k, kCoarseSide,
+                            nullptr, nullptr);
+        }
         if (timed) {
           prof->k[prof->used] = k;
           prof->round[prof->used] = round;
@@ -317,7 +423,7 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
       }
     }
     hip_check(hipGetLastError(), "kernel launch");
-    hip_check(hipMemcpyAsync(B.h_sc, B.d_sc, sizeof(LevelScalars) * nj,
+    hip_check(hipMemcpyAsync(B.h_sc, B.d_sc, sizeof(LevelScalars) * nu,
                              hipMemcpyDeviceToHost, B.stream),
               "hipMemcpyAsync(scalars)");
     hip_check(hipStreamSynchronize(B.stream), "hipStreamSynchronize");
@@ -325,8 +431,8 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
       // CG iterations per queued round, most over the jobs: rounds before
       // the last from the log, the last from its CG scalars
       round_iters.assign(n_rounds, 0);
-      for (int q : act) {
-        const LevelScalars& h = B.h_sc[q];
+      for (int u : act) {
+        const LevelScalars& h = B.h_sc[u];
         for (int rr = 0; rr < n_rounds; ++rr) {
           const int r = r0 + rr;
           const int n = r + 1 < round ? h.cg_log[r % kRoundLog]
@@ -336,9 +442,10 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
       }
       flush_profile(prof, r0, round_iters);
     }
-    for (int q : act) {
-      Job<R>& j = *jobs[q];
-      const NewtonState& st = B.h_sc[q].ns[round & 1];
+    for (int u : act) {
+      Job<R>& j = *jobs[paired ? 2 * u : u];
+      Job<R>* partner = paired ? jobs[2 * u + 1] : nullptr;
+      const NewtonState& st = B.h_sc[u].ns[round & 1];
       if (st.status == kRunning) {
         j.rounds_hint = predict_rounds(st, j.tol);
         continue;
@@ -346,13 +453,19 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
       j.finished = true;
       *j.n_newton += st.n_newton;
       *j.n_cg += st.n_cg;
+      if (j.n_newton_x) *j.n_newton_x += st.n_newton;
+      if (j.n_cg_x) *j.n_cg_x += st.n_cg;
       j.stats->line_search_halvings += st.n_halvings;
       if (j.fine) {
         j.stats->fine_op_bytes += 13.0 * sizeof(R) * j.g.nreal * st.n_cg;
         j.stats->fine_op_applies += st.n_cg;
       }
       if (st.cg_need > 0) *j.last_cg = st.cg_need;
-      if (st.cur == 1) std::swap(*j.T, *j.Tt);
+      if (st.cur == 1) {
+        std::swap(*j.T, *j.Tt);
+        if (partner) std::swap(*partner->T, *partner->Tt);
+      }
+      if (partner) partner->finished = true;
       if (st.status == kConverged) continue;
       j.failed = true;
       j.err = std::string(j.what);
@@ -365,6 +478,10 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof) {
           break;
         default:
           j.err += " Newton did not converge within newton_max iterations";
+      }
+      if (partner) {
+        partner->failed = true;
+        partner->err = j.err;
       }
     }
   }
@@ -487,8 +604,12 @@ struct tl_sim {
   Launch L;
   char* ws;
   // coarse fields
-  double *Tn, *Tpred, *ccur, *ctrial, *lam, *dprev, *cR, *Fall, *Fout, *ext;
+  // lam: interface values of the Dirichlet-Neumann iteration, or the
+  // gathered fine residual rows of a composite solve; gdw: the gathered
+  // fine diagonal and J u rows of a composite solve
+  double *Tn, *Tpred, *ccur, *ctrial, *lam, *gdw, *cR, *Fall, *Fout, *ext;
   CGBufs<double> ccg;
+  CGBufs<float> ccg32;   // coarse CG arrays of a mixed composite solve
   // fine fields
   double *fstate, *fprev, *fcur, *ftrial, *falt, *fR, *fF, *rho;
   double *cHold, *fHold;   // H(T_old) of the level's current solve
@@ -498,6 +619,7 @@ struct tl_sim {
   LedgerDev* led;
   double* partials;
   double* tpart;
+  double* tpart2;       // tile partials of a composite pair's coarse side
   int* gidx;            // padded indices of the coarse interface nodes
   double* gbuf;         // interface gather/scatter staging
   int n_gamma;
@@ -509,7 +631,7 @@ struct tl_sim {
   tl_stats stats;
   long n_macro;
   double theta0;
-  int last_cg_f, last_cg_c;
+  int last_cg_f, last_cg_c, last_cg_x;   // fine, coarse, composite solves
   Profiler prof;   // sampled event timing of the fine CG kernel
   BatchCtx batch;  // one-item batches for this simulation's solves
 };
@@ -766,28 +888,87 @@ void batch_solve(BatchCtx& B, std::vector<StepState*>& list, bool fine,
   }
 }
 
+template <class R>
+CGBufs<R>& coarse_cg(tl_sim* s);
+template <>
+CGBufs<double>& coarse_cg<double>(tl_sim* s) { return s->ccg; }
+template <>
+CGBufs<float>& coarse_cg<float>(tl_sim* s) { return s->ccg32; }
+
+// Composite-grid two-level corrections of the listed simulations (one
+// precision) in batched launches: per simulation a fine job on the window
+// (rows scaled by 1/m, the interface values slaved to the coarse ones) and a
+// coarse job outside the window interior loaded by the reactions of micro
+// steps 1..m-1 (ext), sharing one Newton/CG state.
+template <class R>
+void batch_composite(BatchCtx& B, std::vector<StepState*>& list,
+                     Profiler* prof) {
+  if (list.empty()) return;
+  std::vector<Job<R>> jobs;
+  jobs.reserve(2 * list.size());
+  for (StepState* st : list) {
+    tl_sim* s = st->s;
+    Job<R> f = make_job<R>(s, true, region_window(s), st->dt, s->fprev, s->fF,
+                           nullptr);
+    f.cg = &cg_of<R>(s, true);
+    f.last_cg = &s->last_cg_x;
+    f.what = "composite two-level correction";
+    f.n_newton_x = &s->stats.newton_corr;
+    f.n_cg_x = &s->stats.cg_corr;
+    f.cpl.w = s->win;
+    f.cpl.rscale = 1.0 / st->m;
+    Job<R> c = make_job<R>(s, false, region_outside(s), st->Dt, s->Tn, s->Fout,
+                           s->ext);
+    c.cg = &coarse_cg<R>(s);
+    c.tpart = s->tpart2;
+    c.cpl.w = s->win;
+    c.cpl.rscale = 1.0;
+    c.cpl.gR = s->lam;
+    c.cpl.gDW = s->gdw;
+    c.cpl.gidx = s->gidx;
+    c.cpl.ngamma = s->n_gamma;
+    jobs.push_back(f);
+    jobs.push_back(c);
+  }
+  std::vector<Job<R>*> ptrs;
+  for (Job<R>& j : jobs) ptrs.push_back(&j);
+  solve_batch<R>(B, ptrs, prof, true);
+  for (size_t q = 0; q < list.size(); ++q) {
+    if (jobs[2 * q].failed) fail_step(*list[q], jobs[2 * q].err);
+    ++list[q]->s->stats.fine_solves;
+  }
+}
+
 // Fine solves of the listed simulations, grouped by the precision of their
 // linear solves.
+// `corr`: solves of the two-level correction (also counted there).
 void batch_fine(BatchCtx& B, std::vector<StepState*>& list,
                 const std::function<void(StepState&, Region&, double&,
                                          const double*&)>& told,
-                Profiler* prof) {
+                Profiler* prof, bool corr = false) {
   std::vector<StepState*> f64, f32;
   for (StepState* st : list)
     (st->s->opts.precision == TL_MIXED ? f32 : f64).push_back(st);
+  auto mk = [&](StepState& st, auto j) {
+    if (corr) {
+      j.n_newton_x = &st.s->stats.newton_corr;
+      j.n_cg_x = &st.s->stats.cg_corr;
+    }
+    return j;
+  };
   auto mk64 = [&](StepState& st) {
     Region rg;
     double tau;
     const double* Told;
     told(st, rg, tau, Told);
-    return make_job<double>(st.s, true, rg, tau, Told, st.s->fF, nullptr);
+    return mk(st, make_job<double>(st.s, true, rg, tau, Told, st.s->fF, nullptr));
   };
   auto mk32 = [&](StepState& st) {
     Region rg;
     double tau;
     const double* Told;
     told(st, rg, tau, Told);
-    return make_job<float>(st.s, true, rg, tau, Told, st.s->fF, nullptr);
+    return mk(st, make_job<float>(st.s, true, rg, tau, Told, st.s->fF, nullptr));
   };
   batch_solve<double>(B, f64, true, mk64, prof);
   batch_solve<float>(B, f32, true, mk32, prof);
@@ -917,6 +1098,30 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
     k_copy(s->L, s->ccur, s->Tpred, s->gc.npad);
   }
+  // the composite-grid form: one solve; the reactions of micro steps
+  // 1..m-1 restricted by P^T are its fixed interface load
+  {
+    std::vector<StepState*> c64, c32;
+    for (StepState* st : live(steps)) {
+      tl_sim* s = st->s;
+      if (s->opts.coupling != TL_COUPLE_COMPOSITE) continue;
+      (s->opts.precision == TL_MIXED ? c32 : c64).push_back(st);
+      if (st->m > 1)
+        k_restrict(s->L, s->gf, s->gc, s->win, s->rho, nullptr, -1.0 / st->m,
+                   s->ext);
+      else
+        k_fill(s->L, s->ext, 0.0, s->gc.npad);
+      st->dn_done = true;
+    }
+    batch_composite<double>(B, c64, prof);
+    batch_composite<float>(B, c32, prof);
+    for (StepState* st : live(steps)) {
+      tl_sim* s = st->s;
+      if (s->opts.coupling != TL_COUPLE_COMPOSITE) continue;
+      k_inject(s->L, s->gf, s->gc, s->win, s->fcur, s->ccur);
+      st->it = 1;
+    }
+  }
   for (;;) {
     std::vector<StepState*> list;
     for (StepState* st : live(steps))
@@ -941,7 +1146,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
           tau = st.dt;
           Told = st.s->fprev;
         },
-        prof);
+        prof, true);
     std::vector<StepState*> clist;
     for (StepState* st : list) {
       if (st->failed) continue;
@@ -1008,8 +1213,11 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     s->stats.dn_iters += st->it;
     ++s->stats.micro_steps;
     // bottom heat flow of the last fine step and of the coarse outside solve
-    k_interface_accumulate(L, s->gf, s->win, s->fR, nullptr, 0, -st->dt,
-                           &s->led->bottom, s->partials);
+    // (a composite solve keeps the fine rows scaled by 1/m)
+    const bool comp = s->opts.coupling == TL_COUPLE_COMPOSITE;
+    k_interface_accumulate(L, s->gf, s->win, s->fR, nullptr, 0,
+                           comp ? -st->Dt : -st->dt, &s->led->bottom,
+                           s->partials);
     k_bottom_sum(L, s->gc, s->cR, -st->Dt, &s->led->bottom, s->partials);
     // heat lost through the top by the last fine step and the outside solve
     k_surface_sum(L, s->gf, region_window(s), surf_fine(s), s->fcur, st->dt,
@@ -1096,6 +1304,8 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
     return fail(TL_EINVAL, "invalid tolerance or relaxation");
   if (op->newton_max < 1 || op->cg_max < 1 || op->dn_max < 1)
     return fail(TL_EINVAL, "iteration caps must be >= 1");
+  if (op->coupling != TL_COUPLE_DN && op->coupling != TL_COUPLE_COMPOSITE)
+    return fail(TL_EINVAL, "unknown coupling");
   return TL_OK;
 }
 
@@ -1112,8 +1322,9 @@ struct BatchImpl {
   tl_stats pstats{};  // only the timing and op-byte fields are used
 };
 
+// Items for 2 * max_slots (composite pairs take two), scalars for max_slots.
 size_t batch_tables_bytes(int max_slots) {
-  return align_up(sizeof(SolveItem) * (size_t)max_slots) +
+  return align_up(sizeof(SolveItem) * 2 * (size_t)max_slots) +
          align_up(sizeof(LevelScalars) * (size_t)max_slots);
 }
 
@@ -1123,11 +1334,13 @@ tl_status batch_tables_init(BatchTables* bt, void* dev_area, int max_slots,
   b->prof.stats = &b->pstats;
   char* p = (char*)dev_area;
   b->ctx.d_items = (SolveItem*)p;
-  b->ctx.d_sc = (LevelScalars*)(p + align_up(sizeof(SolveItem) * (size_t)max_slots));
+  b->ctx.d_sc =
+      (LevelScalars*)(p + align_up(sizeof(SolveItem) * 2 * (size_t)max_slots));
   b->ctx.cap = max_slots;
+  b->ctx.item_cap = 2 * max_slots;
   b->ctx.stream = (hipStream_t)hip_stream;
   b->ctx.L.stream = hip_stream;
-  if (hipHostMalloc((void**)&b->ctx.h_items, sizeof(SolveItem) * max_slots,
+  if (hipHostMalloc((void**)&b->ctx.h_items, sizeof(SolveItem) * 2 * max_slots,
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&b->ctx.h_sc, sizeof(LevelScalars) * max_slots,
                     hipHostMallocDefault) != hipSuccess) {
@@ -1312,7 +1525,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->ws = (char*)dev_workspace;
   auto C = [&](int a) { return (double*)(s->ws + lay.off_c[a]); };
   s->Tn = C(0); s->Tpred = C(1); s->ccur = C(2); s->ctrial = C(3);
-  s->lam = C(4); s->dprev = C(5); s->cR = C(6); s->Fall = C(7);
+  s->lam = C(4); s->gdw = C(5); s->cR = C(6); s->Fall = C(7);
   s->Fout = C(8); s->ext = C(9);
   auto cgb64 = [&](auto A) {
     return CGBufs<double>{(double*)A(0), (double*)A(1), (double*)A(2),
@@ -1323,6 +1536,13 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   };
   s->ccg = cgb64([&](int a) { return (void*)C(10 + a); });
   s->cHold = C(22);
+  if (lay.ccg32) {
+    auto A = [&](int a) { return (float*)(s->ws + lay.off_ccg32[a]); };
+    s->ccg32 = CGBufs<float>{A(0), A(1), A(2), {A(3), A(4)}, {A(5), A(6)},
+                             {A(7), A(8)}, A(9), {A(10), A(11)}};
+  } else {
+    s->ccg32 = CGBufs<float>{};
+  }
   auto FD = [&](int a) { return (double*)(s->ws + lay.off_fd[a]); };
   s->fstate = FD(0); s->fprev = FD(1); s->fcur = FD(2); s->ftrial = FD(3);
   s->falt = FD(4); s->fR = FD(5); s->fF = FD(6); s->rho = FD(7);
@@ -1339,6 +1559,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->led = (LedgerDev*)(s->ws + lay.off_ledger);
   s->partials = (double*)(s->ws + lay.off_partials);
   s->tpart = (double*)(s->ws + lay.off_tpart);
+  s->tpart2 = (double*)(s->ws + lay.off_tpart2);
   s->gidx = (int*)(s->ws + lay.off_gidx);
   s->gbuf = (double*)(s->ws + lay.off_gbuf);
   if (hipHostMalloc((void**)&s->h_sc, 2 * sizeof(LevelScalars), hipHostMallocDefault) !=
@@ -1357,6 +1578,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->batch.d_sc = s->sc_c;
   s->batch.h_sc = s->h_sc;
   s->batch.cap = 2;
+  s->batch.item_cap = 2;
   s->batch.stream = s->stream;
   s->batch.L = s->L;
   std::memset(&s->stats, 0, sizeof(s->stats));
@@ -1370,7 +1592,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->n_macro = 0;
   s->theta0 = opts->dn_theta > 0 ? opts->dn_theta
                                  : mesh->refine / (mesh->refine + 1.0);
-  s->last_cg_f = s->last_cg_c = 8;
+  s->last_cg_f = s->last_cg_c = s->last_cg_x = 8;
   int I0, J0;
   window_origin(s->tracks.data(), (int)s->tracks.size(), s->t_start,
                 micro_time(s->t_start, opts->dt_coarse, opts->m_time, 1, 0),
@@ -1494,7 +1716,7 @@ struct CkptHeader {
   int32_t I0, J0;
   int32_t gc_n, gf_n;
   int32_t n_gamma, ncols;
-  int32_t last_cg_f, last_cg_c;
+  int32_t last_cg_f, last_cg_c, last_cg_x, pad;
   int64_t n_macro;
   tl_ledger ledger;
   tl_stats stats;
@@ -1515,8 +1737,8 @@ tl_status tl_save(tl_sim* s, void* host, size_t cap, size_t* used) {
   if (cap < need) return fail(TL_ENOMEM, "checkpoint buffer too small");
   CkptHeader h;
   std::memset(&h, 0, sizeof(h));
-  std::memcpy(h.magic, "TLCKPT2", 8);
-  h.version = 2;
+  std::memcpy(h.magic, "TLCKPT3", 8);
+  h.version = 3;
   h.I0 = s->win.I0;
   h.J0 = s->win.J0;
   h.gc_n = s->gc.nreal;
@@ -1525,6 +1747,7 @@ tl_status tl_save(tl_sim* s, void* host, size_t cap, size_t* used) {
   h.n_gamma = h.ncols ? (int32_t)s->iqn.V[0].size() : 0;
   h.last_cg_f = s->last_cg_f;
   h.last_cg_c = s->last_cg_c;
+  h.last_cg_x = s->last_cg_x;
   h.n_macro = s->n_macro;
   h.ledger = s->ledger;
   h.stats = s->stats;
@@ -1550,7 +1773,7 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
   if (n < sizeof(CkptHeader)) return fail(TL_EINVAL, "checkpoint too short");
   CkptHeader h;
   std::memcpy(&h, host, sizeof(h));
-  if (std::memcmp(h.magic, "TLCKPT2", 8) != 0 || h.version != 2)
+  if (std::memcmp(h.magic, "TLCKPT3", 8) != 0 || h.version != 3)
     return fail(TL_EINVAL, "not a checkpoint of this library");
   if (h.gc_n != s->gc.nreal || h.gf_n != s->gf.nreal)
     return fail(TL_EINVAL, "checkpoint grid sizes differ from this handle");
@@ -1583,6 +1806,7 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
     s->stats = h.stats;
     s->last_cg_f = h.last_cg_f;
     s->last_cg_c = h.last_cg_c;
+    s->last_cg_x = h.last_cg_x;
     // the secant pairs (set_interface above cleared the old ones)
     const double* q = (const double*)(p + ((size_t)s->gc.nreal + s->gf.nreal) * sizeof(double));
     for (int c = 0; c < h.ncols; ++c, q += h.n_gamma)

@@ -52,7 +52,7 @@ class tl_options(C.Structure):
     _fields_ = [("dt_coarse", C.c_double), ("m_time", C.c_int), ("precision", C.c_int),
                 ("face_quad", C.c_int), ("newton_tol", C.c_double), ("cg_rtol", C.c_double),
                 ("dn_tol", C.c_double), ("dn_theta", C.c_double), ("newton_max", C.c_int),
-                ("cg_max", C.c_int), ("dn_max", C.c_int)]
+                ("cg_max", C.c_int), ("dn_max", C.c_int), ("coupling", C.c_int)]
 
 
 class tl_ledger(C.Structure):
@@ -68,7 +68,8 @@ class tl_stats(C.Structure):
                [("fine_dof_steps", C.c_double), ("step_ms", C.c_double),
                 ("fine_op_bytes", C.c_double), ("fine_op_applies", C.c_int64),
                 ("fine_op_timed", C.c_int64), ("fine_op_timed_ms", C.c_double),
-                ("fine_nodes", C.c_int * 3), ("coarse_nodes", C.c_int * 3)]
+                ("fine_nodes", C.c_int * 3), ("coarse_nodes", C.c_int * 3),
+                ("newton_corr", C.c_int64), ("cg_corr", C.c_int64)]
 
 
 class tl_request_info(C.Structure):
@@ -190,7 +191,8 @@ def to_scan(s):
 
 def to_options(o):
     return tl_options(o.dt_coarse, o.m_time, o.precision, o.face_quad, o.newton_tol, o.cg_rtol,
-                      o.dn_tol, o.dn_theta, o.newton_max, o.cg_max, o.dn_max)
+                      o.dn_tol, o.dn_theta, o.newton_max, o.cg_max, o.dn_max,
+                      getattr(o, "coupling", 0))
 
 
 def _stream_ptr(stream):

@@ -1,0 +1,129 @@
+"""GPU parity of both forms of the two-level correction against the FP64
+CPU oracle's Dirichlet-Neumann iteration (the paper's Section 3): the
+composite-grid solve (one Newton solve over the free fine nodes and the
+coarse nodes outside the window interior, the fine interface values slaved
+to the coarse ones; the default) and the GPU's own Dirichlet-Neumann
+iteration with interface quasi-Newton relaxation.  Both reach the oracle's
+discrete solution.  Tolerances: 1e-9 (FP64), 1e-6 (mixed) relative
+max-norm."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests._gpu import say, rel_maxerr, oracle_fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2110_12932_amd import tl  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    tl.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _with(wl, coupling):
+    return replace(wl, options=replace(wl.options, coupling=coupling))
+
+
+def _run(wl, n_macro):
+    say("case", wl.name, "precision", wl.options.precision, "coupling",
+        wl.options.coupling, "macro steps", n_macro)
+    sim = tl.Sim(wl)
+    try:
+        sim.step(n_macro)
+        Tc, _ = sim.temperature(0)
+        Tf, origin = sim.temperature(1)
+        led, st = sim.ledger(), sim.stats()
+    finally:
+        sim.close()
+    return Tc, Tf, origin, led, st
+
+
+def _check_vs_oracle(wl, n_macro, tol, coupling):
+    Tc, Tf, origin, led, st = _run(_with(wl, coupling), n_macro)
+    # the oracle runs the Dirichlet-Neumann iteration, converged far below
+    # the GPU path's tolerances
+    orc = oracle.run(wl, n_macro, newton_tol=1e-10, dn_tol=1e-10)
+    oc, of, oorigin = oracle_fields(orc)
+    assert origin == oorigin
+    ec, ef = rel_maxerr(Tc, oc), rel_maxerr(Tf, of)
+    say("  rel err coarse", ec, "fine", ef, "newton", st["newton_fine"],
+        "cg", st["cg_fine"], "solves", st["fine_solves"])
+    assert ec <= tol and ef <= tol
+    lhs = led["stored"] - led["stored0"]
+    rhs = led["absorbed"] - led["bottom"] - led["surface"] + led["remap"]
+    assert abs(lhs - rhs) <= 1e-8 * abs(led["absorbed"])
+    assert led["absorbed"] == pytest.approx(orc.ledger["absorbed"], rel=1e-12)
+    assert led["stored"] == pytest.approx(orc.ledger["stored"], rel=max(tol, 1e-9))
+    assert led["bottom"] == pytest.approx(orc.ledger["bottom"], rel=max(tol, 1e-7))
+    assert st["window_moves"] == orc.stats["moves"]
+    if coupling == W.COMPOSITE:   # one solve per macro step
+        assert st["dn_iters"] == n_macro
+    else:
+        assert st["dn_iters"] >= n_macro
+    return led, orc
+
+
+COUPLINGS = [pytest.param(W.COMPOSITE, id="composite"), pytest.param(W.DN, id="dn")]
+
+
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_config0_fp64(coupling):
+    _check_vs_oracle(W.config0(), 20, 1e-9, coupling)
+
+
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_config0_mixed(coupling):
+    _check_vs_oracle(W.config0(W.MIXED), 20, 1e-6, coupling)
+
+
+@pytest.mark.parametrize("coupling", COUPLINGS)
+@pytest.mark.parametrize("name", ["r1m1", "r3m2", "fulldepth", "corner"])
+def test_small_cases_fp64(name, coupling):
+    wl = W.small_cases()[name]
+    _check_vs_oracle(wl, wl.n_macro, 1e-9, coupling)
+
+
+@pytest.mark.parametrize("coupling", COUPLINGS)
+@pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
+def test_surface_loss(prec, tol, coupling):
+    wl = W.config0(prec)
+    wl = replace(wl, material=replace(wl.material, h_conv=2.0e4, emissivity=0.8, T_amb=300.0))
+    led, orc = _check_vs_oracle(wl, 12, tol, coupling)
+    assert led["surface"] > 0.0
+    assert led["surface"] == pytest.approx(orc.ledger["surface"], rel=max(tol, 1e-9))
+
+
+def test_composite_equals_dn_on_gpu():
+    """The two GPU forms agree with each other (config 0, FP64)."""
+    a = _run(_with(W.config0(), W.COMPOSITE), 20)
+    b = _run(_with(W.config0(), W.DN), 20)
+    assert rel_maxerr(a[0], b[0]) <= 1e-9 and rel_maxerr(a[1], b[1]) <= 1e-9
+
+
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_checkpoint_roundtrip_bitwise(coupling):
+    wl = _with(W.small_cases()["corner"], coupling)
+    a = tl.Sim(wl)
+    a.step(3)
+    blob = tl.tl_save(a.h)
+    a.step(4)
+    Ta, _ = a.temperature(1)
+    Ca, _ = a.temperature(0)
+    b = tl.Sim(wl)
+    tl.tl_load(b.h, blob)
+    b.step(4)
+    Tb, _ = b.temperature(1)
+    Cb, _ = b.temperature(0)
+    assert np.array_equal(Ta, Tb) and np.array_equal(Ca, Cb)
+    a.close()
+    b.close()

@@ -15,11 +15,7 @@ import pytest
 
 import oracle
 from oracle import twolevel as TW
-from workloads import small_cases, COMPOSITE
-
-
-def _composite(wl):
-    return replace(wl, options=replace(wl.options, coupling=COMPOSITE))
+from workloads import small_cases
 
 
 @pytest.mark.parametrize("name", ["c0", "corner", "fulldepth", "r3m2"])
@@ -27,7 +23,7 @@ def test_composite_equals_dirichlet_neumann(name):
     wl = small_cases()[name]
     n = min(wl.n_macro, 4)
     a = oracle.run(wl, n, newton_tol=1e-11, dn_tol=1e-11)
-    b = oracle.run(_composite(wl), n, newton_tol=1e-11, dn_tol=1e-11)
+    b = oracle.run(wl, n, newton_tol=1e-11, dn_tol=1e-11, composite=True)
     assert a.win.I0 == b.win.I0 and a.win.J0 == b.win.J0
     assert np.abs(a.Tc - b.Tc).max() < 1e-9
     assert np.abs(a.Tf - b.Tf).max() < 1e-9
@@ -38,7 +34,7 @@ def test_composite_equals_dirichlet_neumann(name):
 @pytest.mark.parametrize("name", ["c0", "fulldepth"])
 def test_composite_energy_ledger(name):
     wl = small_cases()[name]
-    sim = oracle.run(_composite(wl), min(wl.n_macro, 6))
+    sim = oracle.run(wl, min(wl.n_macro, 6), composite=True)
     for h in sim.history:
         lhs = h["E_end"] - h["E_start"]
         rhs = h["absorbed"] - h["bottom"] - h["surface"]
@@ -46,9 +42,9 @@ def test_composite_energy_ledger(name):
 
 
 def test_composite_refinement1_is_single_level():
-    wl = _composite(small_cases()["r1m1"])
+    wl = small_cases()["r1m1"]
     n = 6
-    sim = TW.TwoLevel(wl)
+    sim = TW.TwoLevel(wl, composite=True)
     ref = TW.single_level_run(sim.coarse, wl.material, wl.scan, wl.options.dt_coarse, n,
                               tol=1e-11)
     for s in range(n):
@@ -62,7 +58,7 @@ def test_composite_with_surface_loss():
     wl = small_cases()["c0"]
     wl = replace(wl, material=replace(wl.material, h_conv=2e4, emissivity=0.8))
     a = oracle.run(wl, 3, newton_tol=1e-11, dn_tol=1e-11)
-    b = oracle.run(_composite(wl), 3, newton_tol=1e-11, dn_tol=1e-11)
+    b = oracle.run(wl, 3, newton_tol=1e-11, dn_tol=1e-11, composite=True)
     assert np.abs(a.Tc - b.Tc).max() < 1e-9
     assert np.abs(a.Tf - b.Tf).max() < 1e-9
     assert b.ledger["surface"] == pytest.approx(a.ledger["surface"], rel=1e-9)

@@ -90,9 +90,10 @@ class Options:
     for the laser load; tolerances (kelvin for Newton and the two-level
     iteration, relative for CG); two-level relaxation theta (<= 0 selects
     refine/(refine+1)); iteration caps; how the two-level correction is
-    solved: DN (0), the Dirichlet-Neumann iteration, or COMPOSITE (1), one
-    Newton solve on the composite grid with the fine interface values slaved
-    to the coarse ones (the same discrete solution)."""
+    solved: DN (0), the Dirichlet-Neumann iteration, or COMPOSITE (1, the
+    default), one Newton solve on the composite grid with the fine interface
+    values slaved to the coarse ones -- the same discrete solution, without
+    the outer iteration."""
     dt_coarse: float
     m_time: int
     precision: int = FP64
@@ -104,7 +105,7 @@ class Options:
     newton_max: int = 60
     cg_max: int = 500
     dn_max: int = 60
-    coupling: int = 0
+    coupling: int = 1
 
 
 @dataclass
