@@ -44,7 +44,8 @@ Readings adopted where the paper is silent, ambiguous or garbled:
     third of the window length behind the leading edge; clamped inside the
     plate; kept in place while the beam is off.
   * Coarse load: the time average of the surface loads at the m micro times
-    (the intent of the paper's smeared global source, Section 5.2).
+    (the intent of the paper's smeared global source, Section 5.2); with the
+    volume model, the paper's sources themselves (oracle.laser).
   * Top-surface heat loss (Section 2): convection and radiation on the fine
     level's top faces, convection only on the coarse level's (the window's
     faces excluded in the outside solve); lumped over the faces' corners
@@ -196,6 +197,8 @@ class TwoLevel:
         solver for the GPU path does not change the oracle."""
         self.wl = wl
         self.composite = bool(composite)
+        self.volume = getattr(wl.options, "source", 0) == 1
+        self.z_top = wl.mesh.lz
         mesh, mat, opts = wl.mesh, wl.material, wl.options
         if mesh.win_nx > mesh.nx or mesh.win_ny > mesh.ny or mesh.win_nz > mesh.nz:
             raise ValueError("window larger than the plate")
@@ -270,6 +273,15 @@ class TwoLevel:
         m = self.mat
         return S.Surface(area, m.h_conv, 0.0, m.T_amb)
 
+    # -- laser loads ---------------------------------------------------------
+    def fine_load(self, spot):
+        """Load of the window at one micro time: the surface Gaussian, or the
+        volumetric Gaussian of the volume model (oracle.laser)."""
+        if self.volume:
+            depth = self.scan.tracks[spot[5]].depth if spot is not None else 1.0
+            return L.volume_load(self.win.fine, spot, depth, self.z_top)
+        return L.top_load(self.win.fine, spot, self.opts.face_quad)
+
     # -- one macro step (Algorithm 1) ----------------------------------------
     def fine_step(self, T_prev, tau, load, g, guess=None):
         w = self.win
@@ -295,8 +307,14 @@ class TwoLevel:
         w = self.win
         E_start = self.energy()
         spots = [L.laser_at(scan, micro_time(scan, opts, n, j)) for j in range(1, m + 1)]
-        Fc_all = sum(L.top_load(c, s, opts.face_quad) for s in spots) / m
-        Fc_out = sum(L.top_load(c, s, opts.face_quad, w.outside_face) for s in spots) / m
+        if self.volume:
+            boxes = L.swept_boxes(scan, micro_time(scan, opts, n, 0),
+                                  micro_time(scan, opts, n, m), self.z_top)
+            Fc_all = L.box_load(c, boxes)
+            Fc_out = L.box_load(c, boxes, w.outside_e)
+        else:
+            Fc_all = sum(L.top_load(c, s, opts.face_quad) for s in spots) / m
+            Fc_out = sum(L.top_load(c, s, opts.face_quad, w.outside_face) for s in spots) / m
         # predictor over the whole plate
         Tpred, _, it = implicit_step(c, mat, self.Tc, Dt, Fc_all, None, self.bottom_c,
                                      np.full(c.n_nodes, mat.T_bottom), tol=self.newton_tol,
@@ -313,14 +331,14 @@ class TwoLevel:
         sf = self.surf_fine()
         for j in range(1, m):
             g = (1.0 - j / m) * PTn + (j / m) * PTp
-            Ff = L.top_load(w.fine, spots[j - 1], opts.face_quad)
+            Ff = self.fine_load(spots[j - 1])
             T_prev, R = self.fine_step(T_prev, dt, Ff, g)
             rho_sum[w.gamma_f] += R[w.gamma_f]
             bottom -= dt * R[w.bottom_f].sum()
             absorbed += dt * Ff.sum()
             surface += dt * sf.loss(T_prev)
         # two-level correction at t_{n+1}
-        Ff = L.top_load(w.fine, spots[m - 1], opts.face_quad)
+        Ff = self.fine_load(spots[m - 1])
         if self.composite:
             Tf_m, R_m, Tc_new, Rc, it = self.composite_correction(
                 T_prev, dt, Ff, rho_sum, Fc_out, T_prev, Tpred)

@@ -13,7 +13,7 @@ from dataclasses import replace
 import numpy as np
 
 from .spec import (Mesh, Material, Track, ScanPath, Options, Workload,
-                   FP64, MIXED, options_for)
+                   FP64, MIXED, VOLUME, options_for)
 
 UM = 1e-6
 MM = 1e-3
@@ -114,9 +114,25 @@ def config4(precision=MIXED):
                     n_macro)
 
 
+def single_track_3d(precision=FP64):
+    """The paper's three-dimensional single-track example (Section 5.2) with
+    its volumetric local and smeared global sources and its parameters:
+    P = 179.2 W, eta = 0.38, radius 85 um, depth 50 um, 0.8 m/s along x for
+    2 mm on a plate 3 mm long and 1 mm deep (1.5 mm wide here; the width is
+    not given); global h = 100 um, local window 1.2 x 0.5 x 0.1 mm at
+    h = 20 um (refinement 5), local step 1e-4 s and a four times longer
+    global step, 7 macro steps (the track takes 2.5 ms).  The material law is
+    this build's linear one (the paper's IN625 tables are only plotted)."""
+    mesh = Mesh(3.0 * MM, 1.5 * MM, 1.0 * MM, 30, 15, 10, 5, 12, 5, 1)
+    tr = Track(0.5 * MM, 0.75 * MM, 2.5 * MM, 0.75 * MM, speed=0.8, power=179.2,
+               radius=85 * UM, absorptivity=0.38, depth=50 * UM)
+    opts = replace(options_for(precision, 400 * UM, 4), source=VOLUME)
+    return Workload("single_track_3d", mesh, Material(), ScanPath([tr]), opts, 7)
+
+
 def by_name(name, **kw):
     return {"config0": config0, "config1": config1, "config2": config2,
-            "config4": config4}[name](**kw)
+            "config4": config4, "single_track_3d": single_track_3d}[name](**kw)
 
 
 def small_cases():

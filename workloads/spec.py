@@ -8,6 +8,9 @@ MIXED = 1
 DN = 0
 COMPOSITE = 1
 
+SURFACE = 0
+VOLUME = 1
+
 
 @dataclass
 class Mesh:
@@ -60,7 +63,9 @@ def default_material(**kw):
 @dataclass
 class Track:
     """Straight laser pass from (x0,y0) to (x1,y1) on the top surface at
-    `speed` [m/s], beam power [W], radius [m] and absorptivity."""
+    `speed` [m/s], beam power [W], radius [m] and absorptivity; `depth` [m]
+    is the penetration depth of the volumetric source model (unused by the
+    surface model)."""
     x0: float
     y0: float
     x1: float
@@ -69,6 +74,7 @@ class Track:
     power: float
     radius: float
     absorptivity: float
+    depth: float = 0.0
 
 
 @dataclass
@@ -93,7 +99,10 @@ class Options:
     solved: DN (0), the Dirichlet-Neumann iteration, or COMPOSITE (1, the
     default), one Newton solve on the composite grid with the fine interface
     values slaved to the coarse ones -- the same discrete solution, without
-    the outer iteration."""
+    the outer iteration; the laser model: SURFACE (0, default), a Gaussian
+    flux on the top surface on both levels, or VOLUME (1), the paper's
+    volumetric Gaussian on the fine level and a smeared box source on the
+    coarse one (tracks along x or y only)."""
     dt_coarse: float
     m_time: int
     precision: int = FP64
@@ -106,6 +115,7 @@ class Options:
     cg_max: int = 500
     dn_max: int = 60
     coupling: int = 1
+    source: int = 0
 
 
 @dataclass
