@@ -74,11 +74,22 @@ typedef struct {
 } tl_material;
 
 /* One straight laser pass from (x0,y0) to (x1,y1) on the top surface at
- * `speed`.  The absorbed flux is the surface Gaussian
+ * `speed`.  Surface model (TL_SOURCE_SURFACE): the absorbed flux is the
+ * surface Gaussian
  *   q = 3 absorptivity power / (pi radius^2) exp(-3 r^2 / radius^2)
- * (the exponent convention of the paper's source terms, Section 5.2). */
+ * (the exponent convention of the paper's source terms, Section 5.2).
+ * Volume model (TL_SOURCE_VOLUME, the paper's Section 5.2 sources): the
+ * fine level takes the volumetric Gaussian
+ *   A exp(-3 r^2 / radius^2 - 3 (z - z_top)^2 / depth^2),
+ *   A = 6 sqrt(3) absorptivity power / (pi^(3/2) radius^2 depth),
+ * normalised so that the half-space below the surface absorbs
+ * absorptivity * power; the coarse level takes absorptivity power /
+ * (radius depth speed dt_coarse) in the box the beam sweeps during the
+ * macro step (speed dt_coarse along the track, radius across it, depth
+ * below the top).  depth [m] is used by the volume model only. */
 typedef struct {
   double x0, y0, x1, y1, speed, power, radius, absorptivity;
+  double depth;
 } tl_track;
 
 /* Tracks are run back to back starting at t_start; the beam is off before
@@ -100,6 +111,11 @@ typedef struct {
  * solution (to the tolerances). */
 typedef enum { TL_COUPLE_DN = 0, TL_COUPLE_COMPOSITE = 1 } tl_coupling;
 
+/* Laser model (see tl_track).  The volume model needs depth > 0 on every
+ * track and tracks along x or along y (its boxes are axis-aligned), and at
+ * most 8 track pieces per macro step. */
+typedef enum { TL_SOURCE_SURFACE = 0, TL_SOURCE_VOLUME = 1 } tl_source;
+
 /* dt_coarse: macro step; m_time: micro steps per macro step (1..32);
  * face_quad: Gauss points per direction for the surface load (1..4);
  * newton_tol [K]: stop when the applied Newton step has max-norm <= tol;
@@ -109,7 +125,8 @@ typedef enum { TL_COUPLE_DN = 0, TL_COUPLE_COMPOSITE = 1 } tl_coupling;
  * interface quasi-Newton (IQN-ILS) acceleration whose first step is relaxed
  * by refine/(refine+1); *_max: iteration caps.  Any relaxation converges to
  * the same fixed point.  coupling: a tl_coupling value (dn_tol, dn_theta and
- * dn_max apply to TL_COUPLE_DN only). */
+ * dn_max apply to TL_COUPLE_DN only); source: a tl_source value (face_quad
+ * applies to TL_SOURCE_SURFACE only). */
 typedef struct {
   double dt_coarse;
   int m_time;
@@ -118,6 +135,7 @@ typedef struct {
   double newton_tol, cg_rtol, dn_tol, dn_theta;
   int newton_max, cg_max, dn_max;
   int coupling;
+  int source;
 } tl_options;
 
 /* Energy ledger in J (FP64).  stored = sum over coarse nodes of the outside

@@ -3,6 +3,7 @@
 // Gauss-Legendre rules and the structured-grid descriptor.  Built without
 // floating-point contraction so that every decision that depends on these
 // values (laser on/off, window cell) is reproducible.
+#include <algorithm>
 #include <cmath>
 
 #include "tl_internal.h"
@@ -42,6 +43,42 @@ int laser_at(const TrackH* tr, int n, double t_start, double t, double* xc,
   *eta = a.absorptivity;
   *k = found;
   return 1;
+}
+
+int swept_boxes(const TrackH* tr, int n, double t_start, double t0, double t1,
+                BoxSet* out) {
+  out->n = 0;
+  double ts = t_start;
+  for (int k = 0; k < n; ++k) {
+    const TrackH& a = tr[k];
+    const double len = std::hypot(a.x1 - a.x0, a.y1 - a.y0);
+    const double te = ts + len / a.speed;
+    const double lo = std::max(t0, ts), hi = std::min(t1, te);
+    if (hi > lo && len > 0.0) {
+      if (out->n == kMaxBoxes) return -1;
+      const double ux = (a.x1 - a.x0) / len, uy = (a.y1 - a.y0) / len;
+      const double xa = a.x0 + ux * a.speed * (lo - ts);
+      const double ya = a.y0 + uy * a.speed * (lo - ts);
+      const double xb = a.x0 + ux * a.speed * (hi - ts);
+      const double yb = a.y0 + uy * a.speed * (hi - ts);
+      Box& b = out->b[out->n++];
+      if (std::fabs(uy) < 1e-12) {   // along x
+        b.x_lo = std::min(xa, xb);
+        b.x_hi = std::max(xa, xb);
+        b.y_lo = ya - 0.5 * a.radius;
+        b.y_hi = ya + 0.5 * a.radius;
+      } else {                       // along y
+        b.x_lo = xa - 0.5 * a.radius;
+        b.x_hi = xa + 0.5 * a.radius;
+        b.y_lo = std::min(ya, yb);
+        b.y_hi = std::max(ya, yb);
+      }
+      b.depth = a.depth;
+      b.q = a.absorptivity * a.power / (a.radius * a.depth * a.speed * (t1 - t0));
+    }
+    ts = te;
+  }
+  return out->n;
 }
 
 // Window placement: whole coarse cells, flush with the top, centred on the

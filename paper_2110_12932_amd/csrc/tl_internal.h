@@ -60,6 +60,18 @@ constexpr double kSigmaSB = 5.670374419e-8;   // W / (m^2 K^4)
 // a3 = 3 / R^2, and the weight of this position in a time average.
 struct Spot { double xc, yc, q0, a3, weight; };
 
+// Volume laser model (paper Section 5.2).  Local level: the volumetric
+// Gaussian amp * exp(-a3 ((x-xc)^2 + (y-yc)^2) - az (z - z_top)^2) of one
+// spot; global level: constant sources q in axis-aligned boxes (the path the
+// beam sweeps in a macro step), z given as depth below the top surface.
+struct VolSpot { double xc, yc, amp, a3, az; int on; };
+constexpr int kMaxBoxes = 8;
+struct Box { double x_lo, x_hi, y_lo, y_hi, depth, q; };
+struct BoxSet {
+  int n;
+  Box b[kMaxBoxes];
+};
+
 struct SpotSet {
   int n;
   int nq;                  // Gauss points per face direction
@@ -278,6 +290,16 @@ void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,
                   double* ledger_slot, double* partials);
 
+// Volume model loads: F = int Q- phi_i over the grid (its top layer on the
+// plate top), and F = sum over boxes of q int_{box} phi_i over the elements
+// the region keeps (kOutside: outside the window); each adds
+// ledger_scale * sum(F) into *ledger_slot when that is not null.
+void k_volume_load(Launch L, const Geo& g, const VolSpot& sp, double* F,
+                   double ledger_scale, double* ledger_slot, double* partials);
+void k_box_load(Launch L, const Geo& g, const Region& rg, const BoxSet& bs,
+                double* F, double ledger_scale, double* ledger_slot,
+                double* partials);
+
 void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                       double T_bottom, const double* Ta, const double* Tb,
                       double wb, double* Tf);
@@ -327,7 +349,9 @@ void k_unpack(Launch L, const Geo& g, int kind, int elem_bytes,
               const void* padded, void* plain);
 
 // ---- host-side geometry and scan path (tl_host.cpp) -----------------------
-struct TrackH { double x0, y0, x1, y1, speed, power, radius, absorptivity; };
+struct TrackH {
+  double x0, y0, x1, y1, speed, power, radius, absorptivity, depth;
+};
 
 // Beam state at time t: returns 0 when off, else 1 and fills the fields.
 int laser_at(const TrackH* tr, int n, double t_start, double t, double* xc,
@@ -336,6 +360,13 @@ void window_origin(const TrackH* tr, int n, double t_start, double t,
                    double hx, double hy, int nx, int ny, int wx, int wy,
                    int have_current, int cur_I0, int cur_J0, int* I0, int* J0);
 double micro_time(double t_start, double dt, int m, long n, int j);
+// Boxes of the global volume source for the step [t0, t1]: one per piece of
+// track the beam covers, of length v tau along it, width R across it, depth
+// d, with density eta P / (R d v (t1 - t0)).  Tracks run along x or y.
+// Returns the box count, or -1 when the step covers more than kMaxBoxes
+// pieces.
+int swept_boxes(const TrackH* tr, int n, double t_start, double t0, double t1,
+                BoxSet* out);
 void gauss01(int nq, double* x, double* w);
 
 Geo make_geo(int ncx, int ncy, int ncz, double hx, double hy, double hz,

@@ -1467,15 +1467,17 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 // in its support (fewer than r fine cells away on every axis) -- phase 0:
 // the fine residual rows, and sum_k P_kJ^2 of the fine Jacobian diagonal as
 // the preconditioner's share; phases 1 and 2: the fine rows of w = J u of
-// the CG start or of iteration kit.  One wave per interface node.  The
-// support's interface nodes lie on the immersed faces through J; the lanes
-// walk each face's (2r-1)^2 patch, and a node on two faces is taken on the
+// the CG start or of iteration kit.  One workgroup per interface node, one
+// thread per entry of a face patch, so all loads are in flight at once.
+// The support's interface nodes lie on the immersed faces through J; each
+// face's (2r-1)^2 patch is walked, and a node on two faces is taken on the
 // first, so every fine node enters once.  Runs under the same conditions as
 // the coarse side it feeds.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
 couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
                      int round, int phase, int kit) {
+  __shared__ double lds[2 * kBlock / 64];
   const SolveItem& it = items[blockIdx.x / per_item];
   const Couple& cp = it.cp;
   const LevelScalars* sc = it.sc;
@@ -1494,9 +1496,8 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
       if (c.done || kit >= nx.budget) return;
     }
   }
-  const int lane = threadIdx.x & 63;
-  const int q = (blockIdx.x % per_item) * (kBlock / 64) + (threadIdx.x >> 6);
-  if (q >= cp.ngamma) return;   // the whole wave; no barrier follows
+  const int q = blockIdx.x % per_item;
+  if (q >= cp.ngamma) return;   // the whole workgroup
   const Geo& gc = it.g;
   const Geo& gf = cp.go;
   const Window& w = cp.w;
@@ -1508,7 +1509,7 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
   const int ci = r * (I - w.I0), cj = r * (J - w.J0), ck = r * (K - w.K0);
   const R* fw = (const R*)cp.fw[phase == 2 ? 1 - (kit & 1) : 0];
   const R* fdg = (const R*)cp.fdiag;
-  double a0 = 0.0, a1 = 0.0;
+  double a[2] = {0.0, 0.0};
   for (int face = 0; face < 5; ++face) {
     const bool on =
         face == 0 ? ((w.faces & kFx0) && ci == 0)
@@ -1517,7 +1518,7 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
       : face == 3 ? ((w.faces & kFy1) && cj == gf.ny - 1)
                   : ((w.faces & kFz0) && ck == 0);
     if (!on) continue;
-    for (int t = lane; t < span * span; t += 64) {
+    for (int t = threadIdx.x; t < span * span; t += kBlock) {
       const int u = t % span - (r - 1), v = t / span - (r - 1);
       const int fi = face < 2 ? ci : ci + u;
       const int fj = face < 2 ? cj + u : (face < 4 ? cj : cj + v);
@@ -1535,21 +1536,20 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
       const double wt = pweight(fi - ci, fj - cj, fk - ck, r);
       const int fn = pidx(gf, fi, fj, fk);
       if (phase == 0) {
-        a0 += wt * cp.fR[fn];
-        a1 += wt * wt * (double)fdg[fn];
+        a[0] += wt * cp.fR[fn];
+        a[1] += wt * wt * (double)fdg[fn];
       } else {
-        a0 += wt * (double)fw[fn];
+        a[0] += wt * (double)fw[fn];
       }
     }
   }
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
-  if (lane == 0) {
+  block_sum<2>(a, lds);
+  if (threadIdx.x == 0) {
     if (phase == 0) {
-      cp.gR[n] = a0;
-      ((double*)cp.gDW)[n] = a1;
+      cp.gR[n] = a[0];
+      ((double*)cp.gDW)[n] = a[1];
     } else {
-      ((R*)cp.gDW)[n] = (R)a0;
+      ((R*)cp.gDW)[n] = (R)a[0];
     }
   }
 }
@@ -1639,7 +1639,7 @@ void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
 template <class R>
 void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
                      int max_gamma, int round, int phase, int kit) {
-  const int per = std::max(1, (max_gamma + kBlock / 64 - 1) / (kBlock / 64));
+  const int per = std::max(1, max_gamma);   // one workgroup per interface node
   hipLaunchKernelGGL(couple_gather_kernel<R>, dim3(n_items * per),
                      dim3(kBlock), 0, (hipStream_t)L.stream, coarse_items, per,
                      round, phase, kit);
@@ -1750,6 +1750,128 @@ void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
   hipLaunchKernelGGL(laser_load_kernel, dim3(nb), dim3(kBlock), 0,
                      (hipStream_t)L.stream, g, spots, fI0, fI1, fJ0, fJ1, F,
                      partials);
+  if (ledger_slot != nullptr)
+    finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, ledger_scale,
+                 ledger_slot, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Volume laser model (paper Section 5.2).  Depths are measured from the top
+// node layer (the plate top on both levels): node layer k sits at
+// zeta = (k - (nz - 1)) hz <= 0.
+// ---------------------------------------------------------------------------
+// int over [a, b] of exp(-alpha (x - c)^2) and of x exp(-alpha (x - c)^2)
+__device__ inline void gauss_moments(double a, double b, double c, double alpha,
+                                     double& m0, double& m1) {
+  const double sa = sqrt(alpha);
+  m0 = 0.5 * sqrt(M_PI / alpha) * (erf(sa * (b - c)) - erf(sa * (a - c)));
+  m1 = c * m0 - (exp(-alpha * (b - c) * (b - c)) -
+                 exp(-alpha * (a - c) * (a - c))) / (2.0 * alpha);
+}
+// int exp(-alpha (x - c)^2) phi_i(x) dx for the hat function of node i of a
+// line of n nodes x0 + i h
+__device__ inline double hat_gauss(int i, int n, double h, double x0, double c,
+                                   double alpha) {
+  const double xi = x0 + i * h;
+  double G = 0.0, m0, m1;
+  if (i > 0) {
+    gauss_moments(xi - h, xi, c, alpha, m0, m1);
+    G += (m1 - (xi - h) * m0) / h;
+  }
+  if (i < n - 1) {
+    gauss_moments(xi, xi + h, c, alpha, m0, m1);
+    G += ((xi + h) * m0 - m1) / h;
+  }
+  return G;
+}
+
+// F_i = int Q- phi_i dV: the Gaussian and the Q1 basis factor by axis, so
+// F_i = amp Gx(i) Gy(j) Gz(k) with the closed forms above.
+__global__ void __launch_bounds__(kBlock)
+volume_load_kernel(Geo g, VolSpot sp, double* __restrict__ F,
+                   double* partials) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    double f = 0.0;
+    if (sp.on) {
+      f = sp.amp * hat_gauss(i, g.nx, g.hx, g.x0, sp.xc, sp.a3) *
+          hat_gauss(j, g.ny, g.hy, g.y0, sp.yc, sp.a3) *
+          hat_gauss(k, g.nz, g.hz, -(g.nz - 1) * g.hz, 0.0, sp.az);
+    }
+    F[pidx(g, i, j, k)] = f;
+    acc[0] += f;
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
+}
+
+void k_volume_load(Launch L, const Geo& g, const VolSpot& sp, double* F,
+                   double ledger_scale, double* ledger_slot, double* partials) {
+  const int nb = grid_for(g.nreal);
+  hipLaunchKernelGGL(volume_load_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, sp, F, partials);
+  if (ledger_slot != nullptr)
+    finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, ledger_scale,
+                 ledger_slot, 0);
+}
+
+// int over [lo, hi] ∩ [e0, e0 + h] of the falling and the rising 1D basis
+// function of the cell [e0, e0 + h]
+__device__ inline void hat_box(double lo, double hi, double e0, double h,
+                               double& fall, double& rise) {
+  const double a = fmin(fmax(lo, e0), e0 + h);
+  const double b = fmin(fmax(hi, e0), e0 + h);
+  rise = ((b - e0) * (b - e0) - (a - e0) * (a - e0)) / (2.0 * h);
+  fall = (b - a) - rise;
+}
+
+// F_i = sum over boxes of q int_{box ∩ e} phi_i over the elements e around
+// node i that the region keeps: the part of an element inside an
+// axis-aligned box is a box, and the trilinear basis integrates over it as
+// a product of 1D integrals.
+__global__ void __launch_bounds__(kBlock)
+box_load_kernel(Geo g, Region rg, BoxSet bs, double* __restrict__ F,
+                double* partials) {
+  __shared__ double lds[kBlock / 64];
+  double acc[1] = {0.0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    double f = 0.0;
+    for (int e = 0; e < 8; ++e) {
+      const int a = e & 1, b = (e >> 1) & 1, c = e >> 2;
+      // the element of which this node is corner (a, b, c)
+      const int ei = i - a, ej = j - b, ek = k - c;
+      if (!elem_active(g, rg, ei, ej, ek)) continue;
+      const double ex = g.x0 + ei * g.hx, ey = g.y0 + ej * g.hy;
+      const double ez = (ek - (g.nz - 1)) * g.hz;
+      for (int q = 0; q < bs.n; ++q) {
+        const Box& B = bs.b[q];
+        double fx0, fx1, fy0, fy1, fz0, fz1;
+        hat_box(B.x_lo, B.x_hi, ex, g.hx, fx0, fx1);
+        hat_box(B.y_lo, B.y_hi, ey, g.hy, fy0, fy1);
+        hat_box(-B.depth, 0.0, ez, g.hz, fz0, fz1);
+        f += B.q * (a ? fx1 : fx0) * (b ? fy1 : fy0) * (c ? fz1 : fz0);
+      }
+    }
+    F[pidx(g, i, j, k)] = f;
+    acc[0] += f;
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
+}
+
+void k_box_load(Launch L, const Geo& g, const Region& rg, const BoxSet& bs,
+                double* F, double ledger_scale, double* ledger_slot,
+                double* partials) {
+  const int nb = grid_for(g.nreal);
+  hipLaunchKernelGGL(box_load_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, g, rg, bs, F, partials);
   if (ledger_slot != nullptr)
     finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, ledger_scale,
                  ledger_slot, 0);

@@ -756,6 +756,67 @@ SpotSet make_spots(const tl_sim* s, long n, int j0, int j1, double weight) {
   return sp;
 }
 
+// The volume model's local source at micro time j of macro step n.
+VolSpot vol_spot(const tl_sim* s, long n, int j) {
+  VolSpot v{};
+  const double t =
+      micro_time(s->t_start, s->opts.dt_coarse, s->opts.m_time, n, j);
+  double xc, yc, P, Rr, eta;
+  int k;
+  if (!laser_at(s->tracks.data(), (int)s->tracks.size(), s->t_start, t, &xc,
+                &yc, &P, &Rr, &eta, &k))
+    return v;
+  const double d = s->tracks[k].depth;
+  v.xc = xc;
+  v.yc = yc;
+  v.amp = 6.0 * std::sqrt(3.0) * eta * P / (std::pow(M_PI, 1.5) * Rr * Rr * d);
+  v.a3 = 3.0 / (Rr * Rr);
+  v.az = 3.0 / (d * d);
+  v.on = 1;
+  return v;
+}
+
+// Fine load at micro time j of macro step n into fF, booked as absorbed
+// over dt: the surface Gaussian, or the volume model's Gaussian.
+void fine_load(tl_sim* s, long n, int j, double dt) {
+  if (s->opts.source == TL_SOURCE_VOLUME) {
+    k_volume_load(s->L, s->gf, vol_spot(s, n, j), s->fF, dt, &s->led->absorbed,
+                  s->partials);
+  } else {
+    SpotSet sp = make_spots(s, n, j, j, 1.0);
+    k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, &s->led->absorbed,
+                 s->partials);
+  }
+}
+
+// Coarse loads of macro step n: Fall over all elements (the predictor) and
+// Fout outside the window (the correction, booked as absorbed over Dt) --
+// the time average of the surface loads at the micro times, or the volume
+// model's swept boxes.  Returns false when the step covers more track
+// pieces than a box set holds.
+bool coarse_loads(tl_sim* s, long n, int m, double Dt) {
+  const Window& w = s->win;
+  if (s->opts.source == TL_SOURCE_VOLUME) {
+    BoxSet bs;
+    const double t0 = micro_time(s->t_start, Dt, m, n, 0);
+    const double t1 = micro_time(s->t_start, Dt, m, n, m);
+    if (swept_boxes(s->tracks.data(), (int)s->tracks.size(), s->t_start, t0,
+                    t1, &bs) < 0)
+      return false;
+    k_box_load(s->L, s->gc, region_all(), bs, s->Fall, 0.0, nullptr,
+               s->partials);
+    k_box_load(s->L, s->gc, region_outside(s), bs, s->Fout, Dt,
+               &s->led->absorbed, s->partials);
+    return true;
+  }
+  SpotSet avg = make_spots(s, n, 1, m, 1.0 / m);
+  k_laser_load(s->L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr,
+               s->partials);
+  k_laser_load(s->L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy, s->Fout,
+               Dt, &s->led->absorbed, s->partials);
+  return true;
+}
+
 void energy_now(tl_sim* s, double* slot) {
   k_energy(s->L, s->gc, region_outside(s), s->mat, s->Tn, slot, 1,
            s->partials);
@@ -1030,11 +1091,9 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
                 "hipMemcpyAsync(remap)");
       ++s->stats.window_moves;
     }
-    const Window& w = s->win;
-    SpotSet avg = make_spots(s, st.n, 1, st.m, 1.0 / st.m);
-    k_laser_load(L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr, s->partials);
-    k_laser_load(L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy, s->Fout,
-                 st.Dt, &led->absorbed, s->partials);
+    if (!coarse_loads(s, st.n, st.m, st.Dt))
+      fail_step(st, "more track pieces in one macro step than the volume "
+                    "source holds");
     k_copy(L, s->ccur, s->Tn, s->gc.npad);
   }
   // coarse predictor over the whole plate
@@ -1065,9 +1124,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
       k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
       k_fine_dirichlet(s->L, s->gf, s->gc, s->win, s->mat_in.T_bottom, s->Tn,
                        s->Tpred, (double)j / st->m, s->fcur);
-      SpotSet sp = make_spots(s, st->n, j, j, 1.0);
-      k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, st->dt,
-                   &s->led->absorbed, s->partials);
+      fine_load(s, st->n, j, st->dt);
     }
     batch_fine(
         B, list,
@@ -1091,9 +1148,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
   // 4. two-level correction at t_{n+1}
   for (StepState* st : live(steps)) {
     tl_sim* s = st->s;
-    SpotSet sp = make_spots(s, st->n, st->m, st->m, 1.0);
-    k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, st->dt, &s->led->absorbed,
-                 s->partials);
+    fine_load(s, st->n, st->m, st->dt);
     k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
     k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
     k_copy(s->L, s->ccur, s->Tpred, s->gc.npad);
@@ -1286,10 +1341,16 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
   for (int q = 0; q < sp->n_tracks; ++q) {
     const tl_track& t = sp->tracks[q];
     if (!finite_all({t.x0, t.y0, t.x1, t.y1, t.speed, t.power, t.radius,
-                     t.absorptivity}) ||
+                     t.absorptivity, t.depth}) ||
         t.speed <= 0 || t.radius <= 0 || t.power < 0 || t.absorptivity < 0)
       return fail(TL_EINVAL, "invalid track " + std::to_string(q));
+    if (op->source == TL_SOURCE_VOLUME &&
+        (t.depth <= 0 || (t.x0 != t.x1 && t.y0 != t.y1)))
+      return fail(TL_EINVAL, "the volume source needs depth > 0 and tracks "
+                             "along x or y (track " + std::to_string(q) + ")");
   }
+  if (op->source != TL_SOURCE_SURFACE && op->source != TL_SOURCE_VOLUME)
+    return fail(TL_EINVAL, "unknown source model");
   if (!std::isfinite(op->dt_coarse) || op->dt_coarse <= 0)
     return fail(TL_EINVAL, "dt_coarse must be positive");
   if (op->m_time < 1 || op->m_time > kMaxSpots)
@@ -1501,7 +1562,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   for (int q = 0; q < scan->n_tracks; ++q) {
     const tl_track& t = scan->tracks[q];
     s->tracks.push_back(TrackH{t.x0, t.y0, t.x1, t.y1, t.speed, t.power,
-                               t.radius, t.absorptivity});
+                               t.radius, t.absorptivity, t.depth});
   }
   MatDev& m = s->mat;
   m.rho = material->rho;

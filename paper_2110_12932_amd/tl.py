@@ -41,7 +41,7 @@ class tl_material(C.Structure):
 
 class tl_track(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("x0", "y0", "x1", "y1", "speed", "power", "radius",
-                                          "absorptivity")]
+                                          "absorptivity", "depth")]
 
 
 class tl_scan_path(C.Structure):
@@ -52,7 +52,8 @@ class tl_options(C.Structure):
     _fields_ = [("dt_coarse", C.c_double), ("m_time", C.c_int), ("precision", C.c_int),
                 ("face_quad", C.c_int), ("newton_tol", C.c_double), ("cg_rtol", C.c_double),
                 ("dn_tol", C.c_double), ("dn_theta", C.c_double), ("newton_max", C.c_int),
-                ("cg_max", C.c_int), ("dn_max", C.c_int), ("coupling", C.c_int)]
+                ("cg_max", C.c_int), ("dn_max", C.c_int), ("coupling", C.c_int),
+                ("source", C.c_int)]
 
 
 class tl_ledger(C.Structure):
@@ -182,7 +183,8 @@ def to_material(m):
 
 def to_scan(s):
     arr = (tl_track * max(1, len(s.tracks)))(*[
-        tl_track(t.x0, t.y0, t.x1, t.y1, t.speed, t.power, t.radius, t.absorptivity)
+        tl_track(t.x0, t.y0, t.x1, t.y1, t.speed, t.power, t.radius, t.absorptivity,
+                 t.depth)
         for t in s.tracks])
     sp = tl_scan_path(len(s.tracks), arr, s.t_start)
     sp._keep = arr
@@ -192,7 +194,7 @@ def to_scan(s):
 def to_options(o):
     return tl_options(o.dt_coarse, o.m_time, o.precision, o.face_quad, o.newton_tol, o.cg_rtol,
                       o.dn_tol, o.dn_theta, o.newton_max, o.cg_max, o.dn_max,
-                      getattr(o, "coupling", 0))
+                      o.coupling, o.source)
 
 
 def _stream_ptr(stream):

@@ -72,6 +72,14 @@ class _FakeWorkspace:
     (lambda wl: replace(wl, options=replace(wl.options, m_time=0)), "m_time"),
     (lambda wl: replace(wl, options=replace(wl.options, face_quad=7)), "face_quad"),
     (lambda wl: replace(wl, options=replace(wl.options, dt_coarse=-1.0)), "dt_coarse"),
+    (lambda wl: replace(wl, options=replace(wl.options, coupling=5)), "coupling"),
+    (lambda wl: replace(wl, options=replace(wl.options, source=2)), "source"),
+    # the volume model needs a depth and tracks along x or y
+    (lambda wl: replace(wl, options=replace(wl.options, source=W.VOLUME)), "volume"),
+    (lambda wl: replace(W.small_cases()["corner"],
+                        scan=W.ScanPath([replace(t, depth=40e-6)
+                                         for t in W.small_cases()["corner"].scan.tracks]),
+                        options=replace(wl.options, source=W.VOLUME)), "volume"),
 ])
 def test_create_rejects_invalid_input(mutate, what):
     wl = mutate(W.config0())
