@@ -53,6 +53,7 @@ Readings adopted where the paper is silent, ambiguous or garbled:
     E_{n+1} - E_n = absorbed - bottom - surface + remap.
 """
 import math
+from dataclasses import replace
 
 import numpy as np
 import scipy.sparse as sp
@@ -197,6 +198,9 @@ class TwoLevel:
         solver for the GPU path does not change the oracle."""
         self.wl = wl
         self.composite = bool(composite)
+        # the alternate global formulation is a different discrete problem,
+        # so the oracle follows the workload there
+        self.alternate = getattr(wl.options, "coupling", 0) == 2
         self.volume = getattr(wl.options, "source", 0) == 1
         self.z_top = wl.mesh.lz
         mesh, mat, opts = wl.mesh, wl.material, wl.options
@@ -220,6 +224,11 @@ class TwoLevel:
         self.Tf = np.full(self.win.fine.n_nodes, mat.T_init)
         self.Tf[self.win.bottom_f] = mat.T_bottom
         self.area_c = S.top_area(c)
+        # the alternate formulation's global problem: all elements, the same
+        # law without latent heat (the paper keeps latent heat in the local
+        # problem only)
+        self.mat_global = replace(mat, latent=0.0) if self.alternate else mat
+        self.mass_all = G.lumped_mass(c)
         self.ledger = dict(stored=self.energy(), absorbed=0.0, bottom=0.0, remap=0.0,
                            surface=0.0, stored0=0.0)
         self.ledger["stored0"] = self.ledger["stored"]
@@ -229,7 +238,10 @@ class TwoLevel:
 
     # -- energy ledger ------------------------------------------------------
     def energy(self):
-        """E = sum_J m_J^out H(T+_J) + sum_k m_k H(T-_k)."""
+        """E = sum_J m_J^out H(T+_J) + sum_k m_k H(T-_k); with the alternate
+        formulation the global problem's own energy, sum_J m_J H+(T+_J)."""
+        if self.alternate:
+            return float(np.dot(self.mass_all, M.enthalpy(self.Tc, self.mat_global)))
         w = self.win
         return float(np.dot(w.mass_out, M.enthalpy(self.Tc, self.mat))
                      + np.dot(w.mass_f, M.enthalpy(self.Tf, self.mat)))
@@ -315,6 +327,8 @@ class TwoLevel:
         else:
             Fc_all = sum(L.top_load(c, s, opts.face_quad) for s in spots) / m
             Fc_out = sum(L.top_load(c, s, opts.face_quad, w.outside_face) for s in spots) / m
+        if self.alternate:
+            return self._step_alternate(spots, Fc_all, E_start)
         # predictor over the whole plate
         Tpred, _, it = implicit_step(c, mat, self.Tc, Dt, Fc_all, None, self.bottom_c,
                                      np.full(c.n_nodes, mat.T_bottom), tol=self.newton_tol,
@@ -372,6 +386,47 @@ class TwoLevel:
             raise NoConvergence("two-level iteration did not converge")
         self._finish(Tf_m, R_m, Tc_new, Rc, it, Ff, Fc_out, absorbed, bottom, surface,
                      E_start)
+
+    def _step_alternate(self, spots, Fc_all, E_start):
+        """A macro step with the alternate global formulation of Section 3:
+        the global problem over the whole plate with the global law and only
+        the interface jump term, (kappa+ - kappa-) dT-/dn on gamma, which is
+        zero here since both levels share kappa(T); the global step is then
+        the coarse implicit step itself, and the local problem takes all m
+        micro steps with the time-blended Dirichlet data (Algorithm 1, with
+        no correction to iterate).  T+ is the global solution everywhere.
+        The ledger is the global problem's: stored = sum m_J H+(T+_J),
+        absorbed = the global load, bottom = the global bottom reactions,
+        surface = the global top-surface loss."""
+        opts, mat, c, w = self.opts, self.mat, self.coarse, self.win
+        n, m, Dt = self.n, opts.m_time, opts.dt_coarse
+        dt = Dt / m
+        surf_c = self.surf_coarse(self.area_c)
+        Tnew, Rc, it = implicit_step(c, self.mat_global, self.Tc, Dt, Fc_all, None,
+                                     self.bottom_c, np.full(c.n_nodes, mat.T_bottom),
+                                     tol=self.newton_tol, maxit=opts.newton_max,
+                                     surface=surf_c)
+        self.stats["newton_coarse"] += it
+        self.stats["coarse_solves"] += 1
+        PTn, PTp = w.P @ self.Tc, w.P @ Tnew
+        T_prev = self.Tf
+        for j in range(1, m + 1):
+            g = (1.0 - j / m) * PTn + (j / m) * PTp
+            T_prev, _ = self.fine_step(T_prev, dt, self.fine_load(spots[j - 1]), g)
+        self.Tc = Tnew
+        self.Tf = T_prev
+        self.n += 1
+        absorbed = Dt * Fc_all.sum()
+        bottom = -Dt * Rc[self.bottom_c].sum()
+        surface = Dt * surf_c.loss(Tnew)
+        E_end = self.energy()
+        self.ledger["stored"] = E_end
+        self.ledger["absorbed"] += absorbed
+        self.ledger["bottom"] += bottom
+        self.ledger["surface"] += surface
+        self.history.append(dict(n=self.n, E_start=E_start, E_end=E_end, absorbed=absorbed,
+                                 bottom=bottom, surface=surface, dn_iters=0,
+                                 origin=(w.I0, w.J0)))
 
     def composite_correction(self, T_prev, dt, Ff, rho_sum, Fc_out, guess_f, guess_c):
         """The two-level correction at t_{n+1} as one nonlinear solve on the

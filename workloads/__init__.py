@@ -11,12 +11,13 @@ large-build cases on a laser powder-bed plate (Section 5 of the paper
 describes the single-track and multi-track experiments this imitates).
 """
 from .spec import (Mesh, Material, Track, ScanPath, Options, Workload,
-                   FP64, MIXED, DN, COMPOSITE, SURFACE, VOLUME, default_material,
+                   FP64, MIXED, DN, COMPOSITE, ALTERNATE, SURFACE, VOLUME, default_material,
                    options_for)
 from .configs import (config0, config1, config2, config3_requests, config4,
                       single_track_3d, by_name, small_cases, k2_sweep_field)
 
 __all__ = ["Mesh", "Material", "Track", "ScanPath", "Options", "Workload", "options_for",
-           "FP64", "MIXED", "DN", "COMPOSITE", "SURFACE", "VOLUME", "default_material", "config0", "config1",
+           "FP64", "MIXED", "DN", "COMPOSITE", "ALTERNATE", "SURFACE", "VOLUME",
+           "default_material", "config0", "config1",
            "config2", "config3_requests", "config4", "single_track_3d", "by_name",
            "small_cases", "k2_sweep_field"]

@@ -7,6 +7,7 @@ MIXED = 1
 
 DN = 0
 COMPOSITE = 1
+ALTERNATE = 2
 
 SURFACE = 0
 VOLUME = 1
@@ -99,7 +100,9 @@ class Options:
     solved: DN (0), the Dirichlet-Neumann iteration, or COMPOSITE (1, the
     default), one Newton solve on the composite grid with the fine interface
     values slaved to the coarse ones -- the same discrete solution, without
-    the outer iteration; the laser model: SURFACE (0, default), a Gaussian
+    the outer iteration -- or ALTERNATE (2), the paper's alternate global
+    formulation (the global problem over the whole plate without latent
+    heat, the local problem driven by it, no feedback); the laser model: SURFACE (0, default), a Gaussian
     flux on the top surface on both levels, or VOLUME (1), the paper's
     volumetric Gaussian on the fine level and a smeared box source on the
     coarse one (tracks along x or y only)."""
