@@ -108,8 +108,19 @@ typedef struct {
  * holds at its fixed point, over the free fine nodes and the coarse nodes
  * outside the window interior, the fine interface values slaved to the
  * coarse ones by the trilinear prolongation.  Both give the same discrete
- * solution (to the tolerances). */
-typedef enum { TL_COUPLE_DN = 0, TL_COUPLE_COMPOSITE = 1 } tl_coupling;
+ * solution (to the tolerances).  TL_COUPLE_ALTERNATE: the paper's alternate
+ * global formulation -- the global problem over the whole plate keeps only
+ * the interface jump term, zero here since both levels share kappa(T), and
+ * (as in the paper) no latent heat; the local problem takes all m micro
+ * steps with the blended global data and does not feed back.  It is a
+ * different discrete problem; its ledger (tl_get_ledger) is the global
+ * problem's: stored = sum over coarse nodes of the lumped mass times H(T+)
+ * without latent heat, absorbed / bottom / surface of the global solve. */
+typedef enum {
+  TL_COUPLE_DN = 0,
+  TL_COUPLE_COMPOSITE = 1,
+  TL_COUPLE_ALTERNATE = 2
+} tl_coupling;
 
 /* Laser model (see tl_track).  The volume model needs depth > 0 on every
  * track and tracks along x or along y (its boxes are axis-aligned), and at

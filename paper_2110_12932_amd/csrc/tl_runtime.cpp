@@ -594,6 +594,8 @@ struct tl_sim {
   tl_material mat_in;
   tl_options opts;
   MatDev mat;
+  MatDev mat_global;   // the coarse level's law (no latent heat with the
+                       // alternate global formulation)
   std::vector<TrackH> tracks;
   double t_start;
   Interface iqn;   // two-level secant pairs, kept across macro steps
@@ -756,6 +758,10 @@ SpotSet make_spots(const tl_sim* s, long n, int j0, int j1, double weight) {
   return sp;
 }
 
+bool alternate(const tl_sim* s) {
+  return s->opts.coupling == TL_COUPLE_ALTERNATE;
+}
+
 // The volume model's local source at micro time j of macro step n.
 VolSpot vol_spot(const tl_sim* s, long n, int j) {
   VolSpot v{};
@@ -779,13 +785,14 @@ VolSpot vol_spot(const tl_sim* s, long n, int j) {
 // Fine load at micro time j of macro step n into fF, booked as absorbed
 // over dt: the surface Gaussian, or the volume model's Gaussian.
 void fine_load(tl_sim* s, long n, int j, double dt) {
+  // the alternate formulation's ledger is the global problem's
+  double* slot = alternate(s) ? nullptr : &s->led->absorbed;
   if (s->opts.source == TL_SOURCE_VOLUME) {
-    k_volume_load(s->L, s->gf, vol_spot(s, n, j), s->fF, dt, &s->led->absorbed,
+    k_volume_load(s->L, s->gf, vol_spot(s, n, j), s->fF, dt, slot,
                   s->partials);
   } else {
     SpotSet sp = make_spots(s, n, j, j, 1.0);
-    k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, &s->led->absorbed,
-                 s->partials);
+    k_laser_load(s->L, s->gf, sp, 0, 0, 0, 0, s->fF, dt, slot, s->partials);
   }
 }
 
@@ -796,6 +803,8 @@ void fine_load(tl_sim* s, long n, int j, double dt) {
 // pieces than a box set holds.
 bool coarse_loads(tl_sim* s, long n, int m, double Dt) {
   const Window& w = s->win;
+  // the alternate formulation books the global load itself
+  const bool alt = alternate(s);
   if (s->opts.source == TL_SOURCE_VOLUME) {
     BoxSet bs;
     const double t0 = micro_time(s->t_start, Dt, m, n, 0);
@@ -803,21 +812,28 @@ bool coarse_loads(tl_sim* s, long n, int m, double Dt) {
     if (swept_boxes(s->tracks.data(), (int)s->tracks.size(), s->t_start, t0,
                     t1, &bs) < 0)
       return false;
-    k_box_load(s->L, s->gc, region_all(), bs, s->Fall, 0.0, nullptr,
-               s->partials);
-    k_box_load(s->L, s->gc, region_outside(s), bs, s->Fout, Dt,
-               &s->led->absorbed, s->partials);
+    k_box_load(s->L, s->gc, region_all(), bs, s->Fall, alt ? Dt : 0.0,
+               alt ? &s->led->absorbed : nullptr, s->partials);
+    if (!alt)
+      k_box_load(s->L, s->gc, region_outside(s), bs, s->Fout, Dt,
+                 &s->led->absorbed, s->partials);
     return true;
   }
   SpotSet avg = make_spots(s, n, 1, m, 1.0 / m);
-  k_laser_load(s->L, s->gc, avg, 0, 0, 0, 0, s->Fall, 0.0, nullptr,
-               s->partials);
-  k_laser_load(s->L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy, s->Fout,
-               Dt, &s->led->absorbed, s->partials);
+  k_laser_load(s->L, s->gc, avg, 0, 0, 0, 0, s->Fall, alt ? Dt : 0.0,
+               alt ? &s->led->absorbed : nullptr, s->partials);
+  if (!alt)
+    k_laser_load(s->L, s->gc, avg, w.I0, w.I0 + w.wx, w.J0, w.J0 + w.wy,
+                 s->Fout, Dt, &s->led->absorbed, s->partials);
   return true;
 }
 
 void energy_now(tl_sim* s, double* slot) {
+  if (alternate(s)) {   // the global problem's own energy
+    k_energy(s->L, s->gc, region_all(), s->mat_global, s->Tn, slot, 1,
+             s->partials);
+    return;
+  }
   k_energy(s->L, s->gc, region_outside(s), s->mat, s->Tn, slot, 1,
            s->partials);
   k_energy(s->L, s->gf, region_window(s), s->mat, s->fstate, slot, 0,
@@ -883,7 +899,7 @@ Job<R> make_job(tl_sim* s, bool fine, const Region& rg, double tau,
   Job<R> j;
   j.g = fine ? s->gf : s->gc;
   j.rg = rg;
-  j.m = s->mat;
+  j.m = fine ? s->mat : s->mat_global;
   j.sf = fine ? surf_fine(s) : surf_coarse(s);
   j.tau = tau;
   j.Told = Told;
@@ -1112,13 +1128,17 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     std::swap(s->Tpred, s->ccur);
     k_copy(s->L, s->fprev, s->fstate, s->gf.npad);
   }
-  // 3. micro steps j = 1..m-1 with blended Dirichlet data
-  int mmax = 1;
-  for (StepState& st : steps) mmax = std::max(mmax, st.m);
-  for (int j = 1; j < mmax; ++j) {
+  // 3. micro steps j = 1..m-1 with blended Dirichlet data (j = 1..m with
+  // the alternate formulation, which has no correction to iterate)
+  auto last_micro = [](const StepState* st) {
+    return alternate(st->s) ? st->m : st->m - 1;
+  };
+  int jmax = 0;
+  for (StepState* st : live(steps)) jmax = std::max(jmax, last_micro(st));
+  for (int j = 1; j <= jmax; ++j) {
     std::vector<StepState*> list;
     for (StepState* st : live(steps))
-      if (j < st->m) list.push_back(st);
+      if (j <= last_micro(st)) list.push_back(st);
     for (StepState* st : list) {
       tl_sim* s = st->s;
       k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
@@ -1137,17 +1157,35 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     for (StepState* st : list) {
       if (st->failed) continue;
       tl_sim* s = st->s;
-      k_interface_accumulate(s->L, s->gf, s->win, s->fR, s->rho, j == 1 ? 1 : 0,
-                             -st->dt, &s->led->bottom, s->partials);
-      k_surface_sum(s->L, s->gf, region_window(s), surf_fine(s), s->fcur,
-                    st->dt, &s->led->surface, s->partials);
+      if (!alternate(s)) {
+        k_interface_accumulate(s->L, s->gf, s->win, s->fR, s->rho,
+                               j == 1 ? 1 : 0, -st->dt, &s->led->bottom,
+                               s->partials);
+        k_surface_sum(s->L, s->gf, region_window(s), surf_fine(s), s->fcur,
+                      st->dt, &s->led->surface, s->partials);
+      }
       std::swap(s->fprev, s->fcur);
       ++s->stats.micro_steps;
     }
   }
+  // the alternate formulation: the predictor is the global step, the last
+  // micro step the local one; the global problem's ledger
+  for (StepState* st : live(steps)) {
+    tl_sim* s = st->s;
+    if (!alternate(s)) continue;
+    st->dn_done = true;
+    k_bottom_sum(s->L, s->gc, s->cR, -st->Dt, &s->led->bottom, s->partials);
+    k_surface_sum(s->L, s->gc, region_all(), surf_coarse(s), s->Tpred, st->Dt,
+                  &s->led->surface, s->partials);
+    std::swap(s->Tn, s->Tpred);
+    std::swap(s->fstate, s->fprev);
+    energy_now(s, &s->led->stored);
+    s->stats.fine_dof_steps += fine_free_nodes(s->gf, s->win) * st->m;
+  }
   // 4. two-level correction at t_{n+1}
   for (StepState* st : live(steps)) {
     tl_sim* s = st->s;
+    if (alternate(s)) continue;
     fine_load(s, st->n, st->m, st->dt);
     k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
     k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
@@ -1264,6 +1302,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
   // 5. ledger and commit of the new state
   for (StepState* st : live(steps)) {
     tl_sim* s = st->s;
+    if (alternate(s)) continue;   // committed above
     const Launch L = s->L;
     s->stats.dn_iters += st->it;
     ++s->stats.micro_steps;
@@ -1365,7 +1404,8 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
     return fail(TL_EINVAL, "invalid tolerance or relaxation");
   if (op->newton_max < 1 || op->cg_max < 1 || op->dn_max < 1)
     return fail(TL_EINVAL, "iteration caps must be >= 1");
-  if (op->coupling != TL_COUPLE_DN && op->coupling != TL_COUPLE_COMPOSITE)
+  if (op->coupling != TL_COUPLE_DN && op->coupling != TL_COUPLE_COMPOSITE &&
+      op->coupling != TL_COUPLE_ALTERNATE)
     return fail(TL_EINVAL, "unknown coupling");
   return TL_OK;
 }
@@ -1578,6 +1618,8 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   m.cslope = (m.c_hi - m.c_lo) / (m.T_hi - m.T_lo);
   m.kslope = (m.k_hi - m.k_lo) / (m.T_hi - m.T_lo);
   m.sens_full = 0.5 * (m.c_lo + m.c_hi) * (m.T_hi - m.T_lo);
+  s->mat_global = m;
+  if (opts->coupling == TL_COUPLE_ALTERNATE) s->mat_global.latent = 0.0;
   s->lay = lay;
   s->gc = lay.gc;
   s->gf = lay.gf;

@@ -4,8 +4,8 @@ composite-grid solve (one Newton solve over the free fine nodes and the
 coarse nodes outside the window interior, the fine interface values slaved
 to the coarse ones; the default) and the GPU's own Dirichlet-Neumann
 iteration with interface quasi-Newton relaxation.  Both reach the oracle's
-discrete solution.  Tolerances: 1e-9 (FP64), 1e-6 (mixed) relative
-max-norm."""
+discrete solution.  Also the paper's alternate global formulation against
+the oracle's.  Tolerances: 1e-9 (FP64), 1e-6 (mixed) relative max-norm."""
 from dataclasses import replace
 
 import numpy as np
@@ -50,9 +50,10 @@ def _run(wl, n_macro):
 
 def _check_vs_oracle(wl, n_macro, tol, coupling):
     Tc, Tf, origin, led, st = _run(_with(wl, coupling), n_macro)
-    # the oracle runs the Dirichlet-Neumann iteration, converged far below
-    # the GPU path's tolerances
-    orc = oracle.run(wl, n_macro, newton_tol=1e-10, dn_tol=1e-10)
+    # the oracle runs the Dirichlet-Neumann iteration (for either form of
+    # the correction) or the alternate formulation, converged far below the
+    # GPU path's tolerances
+    orc = oracle.run(_with(wl, coupling), n_macro, newton_tol=1e-10, dn_tol=1e-10)
     oc, of, oorigin = oracle_fields(orc)
     assert origin == oorigin
     ec, ef = rel_maxerr(Tc, oc), rel_maxerr(Tf, of)
@@ -69,8 +70,10 @@ def _check_vs_oracle(wl, n_macro, tol, coupling):
     assert st["window_moves"] == orc.stats["moves"]
     if coupling == W.COMPOSITE:   # one solve per macro step
         assert st["dn_iters"] == n_macro
-    else:
+    elif coupling == W.DN:
         assert st["dn_iters"] >= n_macro
+    else:                         # no correction to iterate
+        assert st["dn_iters"] == 0
     return led, orc
 
 
@@ -112,6 +115,16 @@ def test_single_track_3d_volume_sources(prec, tol, coupling):
     wl = W.single_track_3d(prec)
     led, orc = _check_vs_oracle(wl, wl.n_macro, tol, coupling)
     assert led["absorbed"] == pytest.approx(0.38 * 179.2 * 2.5e-3, rel=1e-4)
+
+
+# the paper's alternate global formulation (a different discrete problem:
+# the oracle runs the same formulation)
+@pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
+@pytest.mark.parametrize("name", ["config0", "single_track_3d"])
+def test_alternate_formulation(name, prec, tol):
+    wl = W.config0(prec) if name == "config0" else W.single_track_3d(prec)
+    wl = replace(wl, material=replace(wl.material, h_conv=1.0e4))
+    _check_vs_oracle(wl, min(wl.n_macro, 12), tol, W.ALTERNATE)
 
 
 def test_composite_equals_dn_on_gpu():
