@@ -167,6 +167,9 @@ struct Launch { void* stream; };
 void k_fill(Launch L, double* a, double v, long n);
 void k_zero_bytes(Launch L, void* a, size_t bytes);
 void k_copy(Launch L, double* dst, const double* src, long n);
+// dst = 2 a - b (a linear extrapolation in time)
+void k_extrapolate(Launch L, double* dst, const double* a, const double* b,
+                   long n);
 
 template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R* y);

@@ -227,6 +227,18 @@ __global__ void copy_kernel(double* dst, const double* src, long n) {
     dst[t] = src[t];
 }
 
+__global__ void extrapolate_kernel(double* dst, const double* a,
+                                   const double* b, long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+       t += (long)gridDim.x * blockDim.x)
+    dst[t] = 2.0 * a[t] - b[t];
+}
+void k_extrapolate(Launch L, double* dst, const double* a, const double* b,
+                   long n) {
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, dst, a, b, n);
+}
+
 void k_fill(Launch L, double* a, double v, long n) {
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
                      (hipStream_t)L.stream, a, v, n);

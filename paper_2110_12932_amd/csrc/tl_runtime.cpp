@@ -66,7 +66,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Sizes of everything carved out of the caller's workspace.
 struct Layout {
   Geo gc, gf;
-  size_t off_c[23], off_fd[9], off_fcg[12];
+  size_t off_c[23], off_fd[10], off_fcg[12];
   size_t off_ccg32[12];   // FP32 coarse CG arrays (mixed composite solves)
   bool ccg32 = false;
   size_t off_scal, off_items, off_ledger, off_partials, off_tpart,
@@ -78,7 +78,7 @@ struct Layout {
 };
 
 constexpr int kCoarseArrays = 23;  // Tn Tpred cur trial lam gdw R Fall Fout ext | 12 CG arrays | Hold
-constexpr int kFineD = 9;          // state prev cur trial alt R F rho Hold
+constexpr int kFineD = 10;         // state prev cur trial alt R F rho Hold pp
 constexpr int kFineCG = 12;        // kap d dinv r0 r1 w0 w1 s0 s1 p x0 x1
 
 Layout make_layout(const tl_mesh& me, const tl_options& op) {
@@ -613,7 +613,8 @@ struct tl_sim {
   CGBufs<double> ccg;
   CGBufs<float> ccg32;   // coarse CG arrays of a mixed composite solve
   // fine fields
-  double *fstate, *fprev, *fcur, *ftrial, *falt, *fR, *fF, *rho;
+  // fpp: the micro step before fprev (extrapolated initial guesses)
+  double *fstate, *fprev, *fcur, *ftrial, *falt, *fR, *fF, *rho, *fpp;
   double *cHold, *fHold;   // H(T_old) of the level's current solve
   CGBufs<double> fcg64;
   CGBufs<float> fcg32;
@@ -1141,7 +1142,12 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
       if (j <= last_micro(st)) list.push_back(st);
     for (StepState* st : list) {
       tl_sim* s = st->s;
-      k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
+      // initial guess: the previous micro step, from the third on its
+      // linear extrapolation 2 T_{j-1} - T_{j-2}
+      if (j >= 2)
+        k_extrapolate(s->L, s->fcur, s->fprev, s->fpp, s->gf.npad);
+      else
+        k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
       k_fine_dirichlet(s->L, s->gf, s->gc, s->win, s->mat_in.T_bottom, s->Tn,
                        s->Tpred, (double)j / st->m, s->fcur);
       fine_load(s, st->n, j, st->dt);
@@ -1164,7 +1170,11 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
         k_surface_sum(s->L, s->gf, region_window(s), surf_fine(s), s->fcur,
                       st->dt, &s->led->surface, s->partials);
       }
-      std::swap(s->fprev, s->fcur);
+      // (pp, prev, cur) <- (prev, cur, spare)
+      double* spare = s->fpp;
+      s->fpp = s->fprev;
+      s->fprev = s->fcur;
+      s->fcur = spare;
       ++s->stats.micro_steps;
     }
   }
@@ -1188,7 +1198,10 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     if (alternate(s)) continue;
     fine_load(s, st->n, st->m, st->dt);
     k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
-    k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
+    if (st->m >= 2)   // extrapolated from the last two micro steps
+      k_extrapolate(s->L, s->fcur, s->fprev, s->fpp, s->gf.npad);
+    else
+      k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
     k_copy(s->L, s->ccur, s->Tpred, s->gc.npad);
   }
   // the composite-grid form: one solve; the reactions of micro steps
@@ -1649,6 +1662,7 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   auto FD = [&](int a) { return (double*)(s->ws + lay.off_fd[a]); };
   s->fstate = FD(0); s->fprev = FD(1); s->fcur = FD(2); s->ftrial = FD(3);
   s->falt = FD(4); s->fR = FD(5); s->fF = FD(6); s->rho = FD(7);
+  s->fpp = FD(9);
   s->fHold = FD(8);
   auto FC = [&](int a) { return (void*)(s->ws + lay.off_fcg[a]); };
   s->fcg64 = cgb64(FC);

@@ -34,13 +34,16 @@ def test_exports_every_declared_symbol():
 def test_workspace_bytes():
     wl = W.config1()
     n = tl.tl_workspace_bytes(wl.mesh, wl.options)
-    # 23 coarse + 9 fine FP64 arrays + 12 fine CG arrays, padded layouts
+    # 23 coarse + 10 fine FP64 arrays + 12 fine CG arrays, padded layouts
     pitch = lambda n: (n + 2 + 31) // 32 * 32   # n nodes + 2 ghosts, rounded to 32
     cpad = pitch(51) * (25 + 3) * (13 + 3)
     fpad = pitch(81) * (41 + 2) * (25 + 2)
-    assert n >= (23 * cpad + 21 * fpad) * 8
-    assert n < (23 * cpad + 21 * fpad) * 8 + 10 ** 6
+    assert n >= (23 * cpad + 22 * fpad) * 8
+    assert n < (23 * cpad + 22 * fpad) * 8 + 10 ** 6
+    # mixed: the 12 fine CG arrays in FP32, and with the composite correction
+    # 12 FP32 coarse CG arrays of its own
     mixed = tl.tl_workspace_bytes(wl.mesh, replace(wl.options, precision=W.MIXED))
+    assert mixed >= (23 * cpad + 10 * fpad) * 8 + 12 * (fpad + cpad) * 4
     assert mixed < n
     assert tl.tl_workspace_bytes(replace(wl.mesh, refine=0), wl.options) == 0
 
