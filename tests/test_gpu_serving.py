@@ -87,6 +87,36 @@ def test_result_same_alone_and_in_mix():
     sv.close()
 
 
+def test_heterogeneous_mix_equals_alone():
+    """Requests with different two-level couplings, laser models and
+    precisions share the server's launches: each equals its own run through
+    a plain handle."""
+    base = W.config0()
+    reqs = {
+        "dn": replace(base, name="dn", n_macro=4,
+                      options=replace(base.options, coupling=W.DN)),
+        "alt": replace(base, name="alt", n_macro=4,
+                       options=replace(base.options, coupling=W.ALTERNATE)),
+        "vol": replace(W.single_track_3d(), n_macro=3),
+        "mixloss": replace(W.config0(W.MIXED), name="mixloss", n_macro=4,
+                           material=replace(base.material, h_conv=2e4, emissivity=0.8)),
+    }
+    sv = tl.Server(_pool_bytes(reqs.values()), max_slots=4)
+    ids = {k: sv.submit(w) for k, w in reqs.items()}
+    log = _drain(sv)
+    assert max(a for a, _, _ in log) >= 3
+    for k, w in reqs.items():
+        say("  heterogeneous:", k)
+        Cs, Fs, _, _, _ = sv.result(ids[k])
+        s = tl.Sim(w)
+        s.step(w.n_macro)
+        Cp, _ = s.temperature(0)
+        Fp, _ = s.temperature(1)
+        s.close()
+        assert np.array_equal(Cs, Cp) and np.array_equal(Fs, Fp), k
+    sv.close()
+
+
 def test_served_results_match_oracle():
     R = _requests()
     sv = tl.Server(_pool_bytes(R.values()), max_slots=4)
