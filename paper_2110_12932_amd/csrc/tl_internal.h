@@ -130,7 +130,7 @@ struct LevelScalars {
 
 // Per-workgroup partial sums of the generic reductions (loads, energy,
 // bottom reactions): kMaxBlocks doubles, summed by a one-workgroup kernel.
-enum PartialRegion { kPartGen = 0, kPartRegions = 1 };
+enum PartialRegion { kPartGen = 0, kPartAux = 1, kPartRegions = 2 };
 
 // Per-tile partial sums of the batched Newton/CG kernels: regions of
 // `tstride` doubles indexed by tile.  A consumer sums an item's tiles in
@@ -302,6 +302,47 @@ void k_volume_load(Launch L, const Geo& g, const VolSpot& sp, double* F,
 void k_box_load(Launch L, const Geo& g, const Region& rg, const BoxSet& bs,
                 double* F, double ledger_scale, double* ledger_slot,
                 double* partials);
+
+// The per-simulation work around one fine micro step, for many
+// simulations in one launch: before the solve, the initial guess (prev, or
+// 2 prev - pp), the Dirichlet data (T_bottom on the plate bottom, the
+// prolonged blend (1 - wb) P Ta + wb P Tb on immersed faces) and the laser
+// load F with its absorbed energy; after it, the interface reactions into
+// rho and the bottom and top-surface heat flows.  Every simulation gets
+// kMicroBlocks workgroups whatever the batch, so its sums do not depend on
+// the others.  Ledger slots may be null (nothing booked).
+constexpr int kMicroBlocks = 32;
+struct MicroItem {
+  Geo gf, gc;
+  Window w;
+  double T_bottom, wb;
+  const double* Ta;
+  const double* Tb;
+  const double* prev;
+  const double* pp;        // null: the guess is prev
+  double* cur;
+  int source;              // 0 surface Gaussian, 1 volumetric Gaussian
+  int nq;                  // surface model: Gauss rule on [0, 1]
+  double gx[4], gw[4];
+  Spot spot;               // surface model (weight 0: beam off)
+  VolSpot vs;              // volume model
+  double* F;
+  double* part;            // the simulation's partials, kPartRegions regions
+  double* slot_abs;
+  double scale_abs;
+  const double* R;         // after the solve: residual at the solution
+  double* rho;             // reaction accumulator (null: none)
+  int rho_init;
+  double* slot_bottom;
+  double scale_bottom;
+  Region rgw;              // region for the top-surface areas
+  SurfDev sf;
+  const double* Tsurf;     // temperature for the surface loss
+  double* slot_surf;
+  double scale_surf;
+};
+void k_micro_prep(Launch L, const MicroItem* items, int n_items);
+void k_micro_post(Launch L, const MicroItem* items, int n_items);
 
 void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                       double T_bottom, const double* Ta, const double* Tb,

@@ -1713,15 +1713,40 @@ template void k_op_apply<double>(Launch, const Geo&, const double*,
 // of q phi for the node at corner (ca, cb) is q0 hx hy gx(fi, ca) gy(fj, cb)
 // with gx(fi, ca) = sum_a w_a exp(-a3 (x_a - xc)^2) phi_ca(xi_a) -- 2 n_q
 // exponentials per face and spot instead of n_q^2.
-__device__ inline double gauss_line(const SpotSet& sp, double x0, int f, double h,
-                                    double c, double a3, int side) {
+__device__ inline double gauss_line(int nq, const double* gx, const double* gw,
+                                    double x0, int f, double h, double c,
+                                    double a3, int side) {
   double acc = 0.0;
-  for (int qa = 0; qa < sp.nq; ++qa) {
-    const double xi = sp.gx[qa];
+  for (int qa = 0; qa < nq; ++qa) {
+    const double xi = gx[qa];
     const double r = x0 + (f + xi) * h - c;
-    acc += sp.gw[qa] * exp(-a3 * r * r) * (side ? xi : 1.0 - xi);
+    acc += gw[qa] * exp(-a3 * r * r) * (side ? xi : 1.0 - xi);
   }
   return acc;
+}
+// Surface load of one spot at top node (i, j) with the faces of the box
+// [fI0, fI1) x [fJ0, fJ1) left out.
+__device__ inline double spot_load(const Geo& g, int nq, const double* gx,
+                                   const double* gw, const Spot& S, int i,
+                                   int j, int fI0, int fI1, int fJ0, int fJ1) {
+  // this node is corner (1 - fa, 1 - fb) of face (i - 1 + fa, j - 1 + fb)
+  double fx[2] = {0.0, 0.0}, fy[2] = {0.0, 0.0};
+  for (int fa = 0; fa < 2; ++fa) {
+    const int fi = i - 1 + fa;
+    if (fi >= 0 && fi <= g.nx - 2)
+      fx[fa] = gauss_line(nq, gx, gw, g.x0, fi, g.hx, S.xc, S.a3, 1 - fa);
+    const int fj = j - 1 + fa;
+    if (fj >= 0 && fj <= g.ny - 2)
+      fy[fa] = gauss_line(nq, gx, gw, g.y0, fj, g.hy, S.yc, S.a3, 1 - fa);
+  }
+  double fs = 0.0;
+  for (int fb = 0; fb < 2; ++fb)
+    for (int fa = 0; fa < 2; ++fa) {
+      const int fi = i - 1 + fa, fj = j - 1 + fb;
+      if (fi >= fI0 && fi < fI1 && fj >= fJ0 && fj < fJ1) continue;
+      fs += fx[fa] * fy[fb];
+    }
+  return (S.q0 * g.hx * g.hy) * fs;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -1730,32 +1755,13 @@ laser_load_kernel(Geo g, SpotSet sp, int fI0, int fI1, int fJ0, int fJ1,
   __shared__ double lds[kBlock / 64];
   double acc[1] = {0.0};
   const int ntop = g.nx * g.ny;
-  const double area = g.hx * g.hy;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntop;
        t += gridDim.x * blockDim.x) {
     const int i = t % g.nx, j = t / g.nx;
     double f = 0.0;
-    for (int s = 0; s < sp.n; ++s) {
-      const Spot S = sp.s[s];
-      // this node is corner (1 - fa, 1 - fb) of face (i - 1 + fa, j - 1 + fb)
-      double gx[2] = {0.0, 0.0}, gy[2] = {0.0, 0.0};
-      for (int fa = 0; fa < 2; ++fa) {
-        const int fi = i - 1 + fa;
-        if (fi >= 0 && fi <= g.nx - 2)
-          gx[fa] = gauss_line(sp, g.x0, fi, g.hx, S.xc, S.a3, 1 - fa);
-        const int fj = j - 1 + fa;
-        if (fj >= 0 && fj <= g.ny - 2)
-          gy[fa] = gauss_line(sp, g.y0, fj, g.hy, S.yc, S.a3, 1 - fa);
-      }
-      double fs = 0.0;
-      for (int fb = 0; fb < 2; ++fb)
-        for (int fa = 0; fa < 2; ++fa) {
-          const int fi = i - 1 + fa, fj = j - 1 + fb;
-          if (fi >= fI0 && fi < fI1 && fj >= fJ0 && fj < fJ1) continue;
-          fs += gx[fa] * gy[fb];
-        }
-      f += S.weight * (S.q0 * area) * fs;
-    }
+    for (int s = 0; s < sp.n; ++s)
+      f += sp.s[s].weight *
+           spot_load(g, sp.nq, sp.gx, sp.gw, sp.s[s], i, j, fI0, fI1, fJ0, fJ1);
     F[pidx(g, i, j, g.nz - 1)] = f;
     acc[0] += f;
   }
@@ -1895,6 +1901,116 @@ void k_box_load(Launch L, const Geo& g, const Region& rg, const BoxSet& bs,
   if (ledger_slot != nullptr)
     finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, ledger_scale,
                  ledger_slot, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Batched per-simulation work around a fine micro step (see MicroItem).
+// ---------------------------------------------------------------------------
+__device__ inline double prolong(const Geo& gc, const Window& w,
+                                 const double* __restrict__ Tc, int fi, int fj,
+                                 int fk);
+__device__ inline bool fine_gamma(const Geo& gf, const Window& w, int i, int j,
+                                  int k);
+
+__global__ void __launch_bounds__(kBlock)
+micro_prep_kernel(const MicroItem* __restrict__ items) {
+  __shared__ double lds[kBlock / 64];
+  const MicroItem& it = items[blockIdx.x / kMicroBlocks];
+  const int blk = blockIdx.x % kMicroBlocks;
+  const Geo& g = it.gf;
+  double acc[1] = {0.0};
+  for (int t = blk * kBlock + threadIdx.x; t < g.nreal;
+       t += kMicroBlocks * kBlock) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    double v = it.pp != nullptr ? 2.0 * it.prev[n] - it.pp[n] : it.prev[n];
+    if (it.w.bottom && k == 0) {
+      v = it.T_bottom;
+    } else if (fine_gamma(g, it.w, i, j, k)) {
+      v = prolong(it.gc, it.w, it.Ta, i, j, k);
+      if (it.wb != 0.0)
+        v = (1.0 - it.wb) * v + it.wb * prolong(it.gc, it.w, it.Tb, i, j, k);
+    }
+    it.cur[n] = v;
+    double f = 0.0;
+    if (it.source == 1) {
+      if (it.vs.on)
+        f = it.vs.amp * hat_gauss(i, g.nx, g.hx, g.x0, it.vs.xc, it.vs.a3) *
+            hat_gauss(j, g.ny, g.hy, g.y0, it.vs.yc, it.vs.a3) *
+            hat_gauss(k, g.nz, g.hz, -(g.nz - 1) * g.hz, 0.0, it.vs.az);
+      it.F[n] = f;
+    } else if (k == g.nz - 1) {
+      if (it.spot.weight != 0.0)
+        f = spot_load(g, it.nq, it.gx, it.gw, it.spot, i, j, 0, 0, 0, 0);
+      it.F[n] = f;
+    }
+    acc[0] += f;
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) it.part[kPartGen * kMaxBlocks + blk] = acc[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+micro_post_kernel(const MicroItem* __restrict__ items) {
+  __shared__ double lds[2 * kBlock / 64];
+  const MicroItem& it = items[blockIdx.x / kMicroBlocks];
+  const int blk = blockIdx.x % kMicroBlocks;
+  const Geo& g = it.gf;
+  const bool surf = it.slot_surf != nullptr && (it.sf.h != 0.0 || it.sf.es != 0.0);
+  double acc[2] = {0.0, 0.0};   // bottom reactions, surface loss
+  for (int t = blk * kBlock + threadIdx.x; t < g.nreal;
+       t += kMicroBlocks * kBlock) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    const int n = pidx(g, i, j, k);
+    if (fine_gamma(g, it.w, i, j, k)) {
+      if (it.rho != nullptr) it.rho[n] = it.rho_init ? it.R[n] : it.rho[n] + it.R[n];
+    } else if (it.w.bottom && k == 0) {
+      acc[0] += it.R[n];
+    }
+    if (surf && k == g.nz - 1)
+      acc[1] += top_area(g, it.rgw, i, j) * surface_flux(it.Tsurf[n], it.sf);
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    it.part[kPartGen * kMaxBlocks + blk] = acc[0];
+    it.part[kPartAux * kMaxBlocks + blk] = acc[1];
+  }
+}
+
+// One workgroup per simulation: the kMicroBlocks partials of region reg
+// (in order) times scale, added into the slot the item names for that sum.
+__global__ void __launch_bounds__(64)
+micro_finalize_kernel(const MicroItem* __restrict__ items, int post) {
+  const MicroItem& it = items[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  for (int reg = 0; reg < (post ? 2 : 1); ++reg) {
+    double* slot = post ? (reg == 0 ? it.slot_bottom : it.slot_surf) : it.slot_abs;
+    const double scale = post ? (reg == 0 ? it.scale_bottom : it.scale_surf)
+                              : it.scale_abs;
+    if (slot == nullptr) continue;
+    if (post && reg == 0 && !it.w.bottom) continue;
+    if (post && reg == 1 && it.sf.h == 0.0 && it.sf.es == 0.0) continue;
+    double sum = 0.0;
+    for (int b = 0; b < kMicroBlocks; ++b) sum += it.part[reg * kMaxBlocks + b];
+    *slot += scale * sum;
+  }
+}
+
+void k_micro_prep(Launch L, const MicroItem* items, int n_items) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(micro_prep_kernel, dim3(n_items * kMicroBlocks),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items);
+  hipLaunchKernelGGL(micro_finalize_kernel, dim3(n_items), dim3(64), 0,
+                     (hipStream_t)L.stream, items, 0);
+}
+void k_micro_post(Launch L, const MicroItem* items, int n_items) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(micro_post_kernel, dim3(n_items * kMicroBlocks),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items);
+  hipLaunchKernelGGL(micro_finalize_kernel, dim3(n_items), dim3(64), 0,
+                     (hipStream_t)L.stream, items, 1);
 }
 
 // ---------------------------------------------------------------------------

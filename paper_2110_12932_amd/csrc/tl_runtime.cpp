@@ -69,7 +69,7 @@ struct Layout {
   size_t off_c[23], off_fd[10], off_fcg[12];
   size_t off_ccg32[12];   // FP32 coarse CG arrays (mixed composite solves)
   bool ccg32 = false;
-  size_t off_scal, off_items, off_ledger, off_partials, off_tpart,
+  size_t off_scal, off_items, off_micro, off_ledger, off_partials, off_tpart,
       off_tpart2, off_gidx, off_gbuf;
   int tstride;   // per-tile partial slots per region (both levels)
   int gamma_cap;
@@ -106,6 +106,7 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   }
   L.off_scal = off; off += align_up(2 * sizeof(LevelScalars));
   L.off_items = off; off += align_up(2 * sizeof(SolveItem));
+  L.off_micro = off; off += align_up(2 * sizeof(MicroItem));
   L.off_ledger = off; off += align_up(sizeof(LedgerDev));
   L.off_partials = off;
   off += align_up((size_t)kMaxBlocks * kPartRegions * sizeof(double));
@@ -149,7 +150,10 @@ struct BatchCtx {
   SolveItem* h_items = nullptr;
   LevelScalars* d_sc = nullptr;
   LevelScalars* h_sc = nullptr;
-  int cap = 0;        // solves (scalar sets)
+  MicroItem* d_micro = nullptr;   // per-simulation micro-step work: two
+  MicroItem* h_micro = nullptr;   // halves of micro_cap (before / after)
+  int micro_cap = 0;
+  int cap = 0;        // solves (scalar sets), simulations
   int item_cap = 0;   // items (a composite pair takes two)
   hipStream_t stream = nullptr;
   Launch L{nullptr};
@@ -1059,6 +1063,62 @@ std::vector<StepState*> live(std::vector<StepState>& steps) {
   return out;
 }
 
+// The micro-step work of one simulation (see MicroItem) before the solve
+// of micro step j ...
+void micro_prep_item(const StepState& st, int j, MicroItem& mi) {
+  tl_sim* s = st.s;
+  std::memset(&mi, 0, sizeof(mi));
+  mi.gf = s->gf;
+  mi.gc = s->gc;
+  mi.w = s->win;
+  mi.T_bottom = s->mat_in.T_bottom;
+  mi.wb = (double)j / st.m;
+  mi.Ta = s->Tn;
+  mi.Tb = s->Tpred;
+  mi.prev = s->fprev;
+  mi.pp = j >= 2 ? s->fpp : nullptr;
+  mi.cur = s->fcur;
+  mi.source = s->opts.source == TL_SOURCE_VOLUME ? 1 : 0;
+  if (mi.source == 1) {
+    mi.vs = vol_spot(s, st.n, j);
+  } else {
+    const SpotSet sp = make_spots(s, st.n, j, j, 1.0);
+    mi.nq = sp.nq;
+    for (int q = 0; q < 4; ++q) {
+      mi.gx[q] = sp.gx[q];
+      mi.gw[q] = sp.gw[q];
+    }
+    if (sp.n > 0) mi.spot = sp.s[0];   // weight 0 (zeroed) when off
+  }
+  mi.F = s->fF;
+  mi.part = s->partials;
+  // the alternate formulation's ledger is the global problem's
+  mi.slot_abs = alternate(s) ? nullptr : &s->led->absorbed;
+  mi.scale_abs = st.dt;
+}
+
+// ... and after it: reactions on the interface into rho, the bottom and
+// top-surface heat flows of the solution.
+void micro_post_item(const StepState& st, int j, MicroItem& mi) {
+  tl_sim* s = st.s;
+  const bool alt = alternate(s);
+  std::memset(&mi, 0, sizeof(mi));
+  mi.gf = s->gf;
+  mi.gc = s->gc;
+  mi.w = s->win;
+  mi.part = s->partials;
+  mi.R = s->fR;
+  mi.rho = alt ? nullptr : s->rho;
+  mi.rho_init = j == 1 ? 1 : 0;
+  mi.slot_bottom = alt ? nullptr : &s->led->bottom;
+  mi.scale_bottom = -st.dt;
+  mi.rgw = region_window(s);
+  mi.sf = surf_fine(s);
+  mi.Tsurf = s->fcur;
+  mi.slot_surf = alt ? nullptr : &s->led->surface;
+  mi.scale_surf = st.dt;
+}
+
 // One macro step of Algorithm 1 for several simulations in lockstep: the
 // per-simulation work (window, loads, Dirichlet data, transfers, ledger) is
 // queued simulation by simulation, and every fine or coarse implicit step of
@@ -1140,17 +1200,20 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     std::vector<StepState*> list;
     for (StepState* st : live(steps))
       if (j <= last_micro(st)) list.push_back(st);
-    for (StepState* st : list) {
-      tl_sim* s = st->s;
-      // initial guess: the previous micro step, from the third on its
-      // linear extrapolation 2 T_{j-1} - T_{j-2}
-      if (j >= 2)
-        k_extrapolate(s->L, s->fcur, s->fprev, s->fpp, s->gf.npad);
-      else
-        k_copy(s->L, s->fcur, s->fprev, s->gf.npad);
-      k_fine_dirichlet(s->L, s->gf, s->gc, s->win, s->mat_in.T_bottom, s->Tn,
-                       s->Tpred, (double)j / st->m, s->fcur);
-      fine_load(s, st->n, j, st->dt);
+    // before the solve, for all listed simulations in one launch: the
+    // initial guess (the previous micro step; from the second micro step
+    // on its linear extrapolation 2 T_{j-1} - T_{j-2}), the Dirichlet data
+    // and the laser load
+    if ((int)list.size() > B.micro_cap)
+      throw DevErr{"batch larger than its context"};
+    for (size_t q = 0; q < list.size(); ++q)
+      micro_prep_item(*list[q], j, B.h_micro[q]);
+    if (!list.empty()) {
+      hip_check(hipMemcpyAsync(B.d_micro, B.h_micro,
+                               sizeof(MicroItem) * list.size(),
+                               hipMemcpyHostToDevice, B.stream),
+                "hipMemcpyAsync(micro items)");
+      k_micro_prep(B.L, B.d_micro, (int)list.size());
     }
     batch_fine(
         B, list,
@@ -1160,16 +1223,25 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
           Told = st.s->fprev;
         },
         prof);
+    // after it, in one launch: reactions on the interface, bottom and
+    // top-surface heat flows (the second half of the item table: its first
+    // half may still be in flight to the device)
+    {
+      MicroItem* hp = B.h_micro + B.micro_cap;
+      int n = 0;
+      for (StepState* st : list)
+        if (!st->failed) micro_post_item(*st, j, hp[n++]);
+      if (n > 0) {
+        hip_check(hipMemcpyAsync(B.d_micro + B.micro_cap, hp,
+                                 sizeof(MicroItem) * n, hipMemcpyHostToDevice,
+                                 B.stream),
+                  "hipMemcpyAsync(micro items)");
+        k_micro_post(B.L, B.d_micro + B.micro_cap, n);
+      }
+    }
     for (StepState* st : list) {
       if (st->failed) continue;
       tl_sim* s = st->s;
-      if (!alternate(s)) {
-        k_interface_accumulate(s->L, s->gf, s->win, s->fR, s->rho,
-                               j == 1 ? 1 : 0, -st->dt, &s->led->bottom,
-                               s->partials);
-        k_surface_sum(s->L, s->gf, region_window(s), surf_fine(s), s->fcur,
-                      st->dt, &s->led->surface, s->partials);
-      }
       // (pp, prev, cur) <- (prev, cur, spare)
       double* spare = s->fpp;
       s->fpp = s->fprev;
@@ -1436,10 +1508,12 @@ struct BatchImpl {
   tl_stats pstats{};  // only the timing and op-byte fields are used
 };
 
-// Items for 2 * max_slots (composite pairs take two), scalars for max_slots.
+// Items for 2 * max_slots (composite pairs take two), scalars and
+// micro-step items for max_slots.
 size_t batch_tables_bytes(int max_slots) {
   return align_up(sizeof(SolveItem) * 2 * (size_t)max_slots) +
-         align_up(sizeof(LevelScalars) * (size_t)max_slots);
+         align_up(sizeof(LevelScalars) * (size_t)max_slots) +
+         align_up(sizeof(MicroItem) * 2 * (size_t)max_slots);
 }
 
 tl_status batch_tables_init(BatchTables* bt, void* dev_area, int max_slots,
@@ -1450,13 +1524,19 @@ tl_status batch_tables_init(BatchTables* bt, void* dev_area, int max_slots,
   b->ctx.d_items = (SolveItem*)p;
   b->ctx.d_sc =
       (LevelScalars*)(p + align_up(sizeof(SolveItem) * 2 * (size_t)max_slots));
+  b->ctx.d_micro =
+      (MicroItem*)(p + align_up(sizeof(SolveItem) * 2 * (size_t)max_slots) +
+                   align_up(sizeof(LevelScalars) * (size_t)max_slots));
   b->ctx.cap = max_slots;
   b->ctx.item_cap = 2 * max_slots;
+  b->ctx.micro_cap = max_slots;
   b->ctx.stream = (hipStream_t)hip_stream;
   b->ctx.L.stream = hip_stream;
   if (hipHostMalloc((void**)&b->ctx.h_items, sizeof(SolveItem) * 2 * max_slots,
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&b->ctx.h_sc, sizeof(LevelScalars) * max_slots,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->ctx.h_micro, sizeof(MicroItem) * 2 * max_slots,
                     hipHostMallocDefault) != hipSuccess) {
     batch_tables_free(&(bt->impl = b, *bt));
     return fail(TL_EDEVICE, "hipHostMalloc failed");
@@ -1470,6 +1550,7 @@ void batch_tables_free(BatchTables* bt) {
   if (!b) return;
   if (b->ctx.h_items) (void)hipHostFree(b->ctx.h_items);
   if (b->ctx.h_sc) (void)hipHostFree(b->ctx.h_sc);
+  if (b->ctx.h_micro) (void)hipHostFree(b->ctx.h_micro);
   if (b->prof.ev[0])
     for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(b->prof.ev[q]);
   delete b;
@@ -1684,6 +1765,8 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
       hipHostMalloc((void**)&s->batch.h_items, 2 * sizeof(SolveItem),
                     hipHostMallocDefault) !=
           hipSuccess ||
+      hipHostMalloc((void**)&s->batch.h_micro, 2 * sizeof(MicroItem),
+                    hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&s->h_led, sizeof(LedgerDev), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&s->h_gbuf, 2 * sizeof(double) * lay.gamma_cap,
@@ -1692,10 +1775,12 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
     return fail(TL_EDEVICE, "hipHostMalloc failed");
   }
   s->batch.d_items = (SolveItem*)(s->ws + lay.off_items);
+  s->batch.d_micro = (MicroItem*)(s->ws + lay.off_micro);
   s->batch.d_sc = s->sc_c;
   s->batch.h_sc = s->h_sc;
   s->batch.cap = 2;
   s->batch.item_cap = 2;
+  s->batch.micro_cap = 1;
   s->batch.stream = s->stream;
   s->batch.L = s->L;
   std::memset(&s->stats, 0, sizeof(s->stats));
@@ -1956,6 +2041,7 @@ void tl_destroy(tl_sim* s) {
   if (s->prof.ev[0])
     for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(s->prof.ev[q]);
   if (s->batch.h_items) (void)hipHostFree(s->batch.h_items);
+  if (s->batch.h_micro) (void)hipHostFree(s->batch.h_micro);
   if (s->h_sc) (void)hipHostFree(s->h_sc);
   if (s->h_led) (void)hipHostFree(s->h_led);
   if (s->h_gbuf) (void)hipHostFree(s->h_gbuf);
