@@ -1269,7 +1269,8 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     tl_sim* s = st->s;
     if (alternate(s)) continue;
     fine_load(s, st->n, st->m, st->dt);
-    k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
+    if (s->opts.coupling == TL_COUPLE_DN)   // the interface trace
+      k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
     if (st->m >= 2)   // extrapolated from the last two micro steps
       k_extrapolate(s->L, s->fcur, s->fprev, s->fpp, s->gf.npad);
     else

@@ -127,6 +127,20 @@ def test_alternate_formulation(name, prec, tol):
     _check_vs_oracle(wl, min(wl.n_macro, 12), tol, W.ALTERNATE)
 
 
+# degenerate window: it covers the whole plate, so there is no interface
+# (the correction reduces to the fine solve; the composite pair's coarse
+# side has no free node)
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_whole_plate_window(coupling):
+    UM = 1e-6
+    wl = W.config0()
+    mesh = replace(wl.mesh, nx=6, ny=4, nz=3, lx=6 * 62.5 * UM, ly=4 * 62.5 * UM,
+                   lz=3 * 62.5 * UM, win_nx=6, win_ny=4, win_nz=3)
+    tr = W.Track(0.05e-3, 0.1e-3, 0.3e-3, 0.15e-3, 0.8, 150.0, 50 * UM, 0.4)
+    wl = replace(wl, mesh=mesh, scan=W.ScanPath([tr]), n_macro=4)
+    _check_vs_oracle(wl, 4, 1e-9, coupling)
+
+
 def test_composite_equals_dn_on_gpu():
     """The two GPU forms agree with each other (config 0, FP64)."""
     a = _run(_with(W.config0(), W.COMPOSITE), 20)
