@@ -148,6 +148,19 @@ def test_composite_equals_dn_on_gpu():
     assert rel_maxerr(a[0], b[0]) <= 1e-9 and rel_maxerr(a[1], b[1]) <= 1e-9
 
 
+# every reduction sums in a fixed order (no atomics), so two runs agree bit
+# for bit: a race in a kernel would show up here
+@pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
+def test_run_to_run_bitwise(prec):
+    wl = replace(W.small_cases()["corner"], options=replace(
+        W.small_cases()["corner"].options, precision=prec))
+    a = _run(wl, 8)
+    b = _run(wl, 8)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[3] == b[3]          # ledgers
+    assert a[4]["cg_fine"] == b[4]["cg_fine"]
+
+
 @pytest.mark.parametrize("coupling", COUPLINGS)
 def test_checkpoint_roundtrip_bitwise(coupling):
     wl = _with(W.small_cases()["corner"], coupling)
