@@ -308,11 +308,14 @@ void k_box_load(Launch L, const Geo& g, const Region& rg, const BoxSet& bs,
 // 2 prev - pp), the Dirichlet data (T_bottom on the plate bottom, the
 // prolonged blend (1 - wb) P Ta + wb P Tb on immersed faces) and the laser
 // load F with its absorbed energy; after it, the interface reactions into
-// rho and the bottom and top-surface heat flows.  Every simulation gets
-// kMicroBlocks workgroups whatever the batch, so its sums do not depend on
-// the others.  Ledger slots may be null (nothing booked).
-constexpr int kMicroBlocks = 32;
+// rho and the bottom and top-surface heat flows.  A simulation's
+// workgroup count `nblk` follows from its own size only (micro_blocks), so
+// its sums do not depend on the others.  Ledger slots may be null (nothing
+// booked).
+constexpr int kMaxMicroBlocks = 256;
+int micro_blocks(const Geo& gf);
 struct MicroItem {
+  int nblk;
   Geo gf, gc;
   Window w;
   double T_bottom, wb;
@@ -341,8 +344,9 @@ struct MicroItem {
   double* slot_surf;
   double scale_surf;
 };
-void k_micro_prep(Launch L, const MicroItem* items, int n_items);
-void k_micro_post(Launch L, const MicroItem* items, int n_items);
+// per_item: the launch's workgroups per item, at least every item's nblk
+void k_micro_prep(Launch L, const MicroItem* items, int n_items, int per_item);
+void k_micro_post(Launch L, const MicroItem* items, int n_items, int per_item);
 
 void k_fine_dirichlet(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                       double T_bottom, const double* Ta, const double* Tb,

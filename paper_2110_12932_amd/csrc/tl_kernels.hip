@@ -1912,15 +1912,21 @@ __device__ inline double prolong(const Geo& gc, const Window& w,
 __device__ inline bool fine_gamma(const Geo& gf, const Window& w, int i, int j,
                                   int k);
 
+int micro_blocks(const Geo& gf) {
+  return std::max(1, std::min(kMaxMicroBlocks, (gf.nreal + 4 * kBlock - 1) /
+                                                   (4 * kBlock)));
+}
+
 __global__ void __launch_bounds__(kBlock)
-micro_prep_kernel(const MicroItem* __restrict__ items) {
+micro_prep_kernel(const MicroItem* __restrict__ items, int per_item) {
   __shared__ double lds[kBlock / 64];
-  const MicroItem& it = items[blockIdx.x / kMicroBlocks];
-  const int blk = blockIdx.x % kMicroBlocks;
+  const MicroItem& it = items[blockIdx.x / per_item];
+  const int blk = blockIdx.x % per_item;
+  if (blk >= it.nblk) return;   // the whole workgroup
   const Geo& g = it.gf;
   double acc[1] = {0.0};
   for (int t = blk * kBlock + threadIdx.x; t < g.nreal;
-       t += kMicroBlocks * kBlock) {
+       t += it.nblk * kBlock) {
     int i, j, k;
     node_ijk(g, t, i, j, k);
     const int n = pidx(g, i, j, k);
@@ -1952,15 +1958,16 @@ micro_prep_kernel(const MicroItem* __restrict__ items) {
 }
 
 __global__ void __launch_bounds__(kBlock)
-micro_post_kernel(const MicroItem* __restrict__ items) {
+micro_post_kernel(const MicroItem* __restrict__ items, int per_item) {
   __shared__ double lds[2 * kBlock / 64];
-  const MicroItem& it = items[blockIdx.x / kMicroBlocks];
-  const int blk = blockIdx.x % kMicroBlocks;
+  const MicroItem& it = items[blockIdx.x / per_item];
+  const int blk = blockIdx.x % per_item;
+  if (blk >= it.nblk) return;   // the whole workgroup
   const Geo& g = it.gf;
   const bool surf = it.slot_surf != nullptr && (it.sf.h != 0.0 || it.sf.es != 0.0);
   double acc[2] = {0.0, 0.0};   // bottom reactions, surface loss
   for (int t = blk * kBlock + threadIdx.x; t < g.nreal;
-       t += kMicroBlocks * kBlock) {
+       t += it.nblk * kBlock) {
     int i, j, k;
     node_ijk(g, t, i, j, k);
     const int n = pidx(g, i, j, k);
@@ -1979,7 +1986,7 @@ micro_post_kernel(const MicroItem* __restrict__ items) {
   }
 }
 
-// One workgroup per simulation: the kMicroBlocks partials of region reg
+// One workgroup per simulation: the nblk partials of region reg
 // (in order) times scale, added into the slot the item names for that sum.
 __global__ void __launch_bounds__(64)
 micro_finalize_kernel(const MicroItem* __restrict__ items, int post) {
@@ -1993,22 +2000,22 @@ micro_finalize_kernel(const MicroItem* __restrict__ items, int post) {
     if (post && reg == 0 && !it.w.bottom) continue;
     if (post && reg == 1 && it.sf.h == 0.0 && it.sf.es == 0.0) continue;
     double sum = 0.0;
-    for (int b = 0; b < kMicroBlocks; ++b) sum += it.part[reg * kMaxBlocks + b];
+    for (int b = 0; b < it.nblk; ++b) sum += it.part[reg * kMaxBlocks + b];
     *slot += scale * sum;
   }
 }
 
-void k_micro_prep(Launch L, const MicroItem* items, int n_items) {
+void k_micro_prep(Launch L, const MicroItem* items, int n_items, int per_item) {
   if (n_items <= 0) return;
-  hipLaunchKernelGGL(micro_prep_kernel, dim3(n_items * kMicroBlocks),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items);
+  hipLaunchKernelGGL(micro_prep_kernel, dim3(n_items * per_item),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item);
   hipLaunchKernelGGL(micro_finalize_kernel, dim3(n_items), dim3(64), 0,
                      (hipStream_t)L.stream, items, 0);
 }
-void k_micro_post(Launch L, const MicroItem* items, int n_items) {
+void k_micro_post(Launch L, const MicroItem* items, int n_items, int per_item) {
   if (n_items <= 0) return;
-  hipLaunchKernelGGL(micro_post_kernel, dim3(n_items * kMicroBlocks),
-                     dim3(kBlock), 0, (hipStream_t)L.stream, items);
+  hipLaunchKernelGGL(micro_post_kernel, dim3(n_items * per_item),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, items, per_item);
   hipLaunchKernelGGL(micro_finalize_kernel, dim3(n_items), dim3(64), 0,
                      (hipStream_t)L.stream, items, 1);
 }

@@ -1068,6 +1068,7 @@ std::vector<StepState*> live(std::vector<StepState>& steps) {
 void micro_prep_item(const StepState& st, int j, MicroItem& mi) {
   tl_sim* s = st.s;
   std::memset(&mi, 0, sizeof(mi));
+  mi.nblk = micro_blocks(s->gf);
   mi.gf = s->gf;
   mi.gc = s->gc;
   mi.w = s->win;
@@ -1103,6 +1104,7 @@ void micro_post_item(const StepState& st, int j, MicroItem& mi) {
   tl_sim* s = st.s;
   const bool alt = alternate(s);
   std::memset(&mi, 0, sizeof(mi));
+  mi.nblk = micro_blocks(s->gf);
   mi.gf = s->gf;
   mi.gc = s->gc;
   mi.w = s->win;
@@ -1206,14 +1208,17 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     // and the laser load
     if ((int)list.size() > B.micro_cap)
       throw DevErr{"batch larger than its context"};
-    for (size_t q = 0; q < list.size(); ++q)
+    int per_micro = 1;
+    for (size_t q = 0; q < list.size(); ++q) {
       micro_prep_item(*list[q], j, B.h_micro[q]);
+      per_micro = std::max(per_micro, B.h_micro[q].nblk);
+    }
     if (!list.empty()) {
       hip_check(hipMemcpyAsync(B.d_micro, B.h_micro,
                                sizeof(MicroItem) * list.size(),
                                hipMemcpyHostToDevice, B.stream),
                 "hipMemcpyAsync(micro items)");
-      k_micro_prep(B.L, B.d_micro, (int)list.size());
+      k_micro_prep(B.L, B.d_micro, (int)list.size(), per_micro);
     }
     batch_fine(
         B, list,
@@ -1228,15 +1233,18 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     // half may still be in flight to the device)
     {
       MicroItem* hp = B.h_micro + B.micro_cap;
-      int n = 0;
+      int n = 0, per = 1;
       for (StepState* st : list)
-        if (!st->failed) micro_post_item(*st, j, hp[n++]);
+        if (!st->failed) {
+          micro_post_item(*st, j, hp[n]);
+          per = std::max(per, hp[n++].nblk);
+        }
       if (n > 0) {
         hip_check(hipMemcpyAsync(B.d_micro + B.micro_cap, hp,
                                  sizeof(MicroItem) * n, hipMemcpyHostToDevice,
                                  B.stream),
                   "hipMemcpyAsync(micro items)");
-        k_micro_post(B.L, B.d_micro + B.micro_cap, n);
+        k_micro_post(B.L, B.d_micro + B.micro_cap, n, per);
       }
     }
     for (StepState* st : list) {
