@@ -181,11 +181,17 @@ void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R*
 // Jacobian is symmetric.  The pair is a fine item and a coarse item that
 // share one Newton/CG state; every launch of a round runs the fine side, a
 // gather kernel (P^T of the fine interface rows onto the coarse interface
-// nodes), then the coarse side.  The fine side forms its interface values
-// from the coarse arrays; the coarse side adds the gathered rows on its
-// interface nodes.  Both sides sum the pair's tile partials in the same
+// nodes), then the coarse side.  The fine side reads its interface values
+// as prolonged from the coarse arrays; the coarse side adds the gathered
+// rows on its interface nodes.  Both sides sum the pair's tile partials in the same
 // order (fine tiles, then coarse tiles), so they take the same decisions.
-enum CoupleSide { kAlone = 0, kFineSide = 1, kCoarseSide = 2 };
+// Before each fine launch a prolongation kernel writes the coarse values
+// onto the fine side's interface nodes.
+// kFineSide forms its interface values inside its own kernels (fewest
+// launches: the choice for one or a few simulations); kFineSideP reads them
+// as written by the prolongation kernel before it (cheaper kernels: the
+// choice for large batches).  Both give bitwise the same values.
+enum CoupleSide { kAlone = 0, kFineSide = 1, kCoarseSide = 2, kFineSideP = 3 };
 struct Couple {
   Window w;              // window placement
   Geo go;                // the other level's grid
@@ -288,6 +294,11 @@ void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
 template <class R>
 void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
                      int max_gamma, int round, int phase, int kit);
+// The prolongation onto the fine sides' interface nodes before each fine
+// launch of composite pairs (same phases), per_item workgroups per pair.
+template <class R>
+void k_couple_prolong(Launch L, const SolveItem* fine_items, int n_items,
+                      int per_item, int round, int phase, int kit);
 
 void k_laser_load(Launch L, const Geo& g, const SpotSet& spots, int fI0,
                   int fI1, int fJ0, int fJ1, double* F, double ledger_scale,

@@ -836,11 +836,13 @@ __device__ inline int item_of_block(int per_item) { return blockIdx.x / per_item
 // r.(Dinv r).  LDS-tiled like the CG kernels: the trial temperature is
 // formed once per halo node and each element's conductivity once per tile.
 //
-// Composite pairs (CP = kFineSide / kCoarseSide): the fine side takes the
-// trial values of its interface nodes from the coarse trial (prolonged),
-// scales its rows by 1/m and keeps its Jacobian diagonal on the interface
-// rows (in place of the preconditioner, which is the coarse row's there);
-// the coarse side adds the gathered fine rows on its interface nodes.
+// Composite pairs (CP = kFineSide(P) / kCoarseSide): the fine side takes
+// the trial values of its interface nodes prolonged from the coarse trial
+// (kFineSide here, kFineSideP from couple_prolong_kernel), scales its rows
+// by 1/m and keeps its
+// Jacobian diagonal on the interface rows (in place of the preconditioner,
+// which is the coarse row's there); the coarse side adds the gathered fine
+// rows on its interface nodes.
 template <class R, int CP>
 __global__ void __launch_bounds__(kBlock)
 residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
@@ -999,7 +1001,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       double diag = dn + diagK * g.w[0];
       double kown = k8[0];
       bool keep_diag = false;
-      if constexpr (CP == kFineSide) {
+      if constexpr (CP == kFineSide || CP == kFineSideP) {
         const double sc = it.cp.rscale;
         Rn *= sc;
         dn *= sc;
@@ -1064,9 +1066,11 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 //    partials of gamma0 = r.u, delta0 = w.u are formed here.
 //
 // Composite pairs: both sides take the same decisions from the pair's
-// partials; the fine side forms u0 on its interface nodes from the coarse
-// u0 (prolonged) and leaves those rows out of its dot products, the coarse
-// side adds the gathered fine rows of w0 on its interface nodes.
+// partials; the fine side takes u0 on its interface nodes prolonged from
+// the coarse u0 (kFineSide here, kFineSideP from couple_prolong_kernel) and
+// leaves those rows out of its dot
+// products, the coarse side adds the gathered fine rows of w0 on its
+// interface nodes.
 template <class R, int CP>
 __global__ void __launch_bounds__(kBlock)
 cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
@@ -1135,7 +1139,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     o_act = i < g.nx && j < g.ny && k < g.nz;
     o_n = o_act ? pidx(g, i, j, k) : 0;
-    if (CP == kFineSide) o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
+    if (CP == kFineSide || CP == kFineSideP)
+      o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
     if (CP == kCoarseSide) o_gam = o_act && coarse_gamma(it.cp.w, i, j, k);
     if (o_act) {
       o_r = r[o_n];
@@ -1255,7 +1260,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       R wn = d_own * un + stencil_lds(t, u_s, k_s, wts);
       if (CP == kCoarseSide && gam) wn += ((const R*)it.cp.gDW)[n];
       w[n] = wn;
-      if (CP != kFineSide || !gam) {
+      if ((CP != kFineSide && CP != kFineSideP) || !gam) {
         acc[0] += r_own * un;
         acc[1] += wn * un;
       }
@@ -1270,10 +1275,11 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 }
 
 // One Chronopoulos-Gear PCG iteration `kit` for every item (LDS-tiled).
-// Composite pairs: the fine side forms u_{k+1} on its interface nodes from
-// the coarse vectors (prolonged; the coarse side of iteration k-1 wrote
-// them) and leaves those rows out of its dot products; the coarse side adds
-// the gathered fine rows of w_{k+1} on its interface nodes.
+// Composite pairs: the fine side takes its interface nodes' inputs
+// prolonged from the coarse vectors of iteration k (kFineSide here,
+// kFineSideP from couple_prolong_kernel) and leaves those rows out of its
+// dot products; the coarse side adds the
+// gathered fine rows of w_{k+1} on its interface nodes.
 template <class R, int CP>
 __global__ void __launch_bounds__(kBlock)
 cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
@@ -1327,14 +1333,14 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         // gives u_{k+1} = P (Dinv (r - alpha (w + beta s))) there
         const R* rc = (const R*)it.cp.orr[a];
         const R* wc = (const R*)it.cp.ow[a];
-        const R* sc_ = (const R*)it.cp.os[1 - a];
+        const R* scs = (const R*)it.cp.os[1 - a];
         const R* dc = (const R*)it.cp.odinv;
         double vr = 0.0, vw = 0.0, vs = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
           const R dv = dc[cn];
           vr += wt * (double)(dv * rc[cn]);
           vw += wt * (double)(dv * wc[cn]);
-          if (kit > 0) vs += wt * (double)(dv * sc_[cn]);
+          if (kit > 0) vs += wt * (double)(dv * scs[cn]);
         });
         hr[q] = (R)vr;
         hw[q] = (R)vw;
@@ -1356,7 +1362,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     o_act = i < g.nx && j < g.ny && k < g.nz;
     o_n = o_act ? pidx(g, i, j, k) : 0;
-    if (CP == kFineSide) o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
+    if (CP == kFineSide || CP == kFineSideP)
+      o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
     if (CP == kCoarseSide) o_gam = o_act && coarse_gamma(it.cp.w, i, j, k);
     if (o_act) {
       o_r = r_in[o_n];
@@ -1447,7 +1454,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     if (active) {
       // (a slaved interface node of a fine side keeps zero recurrences: its
       // values come from the coarse side)
-      const bool slave = CP == kFineSide && gam;
+      const bool slave = (CP == kFineSide || CP == kFineSideP) && gam;
       const R s_k = slave ? (R)0 : w_own + beta * s_prev;
       const R u_k = di_own * r_own;
       const R pn = slave ? (R)0 : u_k + beta * p_own;
@@ -1460,7 +1467,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       R w1 = d_own * u1 + stencil_lds(t, u_s, k_s, wts);
       if (CP == kCoarseSide && gam) w1 += ((const R*)it.cp.gDW)[n];
       w_out[n] = w1;
-      if (CP != kFineSide || !gam) {
+      if ((CP != kFineSide && CP != kFineSideP) || !gam) {
         acc[0] += r1 * u1;
         acc[1] += w1 * u1;
       }
@@ -1566,6 +1573,115 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
   }
 }
 
+// Prolongation of composite pairs (over the fine sides' table), before each
+// fine-side launch: the slaved interface nodes of the window get the
+// prolonged coarse values the fine kernel then reads like any other --
+// phase 0, the trial temperature P trial(T+, alpha dx+) into the accepted
+// buffer (its own direction there stays zero); phase 1, u0 = P (Dinv r0)
+// with a unit preconditioner; phase 2, P (Dinv r), P (Dinv w) and
+// P (Dinv s) of CG iteration kit, so that the fine recurrence gives
+// u_{k+1} = P (Dinv (r - alpha (w + beta s))) there by linearity.  The
+// nodes are enumerated face by face (a node on two immersed faces is taken
+// on the first); each is written once.  Runs under the same conditions as
+// the fine side that follows it.
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+couple_prolong_kernel(const SolveItem* __restrict__ items, int per_item,
+                      int round, int phase, int kit) {
+  const SolveItem& it = items[blockIdx.x / per_item];
+  const int blk = blockIdx.x % per_item;
+  const LevelScalars* sc = it.sc;
+  const NewtonState& st = sc->ns[round & 1];
+  if (phase <= 1) {
+    if (st.status != kRunning) return;
+    if (st.pending) {
+      const CGScalars& cgp = sc->cg[(round + 1) & 1];
+      if (cgp.breakdown && cgp.iters == 0) return;
+    }
+  } else {
+    const NewtonState& nx = sc->ns[(round + 1) & 1];
+    const CGScalars& c = sc->cg[round & 1];
+    if (c.done || kit >= nx.budget) return;
+  }
+  const Geo& g = it.g;
+  const Couple& cp = it.cp;
+  const Window& w = cp.w;
+  const int a = kit & 1;
+  const long sx = (long)g.ny * g.nz, sy = (long)g.nx * g.nz,
+             sz = (long)g.nx * g.ny;
+  const long total = 2 * sx + 2 * sy + sz;
+  for (long t = (long)blk * kBlock + threadIdx.x; t < total;
+       t += (long)per_item * kBlock) {
+    int face, i, j, k;
+    long u = t;
+    if (u < 2 * sx) {
+      face = u < sx ? 0 : 1;
+      u -= face * sx;
+      i = face == 0 ? 0 : g.nx - 1;
+      j = (int)(u % g.ny);
+      k = (int)(u / g.ny);
+    } else if (u < 2 * sx + 2 * sy) {
+      u -= 2 * sx;
+      face = u < sy ? 2 : 3;
+      u -= (face - 2) * sy;
+      j = face == 2 ? 0 : g.ny - 1;
+      i = (int)(u % g.nx);
+      k = (int)(u / g.nx);
+    } else {
+      u -= 2 * sx + 2 * sy;
+      face = 4;
+      k = 0;
+      i = (int)(u % g.nx);
+      j = (int)(u / g.nx);
+    }
+    const int bit = face == 0 ? kFx0 : face == 1 ? kFx1 : face == 2 ? kFy0
+                  : face == 3 ? kFy1 : kFz0;
+    if (!(w.faces & bit)) continue;
+    if (w.bottom && k == 0) continue;   // plate bottom: fixed, not slaved
+    // taken on an earlier immersed face
+    if ((face > 0 && (w.faces & kFx0) && i == 0) ||
+        (face > 1 && (w.faces & kFx1) && i == g.nx - 1) ||
+        (face > 2 && (w.faces & kFy0) && j == 0) ||
+        (face > 3 && (w.faces & kFy1) && j == g.ny - 1))
+      continue;
+    const int n = pidx(g, i, j, k);
+    if (phase == 0) {
+      const double* Tc = cp.oT[st.cur];
+      const R* dxc = st.first ? nullptr : (const R*)cp.ox[st.xi];
+      double v = 0.0;
+      prolong_each(cp.go, w, i, j, k, [&](int cn, double wt) {
+        v += wt * (dxc != nullptr ? trial_T(Tc[cn], st.alpha * (double)dxc[cn], it.m)
+                                  : Tc[cn]);
+      });
+      it.Tb[st.cur][n] = v;
+    } else if (phase == 1) {
+      const R* rc = (const R*)cp.orr[0];
+      const R* dc = (const R*)cp.odinv;
+      double v = 0.0;
+      prolong_each(cp.go, w, i, j, k, [&](int cn, double wt) {
+        v += wt * (double)(dc[cn] * rc[cn]);
+      });
+      ((R*)it.r[0])[n] = (R)v;
+      ((R*)it.dinv)[n] = (R)1;
+    } else {
+      const R* rc = (const R*)cp.orr[a];
+      const R* wc = (const R*)cp.ow[a];
+      const R* scs = (const R*)cp.os[1 - a];
+      const R* dc = (const R*)cp.odinv;
+      double vr = 0.0, vw = 0.0, vs = 0.0;
+      prolong_each(cp.go, w, i, j, k, [&](int cn, double wt) {
+        const R dv = dc[cn];
+        vr += wt * (double)(dv * rc[cn]);
+        vw += wt * (double)(dv * wc[cn]);
+        if (kit > 0) vs += wt * (double)(dv * scs[cn]);
+      });
+      ((R*)it.r[a])[n] = (R)vr;
+      ((R*)it.w[a])[n] = (R)vw;
+      ((R*)it.s[1 - a])[n] = (R)vs;
+    }
+  }
+}
+
 int grid_tiles(const Geo& g, int& ntx, int& nty) {
   int ntz;
   tiles_of(g, ntx, nty, ntz);
@@ -1626,6 +1742,8 @@ void k_residual_pair(Launch L, const SolveItem* items, int n_items,
                      int per_item, int round, int side) {
   if (side == kFineSide)
     launch_residual<R, kFineSide>(L, items, n_items, per_item, round);
+  else if (side == kFineSideP)
+    launch_residual<R, kFineSideP>(L, items, n_items, per_item, round);
   else
     launch_residual<R, kCoarseSide>(L, items, n_items, per_item, round);
 }
@@ -1634,6 +1752,8 @@ void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
                      int per_item, int round, int side) {
   if (side == kFineSide)
     launch_cg_start<R, kFineSide>(L, items, n_items, per_item, round);
+  else if (side == kFineSideP)
+    launch_cg_start<R, kFineSideP>(L, items, n_items, per_item, round);
   else
     launch_cg_start<R, kCoarseSide>(L, items, n_items, per_item, round);
 }
@@ -1644,9 +1764,19 @@ void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
   if (side == kFineSide)
     launch_cg_iter<R, kFineSide>(L, items, n_items, per_item, round, kit,
                                  ev_start, ev_stop);
+  else if (side == kFineSideP)
+    launch_cg_iter<R, kFineSideP>(L, items, n_items, per_item, round, kit,
+                                  ev_start, ev_stop);
   else
     launch_cg_iter<R, kCoarseSide>(L, items, n_items, per_item, round, kit,
                                    ev_start, ev_stop);
+}
+template <class R>
+void k_couple_prolong(Launch L, const SolveItem* fine_items, int n_items,
+                      int per_item, int round, int phase, int kit) {
+  hipLaunchKernelGGL(couple_prolong_kernel<R>, dim3(n_items * per_item),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, fine_items,
+                     per_item, round, phase, kit);
 }
 template <class R>
 void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
@@ -1670,7 +1800,9 @@ void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
   template void k_cg_iter_pair<R>(Launch, const SolveItem*, int, int, int,   \
                                   int, int, void*, void*);                   \
   template void k_couple_gather<R>(Launch, const SolveItem*, int, int, int,  \
-                                   int, int);
+                                   int, int);                                \
+  template void k_couple_prolong<R>(Launch, const SolveItem*, int, int, int, \
+                                    int, int);
 TL_BATCH_INST(float)
 TL_BATCH_INST(double)
 #undef TL_BATCH_INST

@@ -57,7 +57,9 @@ inline void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw DevErr{std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-constexpr int kProfPairs = 64;      // event pairs held between host syncs
+constexpr int kProfPairs = 64;
+constexpr int kProlongBatch = 4;   // composite pairs per batch from which the
+                                   // prolongation gets a kernel of its own      // event pairs held between host syncs
 constexpr int kMaxRoundsPerSync = 8;  // Newton rounds queued between syncs
 constexpr size_t kAlign = 256;
 
@@ -342,7 +344,7 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
                            hipMemcpyHostToDevice, B.stream),
             "hipMemcpyAsync(scalars)");
   std::vector<int> act, built, round_iters;
-  int round = 0, per_a = 0, per_c = 0, max_gamma = 0;
+  int round = 0, per_a = 0, per_c = 0, per_p = 0, max_gamma = 0;
   for (;;) {
     act.clear();
     for (int u = 0; u < nu; ++u)
@@ -362,6 +364,15 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
       }
       per_a = item_tile_blocks(most, na);
       per_c = item_tile_blocks(most_c, na);
+      // the prolongation: about four interface nodes per thread
+      long most_face = 1;
+      if (paired)
+        for (int u : act) {
+          const Geo& g = jobs[2 * u]->g;
+          most_face = std::max(most_face, 2l * g.ny * g.nz + 2l * g.nx * g.nz +
+                                              (long)g.nx * g.ny);
+        }
+      per_p = (int)std::max(1l, std::min(256l, most_face / (4 * kBlock) + 1));
       for (int a = 0; a < na; ++a) {
         const int u = act[a];
         if (!paired) {
@@ -389,6 +400,11 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
       n_rounds = std::max(n_rounds, jobs[paired ? 2 * u : u]->rounds_hint);
     }
     const int r0 = round;
+    // composite pairs: interface values prolonged by a kernel of their own
+    // in large batches (cheaper fine kernels), inside the fine kernels for
+    // a few simulations (fewer launches); the values are the same
+    const bool prolong = paired && na >= kProlongBatch;
+    const int fside = prolong ? kFineSideP : kFineSide;
     const SolveItem* fi = B.d_items;
     const SolveItem* ci = B.d_items + na;
     for (int rr = 0; rr < n_rounds; ++rr, ++round) {
@@ -396,10 +412,12 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
         k_residual_batched<R>(B.L, fi, na, per_a, round);
         k_cg_start_batched<R>(B.L, fi, na, per_a, round);
       } else {
-        k_residual_pair<R>(B.L, fi, na, per_a, round, kFineSide);
+        if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 0, 0);
+        k_residual_pair<R>(B.L, fi, na, per_a, round, fside);
         k_couple_gather<R>(B.L, ci, na, max_gamma, round, 0, 0);
         k_residual_pair<R>(B.L, ci, na, per_c, round, kCoarseSide);
-        k_cg_start_pair<R>(B.L, fi, na, per_a, round, kFineSide);
+        if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 1, 0);
+        k_cg_start_pair<R>(B.L, fi, na, per_a, round, fside);
         k_couple_gather<R>(B.L, ci, na, max_gamma, round, 1, 0);
         k_cg_start_pair<R>(B.L, ci, na, per_c, round, kCoarseSide);
       }
@@ -413,7 +431,8 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
         if (!paired) {
           k_cg_iter_batched<R>(B.L, fi, na, per_a, round, k, e0, e1);
         } else {
-          k_cg_iter_pair<R>(B.L, fi, na, per_a, round, k, kFineSide, nullptr,
+          if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 2, k);
+          k_cg_iter_pair<R>(B.L, fi, na, per_a, round, k, fside, nullptr,
                             nullptr);
           k_couple_gather<R>(B.L, ci, na, max_gamma, round, 2, k);
           k_cg_iter_pair<R>(B.L, ci, na, per_c, round, k, kCoarseSide,
