@@ -141,6 +141,14 @@ def test_whole_plate_window(coupling):
     _check_vs_oracle(wl, 4, 1e-9, coupling)
 
 
+# the largest micro-step count (the coarse load averages 32 laser positions)
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_max_micro_steps(coupling):
+    wl = W.config0()
+    wl = replace(wl, options=replace(wl.options, m_time=32, dt_coarse=64e-6), n_macro=3)
+    _check_vs_oracle(wl, 3, 1e-9, coupling)
+
+
 def test_composite_equals_dn_on_gpu():
     """The two GPU forms agree with each other (config 0, FP64)."""
     a = _run(_with(W.config0(), W.COMPOSITE), 20)
