@@ -36,14 +36,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed macro steps")
     ap.add_argument("--warmup", type=int, default=2, help="untimed macro steps (separate run)")
-    ap.add_argument("--workload", default="config1", choices=["config1", "config0", "config2",
-                                                              "config3", "config4"])
-    ap.add_argument("--requests", type=int, default=64, help="config3: requests in the stream")
-    ap.add_argument("--slots", type=int, default=64, help="config3: server slots")
+    ap.add_argument("--workload", default="single_track_2mm",
+                    choices=["single_track_2mm", "single_track_1mm", "raster_5mm",
+                             "served_tracks", "raster_10mm"])
+    ap.add_argument("--requests", type=int, default=64, help="served_tracks: requests in the stream")
+    ap.add_argument("--slots", type=int, default=64, help="served_tracks: server slots")
     ap.add_argument("--budget-mb", type=float, default=0.0,
-                    help="config3: HBM budget for active requests (0: room for every slot)")
+                    help="served_tracks: HBM budget for active requests (0: room for every slot)")
     ap.add_argument("--load", type=float, default=1.5,
-                    help="config3: arrival rate as a multiple of the measured batched capacity")
+                    help="served_tracks: arrival rate as a multiple of the measured batched capacity")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--coupling", default=None, choices=[None, "dn", "composite"],
                     help="two-level correction: Dirichlet-Neumann iteration or one "
@@ -104,7 +105,7 @@ def k2_sweep(tl, W, torch):
     """Bare operator apply y = d v + K[kappa] v, timed with events on the
     current stream (the library launches on it) over repeated launches."""
     out = []
-    shapes = [("config1 fine", 80, 40, 24), ("config4 fine", 120, 80, 30),
+    shapes = [("single_track_2mm fine", 80, 40, 24), ("raster_10mm fine", 120, 80, 30),
               ("HBM-resident 640x640x160", 640, 640, 160)]
     g = torch.Generator(device="cuda").manual_seed(0)
     for name, nx, ny, nz in shapes:
@@ -194,7 +195,7 @@ def serve_stream(tl, W, torch, reqs, slots, budget, arrivals=None, profile_every
 
 
 def main_serving(args):
-    """config 3: a seeded stream of single-track requests through the
+    """The served workload: a seeded stream of single-track requests through the
     continuous-batching server.  A closed-loop run (all requests at t = 0)
     measures the batched capacity; the stream then arrives as a Poisson
     process at `--load` times that capacity, and throughput (fine
@@ -205,7 +206,7 @@ def main_serving(args):
     import workloads as W
     from paper_2110_12932_amd import tl
     tl.load()
-    stream = W.config3_requests(args.requests, seed=0, mean_interarrival=1.0)
+    stream = W.served_tracks(args.requests, seed=0, mean_interarrival=1.0)
     reqs = [w for _, w in stream]
     unit_gaps = np.diff([0.0] + [a for a, _ in stream])   # Exp(1) draws, in order
     budget = int(args.budget_mb * 2 ** 20) if args.budget_mb else 0
@@ -239,7 +240,7 @@ def main_serving(args):
         "ms_per_step": wall * 1e3 / max(1, int(sum(st["macro_steps"] for st in stats))),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "config3", "requests": len(reqs), "slots": args.slots,
+        "config": {"workload": "served_tracks", "requests": len(reqs), "slots": args.slots,
                    "hbm_budget_bytes": budget or "unbounded",
                    "fine_nodes_per_request": list(stats[0]["fine_nodes"]),
                    "arrivals": f"Poisson, {args.load}x the closed-loop capacity "
@@ -254,11 +255,11 @@ def main_serving(args):
 
 def main():
     args = parse()
-    if args.workload == "config3" and args.gpus == 1:
+    if args.workload == "served_tracks" and args.gpus == 1:
         main_serving(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import workloads as W

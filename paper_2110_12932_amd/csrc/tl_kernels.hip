@@ -545,15 +545,19 @@ constexpr int ZEPT = (ZEN + kBlock - 1) / kBlock;
 struct ZPlan {
   int ncx, ncy, nrun, run;   // columns per axis, runs per column, run length
 };
+template <class R>
 static inline ZPlan zplan_of(const Geo& g) {
   ZPlan z;
   z.ncx = (g.nx + 1 + ZX - 1) / ZX;   // columns start at i = -1 (see below)
   z.ncy = (g.ny + ZY - 1) / ZY;
   const int cols = z.ncx * z.ncy;
-  // about 8 work units per workgroup of a full grid (kMaxBlocks), so the
-  // grid-stride loop balances, and runs of at least 16 planes, so the two
-  // halo planes of a run add at most an eighth to its reads
-  const int nrun = std::max(1, std::min(8 * kMaxBlocks / cols, g.nz / 16));
+  // Long runs: the two halo planes of a run are read twice.  Runs of at
+  // least 64 planes in FP64 and whole columns in FP32 were the fastest on
+  // a 640 x 640 x 160 grid (runs of 16 to 161 planes tried: 6 % and 5 %
+  // faster than runs of 18); and no more runs than about 8 work units per
+  // workgroup of a full grid (kMaxBlocks) need
+  const int min_run = sizeof(R) == 8 ? 64 : g.nz + 1;
+  const int nrun = std::max(1, std::min(8 * kMaxBlocks / cols, g.nz / min_run));
   z.run = (g.nz + nrun - 1) / nrun;
   z.nrun = (g.nz + z.run - 1) / z.run;
   return z;
@@ -1815,7 +1819,7 @@ template <class R>
 void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
                 R* y) {
   if ((long)g.nreal > kZmarchNodes && g.nz >= 8) {
-    const ZPlan zp = zplan_of(g);
+    const ZPlan zp = zplan_of<R>(g);
     const int units = zp.ncx * zp.ncy * zp.nrun;
     hipLaunchKernelGGL(op_apply_zmarch_kernel<R>, dim3(tiled_grid(units)),
                        dim3(kBlock), 0, (hipStream_t)L.stream, g, zp, d, kap,

@@ -5,7 +5,7 @@ two-level iteration) on the first macro steps of a workload and stores the
 coarse and fine temperatures, the window origin and the energy ledger in
 tests/golden/<name>_n<steps>.npz.  Nothing here touches the GPU library.
 
-Usage: python tests/golden/make_golden.py config1 3
+Usage: python tests/golden/make_golden.py single_track_2mm 3
 """
 import os
 import sys

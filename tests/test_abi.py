@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_workspace_bytes():
-    wl = W.config1()
+    wl = W.single_track_2mm()
     n = tl.tl_workspace_bytes(wl.mesh, wl.options)
     # 23 coarse + 10 fine FP64 arrays + 12 fine CG arrays, padded layouts
     pitch = lambda n: (n + 2 + 31) // 32 * 32   # n nodes + 2 ghosts, rounded to 32
@@ -85,7 +85,7 @@ class _FakeWorkspace:
                         options=replace(wl.options, source=W.VOLUME)), "volume"),
 ])
 def test_create_rejects_invalid_input(mutate, what):
-    wl = mutate(W.config0())
+    wl = mutate(W.single_track_1mm())
     with pytest.raises(tl.TLError) as e:
         tl.tl_create(wl.mesh, wl.material, wl.scan, wl.options, _FakeWorkspace(1 << 30),
                      stream=0)
@@ -94,7 +94,7 @@ def test_create_rejects_invalid_input(mutate, what):
 
 
 def test_create_rejects_small_workspace():
-    wl = W.config0()
+    wl = W.single_track_1mm()
     with pytest.raises(tl.TLError) as e:
         tl.tl_create(wl.mesh, wl.material, wl.scan, wl.options, _FakeWorkspace(1000), stream=0)
     assert e.value.status == tl.TL_ENOMEM

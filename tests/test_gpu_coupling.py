@@ -81,13 +81,13 @@ COUPLINGS = [pytest.param(W.COMPOSITE, id="composite"), pytest.param(W.DN, id="d
 
 
 @pytest.mark.parametrize("coupling", COUPLINGS)
-def test_config0_fp64(coupling):
-    _check_vs_oracle(W.config0(), 20, 1e-9, coupling)
+def test_single_track_1mm_fp64(coupling):
+    _check_vs_oracle(W.single_track_1mm(), 20, 1e-9, coupling)
 
 
 @pytest.mark.parametrize("coupling", COUPLINGS)
-def test_config0_mixed(coupling):
-    _check_vs_oracle(W.config0(W.MIXED), 20, 1e-6, coupling)
+def test_single_track_1mm_mixed(coupling):
+    _check_vs_oracle(W.single_track_1mm(W.MIXED), 20, 1e-6, coupling)
 
 
 @pytest.mark.parametrize("coupling", COUPLINGS)
@@ -100,7 +100,7 @@ def test_small_cases_fp64(name, coupling):
 @pytest.mark.parametrize("coupling", COUPLINGS)
 @pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
 def test_surface_loss(prec, tol, coupling):
-    wl = W.config0(prec)
+    wl = W.single_track_1mm(prec)
     wl = replace(wl, material=replace(wl.material, h_conv=2.0e4, emissivity=0.8, T_amb=300.0))
     led, orc = _check_vs_oracle(wl, 12, tol, coupling)
     assert led["surface"] > 0.0
@@ -120,9 +120,9 @@ def test_single_track_3d_volume_sources(prec, tol, coupling):
 # the paper's alternate global formulation (a different discrete problem:
 # the oracle runs the same formulation)
 @pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
-@pytest.mark.parametrize("name", ["config0", "single_track_3d"])
+@pytest.mark.parametrize("name", ["single_track_1mm", "single_track_3d"])
 def test_alternate_formulation(name, prec, tol):
-    wl = W.config0(prec) if name == "config0" else W.single_track_3d(prec)
+    wl = W.single_track_1mm(prec) if name == "single_track_1mm" else W.single_track_3d(prec)
     wl = replace(wl, material=replace(wl.material, h_conv=1.0e4))
     _check_vs_oracle(wl, min(wl.n_macro, 12), tol, W.ALTERNATE)
 
@@ -133,7 +133,7 @@ def test_alternate_formulation(name, prec, tol):
 @pytest.mark.parametrize("coupling", COUPLINGS)
 def test_whole_plate_window(coupling):
     UM = 1e-6
-    wl = W.config0()
+    wl = W.single_track_1mm()
     mesh = replace(wl.mesh, nx=6, ny=4, nz=3, lx=6 * 62.5 * UM, ly=4 * 62.5 * UM,
                    lz=3 * 62.5 * UM, win_nx=6, win_ny=4, win_nz=3)
     tr = W.Track(0.05e-3, 0.1e-3, 0.3e-3, 0.15e-3, 0.8, 150.0, 50 * UM, 0.4)
@@ -144,15 +144,15 @@ def test_whole_plate_window(coupling):
 # the largest micro-step count (the coarse load averages 32 laser positions)
 @pytest.mark.parametrize("coupling", COUPLINGS)
 def test_max_micro_steps(coupling):
-    wl = W.config0()
+    wl = W.single_track_1mm()
     wl = replace(wl, options=replace(wl.options, m_time=32, dt_coarse=64e-6), n_macro=3)
     _check_vs_oracle(wl, 3, 1e-9, coupling)
 
 
 def test_composite_equals_dn_on_gpu():
-    """The two GPU forms agree with each other (config 0, FP64)."""
-    a = _run(_with(W.config0(), W.COMPOSITE), 20)
-    b = _run(_with(W.config0(), W.DN), 20)
+    """The two GPU forms agree with each other (single_track_1mm, FP64)."""
+    a = _run(_with(W.single_track_1mm(), W.COMPOSITE), 20)
+    b = _run(_with(W.single_track_1mm(), W.DN), 20)
     assert rel_maxerr(a[0], b[0]) <= 1e-9 and rel_maxerr(a[1], b[1]) <= 1e-9
 
 

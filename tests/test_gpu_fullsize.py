@@ -1,10 +1,10 @@
 """GPU parity at the workloads' full sizes, in the configuration bench.py
 times (the workloads' default options).
 
-* config 1 (the benchmark workload): the first macro steps against FP64
+* single_track_2mm (the benchmark workload): the first macro steps against FP64
   oracle fields stored by tests/golden/make_golden.py (oracle converged to
   1e-10 K): FP64 path <= 1e-9, mixed path <= 1e-6 relative max-norm.
-* configs 2 and 4 (raster and large build, mixed precision): properties
+* raster_5mm and raster_10mm (raster and large build, mixed precision): properties
   that hold at any size -- the mixed path agrees with the FP64 path to
   1e-6, the energy ledger closes, fields are finite and bounded below by
   the plate temperature -- plus oracle goldens when present.
@@ -58,10 +58,10 @@ def _ledger_closes(led):
 
 
 @pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
-def test_config1_against_oracle_golden(prec, tol):
-    g = _golden("config1")
+def test_single_track_2mm_against_oracle_golden(prec, tol):
+    g = _golden("single_track_2mm")
     n = int(g["steps"])
-    Tc, Tf, origin, led, st = _run(W.config1(prec), n)
+    Tc, Tf, origin, led, st = _run(W.single_track_2mm(prec), n)
     assert tuple(origin) == tuple(int(v) for v in g["origin"])
     ec, ef = rel_maxerr(Tc, g["Tc"]), rel_maxerr(Tf, g["Tf"])
     say("  rel err coarse", ec, "fine", ef)
@@ -71,7 +71,7 @@ def test_config1_against_oracle_golden(prec, tol):
     assert led["stored"] == pytest.approx(float(g["stored"]), rel=tol)
 
 
-@pytest.mark.parametrize("name, n", [("config2", 6), ("config4", 3)])
+@pytest.mark.parametrize("name, n", [("raster_5mm", 6), ("raster_10mm", 3)])
 def test_mixed_matches_fp64_at_full_size(name, n):
     a = _run(W.by_name(name, precision=W.FP64), n)
     b = _run(W.by_name(name, precision=W.MIXED), n)
@@ -85,7 +85,7 @@ def test_mixed_matches_fp64_at_full_size(name, n):
         assert _ledger_closes(led)
 
 
-@pytest.mark.parametrize("name", ["config2", "config4"])
+@pytest.mark.parametrize("name", ["raster_5mm", "raster_10mm"])
 def test_large_against_oracle_golden(name):
     g = _golden(name)
     n = int(g["steps"])

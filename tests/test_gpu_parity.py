@@ -84,10 +84,12 @@ def _op_rows(g, Ke, d, kap, v, nodes):
 
 
 # more than 4M nodes: the z-marching kernel, with ragged column tiles in x
-# (301 = 4 x 64 + 45) and y (121 = 30 x 4 + 1) and a short last z run
+# (301 = 4 x 64 + 45) and y (121 = 30 x 4 + 1); FP64 cuts each column into
+# two z runs (67 node planes and a short last one of 66), FP32 takes whole
+# columns
 @pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
 def test_op_apply_large_grid_sampled(prec):
-    nx, ny, nz = 300, 120, 118
+    nx, ny, nz = 300, 120, 132
     say("op_apply large", (nx, ny, nz), prec)
     h = (5.3e-6, 4.1e-6, 6.7e-6)
     g = G.Grid(nx, ny, nz, *h)
@@ -113,7 +115,7 @@ def test_op_apply_large_grid_sampled(prec):
     # every corner and edge class of the domain and of the tiles, plus random
     xs = sorted({0, 1, 63, 64, 65, 127, 128, 255, 256, 299, 300})
     ys = sorted({0, 1, 3, 4, 5, 59, 60, 116, 119, 120})
-    zs = sorted({0, 1, 8, 9, 17, 18, 116, 117, 118})
+    zs = sorted({0, 1, 8, 9, 17, 18, 65, 66, 67, 68, 130, 131, 132})
     nodes = [(i, j, k) for i in xs for j in ys for k in zs]
     nodes += [tuple(int(t) for t in rng.integers(0, (nx + 1, ny + 1, nz + 1)))
               for _ in range(300)]
@@ -125,7 +127,7 @@ def test_op_apply_large_grid_sampled(prec):
 
 
 def test_nonconvergence_rolls_back():
-    wl = W.config0()
+    wl = W.single_track_1mm()
     sim = tl.Sim(replace(wl, options=replace(wl.options, newton_max=1)))
     T0, _ = sim.temperature(1)
     with pytest.raises(tl.TLError) as e:

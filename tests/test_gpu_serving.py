@@ -28,7 +28,7 @@ def _gpu():
 def _requests():
     """Small two-level requests of different sizes, parameters and
     precisions."""
-    base = W.config0()
+    base = W.single_track_1mm()
     cases = W.small_cases()
     a = replace(base, name="A", n_macro=6)
     b = replace(base, name="B", n_macro=4,
@@ -91,14 +91,14 @@ def test_heterogeneous_mix_equals_alone():
     """Requests with different two-level couplings, laser models and
     precisions share the server's launches: each equals its own run through
     a plain handle."""
-    base = W.config0()
+    base = W.single_track_1mm()
     reqs = {
         "dn": replace(base, name="dn", n_macro=4,
                       options=replace(base.options, coupling=W.DN)),
         "alt": replace(base, name="alt", n_macro=4,
                        options=replace(base.options, coupling=W.ALTERNATE)),
         "vol": replace(W.single_track_3d(), n_macro=3),
-        "mixloss": replace(W.config0(W.MIXED), name="mixloss", n_macro=4,
+        "mixloss": replace(W.single_track_1mm(W.MIXED), name="mixloss", n_macro=4,
                            material=replace(base.material, h_conv=2e4, emissivity=0.8)),
     }
     sv = tl.Server(_pool_bytes(reqs.values()), max_slots=4)

@@ -16,7 +16,7 @@ import pytest
 import oracle
 from oracle import grid as G
 from oracle import twolevel as TW
-from workloads import config0, small_cases, ScanPath, Track
+from workloads import single_track_1mm, small_cases, ScanPath, Track
 
 UM = 1e-6
 
@@ -41,8 +41,8 @@ def test_energy_ledger_identity(name):
                                   rel=1e-9)
 
 
-def test_full_config0_runs_and_moves():
-    sim = oracle.run(config0())
+def test_full_single_track_1mm_runs_and_moves():
+    sim = oracle.run(single_track_1mm())
     assert sim.stats["moves"] >= 5
     assert max(_ledger_errors(sim)) < 1e-9
     assert np.isfinite(sim.Tf).all() and sim.Tf.max() > 1623.0   # the track melts
@@ -66,7 +66,7 @@ def test_refinement1_single_macro_step_is_single_level():
 
 
 def test_whole_plate_window_is_single_level_fine():
-    wl = config0()
+    wl = single_track_1mm()
     mesh = replace(wl.mesh, nx=6, ny=4, nz=3, lx=6 * 62.5 * UM, ly=4 * 62.5 * UM,
                    lz=3 * 62.5 * UM, win_nx=6, win_ny=4, win_nz=3)
     tr = Track(0.05e-3, 0.1e-3, 0.3e-3, 0.15e-3, 0.8, 150.0, 50 * UM, 0.4)
@@ -95,7 +95,7 @@ def test_prolongation_exact_on_trilinear_and_injection():
 
 
 def test_window_rule_hand_values():
-    wl = config0()
+    wl = single_track_1mm()
     c = TW.coarse_grid(wl.mesh)
     # t = 50 us: beam at x = 0.14 mm, y = 0.25 mm, moving +x; window 6x4 cells
     # of 62.5 um: x_lo = 0.14 - 0.25 < 0 -> clamp 0; y_lo = 0.125 mm -> J0 = 2

@@ -20,7 +20,7 @@ import pytest
 import oracle
 from oracle import grid as G
 from oracle import laser as L
-from workloads import ScanPath, Track, single_track_3d, config0, VOLUME
+from workloads import ScanPath, Track, single_track_3d, single_track_1mm, VOLUME
 
 UM = 1e-6
 

@@ -25,17 +25,17 @@ def _laser(**kw):
     return base
 
 
-def config0(precision=FP64):
+def single_track_1mm(precision=FP64):
     """Plain FP64 two-level solve, one straight track: 1.0x0.5x0.25 mm,
     16x8x4 coarse cells, window 6x4x2 cells refined 2x, 4 micro steps per
     50 us macro step, 20 macro steps, track x = 0.1 -> 0.9 mm at y = 0.25 mm."""
     mesh = Mesh(1.0 * MM, 0.5 * MM, 0.25 * MM, 16, 8, 4, 2, 6, 4, 2)
     tr = Track(0.1 * MM, 0.25 * MM, 0.9 * MM, 0.25 * MM, **_laser())
     opts = options_for(precision, 50 * UM, 4)
-    return Workload("config0", mesh, Material(), ScanPath([tr]), opts, 20)
+    return Workload("single_track_1mm", mesh, Material(), ScanPath([tr]), opts, 20)
 
 
-def config1(precision=FP64):
+def single_track_2mm(precision=FP64):
     """Single track at paper-like resolution: 2x1x0.5 mm, 50x25x13 coarse
     cells (40 um in x,y), window 10x5x3 cells refined 8x (5 um), macro
     step 25 us with 8 micro steps, 100 macro steps, track x = 0 -> 2 mm at
@@ -43,10 +43,10 @@ def config1(precision=FP64):
     mesh = Mesh(2.0 * MM, 1.0 * MM, 0.5 * MM, 50, 25, 13, 8, 10, 5, 3)
     tr = Track(0.0, 0.5 * MM, 2.0 * MM, 0.5 * MM, **_laser())
     opts = options_for(precision, 25 * UM, 8)
-    return Workload("config1", mesh, Material(), ScanPath([tr]), opts, 100)
+    return Workload("single_track_2mm", mesh, Material(), ScanPath([tr]), opts, 100)
 
 
-def config2(precision=MIXED, seed=0):
+def raster_5mm(precision=MIXED, seed=0):
     """Raster of 10 alternating 4 mm tracks at 100 um hatch over a 5x5x1 mm
     plate, coarse h = 50 um, window 10x6x3 cells refined 8x (6.25 um),
     macro step 50 us, 8 micro steps, 1000 macro steps.  Track powers are
@@ -60,10 +60,10 @@ def config2(precision=MIXED, seed=0):
         tracks.append(Track(xa, y, xb, y, **_laser(power=float(powers[k]))))
     mesh = Mesh(5.0 * MM, 5.0 * MM, 1.0 * MM, 100, 100, 20, 8, 10, 6, 3)
     opts = options_for(precision, 50 * UM, 8)
-    return Workload("config2", mesh, Material(), ScanPath(tracks), opts, 1000)
+    return Workload("raster_5mm", mesh, Material(), ScanPath(tracks), opts, 1000)
 
 
-def config3_requests(n=64, seed=0, mean_interarrival=1e-3, precision=MIXED):
+def served_tracks(n=64, seed=0, mean_interarrival=1e-3, precision=MIXED):
     """Served stream: n single-track requests.  Per request, in this draw
     order: exponential inter-arrival [s], L_x ~ U(1,4) mm, coarse h in
     {40, 50} um, P ~ U(100,300) W, v ~ U(0.4,1.5) m/s, R ~ U(40,80) um.
@@ -90,12 +90,12 @@ def config3_requests(n=64, seed=0, mean_interarrival=1e-3, precision=MIXED):
                    absorptivity=0.4)
         n_macro = int(math.ceil((lx / v) / dt - 1e-9))
         opts = options_for(precision, dt, 8)
-        out.append((t, Workload(f"config3_req{q}", mesh, Material(),
+        out.append((t, Workload(f"served_req{q}", mesh, Material(),
                                 ScanPath([tr]), opts, n_macro)))
     return out
 
 
-def config4(precision=MIXED):
+def raster_10mm(precision=MIXED):
     """Large multi-track build: 10x10x2 mm plate, 200x200x40 coarse cells
     (50 um), 20 alternating raster tracks x = 1 -> 9 mm at 100 um hatch,
     powers/speeds alternating (200 W, 0.8 m/s) and (280 W, 1.2 m/s), window
@@ -110,7 +110,7 @@ def config4(precision=MIXED):
     opts = options_for(precision, 25 * UM, 8)
     total = sum(8.0 * MM / t.speed for t in tracks)
     n_macro = int(math.ceil(total / opts.dt_coarse - 1e-9))
-    return Workload("config4", mesh, Material(), ScanPath(tracks), opts,
+    return Workload("raster_10mm", mesh, Material(), ScanPath(tracks), opts,
                     n_macro)
 
 
@@ -122,7 +122,7 @@ def single_track_3d(precision=FP64):
     not given); global h = 100 um, local window 1.2 x 0.5 x 0.1 mm at
     h = 20 um (refinement 5), local step 1e-4 s and a four times longer
     global step, 7 macro steps (the track takes 2.5 ms).  The material law is
-    this build's linear one (the paper's IN625 tables are only plotted)."""
+    the linear law of this library (the paper's IN625 tables are only plotted)."""
     mesh = Mesh(3.0 * MM, 1.5 * MM, 1.0 * MM, 30, 15, 10, 5, 12, 5, 1)
     tr = Track(0.5 * MM, 0.75 * MM, 2.5 * MM, 0.75 * MM, speed=0.8, power=179.2,
                radius=85 * UM, absorptivity=0.38, depth=50 * UM)
@@ -131,15 +131,15 @@ def single_track_3d(precision=FP64):
 
 
 def by_name(name, **kw):
-    return {"config0": config0, "config1": config1, "config2": config2,
-            "config4": config4, "single_track_3d": single_track_3d}[name](**kw)
+    return {"single_track_1mm": single_track_1mm, "single_track_2mm": single_track_2mm, "raster_5mm": raster_5mm,
+            "raster_10mm": raster_10mm, "single_track_3d": single_track_3d}[name](**kw)
 
 
 def small_cases():
-    """Tiny two-level problems used by parity tests: variations of config 0
+    """Tiny two-level problems used by parity tests: variations of single_track_1mm
     that exercise clamped windows, window moves, m = 1, r = 1 and a
     window spanning the full depth."""
-    base = config0()
+    base = single_track_1mm()
     cases = {}
     cases["c0"] = base
     w = replace(base, name="r1m1", n_macro=12,
