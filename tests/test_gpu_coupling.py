@@ -97,6 +97,41 @@ def test_small_cases_fp64(name, coupling):
     _check_vs_oracle(wl, wl.n_macro, 1e-9, coupling)
 
 
+# The path starts at t = 0.1 ms (beam off for the first two macro steps)
+# and its track ends at 0.725 ms, partway through macro step 14: loads
+# switch on and off inside macro steps, the window follows the beam five
+# times and stays where it is while the beam is off.
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_beam_off_before_and_after_the_path(coupling):
+    base = W.single_track_1mm()
+    tr = replace(base.scan.tracks[0], x1=0.6e-3)
+    wl = replace(base, name="beam_off", n_macro=17,
+                 scan=W.ScanPath([tr], t_start=0.1e-3))
+    led, orc = _check_vs_oracle(wl, wl.n_macro, 1e-9, coupling)
+    assert orc.stats["moves"] == 5
+    # eta P over the 0.625 ms the beam is on (the face quadrature of a
+    # 50 um spot on 31 um faces integrates it to within a few per cent)
+    assert led["absorbed"] == pytest.approx(0.4 * 180.0 * 0.625e-3, rel=0.05)
+
+
+# No heat input: every node keeps the plate temperature (the oracle's field
+# is exactly 300 K), while the window still follows the beam.
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_zero_power_keeps_the_plate_temperature(coupling):
+    base = W.single_track_1mm()
+    tr = replace(base.scan.tracks[0], power=0.0)
+    wl = _with(replace(base, name="zero_power", scan=W.ScanPath([tr])), coupling)
+    Tc, Tf, origin, led, st = _run(wl, 6)
+    orc = oracle.run(wl, 6, newton_tol=1e-10, dn_tol=1e-10)
+    oc, of, oorigin = oracle_fields(orc)
+    assert origin == oorigin and st["window_moves"] == orc.stats["moves"] == 1
+    T0 = wl.material.T_init
+    assert np.all(oc == T0) and np.all(of == T0)
+    assert np.abs(Tc - T0).max() <= 1e-9 and np.abs(Tf - T0).max() <= 1e-9
+    assert led["absorbed"] == 0.0
+    assert np.isfinite(led["stored"]) and np.isfinite(led["bottom"])
+
+
 @pytest.mark.parametrize("coupling", COUPLINGS)
 @pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
 def test_surface_loss(prec, tol, coupling):
