@@ -104,6 +104,7 @@ def cpu_baseline(wl):
 def k2_sweep(tl, W, torch):
     """Bare operator apply y = d v + K[kappa] v, timed with events on the
     current stream (the library launches on it) over repeated launches."""
+    import numpy as np
     out = []
     shapes = [("single_track_2mm fine", 80, 40, 24), ("raster_10mm fine", 120, 80, 30),
               ("HBM-resident 640x640x160", 640, 640, 160)]
@@ -119,12 +120,16 @@ def k2_sweep(tl, W, torch):
             y = torch.empty_like(v)
             reps = 20 if nodes > 1e7 else 200
             tl.tl_op_apply(grid, prec, d, kap, v, y, 3)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            tl.tl_op_apply(grid, prec, d, kap, v, y, reps)
-            e1.record()
-            torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) * 1e3 / reps
+            # the median of 5 batches of `reps` launches
+            batch_us = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                tl.tl_op_apply(grid, prec, d, kap, v, y, reps)
+                e1.record()
+                torch.cuda.synchronize()
+                batch_us.append(e0.elapsed_time(e1) * 1e3 / reps)
+            us = float(np.median(batch_us))
             gbs = 4 * eb * nodes / (us * 1e-6) / 1e9
             out.append({"shape": name, "nodes": nodes, "dtype": "f64" if eb == 8 else "f32",
                         "us_per_launch": round(us, 3), "GB/s": round(gbs, 1),

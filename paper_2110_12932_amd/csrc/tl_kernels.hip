@@ -629,7 +629,10 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
       }
     };
     auto load_d = [&](int k) {
-      return k < k1 ? d[(long)(k + 1) * g.pxy + doff] : (R)0;
+      // d and y are touched once per node: streamed past the caches
+      // (nontemporal), which leaves them to the halo-shared v and kappa
+      return k < k1 ? __builtin_nontemporal_load(&d[(long)(k + 1) * g.pxy + doff])
+                    : (R)0;
     };
     auto put_plane = [&](int p, const R (&rv)[ZHPT]) {
 #pragma unroll
@@ -716,7 +719,7 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
           yn = dq0 * V0[4] + stencil_elementwise(V, k8, wts);
         else
           yn = dq0 * V0[4] + stencil_grouped(V, k8, wts);
-        y[(long)(k + 1) * g.pxy + doff] = yn;
+        __builtin_nontemporal_store(yn, &y[(long)(k + 1) * g.pxy + doff]);
       }
       // plane k+2 replaces plane k, layer k+1 replaces layer k-1: both were
       // last read before the previous barrier
