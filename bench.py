@@ -81,22 +81,24 @@ def measured_traffic(path, workload, elem):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl):
-    """The oracle on one complete macro step of the same workload, one core."""
+def cpu_baseline(wl, n_macro=2):
+    """The oracle on the first `n_macro` complete macro steps of the same
+    workload (about 10-20 s of CPU work at the benchmark size), one core."""
     from threadpoolctl import threadpool_limits
     import oracle
+    el, dof_steps = 0.0, 0
     with threadpool_limits(1):
         sim = oracle.TwoLevel(wl)
-        t0 = time.perf_counter()
-        sim.step()
-        el = time.perf_counter() - t0
-    w = sim.win
-    free = int((~w.dir_f).sum())
-    dof_steps = free * wl.options.m_time
+        for _ in range(n_macro):
+            t0 = time.perf_counter()
+            sim.step()
+            el += time.perf_counter() - t0
+            dof_steps += int((~sim.win.dir_f).sum()) * wl.options.m_time
     return {"value": dof_steps / el, "unit": "fine DOF-timesteps/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{wl.name} macro step 0 in full ({wl.options.m_time} micro steps, "
-                      f"{free} free fine nodes, two-level correction included): "
+            "sample": f"{wl.name} macro steps 0-{n_macro - 1} in full "
+                      f"({n_macro * wl.options.m_time} micro steps, {dof_steps} fine "
+                      f"DOF-steps, two-level correction included): "
                       f"{el:.1f} s on 1 core of {os.cpu_count()} "
                       f"(affinity {len(os.sched_getaffinity(0))})"}
 
