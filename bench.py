@@ -109,6 +109,7 @@ def k2_sweep(tl, W, torch):
     import numpy as np
     out = []
     shapes = [("single_track_2mm fine", 80, 40, 24), ("raster_10mm fine", 120, 80, 30),
+              ("mid-size 300x120x132", 300, 120, 132),
               ("HBM-resident 640x640x160", 640, 640, 160)]
     g = torch.Generator(device="cuda").manual_seed(0)
     for name, nx, ny, nz in shapes:

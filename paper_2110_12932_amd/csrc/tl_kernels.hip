@@ -555,9 +555,14 @@ static inline ZPlan zplan_of(const Geo& g) {
   // least 64 planes in FP64 and whole columns in FP32 were the fastest on
   // a 640 x 640 x 160 grid (runs of 16 to 161 planes tried: 6 % and 5 %
   // faster than runs of 18); and no more runs than about 8 work units per
-  // workgroup of a full grid (kMaxBlocks) need
+  // workgroup of a full grid (kMaxBlocks) need.  A grid with few columns
+  // is still cut into at least 512 work units (two per compute unit), in
+  // runs of at least 8 planes: on a 300 x 120 x 132 grid (155 columns)
+  // that took 27 % (FP64) and 60 % (FP32) off the time of long runs, and
+  // 1024 or 2048 units were no better
   const int min_run = sizeof(R) == 8 ? 64 : g.nz + 1;
-  const int nrun = std::max(1, std::min(8 * kMaxBlocks / cols, g.nz / min_run));
+  int nrun = std::max(1, std::min(8 * kMaxBlocks / cols, g.nz / min_run));
+  nrun = std::max(nrun, std::min(g.nz / 8, (512 + cols - 1) / cols));
   z.run = (g.nz + nrun - 1) / nrun;
   z.nrun = (g.nz + z.run - 1) / z.run;
   return z;
@@ -659,12 +664,14 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
         w4[e] = la[(ty + 1 - (e >> 1)) * ZEX + (tx + 1 - (e & 1))];
     };
     // Register window: planes k-1, k, k+1 (VM, V0, VP) and element layers
-    // k-1, k (KM, K0).  Global loads run two planes ahead: queue slots QA
-    // (node plane k+2, element layer k+1, loaded one step earlier) and QB
-    // (plane k+3, layer k+2, loaded now); the node's own d at k, k+1.
+    // k-1, k (KM, K0).  Global loads run three planes ahead, so that two
+    // steps' loads are in flight: queue slots QA (node plane k+2, element
+    // layer k+1, loaded two steps earlier), QB (plane k+3, layer k+2, loaded
+    // one step earlier) and QC (plane k+4, layer k+3, loaded now); the
+    // node's own d at k, k+1, k+2.
     R V1[9], V2[9], V3[9], K1[4], K2[4];
-    R Q1[ZHPT], Q1k[ZEPT], Q2[ZHPT], Q2k[ZEPT];
-    R dq0, dq1;
+    R Q1[ZHPT], Q1k[ZEPT], Q2[ZHPT], Q2k[ZEPT], Q3[ZHPT], Q3k[ZEPT];
+    R dq0, dq1, dq2;
     {
       R a[ZHPT], b[ZHPT], c[ZHPT], ka[ZEPT], kb[ZEPT];
       load_plane(k0 - 1, a);
@@ -674,8 +681,11 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
       load_layer(k0, kb);
       dq0 = load_d(k0);
       dq1 = load_d(k0 + 1);
+      dq2 = load_d(k0 + 2);
       load_plane(k0 + 2, Q1);
       load_layer(k0 + 1, Q1k);
+      load_plane(k0 + 3, Q2);
+      load_layer(k0 + 2, Q2k);
       put_plane(k0 - 1, a);
       put_plane(k0, b);
       put_layer(k0 - 1, ka);
@@ -690,17 +700,17 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
     }
     // One plane.  The register roles rotate between calls instead of being
     // copied: the window by three (VM, V0, VP -> V0, VP, VM), the element
-    // layers and the load queue by two.
+    // layers by two and the load queue by three (QA, QB, QC -> QB, QC, QA).
     auto step = [&](int k, R (&VM)[9], R (&V0)[9], R (&VP)[9], R (&KM)[4],
-                    R (&K0)[4], R (&QA)[ZHPT], R (&QAk)[ZEPT], R (&QB)[ZHPT],
-                    R (&QBk)[ZEPT]) {
+                    R (&K0)[4], R (&QA)[ZHPT], R (&QAk)[ZEPT], R (&QC)[ZHPT],
+                    R (&QCk)[ZEPT]) {
       // steps are not interleaved by the scheduler (that would only raise
       // the register count); nothing loaded here is waited for before the
-      // next step (memory counters complete in issue order)
+      // step after next (memory counters complete in issue order)
       __builtin_amdgcn_sched_barrier(0);
-      const R dn = load_d(k + 2);
-      load_plane(k + 3, QB);
-      load_layer(k + 2, QBk);
+      const R dn = load_d(k + 3);
+      load_plane(k + 4, QC);
+      load_layer(k + 3, QCk);
       get_plane(k + 1, VP);
       get_layer(k, K0);
       if (col_active) {
@@ -727,26 +737,29 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
       put_layer(k + 1, QAk);
       __syncthreads();
       dq0 = dq1;
-      dq1 = dn;
+      dq1 = dq2;
+      dq2 = dn;
     };
+    // a step names the slot it drains (QA) and the one it fills (QC); the
+    // middle slot (QB) waits
     int k = k0;
     for (; k + 6 <= k1; k += 6) {
-      step(k, V1, V2, V3, K1, K2, Q1, Q1k, Q2, Q2k);
+      step(k, V1, V2, V3, K1, K2, Q1, Q1k, Q3, Q3k);
       step(k + 1, V2, V3, V1, K2, K1, Q2, Q2k, Q1, Q1k);
-      step(k + 2, V3, V1, V2, K1, K2, Q1, Q1k, Q2, Q2k);
-      step(k + 3, V1, V2, V3, K2, K1, Q2, Q2k, Q1, Q1k);
-      step(k + 4, V2, V3, V1, K1, K2, Q1, Q1k, Q2, Q2k);
-      step(k + 5, V3, V1, V2, K2, K1, Q2, Q2k, Q1, Q1k);
+      step(k + 2, V3, V1, V2, K1, K2, Q3, Q3k, Q2, Q2k);
+      step(k + 3, V1, V2, V3, K2, K1, Q1, Q1k, Q3, Q3k);
+      step(k + 4, V2, V3, V1, K1, K2, Q2, Q2k, Q1, Q1k);
+      step(k + 5, V3, V1, V2, K2, K1, Q3, Q3k, Q2, Q2k);
     }
     if (k < k1) {
-      step(k, V1, V2, V3, K1, K2, Q1, Q1k, Q2, Q2k);
+      step(k, V1, V2, V3, K1, K2, Q1, Q1k, Q3, Q3k);
       if (k + 1 < k1) {
         step(k + 1, V2, V3, V1, K2, K1, Q2, Q2k, Q1, Q1k);
         if (k + 2 < k1) {
-          step(k + 2, V3, V1, V2, K1, K2, Q1, Q1k, Q2, Q2k);
+          step(k + 2, V3, V1, V2, K1, K2, Q3, Q3k, Q2, Q2k);
           if (k + 3 < k1) {
-            step(k + 3, V1, V2, V3, K2, K1, Q2, Q2k, Q1, Q1k);
-            if (k + 4 < k1) step(k + 4, V2, V3, V1, K1, K2, Q1, Q1k, Q2, Q2k);
+            step(k + 3, V1, V2, V3, K2, K1, Q1, Q1k, Q3, Q3k);
+            if (k + 4 < k1) step(k + 4, V2, V3, V1, K1, K2, Q2, Q2k, Q1, Q1k);
           }
         }
       }

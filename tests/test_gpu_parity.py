@@ -84,9 +84,9 @@ def _op_rows(g, Ke, d, kap, v, nodes):
 
 
 # more than 4M nodes: the z-marching kernel, with ragged column tiles in x
-# (301 = 4 x 64 + 45) and y (121 = 30 x 4 + 1); FP64 cuts each column into
-# two z runs (67 node planes and a short last one of 66), FP32 takes whole
-# columns
+# (301 = 4 x 64 + 45) and y (121 = 30 x 4 + 1); the grid has 155 columns,
+# so each is cut into four z runs (34 node planes and a short last one of
+# 31) to make at least 512 work units
 @pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
 def test_op_apply_large_grid_sampled(prec):
     nx, ny, nz = 300, 120, 132
@@ -115,7 +115,7 @@ def test_op_apply_large_grid_sampled(prec):
     # every corner and edge class of the domain and of the tiles, plus random
     xs = sorted({0, 1, 63, 64, 65, 127, 128, 255, 256, 299, 300})
     ys = sorted({0, 1, 3, 4, 5, 59, 60, 116, 119, 120})
-    zs = sorted({0, 1, 8, 9, 17, 18, 65, 66, 67, 68, 130, 131, 132})
+    zs = sorted({0, 1, 8, 9, 17, 18, 33, 34, 35, 67, 68, 101, 102, 131, 132})
     nodes = [(i, j, k) for i in xs for j in ys for k in zs]
     nodes += [tuple(int(t) for t in rng.integers(0, (nx + 1, ny + 1, nz + 1)))
               for _ in range(300)]
