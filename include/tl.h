@@ -232,7 +232,9 @@ tl_status tl_get_time(tl_sim* sim, double* t, int64_t* n_macro);
  * *used receives the byte count (call with host = NULL to query; the count
  * changes as the history grows).  tl_load restores a buffer written by
  * tl_save for a handle created with the same mesh and options; a buffer of
- * another format or grid returns TL_EINVAL. */
+ * another format or grid, a truncated one, or one whose window or solver
+ * history does not fit the handle returns TL_EINVAL and leaves the handle
+ * as it was. */
 tl_status tl_save(tl_sim* sim, void* host, size_t cap, size_t* used);
 tl_status tl_load(tl_sim* sim, const void* host, size_t n);
 

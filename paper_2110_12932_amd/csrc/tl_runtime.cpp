@@ -736,9 +736,9 @@ double fine_free_nodes(const Geo& gf, const Window& w) {
   return (double)cnt;
 }
 
-void set_interface(tl_sim* s) {
-  const Window& w = s->win;
-  s->iqn.clear();   // secant pairs belong to the previous interface
+// The coarse interface nodes of window w (padded indices on the coarse
+// grid gc), in the order of the interface vectors.
+std::vector<int> interface_nodes(const Geo& gc, const Window& w) {
   std::vector<int> idx;
   for (int k = w.K0; k <= w.K0 + w.wz; ++k)
     for (int j = w.J0; j <= w.J0 + w.wy; ++j)
@@ -748,8 +748,14 @@ void set_interface(tl_sim* s) {
                        ((w.faces & kFy0) && j == w.J0) ||
                        ((w.faces & kFy1) && j == w.J0 + w.wy) ||
                        ((w.faces & kFz0) && k == w.K0);
-        if (g) idx.push_back((k + 1) * s->gc.pxy + (j + 1) * s->gc.px + (i + 1));
+        if (g) idx.push_back((k + 1) * gc.pxy + (j + 1) * gc.px + (i + 1));
       }
+  return idx;
+}
+
+void set_interface(tl_sim* s) {
+  s->iqn.clear();   // secant pairs belong to the previous interface
+  const std::vector<int> idx = interface_nodes(s->gc, s->win);
   s->n_gamma = (int)idx.size();
   if (!idx.empty())
     hip_check(hipMemcpy(s->gidx, idx.data(), idx.size() * sizeof(int),
@@ -2017,6 +2023,11 @@ tl_status tl_load(tl_sim* s, const void* host, size_t n) {
   if (h.I0 < 0 || h.J0 < 0 || h.I0 + s->mesh.win_nx > s->mesh.nx ||
       h.J0 + s->mesh.win_ny > s->mesh.ny)
     return fail(TL_EINVAL, "checkpoint window outside the plate");
+  // the secant pairs must have the length of the restored window's
+  // interface (checked before anything of the handle changes)
+  if (h.ncols > 0 &&
+      (size_t)h.n_gamma != interface_nodes(s->gc, make_window(s->mesh, h.I0, h.J0)).size())
+    return fail(TL_EINVAL, "checkpoint interface history does not fit its window");
   const char* p = (const char*)host + sizeof(h);
   try {
     s->win = make_window(s->mesh, h.I0, h.J0);

@@ -221,3 +221,42 @@ def test_checkpoint_roundtrip_bitwise(coupling):
     assert np.array_equal(Ta, Tb) and np.array_equal(Ca, Cb)
     a.close()
     b.close()
+
+
+
+# tl_load rejects a damaged or foreign buffer before it changes anything:
+# the handle then continues exactly like one that was never touched.
+def test_checkpoint_rejects_damaged_or_foreign_data():
+    import struct
+    wl = _with(W.small_cases()["corner"], W.DN)
+    a, b = tl.Sim(wl), tl.Sim(wl)
+    a.step(3)
+    b.step(3)
+    blob = tl.tl_save(a.h)
+    # header: magic[8], version, I0, J0, gc_n, gf_n, n_gamma, ncols (int32)
+    n_gamma, ncols = struct.unpack_from("<ii", blob, 28)
+    assert ncols > 0 and n_gamma > 0    # the DN iteration's secant pairs
+    wrong_len = bytearray(blob)
+    struct.pack_into("<i", wrong_len, 28, n_gamma - 1)
+    bad_window = bytearray(blob)
+    struct.pack_into("<i", bad_window, 12, 10 ** 6)
+    damaged = [blob[:40], b"X" + blob[1:], blob[:-8], bytes(wrong_len), bytes(bad_window)]
+    other = W.small_cases()["r3m2"]
+    c = tl.Sim(_with(other, W.DN))
+    c.step(1)
+    damaged.append(tl.tl_save(c.h))     # another grid
+    c.close()
+    for data in damaged:
+        with pytest.raises(tl.TLError) as e:
+            tl.tl_load(b.h, data)
+        assert e.value.status == tl.TL_EINVAL
+    a.step(2)
+    b.step(2)
+    for level in (0, 1):
+        assert np.array_equal(a.temperature(level)[0], b.temperature(level)[0])
+    sa, sb = a.stats(), b.stats()
+    for key in ("newton_fine", "newton_coarse", "cg_fine", "cg_coarse", "dn_iters",
+                "window_moves", "fine_dof_steps"):
+        assert sa[key] == sb[key], key
+    a.close()
+    b.close()
