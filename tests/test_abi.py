@@ -98,3 +98,26 @@ def test_create_rejects_small_workspace():
     with pytest.raises(tl.TLError) as e:
         tl.tl_create(wl.mesh, wl.material, wl.scan, wl.options, _FakeWorkspace(1000), stream=0)
     assert e.value.status == tl.TL_ENOMEM
+
+
+class _FakePool(_FakeWorkspace):
+    def __init__(self, n, ptr=256):
+        super().__init__(n)
+        self.ptr = ptr
+
+    def data_ptr(self):
+        return self.ptr     # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("pool, slots, status", [
+    (_FakePool(1 << 30, ptr=0), 8, tl.TL_EINVAL),      # null pool
+    (_FakePool(1 << 30, ptr=264), 8, tl.TL_EINVAL),    # not 256-byte aligned
+    (_FakePool(1 << 30), 0, tl.TL_EINVAL),             # no slots
+    (_FakePool(1 << 30), 1025, tl.TL_EINVAL),          # too many slots
+    (_FakePool(4096), 64, tl.TL_ENOMEM),               # smaller than its tables
+])
+def test_server_create_rejects_invalid_input(pool, slots, status):
+    with pytest.raises(tl.TLError) as e:
+        tl.tl_server_create(pool, 1 << 30, slots, stream=0)
+    assert e.value.status == status
+    assert tl.tl_last_error() != ""
