@@ -173,3 +173,36 @@ def test_failed_request_does_not_disturb_others():
     s.close()
     assert np.array_equal(Cs, Cp) and np.array_equal(Fs, Fp)
     sv.close()
+
+
+def test_request_errors():
+    """Invalid requests are refused at submit (EINVAL), one larger than the
+    budget with EBUSY; an unknown id gives EINVAL and an unfinished request
+    EBUSY; none of them disturbs a valid request."""
+    R = _requests()
+    sv = tl.Server(_pool_bytes([R["A"]]), max_slots=2)
+    bad_mesh = replace(R["A"], mesh=replace(R["A"].mesh, win_nx=R["A"].mesh.nx + 1))
+    for wl, n in ((bad_mesh, None), (R["A"], 0)):
+        with pytest.raises(tl.TLError) as e:
+            sv.submit(wl, n)
+        assert e.value.status == tl.TL_EINVAL
+    small = tl.Server(tl.tl_workspace_bytes(R["A"].mesh, R["A"].options) // 2
+                      + tl.tl_server_overhead_bytes(2) + 4096, max_slots=2)
+    with pytest.raises(tl.TLError) as e:
+        small.submit(R["A"])
+    assert e.value.status == tl.TL_EBUSY
+    small.close()
+    ia = sv.submit(R["A"])
+    with pytest.raises(tl.TLError) as e:
+        sv.result(ia)           # nothing has run yet
+    assert e.value.status == tl.TL_EBUSY
+    with pytest.raises(tl.TLError) as e:
+        sv.result(ia + 1000)
+    assert e.value.status == tl.TL_EINVAL
+    _drain(sv)
+    Cs, Fs, _, _, _ = sv.result(ia)
+    s = tl.Sim(R["A"])
+    s.step(R["A"].n_macro)
+    assert np.array_equal(Cs, s.temperature(0)[0]) and np.array_equal(Fs, s.temperature(1)[0])
+    s.close()
+    sv.close()
