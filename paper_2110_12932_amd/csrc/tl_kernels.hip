@@ -529,9 +529,10 @@ op_apply_tiled_kernel(Geo g, int ntx, int nty, int ntiles,
 // registers as a sliding window, so a step reads from LDS only the nine
 // values of the next node plane and the four of the next element layer;
 // LDS holds two node planes and two element layers (with x-y halo).  Global
-// loads run two planes ahead of the stencil, so each input value is read
-// from memory once (its x-y halo copies hit the L2 of neighbouring columns
-// on the same XCD) and one barrier per plane suffices.
+// loads run three planes ahead of the stencil (two steps' loads in flight),
+// so each input value is read from memory once (its x-y halo copies hit the
+// L2 of neighbouring columns on the same XCD) and one barrier per plane
+// suffices.
 // ---------------------------------------------------------------------------
 constexpr int ZX = 64, ZY = kBlock / ZX;
 constexpr int ZHX = ZX + 2, ZHY = ZY + 2, ZHN = ZHX * ZHY;   // node plane
