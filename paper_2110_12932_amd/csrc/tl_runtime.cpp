@@ -1474,9 +1474,14 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
   if (me->win_nx < 1 || me->win_ny < 1 || me->win_nz < 1 ||
       me->win_nx > me->nx || me->win_ny > me->ny || me->win_nz > me->nz)
     return fail(TL_EINVAL, "window must fit inside the plate");
-  const double nf = (double)((me->refine * me->win_nx + 3 + 31) / 32 * 32) *
-                    (me->refine * me->win_ny + 3) * (me->refine * me->win_nz + 3);
-  const double nc = (double)((me->nx + 3 + 31) / 32 * 32) * (me->ny + 3) * (me->nz + 3);
+  // padded node counts in floating point (no integer overflow for any
+  // input); every index of a grid below the limit fits an int
+  auto padded = [](double nx, double ny, double nz) {
+    return (std::floor((nx + 34.0) / 32.0) * 32.0) * (ny + 3.0) * (nz + 3.0);
+  };
+  const double r = me->refine;
+  const double nf = padded(r * me->win_nx, r * me->win_ny, r * me->win_nz);
+  const double nc = padded(me->nx, me->ny, me->nz);
   if (nf > 2.0e8 || nc > 2.0e8) return fail(TL_EINVAL, "grid too large");
   if (!finite_all({ma->rho, ma->T_lo, ma->T_hi, ma->c_lo, ma->c_hi, ma->k_lo,
                    ma->k_hi, ma->latent, ma->T_sol, ma->T_liq, ma->sharpness,
@@ -2098,7 +2103,8 @@ static tl_status check_grid(const tl_grid* g) {
   if (!(g->hx > 0) || !(g->hy > 0) || !(g->hz > 0) || !std::isfinite(g->hx) ||
       !std::isfinite(g->hy) || !std::isfinite(g->hz))
     return fail(TL_EINVAL, "spacings must be positive and finite");
-  if ((double)((g->nx + 3 + 31) / 32 * 32) * (g->ny + 3) * (g->nz + 3) > 2.0e9)
+  // in floating point: no integer overflow for any input
+  if (std::floor((g->nx + 34.0) / 32.0) * 32.0 * (g->ny + 3.0) * (g->nz + 3.0) > 2.0e9)
     return fail(TL_EINVAL, "grid too large");
   return TL_OK;
 }

@@ -76,6 +76,9 @@ class _FakeWorkspace:
     (lambda wl: replace(wl, options=replace(wl.options, face_quad=7)), "face_quad"),
     (lambda wl: replace(wl, options=replace(wl.options, dt_coarse=-1.0)), "dt_coarse"),
     (lambda wl: replace(wl, options=replace(wl.options, coupling=5)), "coupling"),
+    # sizes whose padded node counts would overflow a 32-bit int
+    (lambda wl: replace(wl, mesh=replace(wl.mesh, nx=2**31 - 1, ny=2**31 - 1)), "too large"),
+    (lambda wl: replace(wl, mesh=replace(wl.mesh, refine=2**30)), "too large"),
     (lambda wl: replace(wl, options=replace(wl.options, source=2)), "source"),
     # the volume model needs a depth and tracks along x or y
     (lambda wl: replace(wl, options=replace(wl.options, source=W.VOLUME)), "volume"),
@@ -121,3 +124,9 @@ def test_server_create_rejects_invalid_input(pool, slots, status):
         tl.tl_server_create(pool, 1 << 30, slots, stream=0)
     assert e.value.status == status
     assert tl.tl_last_error() != ""
+
+
+def test_op_grid_too_large_is_rejected():
+    for dims in ((2**31 - 1, 1, 1), (100000, 100000, 10)):
+        grid = tl.to_grid(*dims, 1e-6, 1e-6, 1e-6)
+        assert tl.tl_op_padded_size(grid) == 0
