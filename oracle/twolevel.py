@@ -235,6 +235,9 @@ class TwoLevel:
         self.stats = dict(newton_fine=0, newton_coarse=0, dn_iters=0, moves=0,
                           fine_solves=0, coarse_solves=0)
         self.history = []
+        # (macro step, micro step j, fine field) of every fine step when a
+        # list is set here: micro steps j = 1..m-1 and the corrected step m
+        self.record = None
 
     # -- energy ledger ------------------------------------------------------
     def energy(self):
@@ -347,6 +350,8 @@ class TwoLevel:
             g = (1.0 - j / m) * PTn + (j / m) * PTp
             Ff = self.fine_load(spots[j - 1])
             T_prev, R = self.fine_step(T_prev, dt, Ff, g)
+            if self.record is not None:
+                self.record.append((n, j, T_prev.copy()))
             rho_sum[w.gamma_f] += R[w.gamma_f]
             bottom -= dt * R[w.bottom_f].sum()
             absorbed += dt * Ff.sum()
@@ -536,6 +541,8 @@ class TwoLevel:
         surface += Dt * self.surf_coarse(w.area_out).loss(Tc_new)
         self.Tc = Tc_new
         self.Tf = Tf_m
+        if self.record is not None:
+            self.record.append((self.n, m, Tf_m.copy()))
         self.n += 1
         E_end = self.energy()
         self.ledger["stored"] = E_end

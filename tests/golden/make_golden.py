@@ -1,12 +1,19 @@
 """Write oracle reference fields for the full-size parity tests.
 
 Runs the FP64 CPU oracle (converged to 1e-10 K in Newton and in the
-two-level iteration) on the first macro steps of a workload and stores the
-coarse and fine temperatures, the window origin and the energy ledger in
-tests/golden/<name>_n<steps>.npz.  Nothing here touches the GPU library.
+two-level iteration) on the first macro steps of a workload and stores, at
+each requested step count, the coarse and fine temperatures, the window
+origin and the energy ledger in tests/golden/<name>_n<steps>.npz.  Nothing
+here touches the GPU library.
 
-Usage: python tests/golden/make_golden.py single_track_2mm 3
+Usage:
+  python tests/golden/make_golden.py single_track_2mm 20
+  python tests/golden/make_golden.py raster_10mm 20 --snap 2,20
+  python tests/golden/make_golden.py served_tracks 4 --requests 0,1,2
+    (requests q of the served stream, each alone, after 4 macro steps:
+     tests/golden/served_req<q>_n4.npz)
 """
+import argparse
 import os
 import sys
 import time
@@ -19,25 +26,51 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 
-def main(name, steps):
-    wl = W.by_name(name)
-    t0 = time.time()
-    sim = oracle.TwoLevel(wl, newton_tol=1e-10, dn_tol=1e-10)
-    for n in range(steps):
-        sim.step()
-        print(f"{name}: macro step {n + 1}/{steps} done after {time.time() - t0:.0f} s",
-              flush=True)
+
+def save(sim, name, steps):
     c, f = sim.coarse, sim.win.fine
     led = sim.ledger
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_n{steps}.npz")
+    out = os.path.join(HERE, f"{name}_n{steps}.npz")
     np.savez_compressed(out, Tc=sim.Tc.reshape(c.shape), Tf=sim.Tf.reshape(f.shape),
                         origin=np.array(sim.fine_origin()), steps=steps,
                         stored=led["stored"], stored0=led["stored0"],
                         absorbed=led["absorbed"], bottom=led["bottom"], remap=led["remap"],
-                        dn_iters=sim.stats["dn_iters"])
-    print("wrote", out, os.path.getsize(out), "bytes")
+                        surface=led["surface"], dn_iters=sim.stats["dn_iters"],
+                        moves=sim.stats["moves"])
+    print("wrote", out, os.path.getsize(out), "bytes", flush=True)
+
+
+def run(wl, name, steps, snaps):
+    t0 = time.time()
+    sim = oracle.TwoLevel(wl, newton_tol=1e-10, dn_tol=1e-10)
+    for n in range(1, steps + 1):
+        sim.step()
+        print(f"{name}: macro step {n}/{steps} done after {time.time() - t0:.0f} s "
+              f"(moves {sim.stats['moves']})", flush=True)
+        if n in snaps:
+            save(sim, name, n)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("name")
+    ap.add_argument("steps", type=int)
+    ap.add_argument("--snap", default=None,
+                    help="comma-separated step counts to store (default: the last)")
+    ap.add_argument("--requests", default="0",
+                    help="served_tracks: comma-separated request numbers")
+    a = ap.parse_args()
+    snaps = {a.steps} if a.snap is None else {int(s) for s in a.snap.split(",")}
+    if a.name == "served_tracks":
+        stream = W.served_tracks(64, seed=0)
+        for q in (int(s) for s in a.requests.split(",")):
+            wl = stream[q][1]
+            run(wl, wl.name, min(a.steps, wl.n_macro), snaps)
+        return
+    run(W.by_name(a.name), a.name, a.steps, snaps)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]))
+    main()

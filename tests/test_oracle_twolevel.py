@@ -7,7 +7,10 @@
   * the window rule on hand-computed positions;
   * the multirate error grows with the number of micro steps per macro step
     (Section 5.1: error falls as the global step approaches the local one);
-  * the two-level fixed point does not depend on the relaxation."""
+  * the two-level fixed point does not depend on the relaxation;
+  * at refinement 2, against the brute-force single-level run on the whole
+    plate refined twice: the difference grows with the macro step at fixed
+    micro step and shows Section 5.1's sawtooth within each macro step."""
 from dataclasses import replace
 
 import numpy as np
@@ -138,3 +141,48 @@ def test_fixed_point_independent_of_relaxation():
     b = oracle.run(replace(wl, options=replace(wl.options, dn_theta=0.75)), 3)
     assert np.abs(a.Tc - b.Tc).max() < 1e-7
     assert np.abs(a.Tf - b.Tf).max() < 1e-7
+
+
+def test_two_level_against_full_fine_single_level():
+    """Refinement 2 against brute force: the single-level run on the whole
+    plate refined twice, with the micro step dt.  Section 5.1's temporal
+    study fixes the expected shape: at fixed dt the two-level field moves
+    towards the reference as the macro step Dt = m dt shrinks to dt, and
+    within each macro step the difference grows over the micro steps (their
+    Dirichlet data blend the coarse field with an uncorrected predictor) and
+    falls back at the corrected step.  The window (10 x 6 x 2 coarse cells)
+    holds the beam for all 16 micro steps, so it never moves."""
+    base = single_track_1mm()
+    r, dt, n_fine = 2, 12.5 * UM, 16
+    mesh = replace(base.mesh, win_nx=10, win_ny=6, win_nz=2, refine=r)
+    c = TW.coarse_grid(mesh)
+    full = G.Grid(r * mesh.nx, r * mesh.ny, r * mesh.nz, c.hx / r, c.hy / r, c.hz / r)
+    ref = TW.single_level_run(full, base.material, base.scan, dt, n_fine, tol=1e-10)
+    err, multirate = {}, {}
+    for m in (1, 2, 4):
+        wl = replace(base, mesh=mesh, options=replace(base.options, m_time=m, dt_coarse=dt * m))
+        sim = TW.TwoLevel(wl, newton_tol=1e-10, dn_tol=1e-10)
+        sim.record = []
+        sim.run(n_fine // m)
+        assert sim.stats["moves"] == 0
+        fi, fj, fk = sim.win.fine.node_ijk()
+        oi, oj, ok = sim.fine_origin()
+        on_full = full.node(fi + oi, fj + oj, fk + ok)
+        assert [(n, j) for n, j, _ in sim.record] == [(q // m, q % m + 1) for q in range(n_fine)]
+        fields = [T for _, _, T in sim.record]
+        err[m] = [np.abs(T - ref[q][on_full]).max() for q, T in enumerate(fields)]
+        multirate[m] = fields
+    # the two-level field differs from the full-fine one (the plate outside
+    # the window is coarse) ...
+    assert err[1][-1] > 1.0
+    # ... and at every common macro step the difference grows with m
+    for q in range(3, n_fine, 4):
+        assert err[1][q] < err[2][q] < err[4][q], (q, err[1][q], err[2][q], err[4][q])
+    # sawtooth at m = 4: rising over micro steps 1..3, falling at the
+    # correction, against the full-fine field and against the m = 1 run
+    # (the same spatial discretisation: the multirate part alone)
+    for n in range(n_fine // 4):
+        e = err[4][4 * n:4 * n + 4]
+        d = [np.abs(multirate[4][4 * n + j] - multirate[1][4 * n + j]).max() for j in range(4)]
+        assert e[0] < e[1] < e[2] and e[3] < e[2], (n, e)
+        assert d[0] < d[1] < d[2] and d[3] < d[2] / 5, (n, d)
