@@ -210,16 +210,29 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
  * step. */
 tl_status tl_step(tl_sim* sim, int n_macro);
 
-/* Copy the coarse (level 0) or fine (level 1) temperature to host_out, node
- * (i,j,k) at i + nx*(j + ny*k) with (nx,ny,nz) = dims_out.  cap is the
- * capacity of host_out in doubles (TL_ENOMEM if too small).  fine_origin_out
- * (may be NULL) receives the fine-grid index of the window's first node on
- * the plate-wide fine lattice (refine * coarse cell origin). */
+/* The two temperature fields of the method (paper Section 3): the global
+ * field T+ on the coarse plate (level 0) and the local field T- on the fine
+ * window (level 1), at the end of the last completed macro step.  Copies the
+ * field to host_out (host memory owned by the caller), node (i,j,k) at
+ * i + nx*(j + ny*k) with (nx,ny,nz) = dims_out.  With the Dirichlet-Neumann
+ * or composite correction, the coarse nodes strictly inside the window hold
+ * the injected fine values.  cap is the capacity of host_out in doubles
+ * (TL_ENOMEM if too small, nothing copied); TL_EINVAL for a null handle or
+ * buffer or a level other than 0 or 1.  fine_origin_out (may be NULL)
+ * receives the fine-grid index of the window's first node on the plate-wide
+ * fine lattice (refine * coarse cell origin). */
 tl_status tl_get_temperature(tl_sim* sim, int level, double* host_out,
                              size_t cap, int dims_out[3],
                              int fine_origin_out[3]);
 
+/* Energy balance of the thermal model (paper Section 2: enthalpy change =
+ * absorbed laser heat - heat through the plate bottom - top-surface loss),
+ * accumulated over the completed macro steps; see tl_ledger for the terms
+ * and the identity they satisfy.  TL_EINVAL for null arguments. */
 tl_status tl_get_ledger(tl_sim* sim, tl_ledger* out);
+
+/* Counters and timings (tl_stats) over the handle's life.  TL_EINVAL for
+ * null arguments. */
 tl_status tl_get_stats(tl_sim* sim, tl_stats* out);
 
 /* Simulation time of the committed state and the number of macro steps. */
@@ -280,8 +293,12 @@ tl_status tl_server_create(void* dev_pool, size_t pool_bytes,
                            size_t hbm_budget, int max_slots, void* hip_stream,
                            tl_server** out);
 
-/* Queue a request of n_macro macro steps; inputs are copied.  TL_EINVAL as
- * for tl_create; TL_EBUSY if the request alone exceeds the budget. */
+/* Queue a request of n_macro macro steps of the paper's Algorithm 1 (the
+ * request ends at t_start + n_macro * dt_coarse); inputs are copied.  The
+ * horizon is a step count rather than an end time so that the number of
+ * macro steps, and with it the request's result, never depends on how an
+ * end time rounds against dt_coarse.  TL_EINVAL as for tl_create or for
+ * n_macro < 1; TL_EBUSY if the request alone exceeds the budget. */
 tl_status tl_server_submit(tl_server* sv, const tl_mesh* mesh,
                            const tl_material* material,
                            const tl_scan_path* scan, const tl_options* opts,

@@ -109,7 +109,8 @@ struct NewtonState {
   int n_newton;       // directions taken
   int n_cg;           // CG iterations summed over the solve
   int n_halvings;     // line-search halvings summed over the solve
-  int pad;
+  int dir_cut;        // the direction being line-searched comes from a CG
+                      // that its budget stopped before it reached cg_rtol
 };
 // CG scalars of one round, double-buffered by round parity: round r's CG
 // kernels use cg[r & 1] and the next round's CG-start reads its outcome.

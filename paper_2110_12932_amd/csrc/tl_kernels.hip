@@ -1080,7 +1080,9 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 //    down at once.
 //  * The trial is accepted on the first evaluation, on sufficient decrease
 //    |R| <= (1 - 1e-4 alpha) rn0, when its step is within tol, or on the last
-//    halving; Newton has converged when an accepted step is within tol.
+//    halving; Newton has converged when an accepted step is within tol
+//    (and, when its direction's CG was cut by the budget, the accepted step
+//    before it was within tol too).
 //  * Rejected: the step is halved for the next round.  Accepted and not
 //    converged: the trial becomes the accepted temperature and this round's
 //    CG computes the next direction; w0 = J u0 (u0 = Dinv r0) and the
@@ -1118,6 +1120,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       nx.n_newton += 1;
       nx.n_cg += cgp.iters;
       nx.cg_need = max(nx.cg_need, cgp.done ? cgp.iters : cgp.iters + 2);
+      nx.dir_cut = cgp.done ? 0 : 1;
     }
   }
   // inputs of w0 = J u0 for a tile, loaded into registers in one batch
@@ -1209,7 +1212,11 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const bool accepted =
         st.first || !finite || rn <= (1.0 - 1e-4 * st.alpha) * st.rn0 ||
         dmax <= it.tol || st.h == kLineSearchMax - 1;
-    const bool converged = !st.first && accepted && finite && dmax <= it.tol;
+    // A step from a CG cut short by its budget can be shorter than the
+    // Newton correction; it ends the iteration only when the accepted step
+    // before it was within tol as well.
+    const bool converged = !st.first && accepted && finite && dmax <= it.tol &&
+                           (!st.dir_cut || st.dmax_last <= it.tol);
     if (!finite) {
       nx.status = kFailNonFinite;
     } else if (!accepted) {

@@ -8,8 +8,10 @@
 // backtracking line search whose linear systems are solved by
 // Jacobi-preconditioned CG in FP64, or in FP32 for the fine level of the
 // mixed-precision path.  All arithmetic on fields runs in the HIP kernels of
-// tl_kernels.hip; the host reads back a few scalars per Newton iteration, per
-// CG chunk and per two-level iteration to steer the loops.
+// tl_kernels.hip.  Newton, its line search and the CG control run on the
+// device (a state machine in the CG-start kernel); the host queues several
+// Newton rounds at a time and reads the solvers' states back once per group
+// of rounds, and once per iteration of the Dirichlet-Neumann correction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1864,9 +1866,19 @@ tl_status tl_step(tl_sim* s, int n_macro) {
   for (int q = 0; q < n_macro; ++q) {
     const Window w_saved = s->win;
     const Geo gf_saved = s->gf;
-    double* state_saved = s->fstate;
-    double* alt_saved = s->falt;
+    // every field pointer a macro step permutes (window moves, solves,
+    // micro-step rotation, commit), so that a failure at any point restores
+    // the committed buffers and a set of distinct work buffers
+    double** const perm[] = {&s->Tn,     &s->Tpred, &s->ccur,  &s->ctrial,
+                             &s->fstate, &s->fprev, &s->fcur,  &s->ftrial,
+                             &s->falt,   &s->fpp};
+    constexpr int kPerm = (int)(sizeof(perm) / sizeof(perm[0]));
+    double* perm_saved[kPerm];
+    for (int q2 = 0; q2 < kPerm; ++q2) perm_saved[q2] = *perm[q2];
     const tl_stats stats_saved = s->stats;
+    // solver history later steps depend on: CG budgets, secant pairs
+    const int cg_saved[3] = {s->last_cg_f, s->last_cg_c, s->last_cg_x};
+    const Interface iqn_saved = s->iqn;
     try {
       std::vector<StepState> steps(1);
       steps[0].s = s;
@@ -1885,11 +1897,14 @@ tl_status tl_step(tl_sim* s, int n_macro) {
       (void)hipStreamSynchronize(s->stream);
       s->win = w_saved;
       s->gf = gf_saved;
-      s->fstate = state_saved;
-      s->falt = alt_saved;
+      for (int q2 = 0; q2 < kPerm; ++q2) *perm[q2] = perm_saved[q2];
       s->stats = stats_saved;
+      s->last_cg_f = cg_saved[0];
+      s->last_cg_c = cg_saved[1];
+      s->last_cg_x = cg_saved[2];
       try {
         set_interface(s);
+        s->iqn = iqn_saved;
         k_fill(s->L, s->ext, 0.0, s->gc.npad);
         write_ledger(s);
       } catch (const DevErr& e) {

@@ -260,3 +260,12 @@ def test_checkpoint_rejects_damaged_or_foreign_data():
         assert sa[key] == sb[key], key
     a.close()
     b.close()
+
+# CG budget of 2 iterations per direction (below what cg_rtol needs): every
+# direction is cut, so Newton may stop only after two accepted steps within
+# tol; the result still meets the FP64 bar
+@pytest.mark.parametrize("coupling", COUPLINGS)
+def test_small_cg_budget(coupling):
+    wl = W.single_track_1mm()
+    wl = replace(wl, options=replace(wl.options, cg_max=2))
+    _check_vs_oracle(wl, 8, 1e-9, coupling)

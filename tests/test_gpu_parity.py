@@ -126,6 +126,44 @@ def test_op_apply_large_grid_sampled(prec):
     assert err.max() < tol, err.max()
 
 
+def test_rollback_after_window_move_restores_every_buffer():
+    """A step that fails after the window has moved and after its fine
+    micro steps rolled the field buffers leaves exactly the committed state:
+    saved again it equals the checkpoint it started from, and a healthy
+    handle restored from it continues bitwise as the uninterrupted run."""
+    wl = W.single_track_1mm()
+    a = tl.Sim(wl)
+    a.step(6)
+    ck = tl.tl_save(a.h)
+    a.step(1)
+    moves_a = a.stats()["window_moves"]
+    Tc7, _ = a.temperature(0)
+    Tf7, o7 = a.temperature(1)
+    a.close()
+    b = tl.Sim(replace(wl, options=replace(wl.options, newton_max=1)))
+    tl.tl_load(b.h, ck)
+    Tc6, _ = b.temperature(0)
+    Tf6, o6 = b.temperature(1)
+    with pytest.raises(tl.TLError) as e:
+        b.step(1)
+    assert e.value.status == tl.TL_ENOCONV
+    assert tl.tl_get_time(b.h)[1] == 6
+    Tcb, _ = b.temperature(0)
+    Tfb, ob = b.temperature(1)
+    assert ob == o6 and np.array_equal(Tcb, Tc6) and np.array_equal(Tfb, Tf6)
+    ck_b = tl.tl_save(b.h)
+    b.close()
+    c = tl.Sim(wl)
+    tl.tl_load(c.h, ck_b)
+    c.step(1)
+    Tcc, _ = c.temperature(0)
+    Tfc, oc = c.temperature(1)
+    c.close()
+    say("  window moves", moves_a, "origin", o6, "->", o7)
+    assert o7 != o6   # the failed step was one with a window move
+    assert oc == o7 and np.array_equal(Tcc, Tc7) and np.array_equal(Tfc, Tf7)
+
+
 def test_nonconvergence_rolls_back():
     wl = W.single_track_1mm()
     sim = tl.Sim(replace(wl, options=replace(wl.options, newton_max=1)))
