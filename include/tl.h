@@ -204,6 +204,30 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
                     void* dev_workspace, size_t ws_bytes, void* hip_stream,
                     tl_sim** out);
 
+/* Size of the static device workspace of tl_create_static: 32 MiB, enough
+ * for the single-track problems of up to about 90k fine nodes in FP64. */
+#define TL_STATIC_WORKSPACE_BYTES (32u * 1024u * 1024u)
+
+/* tl_create for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same simulation, the same kernels and bitwise the same results, with the
+ * workspace taken from a static device array of TL_STATIC_WORKSPACE_BYTES
+ * that the library holds on every device it runs on until the process ends.
+ * Calls no HIP allocator (device or pinned host memory); its host-side
+ * tables are plain heap memory.  The array is the current device's;
+ * hip_stream (NULL = default stream) must belong to that device (else
+ * TL_EINVAL).  Only one handle per device may hold the array at a time: a
+ * second tl_create_static on that device before tl_destroy of the first
+ * returns TL_EBUSY and leaves the first untouched.  The array keeps the last
+ * handle's contents; creation zero-fills it before use.  Problems whose
+ * tl_workspace_bytes exceed TL_STATIC_WORKSPACE_BYTES return TL_ENOMEM (use
+ * tl_create).  Other errors as for tl_create.  Work queued on the handle and
+ * other work on the same array must not overlap: tl_destroy waits for the
+ * handle's stream before it gives the array back. */
+tl_status tl_create_static(const tl_mesh* mesh, const tl_material* material,
+                           const tl_scan_path* scan, const tl_options* opts,
+                           void* hip_stream, tl_sim** out);
+
 /* Advance n_macro macro steps (Algorithm 1: window update, coarse predictor,
  * m-1 fine micro steps with time-blended Dirichlet data, two-level
  * correction).  On TL_ENOCONV the state is that of the last completed macro

@@ -19,7 +19,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -651,10 +653,13 @@ struct tl_sim {
   int* gidx;            // padded indices of the coarse interface nodes
   double* gbuf;         // interface gather/scatter staging
   int n_gamma;
-  // host side
-  LevelScalars* h_sc;   // pinned
-  LedgerDev* h_led;     // pinned
-  double* h_gbuf;       // pinned, 2 * gamma_cap doubles
+  // host side: pinned (hipHostMalloc), or plain heap memory for a handle
+  // of tl_create_static, which calls no HIP allocator
+  LevelScalars* h_sc;
+  LedgerDev* h_led;
+  double* h_gbuf;       // 2 * gamma_cap doubles
+  bool pinned_host = true;
+  int static_dev = -1;  // device whose static workspace the handle holds
   tl_ledger ledger;     // committed ledger
   tl_stats stats;
   long n_macro;
@@ -1704,7 +1709,8 @@ static tl_status init_state(tl_sim* s) {
 static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
                             const tl_scan_path* scan, const tl_options* opts,
                             void* dev_workspace, size_t ws_bytes,
-                            void* hip_stream, tl_sim** out);
+                            void* hip_stream, bool pinned_host, int static_dev,
+                            tl_sim** out);
 
 tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
                     const tl_scan_path* scan, const tl_options* opts,
@@ -1713,13 +1719,14 @@ tl_status tl_create(const tl_mesh* mesh, const tl_material* material,
   if (!out) return fail(TL_EINVAL, "out is null");
   *out = nullptr;
   return create_sim(mesh, material, scan, opts, dev_workspace, ws_bytes,
-                    hip_stream, out);
+                    hip_stream, true, -1, out);
 }
 
 static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
                             const tl_scan_path* scan, const tl_options* opts,
                             void* dev_workspace, size_t ws_bytes,
-                            void* hip_stream, tl_sim** out) {
+                            void* hip_stream, bool pinned_host, int static_dev,
+                            tl_sim** out) {
   tl_status st = validate(mesh, material, scan, opts);
   if (st != TL_OK) return st;
   Layout lay = make_layout(*mesh, *opts);
@@ -1801,19 +1808,25 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->tpart2 = (double*)(s->ws + lay.off_tpart2);
   s->gidx = (int*)(s->ws + lay.off_gidx);
   s->gbuf = (double*)(s->ws + lay.off_gbuf);
-  if (hipHostMalloc((void**)&s->h_sc, 2 * sizeof(LevelScalars), hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc((void**)&s->batch.h_items, 2 * sizeof(SolveItem),
-                    hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc((void**)&s->batch.h_micro, 2 * sizeof(MicroItem),
-                    hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_led, sizeof(LedgerDev), hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc((void**)&s->h_gbuf, 2 * sizeof(double) * lay.gamma_cap,
-                    hipHostMallocDefault) != hipSuccess) {
-    delete s;
-    return fail(TL_EDEVICE, "hipHostMalloc failed");
+  s->pinned_host = pinned_host;
+  s->static_dev = static_dev;
+  s->h_sc = nullptr;
+  s->h_led = nullptr;
+  s->h_gbuf = nullptr;
+  auto halloc = [&](void** p, size_t n) {
+    if (pinned_host) return hipHostMalloc(p, n, hipHostMallocDefault) == hipSuccess;
+    *p = std::calloc(1, n);
+    return *p != nullptr;
+  };
+  if (!halloc((void**)&s->h_sc, 2 * sizeof(LevelScalars)) ||
+      !halloc((void**)&s->batch.h_items, 2 * sizeof(SolveItem)) ||
+      !halloc((void**)&s->batch.h_micro, 2 * sizeof(MicroItem)) ||
+      !halloc((void**)&s->h_led, sizeof(LedgerDev)) ||
+      !halloc((void**)&s->h_gbuf, 2 * sizeof(double) * lay.gamma_cap)) {
+    s->static_dev = -1;   // the caller keeps its claim on the device's array
+    tl_destroy(s);
+    return fail(TL_EDEVICE, pinned_host ? "hipHostMalloc failed"
+                                        : "host memory allocation failed");
   }
   s->batch.d_items = (SolveItem*)(s->ws + lay.off_items);
   s->batch.d_micro = (MicroItem*)(s->ws + lay.off_micro);
@@ -1851,11 +1864,85 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
     st = fail(TL_EDEVICE, e.msg);
   }
   if (st != TL_OK) {
+    s->static_dev = -1;   // the caller keeps its claim on the device's array
     tl_destroy(s);
     return st;
   }
   *out = s;
   return TL_OK;
+}
+
+// ---- allocation-free creation (tl_create_static) ---------------------------
+// The workspace of a handle made by tl_create_static is this device array:
+// every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory; the
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and only that address is ever passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[TL_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices];   // device address of `scratch`
+bool g_static_held[kMaxStaticDevices];   // a live handle holds the array
+
+void release_static(int dev) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (dev >= 0 && dev < kMaxStaticDevices) g_static_held[dev] = false;
+}
+}  // namespace
+
+tl_status tl_create_static(const tl_mesh* mesh, const tl_material* material,
+                           const tl_scan_path* scan, const tl_options* opts,
+                           void* hip_stream, tl_sim** out) {
+  if (!out) return fail(TL_EINVAL, "out is null");
+  *out = nullptr;
+  tl_status st = validate(mesh, material, scan, opts);
+  if (st != TL_OK) return st;
+  const size_t need = make_layout(*mesh, *opts).total;
+  if (need > (size_t)TL_STATIC_WORKSPACE_BYTES)
+    return fail(TL_ENOMEM, "tl_create_static: the problem needs " +
+                               std::to_string(need) +
+                               " bytes of workspace, more than the static "
+                               "workspace's " +
+                               std::to_string((size_t)TL_STATIC_WORKSPACE_BYTES) +
+                               "; use tl_create with a caller-owned workspace");
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (hip_stream != nullptr) {
+    int sdev = -1;
+    HIP_OK(hipStreamGetDevice((hipStream_t)hip_stream, &sdev));
+    if (sdev != dev)
+      return fail(TL_EINVAL,
+                  "tl_create_static: the stream belongs to another device "
+                  "than the current one");
+  }
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return fail(TL_EDEVICE, "tl_create_static: device index out of range");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_ptr[dev] == nullptr) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || p == nullptr)
+        return fail(TL_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e));
+      g_static_ptr[dev] = p;
+    }
+    if (g_static_held[dev])
+      return fail(TL_EBUSY,
+                  "tl_create_static: a live handle already holds this "
+                  "device's static workspace (destroy it first)");
+    g_static_held[dev] = true;
+    ws = g_static_ptr[dev];
+  }
+  // create_sim zero-fills the whole workspace before use, so nothing of the
+  // previous handle's contents survives
+  st = create_sim(mesh, material, scan, opts, ws,
+                  (size_t)TL_STATIC_WORKSPACE_BYTES, hip_stream, false, dev, out);
+  if (st != TL_OK) release_static(dev);
+  return st;
 }
 
 tl_status tl_step(tl_sim* s, int n_macro) {
@@ -2099,11 +2186,18 @@ void tl_destroy(tl_sim* s) {
   else (void)hipDeviceSynchronize();
   if (s->prof.ev[0])
     for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(s->prof.ev[q]);
-  if (s->batch.h_items) (void)hipHostFree(s->batch.h_items);
-  if (s->batch.h_micro) (void)hipHostFree(s->batch.h_micro);
-  if (s->h_sc) (void)hipHostFree(s->h_sc);
-  if (s->h_led) (void)hipHostFree(s->h_led);
-  if (s->h_gbuf) (void)hipHostFree(s->h_gbuf);
+  auto hfree = [&](void* p) {
+    if (!p) return;
+    if (s->pinned_host) (void)hipHostFree(p);
+    else std::free(p);
+  };
+  hfree(s->batch.h_items);
+  hfree(s->batch.h_micro);
+  hfree(s->h_sc);
+  hfree(s->h_led);
+  hfree(s->h_gbuf);
+  // the stream has drained: the device's static workspace is free again
+  if (s->static_dev >= 0) release_static(s->static_dev);
   delete s;
 }
 

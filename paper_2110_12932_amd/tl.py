@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtl.so")
 
 TL_OK, TL_EINVAL, TL_ENOMEM, TL_EDEVICE, TL_ENOCONV, TL_ESTATE, TL_EBUSY = 0, -1, -2, -3, -4, -5, -6
+TL_STATIC_WORKSPACE_BYTES = 32 * 1024 * 1024   # as in include/tl.h
 TL_FP64, TL_MIXED = 0, 1
 STATUS_NAMES = {0: "TL_OK", -1: "TL_EINVAL", -2: "TL_ENOMEM", -3: "TL_EDEVICE",
                 -4: "TL_ENOCONV", -5: "TL_ESTATE", -6: "TL_EBUSY"}
@@ -84,7 +85,7 @@ class tl_grid(C.Structure):
 
 
 # every symbol declared in include/tl.h and include/tl_ops.h
-SYMBOLS = ["tl_workspace_bytes", "tl_create", "tl_step", "tl_get_temperature", "tl_get_ledger",
+SYMBOLS = ["tl_workspace_bytes", "tl_create", "tl_create_static", "tl_step", "tl_get_temperature", "tl_get_ledger",
            "tl_get_stats", "tl_get_time", "tl_save", "tl_load", "tl_set_profiling", "tl_destroy",
            "tl_last_error",
            "tl_server_overhead_bytes", "tl_server_create", "tl_server_submit",
@@ -110,6 +111,10 @@ def load():
     lib.tl_create.restype = C.c_int
     lib.tl_create.argtypes = [C.POINTER(tl_mesh), C.POINTER(tl_material), C.POINTER(tl_scan_path),
                               C.POINTER(tl_options), vp, sz, vp, C.POINTER(vp)]
+    lib.tl_create_static.restype = C.c_int
+    lib.tl_create_static.argtypes = [C.POINTER(tl_mesh), C.POINTER(tl_material),
+                                     C.POINTER(tl_scan_path), C.POINTER(tl_options), vp,
+                                     C.POINTER(vp)]
     lib.tl_step.restype = C.c_int
     lib.tl_step.argtypes = [vp, C.c_int]
     lib.tl_get_temperature.restype = C.c_int
@@ -221,6 +226,17 @@ def tl_create(mesh, material, scan, opts, workspace, stream=None):
     return h
 
 
+def tl_create_static(mesh, material, scan, opts, stream=None):
+    """tl_create on the library's static device workspace (no allocation)."""
+    lib = load()
+    h = C.c_void_p()
+    sp = to_scan(scan)
+    _check(lib.tl_create_static(C.byref(to_mesh(mesh)), C.byref(to_material(material)),
+                                C.byref(sp), C.byref(to_options(opts)),
+                                C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+    return h
+
+
 def tl_step(h, n_macro):
     _check(load().tl_step(h, int(n_macro)))
 
@@ -318,16 +334,23 @@ def tl_op_apply(grid, precision, d, kappa, v, y, repeat=1, stream=None):
 
 # ---- convenience wrapper -------------------------------------------------------
 class Sim:
-    """One simulation on cuda:0 with a torch-allocated workspace."""
+    """One simulation on cuda:0 with a torch-allocated workspace, or with
+    static=True on the library's static device workspace (tl_create_static)."""
 
-    def __init__(self, workload, device="cuda", stream=None):
-        import torch
+    def __init__(self, workload, device="cuda", stream=None, static=False):
         self.wl = workload
+        self.stream = stream
+        self.workspace = None
+        self.h = None
+        if static:
+            self.h = tl_create_static(workload.mesh, workload.material, workload.scan,
+                                      workload.options, stream)
+            return
+        import torch
         nbytes = tl_workspace_bytes(workload.mesh, workload.options)
         if nbytes == 0:
             raise TLError(TL_EINVAL, "invalid mesh")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream
         self.h = tl_create(workload.mesh, workload.material, workload.scan, workload.options,
                            self.workspace, stream)
 

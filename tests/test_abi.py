@@ -130,3 +130,23 @@ def test_op_grid_too_large_is_rejected():
     for dims in ((2**31 - 1, 1, 1), (100000, 100000, 10)):
         grid = tl.to_grid(*dims, 1e-6, 1e-6, 1e-6)
         assert tl.tl_op_padded_size(grid) == 0
+
+
+def test_create_static_rejects_before_the_device():
+    """tl_create_static validates and sizes the problem before any HIP call:
+    a problem larger than the static workspace is TL_ENOMEM with a message
+    naming both sizes, an invalid mesh TL_EINVAL."""
+    wl = W.raster_5mm(W.FP64)
+    assert tl.tl_workspace_bytes(wl.mesh, wl.options) > tl.TL_STATIC_WORKSPACE_BYTES
+    with pytest.raises(tl.TLError) as e:
+        tl.tl_create_static(wl.mesh, wl.material, wl.scan, wl.options, stream=0)
+    assert e.value.status == tl.TL_ENOMEM
+    assert str(tl.TL_STATIC_WORKSPACE_BYTES) in str(e.value)
+    bad = replace(wl.mesh, refine=0)
+    with pytest.raises(tl.TLError) as e:
+        tl.tl_create_static(bad, wl.material, wl.scan, wl.options, stream=0)
+    assert e.value.status == tl.TL_EINVAL
+    # the size limit in the header is the one the binding states
+    src = open(os.path.join(ROOT, "include", "tl.h")).read()
+    m = re.search(r"#define TL_STATIC_WORKSPACE_BYTES \((\d+)u \* (\d+)u \* (\d+)u\)", src)
+    assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == tl.TL_STATIC_WORKSPACE_BYTES
