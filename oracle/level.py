@@ -38,10 +38,29 @@ class NoConvergence(RuntimeError):
 LINE_SEARCH_MAX = 12
 
 
-def residual(grid, mat, T, T_old, tau, load, elem_mask, mass, surface=None):
+class Fictitious:
+    """Elements of a level that carry constant coefficients in place of the
+    material law -- the global problem's own coefficients inside the local
+    domain in the consistent formulation of Section 3: conductivity `kappa`
+    [W/m/K] and volumetric heat capacity `rhoc` [J/m3/K] on the elements
+    where `elems` is 1.  Their lumped mass enters the time term with rhoc
+    (T - T_old) / tau instead of H(T) - H(T_old)."""
+
+    def __init__(self, grid, elems, kappa, rhoc):
+        self.elems = np.asarray(elems, dtype=np.float64)
+        self.kappa = float(kappa)
+        self.rhoc = float(rhoc)
+        self.mass = G.lumped_mass(grid, self.elems)
+
+
+def residual(grid, mat, T, T_old, tau, load, elem_mask, mass, surface=None, fict=None):
     kap = M.conductivity(G.element_mean(grid, T), mat) * elem_mask
+    if fict is not None:
+        kap = np.where(fict.elems > 0, fict.kappa, kap)
     K = G.stiffness(grid, kap)
     R = mass * (M.enthalpy(T, mat) - M.enthalpy(T_old, mat)) / tau + K @ T - load
+    if fict is not None:
+        R = R + fict.mass * fict.rhoc * (T - T_old) / tau
     if surface is not None and surface.active:
         R = R + surface.term(T)
     return R, K
@@ -65,14 +84,18 @@ def solve_spd(A, b):
 
 def implicit_step(grid, mat, T_old, tau, load, elem_mask=None,
                   dirichlet=None, dirichlet_values=None, T_guess=None,
-                  tol=1e-10, maxit=30, surface=None):
+                  tol=1e-10, maxit=30, surface=None, fict=None):
     """Backward-Euler step of one level.  Returns (T, R, iterations) with R
     the residual at the converged T (reactions on Dirichlet rows, ~0 on free
     rows).  `surface` (oracle.surface.Surface) adds the top-surface heat
-    loss A q(T) to the residual and A q'(T) to the Jacobian diagonal."""
+    loss A q(T) to the residual and A q'(T) to the Jacobian diagonal.
+    `fict` (Fictitious) gives some elements constant coefficients; the
+    material law then applies on the other elements of elem_mask only."""
     if elem_mask is None:
         elem_mask = np.ones(grid.n_elems)
     elem_mask = np.asarray(elem_mask, dtype=np.float64)
+    if fict is not None:
+        elem_mask = elem_mask * (1.0 - fict.elems)
     mass = G.lumped_mass(grid, elem_mask)
     if dirichlet is None:
         dirichlet = np.zeros(grid.n_nodes, dtype=bool)
@@ -80,9 +103,11 @@ def implicit_step(grid, mat, T_old, tau, load, elem_mask=None,
     if dirichlet_values is not None:
         T[dirichlet] = np.asarray(dirichlet_values)[dirichlet]
     free = np.flatnonzero(~dirichlet)
-    R, K = residual(grid, mat, T, T_old, tau, load, elem_mask, mass, surface)
+    R, K = residual(grid, mat, T, T_old, tau, load, elem_mask, mass, surface, fict)
     for it in range(1, maxit + 1):
         diag = mass * M.enthalpy_slope(T, mat) / tau
+        if fict is not None:
+            diag = diag + fict.mass * fict.rhoc / tau
         if surface is not None and surface.active:
             diag = diag + surface.slope(T)
         J = K + sp.diags(diag)
@@ -98,7 +123,7 @@ def implicit_step(grid, mat, T_old, tau, load, elem_mask=None,
             T_try = T.copy()
             T_try[free] -= alpha * delta
             R_try, K_try = residual(grid, mat, T_try, T_old, tau, load, elem_mask, mass,
-                                    surface)
+                                    surface, fict)
             if (np.linalg.norm(R_try[free]) <= (1.0 - 1e-4 * alpha) * r0
                     or alpha * dmax <= tol):
                 break

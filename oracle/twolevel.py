@@ -62,7 +62,8 @@ from . import grid as G
 from . import laser as L
 from . import material as M
 from . import surface as S
-from .level import implicit_step, residual, solve_spd, NoConvergence, LINE_SEARCH_MAX
+from .level import (implicit_step, residual, solve_spd, NoConvergence, LINE_SEARCH_MAX,
+                    Fictitious)
 
 
 class Window:
@@ -112,6 +113,7 @@ class Window:
         self.outside_face = ~((fi2 >= I0) & (fi2 < I0 + self.wx)
                               & (fj2 >= J0) & (fj2 < J0 + self.wy))
         self.mass_out = G.lumped_mass(c, self.outside_e)
+        self.mass_in = G.lumped_mass(c, 1.0 - self.outside_e)
         self.mass_f = G.lumped_mass(f)
         # lumped top-surface areas: every fine top face; coarse top faces
         # outside the window
@@ -201,6 +203,9 @@ class TwoLevel:
         # the alternate global formulation is a different discrete problem,
         # so the oracle follows the workload there
         self.alternate = getattr(wl.options, "coupling", 0) == 2
+        # the consistent global formulation (Section 3) with constant global
+        # coefficients inside the window: another discrete problem too
+        self.consistent = getattr(wl.options, "coupling", 0) == 3
         self.volume = getattr(wl.options, "source", 0) == 1
         self.z_top = wl.mesh.lz
         mesh, mat, opts = wl.mesh, wl.material, wl.options
@@ -229,6 +234,12 @@ class TwoLevel:
         # problem only)
         self.mat_global = replace(mat, latent=0.0) if self.alternate else mat
         self.mass_all = G.lumped_mass(c)
+        # the consistent formulation's global coefficients inside the window;
+        # zero selects the material law's values at T_init
+        T0 = np.array([mat.T_init])
+        kf, cf = getattr(mat, "k_fict", 0.0), getattr(mat, "rhoc_fict", 0.0)
+        self.k_fict = kf if kf > 0 else float(M.conductivity(T0, mat)[0])
+        self.rhoc_fict = cf if cf > 0 else mat.rho * float(M.heat_capacity(T0, mat)[0])
         self.ledger = dict(stored=self.energy(), absorbed=0.0, bottom=0.0, remap=0.0,
                            surface=0.0, stored0=0.0)
         self.ledger["stored0"] = self.ledger["stored"]
@@ -246,6 +257,14 @@ class TwoLevel:
         if self.alternate:
             return float(np.dot(self.mass_all, M.enthalpy(self.Tc, self.mat_global)))
         w = self.win
+        if self.consistent:
+            # plus the energy the global problem's own coefficients hold
+            # inside the window beyond the local field's (see
+            # _correct_consistent)
+            return float(np.dot(w.mass_out, M.enthalpy(self.Tc, self.mat))
+                         + np.dot(w.mass_f, M.enthalpy(self.Tf, self.mat))
+                         + self.rhoc_fict * (np.dot(w.mass_in, self.Tc)
+                                             - np.dot(w.mass_f, self.Tf)))
         return float(np.dot(w.mass_out, M.enthalpy(self.Tc, self.mat))
                      + np.dot(w.mass_f, M.enthalpy(self.Tf, self.mat)))
 
@@ -341,6 +360,8 @@ class TwoLevel:
         PTn = w.P @ self.Tc
         PTp = w.P @ Tpred
         T_prev = self.Tf
+        T_start = self.Tf
+        T_sum = np.zeros(w.fine.n_nodes)
         rho_sum = np.zeros(w.fine.n_nodes)
         absorbed = 0.0
         bottom = 0.0
@@ -353,11 +374,15 @@ class TwoLevel:
             if self.record is not None:
                 self.record.append((n, j, T_prev.copy()))
             rho_sum[w.gamma_f] += R[w.gamma_f]
+            T_sum += T_prev
             bottom -= dt * R[w.bottom_f].sum()
             absorbed += dt * Ff.sum()
             surface += dt * sf.loss(T_prev)
         # two-level correction at t_{n+1}
         Ff = self.fine_load(spots[m - 1])
+        if self.consistent:
+            return self._correct_consistent(T_start, T_prev, T_sum, rho_sum, Ff, Fc_out,
+                                            Tpred, absorbed, bottom, surface, E_start)
         if self.composite:
             Tf_m, R_m, Tc_new, Rc, it = self.composite_correction(
                 T_prev, dt, Ff, rho_sum, Fc_out, T_prev, Tpred)
@@ -381,6 +406,67 @@ class TwoLevel:
             self.stats["coarse_solves"] += 1
             d = np.where(w.gamma_c, Tc_new - lam, 0.0)
             diff = float(np.max(np.abs(d)))
+            theta = self.relaxation(it, d, d_prev, theta)
+            d_prev = d
+            lam = lam + theta * d
+            guess_f, guess_c = Tf_m, Tc_new
+            if diff <= self.dn_tol:
+                break
+        else:
+            raise NoConvergence("two-level iteration did not converge")
+        self._finish(Tf_m, R_m, Tc_new, Rc, it, Ff, Fc_out, absorbed, bottom, surface,
+                     E_start)
+
+    def _correct_consistent(self, T_start, T_prev, T_sum, rho_sum, Ff, Fc_out, Tpred,
+                            absorbed, bottom, surface, E_start):
+        """The two-level correction with the consistent global problem of
+        Section 3.  The global problem is posed on every coarse element:
+        outside the window with the material law, inside it with the global
+        problem's own constant coefficients (k_fict, rhoc_fict), loaded inside
+        by the local solution.  Section 3 writes that load as the volume
+        terms (the T- time derivative weighted by the coefficient ratios, Q
+        scaled by kappa+/kappa-, the two grad T- . grad kappa terms) and the
+        interface jump term.  Integrating them against a coarse test function
+        and using the local equation, they add up to the global operator with
+        the global coefficients applied to T- over the window, minus the
+        flux of T- through gamma_D.  Discretely, with the coarse basis in the
+        fine space (phi_J = sum_k P_kJ phi_k), that is the load P^T s with
+            s = rhoc_fict m_k (T-_m - T-_0) / Dt + k_fict (K1 Tavg)_k - rho_k,
+        K1 the unit-conductivity fine stiffness of the window, Tavg the mean
+        of the m micro-step fields, rho the mean over the micro steps of the
+        local reactions on gamma_D (the local residual, zero on the free rows
+        once solved).  The mean over the micro steps is the local equation
+        summed over the macro step, so the time term telescopes to the
+        change over Dt.  Dirichlet data of the local problem come from T+ on
+        gamma_D as before; the iteration between the last micro step and the
+        global solve is the same relaxed fixed point on the interface values
+        as the Dirichlet-Neumann correction.  The global field keeps its own
+        values inside the window (no injection): with equal levels (r = 1,
+        m = 1) it equals the local field there and the single-level solution
+        everywhere, the stronger consistency of Section 3."""
+        mesh, opts, mat, c, w = self.mesh, self.opts, self.mat, self.coarse, self.win
+        m, Dt = opts.m_time, opts.dt_coarse
+        dt = Dt / m
+        fict = Fictitious(c, 1.0 - w.outside_e, self.k_fict, self.rhoc_fict)
+        K1 = G.stiffness(w.fine, np.ones(w.fine.n_elems))
+        lam = Tpred.copy()
+        guess_f, guess_c = T_prev, Tpred
+        d_prev, theta = None, self.theta
+        for it in range(1, opts.dn_max + 1):
+            Tf_m, R_m = self.fine_step(T_prev, dt, Ff, w.P @ lam, guess_f)
+            rho_avg = np.where(w.gamma_f, rho_sum + R_m, 0.0) / m
+            T_avg = (T_sum + Tf_m) / m
+            s = (self.rhoc_fict * w.mass_f * (Tf_m - T_start) / Dt
+                 + self.k_fict * (K1 @ T_avg) - rho_avg)
+            Tc_new, Rc, itc = implicit_step(c, mat, self.Tc, Dt, Fc_out + w.P.T @ s, None,
+                                            self.bottom_c, np.full(c.n_nodes, mat.T_bottom),
+                                            T_guess=guess_c, tol=self.newton_tol,
+                                            maxit=opts.newton_max,
+                                            surface=self.surf_coarse(w.area_out), fict=fict)
+            self.stats["newton_coarse"] += itc
+            self.stats["coarse_solves"] += 1
+            d = np.where(w.gamma_c, Tc_new - lam, 0.0)
+            diff = float(np.max(np.abs(d))) if w.gamma_c.any() else 0.0
             theta = self.relaxation(it, d, d_prev, theta)
             d_prev = d
             lam = lam + theta * d

@@ -8,6 +8,7 @@ MIXED = 1
 DN = 0
 COMPOSITE = 1
 ALTERNATE = 2
+CONSISTENT = 3
 
 SURFACE = 0
 VOLUME = 1
@@ -37,7 +38,10 @@ class Material:
     sharpness [1/K] centred between T_sol and T_liq; temperatures in K.
     Top-surface heat loss: convection h_conv [W/m2/K] to T_amb on both
     levels, radiation of emissivity `emissivity` on the fine level only (the
-    paper's boundary conditions); zero (adiabatic top) by default."""
+    paper's boundary conditions); zero (adiabatic top) by default.
+    k_fict [W/m/K] and rhoc_fict [J/m3/K]: the global problem's own constant
+    coefficients inside the window in the consistent global formulation
+    (coupling CONSISTENT); 0 selects kappa(T_init) and rho c(T_init)."""
     rho: float = 8000.0
     T_lo: float = 300.0
     T_hi: float = 1563.0
@@ -55,6 +59,8 @@ class Material:
     h_conv: float = 0.0
     emissivity: float = 0.0
     T_amb: float = 300.0
+    k_fict: float = 0.0
+    rhoc_fict: float = 0.0
 
 
 def default_material(**kw):
@@ -102,7 +108,11 @@ class Options:
     values slaved to the coarse ones -- the same discrete solution, without
     the outer iteration -- or ALTERNATE (2), the paper's alternate global
     formulation (the global problem over the whole plate without latent
-    heat, the local problem driven by it, no feedback); the laser model: SURFACE (0, default), a Gaussian
+    heat, the local problem driven by it, no feedback), or CONSISTENT (3),
+    the paper's consistent global formulation (the global problem over the
+    whole plate with constant coefficients of its own inside the window,
+    loaded there by the local solution, iterated with the local problem like
+    the Dirichlet-Neumann correction); the laser model: SURFACE (0, default), a Gaussian
     flux on the top surface on both levels, or VOLUME (1), the paper's
     volumetric Gaussian on the fine level and a smeared box source on the
     coarse one (tracks along x or y only)."""
