@@ -1,25 +1,36 @@
 """Benchmark of the fine-level two-level time stepping on one MI355X.
 
-Workload (default): the single-track case at paper-like resolution -- a
-2 x 1 x 0.5 mm plate with 50 x 25 x 13 coarse Q1 cells, a window of 10 x 5 x 3
-coarse cells refined 8x (81 x 41 x 25 = 83,025 fine nodes), 8 micro steps per
-25 us macro step, FP64 linear solves.  One benchmark step is one macro step
-of the method (window update, coarse predictor, 7 fine micro steps, the
-two-level correction with its fine and coarse solves, injection, ledger).
+Workload (default): the large multi-track build -- a 10 x 10 x 2 mm plate
+with 200 x 200 x 40 coarse Q1 cells (1.66 M coarse nodes), 20 alternating
+raster tracks at 100 um hatch, a window of 12 x 8 x 3 coarse cells refined
+10x (121 x 81 x 31 = 303,831 fine nodes), 8 micro steps per 25 us macro
+step, FP64 linear solves.  One benchmark step is one macro step of the
+method (window update, coarse predictor, 7 fine micro steps, the composite
+two-level correction, injection, ledger).
 
 Metric: fine DOF-timesteps per second = (free fine nodes x micro steps) /
-wall time of the timed macro steps, inputs resident in HBM.  The result is
-checked against the FP64 CPU oracle by the parity tests, not here.
+wall time of the timed macro steps, inputs resident in HBM.  The timed run
+starts from the initial state, so its fields are compared with the oracle's
+fields for the same number of macro steps where tests/golden holds them
+(`oracle_rel_err`: max-norm error relative to the largest temperature, and
+to the largest rise above the plate).  `mixed` repeats the run with the
+mixed-precision path (FP32 operator and CG, FP64 residual, ledger and
+coarse-level correction) and reports its speedup over the FP64 path.
+`serving` runs the served stream of 64 single-track requests (closed loop,
+then Poisson arrivals at 1.5x that capacity) with its p50/p99 latency.
 
 Prints one JSON line.  `roofline` reports the fine CG iteration kernel (one
 Chronopoulos-Gear PCG iteration fused with the matrix-free Q1 apply):
 algorithmic bytes per launch (read r, w, s_old, p, x, d, kappa, Dinv; write
 r', w', s, p, x) over its average launch duration, timed with HIP events on
-the library's stream for a sample of the launches that did work inside the
-timed region.  `k2_sweep` times the bare operator apply (read v, d, kappa;
-write y) at the workloads' fine shapes and at an HBM-resident grid.
-`cpu_baseline` times the CPU oracle on one complete macro step of the same
-workload.
+the library's stream for a sample of the fine micro steps' launches that
+did work inside the timed region.  `k2_sweep` times the bare operator apply
+(read v, d, kappa; write y) at the workloads' fine shapes and at an
+HBM-resident grid.  `cpu_baseline` times the CPU oracle on a bounded sample
+of the same workload: whole macro steps where one takes a few seconds, else
+the first fine micro steps of the first macro step (the fine-level implicit
+solves alone; the oracle's coarse predictor and correction on the 1.66 M-node
+plate take several times longer and are left out).
 """
 import argparse
 import json
@@ -29,14 +40,15 @@ import time
 from dataclasses import replace
 
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "raster_10mm"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed macro steps")
+    ap.add_argument("--steps", type=int, default=20, help="timed macro steps")
     ap.add_argument("--warmup", type=int, default=2, help="untimed macro steps (separate run)")
-    ap.add_argument("--workload", default="single_track_2mm",
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=["single_track_2mm", "single_track_1mm", "raster_5mm",
                              "served_tracks", "raster_10mm"])
     ap.add_argument("--requests", type=int, default=64, help="served_tracks: requests in the stream")
@@ -50,6 +62,10 @@ def parse():
                     help="two-level correction: Dirichlet-Neumann iteration or one "
                          "composite-grid solve (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run of the FP64 workload")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the served stream of the default run")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time every Nth fine operator launch with HIP events (0: off)")
     ap.add_argument("--k2-sweep", action="store_true",
@@ -81,26 +97,46 @@ def measured_traffic(path, workload, elem):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, n_macro=2):
-    """The oracle on the first `n_macro` complete macro steps of the same
-    workload (about 10-20 s of CPU work at the benchmark size), one core."""
+def cpu_baseline(wl, n_macro=2, budget_s=15.0):
+    """The oracle, one core, on a bounded sample of the same workload:
+    `n_macro` complete macro steps when the plate is small (about 10-20 s of
+    CPU work at the single-track size), else the first fine micro steps of
+    macro step 0 until `budget_s` has passed (at least one), with Dirichlet
+    data from the initial coarse field."""
     from threadpoolctl import threadpool_limits
     import oracle
-    el, dof_steps = 0.0, 0
+    from oracle import laser as OL
+    from oracle.twolevel import micro_time
+    el, dof_steps, what = 0.0, 0, ""
     with threadpool_limits(1):
         sim = oracle.TwoLevel(wl)
-        for _ in range(n_macro):
-            t0 = time.perf_counter()
-            sim.step()
-            el += time.perf_counter() - t0
-            dof_steps += int((~sim.win.dir_f).sum()) * wl.options.m_time
+        free = int((~sim.win.dir_f).sum())
+        if sim.coarse.n_nodes <= 100_000:
+            for _ in range(n_macro):
+                t0 = time.perf_counter()
+                sim.step()
+                el += time.perf_counter() - t0
+                dof_steps += free * wl.options.m_time
+            what = (f"macro steps 0-{n_macro - 1} in full ({n_macro * wl.options.m_time} "
+                    "micro steps, two-level correction included)")
+        else:
+            m, dt = wl.options.m_time, wl.options.dt_coarse / wl.options.m_time
+            g = sim.win.P @ sim.Tc
+            T = sim.Tf
+            j = 0
+            while j < m - 1 and (j == 0 or el < budget_s):
+                j += 1
+                t0 = time.perf_counter()
+                Ff = sim.fine_load(OL.laser_at(wl.scan, micro_time(wl.scan, wl.options, 0, j)))
+                T, _ = sim.fine_step(T, dt, Ff, g)
+                el += time.perf_counter() - t0
+                dof_steps += free
+            what = (f"fine micro steps 1-{j} of macro step 0 ({sim.win.fine.n_nodes} fine "
+                    "nodes; coarse predictor and correction not included)")
     return {"value": dof_steps / el, "unit": "fine DOF-timesteps/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{wl.name} macro steps 0-{n_macro - 1} in full "
-                      f"({n_macro * wl.options.m_time} micro steps, {dof_steps} fine "
-                      f"DOF-steps, two-level correction included): "
-                      f"{el:.1f} s on 1 core of {os.cpu_count()} "
-                      f"(affinity {len(os.sched_getaffinity(0))})"}
+            "sample": f"{wl.name} {what}: {dof_steps} fine DOF-steps in {el:.1f} s on 1 core "
+                      f"of {os.cpu_count()} (affinity {len(os.sched_getaffinity(0))})"}
 
 
 def k2_sweep(tl, W, torch):
@@ -202,7 +238,7 @@ def serve_stream(tl, W, torch, reqs, slots, budget, arrivals=None, profile_every
     return wall, lat, stats, prof
 
 
-def main_serving(args):
+def serving_run(args, tl, W, torch, profile_every=0):
     """The served workload: a seeded stream of single-track requests through the
     continuous-batching server.  A closed-loop run (all requests at t = 0)
     measures the batched capacity; the stream then arrives as a Poisson
@@ -210,9 +246,6 @@ def main_serving(args):
     DOF-timesteps/s over the stream's wall time) and p50/p99 latency come
     from that run."""
     import numpy as np
-    import torch
-    import workloads as W
-    from paper_2110_12932_amd import tl
     tl.load()
     stream = W.served_tracks(args.requests, seed=0, mean_interarrival=1.0)
     reqs = [w for _, w in stream]
@@ -226,8 +259,32 @@ def main_serving(args):
     mean_gap = 1.0 / (args.load * capacity)
     arrivals = np.cumsum(unit_gaps * mean_gap)
     wall, lat, stats, prof = serve_stream(tl, W, torch, reqs, args.slots, budget,
-                                          arrivals, args.profile_every)
+                                          arrivals, profile_every)
     dof = sum(st["fine_dof_steps"] for st in stats)
+    lat = np.array(lat)
+    return {"wall": wall, "wall_closed": wall_c, "dof": dof, "stats": stats, "prof": prof,
+            "capacity": capacity, "mean_gap": mean_gap, "budget": budget, "n": len(reqs),
+            "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+
+def serving_summary(args, tl, W, torch):
+    r = serving_run(args, tl, W, torch)
+    return {"workload": "served_tracks", "requests": r["n"], "slots": args.slots,
+            "precision": "mixed", "hbm_budget_bytes": r["budget"] or "unbounded",
+            "fine_dof_steps_per_s": r["dof"] / r["wall"],
+            "latency_p50_s": r["p50"], "latency_p99_s": r["p99"],
+            "arrivals": f"Poisson, {args.load}x the closed-loop capacity "
+                        f"({r['capacity']:.2f} req/s)",
+            "closed_loop_fine_dof_steps_per_s": r["dof"] / r["wall_closed"]}
+
+
+def main_serving(args):
+    """The served workload as the headline line (--workload served_tracks)."""
+    import torch
+    import workloads as W
+    from paper_2110_12932_amd import tl
+    r = serving_run(args, tl, W, torch, args.profile_every)
+    stats, prof, wall = r["stats"], r["prof"], r["wall"]
     fine_bytes = sum(st["fine_op_bytes"] for st in stats)
     roofline = None
     if prof[0] > 0:
@@ -241,34 +298,88 @@ def main_serving(args):
                     "avg_launch_us": prof[1] * 1e3 / prof[0],
                     "bytes_per_launch": fine_bytes / max(1.0, launches_work),
                     "launches_timed": prof[0], "fine_cg_item_iterations": fine_iters}
-    lat = np.array(lat)
+    n_steps = int(sum(st["macro_steps"] for st in stats))
     out = {
-        "metric": "fine DOF-timesteps/s", "value": dof / wall, "unit": "fine DOF-timesteps/s",
-        "n_gpus": 1, "steps": int(sum(st["macro_steps"] for st in stats)), "warmup": 1,
-        "ms_per_step": wall * 1e3 / max(1, int(sum(st["macro_steps"] for st in stats))),
+        "metric": "fine DOF-timesteps/s", "value": r["dof"] / wall, "unit": "fine DOF-timesteps/s",
+        "n_gpus": 1, "steps": n_steps, "warmup": 1,
+        "ms_per_step": wall * 1e3 / max(1, n_steps),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "served_tracks", "requests": len(reqs), "slots": args.slots,
-                   "hbm_budget_bytes": budget or "unbounded",
+        "config": {"workload": "served_tracks", "requests": r["n"], "slots": args.slots,
+                   "hbm_budget_bytes": r["budget"] or "unbounded",
                    "fine_nodes_per_request": list(stats[0]["fine_nodes"]),
                    "arrivals": f"Poisson, {args.load}x the closed-loop capacity "
-                               f"({capacity:.2f} req/s), mean gap {mean_gap * 1e3:.1f} ms"},
-        "latency_p50_s": float(np.percentile(lat, 50)),
-        "latency_p99_s": float(np.percentile(lat, 99)),
-        "closed_loop": {"wall_s": wall_c, "fine_dof_steps_per_s": dof / wall_c},
+                               f"({r['capacity']:.2f} req/s), mean gap {r['mean_gap'] * 1e3:.1f} ms"},
+        "latency_p50_s": r["p50"],
+        "latency_p99_s": r["p99"],
+        "closed_loop": {"wall_s": r["wall_closed"],
+                        "fine_dof_steps_per_s": r["dof"] / r["wall_closed"]},
         "roofline": roofline,
     }
     print(json.dumps(out), flush=True)
 
 
+def golden_error(name, steps, Tc, Tf, origin):
+    """Max-norm error of a run's fields against the oracle fields stored for
+    the same workload and macro-step count (tests/golden, written by the
+    oracle only), or None when there is none."""
+    import numpy as np
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        f"{name}_n{steps}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    if tuple(int(v) for v in g["origin"]) != tuple(origin):
+        return {"golden": os.path.relpath(path), "window_origin_differs": True}
+    out = {"golden": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__)))}
+    for lvl, a, b in (("coarse", Tc, g["Tc"]), ("fine", Tf, g["Tf"])):
+        d = float(np.max(np.abs(a - b)))
+        out[lvl] = d / float(np.max(np.abs(b)))
+        # the stricter norm: relative to the largest rise above the plate
+        out[lvl + "_vs_rise"] = d / float(np.max(np.abs(b - 300.0)))
+    return out
+
+
+def timed_run(tl, torch, wl, steps, warmup, profile_every):
+    """Warm-up on a handle of its own, then `steps` macro steps from the
+    initial state on a fresh handle, bracketed by device synchronisation."""
+    if warmup > 0:
+        s = tl.Sim(wl)
+        s.step(min(warmup, wl.n_macro))
+        s.close()
+    torch.cuda.synchronize()
+    sim = tl.Sim(wl)
+    try:
+        if profile_every > 0:
+            tl.tl_set_profiling(sim.h, profile_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st, led = sim.stats(), sim.ledger()
+        Tc, _ = sim.temperature(0)
+        Tf, origin = sim.temperature(1)
+    finally:
+        sim.close()
+    return {"el": el, "st": st, "led": led, "err": golden_error(wl.name, steps, Tc, Tf, origin)}
+
+
+def ledger_defect(led):
+    return abs((led["stored"] - led["stored0"])
+               - (led["absorbed"] - led["bottom"] - led["surface"] + led["remap"])) \
+        / max(abs(led["absorbed"]), 1e-300)
+
+
 def main():
     args = parse()
-    if args.workload == "served_tracks" and args.gpus == 1:
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the path's sharding across "
+                                   "GPUs is a design only, so --gpus must be 1"}))
+        sys.exit(2)
+    if args.workload == "served_tracks":
         main_serving(args)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
     import torch
     import workloads as W
     from paper_2110_12932_amd import tl
@@ -276,36 +387,21 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
-    kw = {}
-    if args.precision:
-        kw["precision"] = W.FP64 if args.precision == "fp64" else W.MIXED
-    wl = W.by_name(args.workload, **kw)
-    if args.coupling:
-        from dataclasses import replace
-        wl = replace(wl, options=replace(
-            wl.options, coupling=W.COMPOSITE if args.coupling == "composite" else W.DN))
+    prec = W.FP64 if args.precision in (None, "fp64") else W.MIXED
+
+    def make_wl(p):
+        w = W.by_name(args.workload, precision=p)
+        if args.coupling:
+            w = replace(w, options=replace(
+                w.options, coupling=W.COMPOSITE if args.coupling == "composite" else W.DN))
+        return w
+
+    wl = make_wl(prec)
     steps = min(args.steps, wl.n_macro)
     tl.load()
 
-    # warm-up on its own handle (first launches, code objects, caches)
-    if args.warmup > 0:
-        s = tl.Sim(wl)
-        s.step(min(args.warmup, wl.n_macro))
-        s.close()
-    torch.cuda.synchronize()
-
-    sim = tl.Sim(wl)
-    if args.profile_every > 0:
-        tl.tl_set_profiling(sim.h, args.profile_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    st = sim.stats()
-    led = sim.ledger()
-    sim.close()
-
+    run = timed_run(tl, torch, wl, steps, args.warmup, args.profile_every)
+    el, st, led = run["el"], run["st"], run["led"]
     value = st["fine_dof_steps"] / el
     fine_nodes = st["fine_nodes"][0] * st["fine_nodes"][1] * st["fine_nodes"][2]
     elem = 8 if wl.options.precision == W.FP64 else 4
@@ -341,14 +437,23 @@ def main():
                    "precision": "fp64" if wl.options.precision == W.FP64 else "mixed",
                    "coupling": "composite" if wl.options.coupling == W.COMPOSITE else "dn",
                    "macro_steps_timed": steps},
+        "oracle_rel_err": run["err"],
         "roofline": roofline,
         "counters": {k: st[k] for k in ("micro_steps", "newton_fine", "newton_coarse", "cg_fine",
                                         "cg_coarse", "dn_iters", "window_moves", "fine_solves",
                                         "coarse_solves", "line_search_halvings")},
-        "ledger_rel_defect": abs((led["stored"] - led["stored0"])
-                                 - (led["absorbed"] - led["bottom"] - led["surface"] + led["remap"]))
-                             / max(abs(led["absorbed"]), 1e-300),
+        "ledger_rel_defect": ledger_defect(led),
     }
+    if prec == W.FP64 and not args.no_mixed:
+        # the mixed-precision path (FP32 operator and CG, FP64 residual, ledger
+        # and coarse correction) on the same workload and steps
+        wm = make_wl(W.MIXED)
+        mr = timed_run(tl, torch, wm, steps, min(args.warmup, 1), 0)
+        mv = mr["st"]["fine_dof_steps"] / mr["el"]
+        out["mixed"] = {"value": mv, "ms_per_step": mr["el"] * 1e3 / steps,
+                        "speedup_vs_fp64": mv / value, "oracle_rel_err": mr["err"],
+                        "newton_fine": mr["st"]["newton_fine"], "cg_fine": mr["st"]["cg_fine"],
+                        "ledger_rel_defect": ledger_defect(mr["led"])}
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.rand(n, device="cuda")
@@ -360,6 +465,8 @@ def main():
         out["calibrate_copy_bytes"] = n * 4
     if args.k2_sweep:
         out["k2_sweep"] = k2_sweep(tl, W, torch)
+    if not args.no_serving and args.workload == DEFAULT_WORKLOAD:
+        out["serving"] = serving_summary(args, tl, W, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
