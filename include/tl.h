@@ -64,13 +64,19 @@ typedef struct {
  * sigma emissivity (T^4 - T_amb^4) through the fine window's top faces
  * (sigma = 5.670374419e-8); both are lumped onto the faces' corner nodes.
  * h_conv >= 0, 0 <= emissivity <= 1, T_amb > 0; zero h_conv and emissivity
- * give an adiabatic top. */
+ * give an adiabatic top.
+ * k_fict [W/m/K] and rhoc_fict [J/m^3/K] are the global problem's own
+ * constant conductivity and volumetric heat capacity inside the window in
+ * the consistent global formulation (TL_COUPLE_CONSISTENT, paper Section 3:
+ * the global coefficients kappa+, c+ rho+ inside the local domain); 0
+ * selects kappa(T_init) and rho c(T_init); both finite and >= 0. */
 typedef struct {
   double rho, T_lo, T_hi, c_lo, c_hi, k_lo, k_hi;
   double latent, T_sol, T_liq, sharpness;
   int pc_kind;
   double T_init, T_bottom;
   double h_conv, emissivity, T_amb;
+  double k_fict, rhoc_fict;
 } tl_material;
 
 /* One straight laser pass from (x0,y0) to (x1,y1) on the top surface at
@@ -115,11 +121,24 @@ typedef struct {
  * steps with the blended global data and does not feed back.  It is a
  * different discrete problem; its ledger (tl_get_ledger) is the global
  * problem's: stored = sum over coarse nodes of the lumped mass times H(T+)
- * without latent heat, absorbed / bottom / surface of the global solve. */
+ * without latent heat, absorbed / bottom / surface of the global solve.
+ * TL_COUPLE_CONSISTENT: the paper's consistent global formulation -- the
+ * global problem over every coarse element, the window's with the constant
+ * coefficients k_fict, rhoc_fict (tl_material), loaded inside the window by
+ * the local solution: P^T s with s = rhoc_fict m_k (T-_m - T-_0)/dt_coarse
+ * + k_fict (K1 Tavg)_k - (mean local reaction on the interface)_k, which is
+ * Section 3's volume and interface-jump terms after the local equation is
+ * used (K1: unit-conductivity fine stiffness, Tavg: mean of the m micro-step
+ * fields).  It is iterated with the last micro step on the interface
+ * values like TL_COUPLE_DN (dn_tol, dn_theta, dn_max apply).  The coarse
+ * field keeps its own values inside the window (no injection); the stored
+ * energy adds rhoc_fict (sum m_in T+ - sum m_k T-), the energy the global
+ * coefficients hold inside the window beyond the local field's. */
 typedef enum {
   TL_COUPLE_DN = 0,
   TL_COUPLE_COMPOSITE = 1,
-  TL_COUPLE_ALTERNATE = 2
+  TL_COUPLE_ALTERNATE = 2,
+  TL_COUPLE_CONSISTENT = 3
 } tl_coupling;
 
 /* Laser model (see tl_track).  The volume model needs depth > 0 on every
@@ -136,7 +155,7 @@ typedef enum { TL_SOURCE_SURFACE = 0, TL_SOURCE_VOLUME = 1 } tl_source;
  * interface quasi-Newton (IQN-ILS) acceleration whose first step is relaxed
  * by refine/(refine+1); *_max: iteration caps.  Any relaxation converges to
  * the same fixed point.  coupling: a tl_coupling value (dn_tol, dn_theta and
- * dn_max apply to TL_COUPLE_DN only); source: a tl_source value (face_quad
+ * dn_max apply to TL_COUPLE_DN and TL_COUPLE_CONSISTENT only); source: a tl_source value (face_quad
  * applies to TL_SOURCE_SURFACE only). */
 typedef struct {
   double dt_coarse;
@@ -240,7 +259,8 @@ tl_status tl_step(tl_sim* sim, int n_macro);
  * field to host_out (host memory owned by the caller), node (i,j,k) at
  * i + nx*(j + ny*k) with (nx,ny,nz) = dims_out.  With the Dirichlet-Neumann
  * or composite correction, the coarse nodes strictly inside the window hold
- * the injected fine values.  cap is the capacity of host_out in doubles
+ * the injected fine values; with the alternate or consistent formulation
+ * they hold the global problem's own values.  cap is the capacity of host_out in doubles
  * (TL_ENOMEM if too small, nothing copied); TL_EINVAL for a null handle or
  * buffer or a level other than 0 or 1.  fine_origin_out (may be NULL)
  * receives the fine-grid index of the window's first node on the plate-wide

@@ -32,8 +32,13 @@ enum RegionMode {
   kAllBottom = 0,   // all elements; Dirichlet on k = 0 (coarse predictor)
   kOutside = 1,     // coarse elements outside the window box; Dirichlet on
                     // k = 0 and on window nodes not on an immersed face
-  kWindow = 2       // fine window: all elements; Dirichlet on immersed faces
+  kWindow = 2,      // fine window: all elements; Dirichlet on immersed faces
                     // and, when the window reaches the plate bottom, k = 0
+  kFictitious = 3   // coarse plate, all elements, Dirichlet on k = 0; the
+                    // elements of the window box [I0,I1) x [J0,J1) x [K0,..)
+                    // carry the constant coefficients kf, rhocf (the
+                    // consistent global problem); top-surface loss outside
+                    // the window only
 };
 enum FaceBits { kFx0 = 1, kFx1 = 2, kFy0 = 4, kFy1 = 8, kFz0 = 16 };
 
@@ -42,6 +47,8 @@ struct Region {
   int I0, I1, J0, J1, K0;  // kOutside: coarse window box in cells [I0,I1) ...
   int faces;               // immersed faces (FaceBits) for kOutside/kWindow
   int bottom;              // kWindow: 1 if node layer k = 0 is on the plate bottom
+  double kf, rhocf;        // kFictitious: conductivity and volumetric heat
+                           // capacity of the window box's elements
 };
 
 struct MatDev {
@@ -258,25 +265,30 @@ struct SolveItem {
 
 // Tiles of a grid in the batched kernels.
 int grid_tiles(const Geo& g, int& ntx, int& nty);
-// Workgroups every item of a batched launch gets (a multiple of 8), for a
-// largest item of ntiles tiles: one per tile up to kMaxBlocks when alone,
-// fewer in larger batches so that a launch stays near kMaxBlocks workgroups
-// (each then walks several tiles; an item with fewer tiles leaves some
-// workgroups without work).
-int item_tile_blocks(int ntiles, int n_items);
+// Workgroups every item of a batched tiled launch gets (a multiple of 8),
+// for a largest item of ntiles tiles and a kernel of which the device holds
+// `resident` workgroups at once: one per tile up to kResidentShare times
+// that residency when alone, a share of it in larger batches but at least
+// 64 (each workgroup then walks several tiles, the next tile's loads in
+// flight during the current one; an item with fewer tiles leaves some
+// workgroups without work).  A launch larger than the device holds would
+// run its last workgroups as a partly filled second wave.
+constexpr double kResidentShare = 1.0;
+int item_tile_blocks(int ntiles, int n_items, int resident);
 
 // Batched launches of Newton round `round` over a device table of n_items
-// items, per_item workgroups each.  ev_start/ev_stop (hipEvent_t, may be
-// null) are recorded with the CG dispatch itself.
+// items whose largest has ntiles tiles (the grid follows item_tile_blocks).
+// ev_start/ev_stop (hipEvent_t, may be null) are recorded with the CG
+// dispatch itself.
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
-                        int per_item, int round);
+                        int ntiles, int round);
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int per_item, int round);
+                        int ntiles, int round);
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int per_item, int round, int kit, void* ev_start,
+                       int ntiles, int round, int kit, void* ev_start,
                        void* ev_stop);
 // The same launches for the two sides of composite pairs (side =
 // kFineSide or kCoarseSide), and the gather between them over the coarse
@@ -284,13 +296,13 @@ void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
 // CG iteration kit.
 template <class R>
 void k_residual_pair(Launch L, const SolveItem* items, int n_items,
-                     int per_item, int round, int side);
+                     int ntiles, int round, int side);
 template <class R>
 void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
-                     int per_item, int round, int side);
+                     int ntiles, int round, int side);
 template <class R>
 void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
-                    int per_item, int round, int kit, int side,
+                    int ntiles, int round, int kit, int side,
                     void* ev_start, void* ev_stop);
 template <class R>
 void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
@@ -373,6 +385,21 @@ void k_restrict(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                 const double* rho_acc, const double* Rm, double scale,
                 double* ext);
 
+// ext = P^T s over every fine node of the window, on every coarse node of
+// the closed window (other coarse entries untouched).
+void k_restrict_all(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+                    const double* s, double* ext);
+// The consistent global problem's load from the local solution, on the
+// fine window: src = rhocf m_k (Tm - T0)/Dt + kf (K1 Tavg)_k - (rho + Rm)_k/m
+// (the last term on interface nodes), Tavg = (Tsum + Tm)/m; Tsum and rho
+// may be null (m = 1).
+void k_consistent_source(Launch L, const Geo& gf, const Window& w,
+                         const double* Tm, const double* T0, const double* Tsum,
+                         const double* rho, const double* Rm, int m, double Dt,
+                         double kf, double rhocf, double* src);
+// dst = src (assign) or dst += src, over n entries.
+void k_accumulate(Launch L, double* dst, const double* src, long n, int assign);
+
 void k_inject(Launch L, const Geo& gf, const Geo& gc, const Window& w,
               const double* Tf, double* Tc);
 
@@ -382,7 +409,8 @@ void k_window_shift(Launch L, const Geo& gf, const Geo& gc, const Window& wn,
 
 // Sum over nodes of mass(region) * H(T) (+ into slot, or = when assign).
 void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
-              const double* T, double* slot, int assign, double* partials);
+              const double* T, double* slot, int assign, double* partials,
+              double lin = 0.0);
 
 // Sum over nodes with k = 0 of R (scaled, added into slot).
 void k_bottom_sum(Launch L, const Geo& g, const double* R, double scale,

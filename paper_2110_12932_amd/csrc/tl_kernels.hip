@@ -149,17 +149,21 @@ __device__ inline double trial_T(double T, double step, const MatDev& m) {
 // ---------------------------------------------------------------------------
 // region rules (which elements are active, which nodes are Dirichlet)
 // ---------------------------------------------------------------------------
+__device__ inline bool in_window_box(const Region& rg, int ei, int ej, int ek) {
+  return ei >= rg.I0 && ei < rg.I1 && ej >= rg.J0 && ej < rg.J1 && ek >= rg.K0;
+}
 __device__ inline bool elem_active(const Geo& g, const Region& rg, int ei,
                                    int ej, int ek) {
   if (ei < 0 || ej < 0 || ek < 0 || ei > g.nx - 2 || ej > g.ny - 2 ||
       ek > g.nz - 2)
     return false;
-  if (rg.mode == kOutside) {
-    bool in = ei >= rg.I0 && ei < rg.I1 && ej >= rg.J0 && ej < rg.J1 &&
-              ek >= rg.K0;
-    return !in;
-  }
+  if (rg.mode == kOutside) return !in_window_box(rg, ei, ej, ek);
   return true;
+}
+// An active element with the constant global coefficients of the consistent
+// formulation (inside the window box of a kFictitious region).
+__device__ inline bool elem_fictitious(const Region& rg, int ei, int ej, int ek) {
+  return rg.mode == kFictitious && in_window_box(rg, ei, ej, ek);
 }
 __device__ inline bool on_immersed_face(const Region& rg, int i, int j, int k,
                                         int i0, int i1, int j0, int j1,
@@ -170,7 +174,7 @@ __device__ inline bool on_immersed_face(const Region& rg, int i, int j, int k,
 }
 __device__ inline bool node_dirichlet(const Geo& g, const Region& rg, int i,
                                       int j, int k) {
-  if (rg.mode == kAllBottom) return k == 0;
+  if (rg.mode == kAllBottom || rg.mode == kFictitious) return k == 0;
   if (rg.mode == kOutside) {
     if (k == 0) return true;
     bool inwin = i >= rg.I0 && i <= rg.I1 && j >= rg.J0 && j <= rg.J1 &&
@@ -194,7 +198,7 @@ __device__ inline double top_area(const Geo& g, const Region& rg, int i, int j) 
     for (int a = 0; a < 2; ++a) {
       const int fi = i - a, fj = j - b;
       bool keep = fi >= 0 && fj >= 0 && fi <= g.nx - 2 && fj <= g.ny - 2;
-      if (keep && rg.mode == kOutside)
+      if (keep && (rg.mode == kOutside || rg.mode == kFictitious))
         keep = !(fi >= rg.I0 && fi < rg.I1 && fj >= rg.J0 && fj < rg.J1);
       n += keep ? 1 : 0;
     }
@@ -962,7 +966,10 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       if (e < EN) {
         const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
         double ke = 0.0;
-        if (elem_active(g, it.rg, t.ox + ex - 1, t.oy + ey - 1, t.oz + ez - 1)) {
+        const int gi = t.ox + ex - 1, gj = t.oy + ey - 1, gk = t.oz + ez - 1;
+        if (elem_fictitious(it.rg, gi, gj, gk) && elem_active(g, it.rg, gi, gj, gk)) {
+          ke = it.rg.kf;
+        } else if (elem_active(g, it.rg, gi, gj, gk)) {
           double sm = 0.0;
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
@@ -987,14 +994,19 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                 t_s[(t.tz + 1 + dz) * (HX * HY) + (t.ty + 1 + dy) * HX +
                     (t.tx + 1 + dxx)];
       double k8[8];
-      double nact = 0.0;
+      double nact = 0.0, nfict = 0.0;
       double diagK = 0.0;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
         const double ke = k_s[(t.tz + 1 - ez) * (EX * EY) +
                               (t.ty + 1 - ey) * EX + (t.tx + 1 - ex)];
-        if (elem_active(g, it.rg, i - ex, j - ey, k - ez)) nact += 1.0;
+        if (elem_active(g, it.rg, i - ex, j - ey, k - ez)) {
+          if (elem_fictitious(it.rg, i - ex, j - ey, k - ez))
+            nfict += 1.0;
+          else
+            nact += 1.0;
+        }
         k8[e] = ke;
         diagK += ke;
       }
@@ -1008,6 +1020,10 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         it.Hold[n] = Ho;
       }
       double Rn = mass * (Hn - Ho) / it.tau + stencil_apply(T27, k8, w) - F_n;
+      // elements with the consistent global problem's own coefficients:
+      // their lumped mass takes rhoc_f (T - T_old) / tau
+      const double mfict = g.vol8 * nfict * it.rg.rhocf;
+      if (nfict > 0.0) Rn += mfict * (Tn - it.Told[n]) / it.tau;
       if (it.Fext != nullptr) Rn -= Fx_n;
       // heat loss through the top surface and its (exact) slope
       double sd = 0.0;
@@ -1018,7 +1034,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       }
       // coefficients of the frozen-kappa Jacobian J = diag(m H'/tau) + K[kap]
       const bool dir = node_dirichlet(g, it.rg, i, j, k);
-      double dn = mass * dHn / it.tau + sd;
+      double dn = (mass * dHn + mfict) / it.tau + sd;
       double diag = dn + diagK * g.w[0];
       double kown = k8[0];
       bool keep_diag = false;
@@ -1715,29 +1731,57 @@ int grid_tiles(const Geo& g, int& ntx, int& nty) {
   tiles_of(g, ntx, nty, ntz);
   return ntx * nty * ntz;
 }
-int item_tile_blocks(int ntiles, int n_items) {
-  const int share = std::max(64, kMaxBlocks / std::max(1, n_items)) / kXcd * kXcd;
+// Workgroups of a kernel that the device holds at once: the occupancy
+// limit per compute unit (set by its registers and LDS) times the compute
+// units.  Taken once per kernel.
+template <class F>
+static int resident_blocks(F kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+          hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  return per_cu * cus;
+}
+
+int item_tile_blocks(int ntiles, int n_items, int resident) {
+  const int share =
+      std::max(64, (int)(kResidentShare * resident) / std::max(1, n_items)) /
+      kXcd * kXcd;
   return std::min(tiled_grid(ntiles), share);
 }
 
+// The tiled launches below take the tile count of the batch's largest item
+// and size the grid from the kernel's own residency.
 template <class R, int CP>
 static void launch_residual(Launch L, const SolveItem* items, int n_items,
-                            int per_item, int round) {
+                            int ntiles, int round) {
+  static const int resident = resident_blocks(residual_batched_kernel<R, CP>);
+  const int per_item = item_tile_blocks(ntiles, n_items, resident);
   hipLaunchKernelGGL((residual_batched_kernel<R, CP>),
                      dim3(n_items * per_item), dim3(kBlock), 0,
                      (hipStream_t)L.stream, items, per_item, round);
 }
 template <class R, int CP>
 static void launch_cg_start(Launch L, const SolveItem* items, int n_items,
-                            int per_item, int round) {
+                            int ntiles, int round) {
+  static const int resident = resident_blocks(cg_start_batched_kernel<R, CP>);
+  const int per_item = item_tile_blocks(ntiles, n_items, resident);
   hipLaunchKernelGGL((cg_start_batched_kernel<R, CP>),
                      dim3(n_items * per_item), dim3(kBlock), 0,
                      (hipStream_t)L.stream, items, per_item, round);
 }
 template <class R, int CP>
 static void launch_cg_iter(Launch L, const SolveItem* items, int n_items,
-                           int per_item, int round, int kit, void* ev_start,
+                           int ntiles, int round, int kit, void* ev_start,
                            void* ev_stop) {
+  static const int resident = resident_blocks(cg_iter_batched_kernel<R, CP>);
+  const int per_item = item_tile_blocks(ntiles, n_items, resident);
   if (ev_start != nullptr)
     hipExtLaunchKernelGGL((cg_iter_batched_kernel<R, CP>),
                           dim3(n_items * per_item), dim3(kBlock), 0,
@@ -1750,53 +1794,53 @@ static void launch_cg_iter(Launch L, const SolveItem* items, int n_items,
 }
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
-                        int per_item, int round) {
-  launch_residual<R, kAlone>(L, items, n_items, per_item, round);
+                        int ntiles, int round) {
+  launch_residual<R, kAlone>(L, items, n_items, ntiles, round);
 }
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int per_item, int round) {
-  launch_cg_start<R, kAlone>(L, items, n_items, per_item, round);
+                        int ntiles, int round) {
+  launch_cg_start<R, kAlone>(L, items, n_items, ntiles, round);
 }
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int per_item, int round, int kit, void* ev_start,
+                       int ntiles, int round, int kit, void* ev_start,
                        void* ev_stop) {
-  launch_cg_iter<R, kAlone>(L, items, n_items, per_item, round, kit, ev_start,
+  launch_cg_iter<R, kAlone>(L, items, n_items, ntiles, round, kit, ev_start,
                             ev_stop);
 }
 template <class R>
 void k_residual_pair(Launch L, const SolveItem* items, int n_items,
-                     int per_item, int round, int side) {
+                     int ntiles, int round, int side) {
   if (side == kFineSide)
-    launch_residual<R, kFineSide>(L, items, n_items, per_item, round);
+    launch_residual<R, kFineSide>(L, items, n_items, ntiles, round);
   else if (side == kFineSideP)
-    launch_residual<R, kFineSideP>(L, items, n_items, per_item, round);
+    launch_residual<R, kFineSideP>(L, items, n_items, ntiles, round);
   else
-    launch_residual<R, kCoarseSide>(L, items, n_items, per_item, round);
+    launch_residual<R, kCoarseSide>(L, items, n_items, ntiles, round);
 }
 template <class R>
 void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
-                     int per_item, int round, int side) {
+                     int ntiles, int round, int side) {
   if (side == kFineSide)
-    launch_cg_start<R, kFineSide>(L, items, n_items, per_item, round);
+    launch_cg_start<R, kFineSide>(L, items, n_items, ntiles, round);
   else if (side == kFineSideP)
-    launch_cg_start<R, kFineSideP>(L, items, n_items, per_item, round);
+    launch_cg_start<R, kFineSideP>(L, items, n_items, ntiles, round);
   else
-    launch_cg_start<R, kCoarseSide>(L, items, n_items, per_item, round);
+    launch_cg_start<R, kCoarseSide>(L, items, n_items, ntiles, round);
 }
 template <class R>
 void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
-                    int per_item, int round, int kit, int side,
+                    int ntiles, int round, int kit, int side,
                     void* ev_start, void* ev_stop) {
   if (side == kFineSide)
-    launch_cg_iter<R, kFineSide>(L, items, n_items, per_item, round, kit,
+    launch_cg_iter<R, kFineSide>(L, items, n_items, ntiles, round, kit,
                                  ev_start, ev_stop);
   else if (side == kFineSideP)
-    launch_cg_iter<R, kFineSideP>(L, items, n_items, per_item, round, kit,
+    launch_cg_iter<R, kFineSideP>(L, items, n_items, ntiles, round, kit,
                                   ev_start, ev_stop);
   else
-    launch_cg_iter<R, kCoarseSide>(L, items, n_items, per_item, round, kit,
+    launch_cg_iter<R, kCoarseSide>(L, items, n_items, ntiles, round, kit,
                                    ev_start, ev_stop);
 }
 template <class R>
@@ -2289,10 +2333,13 @@ void k_interface_accumulate(Launch L, const Geo& gf, const Window& w,
 // One workgroup per coarse node of the closed window box; nodes of the box
 // that are not interface nodes get 0.
 // ---------------------------------------------------------------------------
+// With `all`, the restriction P^T of rho + Rm over every fine node of the
+// window onto every coarse node of the closed window (the consistent
+// global problem's load).
 __global__ void __launch_bounds__(kBlock)
 restrict_kernel(Geo gf, Geo gc, Window w, const double* __restrict__ rho,
                 const double* __restrict__ Rm, double scale,
-                double* __restrict__ ext) {
+                double* __restrict__ ext, int all) {
   __shared__ double lds[kBlock / 64];
   const int bx = w.wx + 1, by = w.wy + 1;
   const int b = blockIdx.x;
@@ -2300,8 +2347,8 @@ restrict_kernel(Geo gf, Geo gc, Window w, const double* __restrict__ rho,
   const int I = w.I0 + li, J = w.J0 + lj, K = w.K0 + lk;
   Region rg;
   rg.faces = w.faces;
-  const bool gamma = on_immersed_face(rg, I, J, K, w.I0, w.I0 + w.wx, w.J0,
-                                      w.J0 + w.wy, w.K0);
+  const bool gamma = all || on_immersed_face(rg, I, J, K, w.I0, w.I0 + w.wx,
+                                             w.J0, w.J0 + w.wy, w.K0);
   const int r = w.r;
   const int span = 2 * r - 1;
   const int fi0 = r * li, fj0 = r * lj, fk0 = r * lk;
@@ -2315,7 +2362,7 @@ restrict_kernel(Geo gf, Geo gc, Window w, const double* __restrict__ rho,
       if (fi < 0 || fj < 0 || fk < 0 || fi > gf.nx - 1 || fj > gf.ny - 1 ||
           fk > gf.nz - 1)
         continue;
-      if (!fine_gamma(gf, w, fi, fj, fk)) continue;
+      if (!all && !fine_gamma(gf, w, fi, fj, fk)) continue;
       const double wt = ((double)(r - abs(di)) / (double)r) *
                         ((double)(r - abs(dj)) / (double)r) *
                         ((double)(r - abs(dk)) / (double)r);
@@ -2333,7 +2380,92 @@ void k_restrict(Launch L, const Geo& gf, const Geo& gc, const Window& w,
                 double* ext) {
   const int nb = (w.wx + 1) * (w.wy + 1) * (w.wz + 1);
   hipLaunchKernelGGL(restrict_kernel, dim3(nb), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, gf, gc, w, rho_acc, Rm, scale, ext);
+                     (hipStream_t)L.stream, gf, gc, w, rho_acc, Rm, scale, ext,
+                     0);
+}
+void k_restrict_all(Launch L, const Geo& gf, const Geo& gc, const Window& w,
+                    const double* s, double* ext) {
+  const int nb = (w.wx + 1) * (w.wy + 1) * (w.wz + 1);
+  hipLaunchKernelGGL(restrict_kernel, dim3(nb), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, gf, gc, w, (const double*)nullptr,
+                     s, 1.0, ext, 1);
+}
+
+// ---------------------------------------------------------------------------
+// The consistent global problem's load from the local solution (paper
+// Section 3: the volume terms inside the local domain and the interface
+// jump, rewritten with the local equation): on every fine node of the
+// window
+//   s = rhoc_f m_k (Tm - T0) / Dt + k_f (K1 Tavg)_k - (rho + Rm)_k / m,
+// K1 the unit-conductivity stiffness of the window's elements, Tavg =
+// (Tsum + Tm) / m the mean of the m micro-step fields, and the last term --
+// the mean of the local reactions -- on the interface nodes only.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+consistent_source_kernel(Geo gf, Window w, const double* __restrict__ Tm,
+                         const double* __restrict__ T0,
+                         const double* __restrict__ Tsum,
+                         const double* __restrict__ rho,
+                         const double* __restrict__ Rm, double inv_m,
+                         double Dt, double kf, double rhocf,
+                         double* __restrict__ src) {
+  double wts[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wts[q] = gf.w[q];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < gf.nreal;
+       t += gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(gf, t, i, j, k);
+    const int n = pidx(gf, i, j, k);
+    double v27[27];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int q = n + dz * gf.pxy + dy * gf.px + dx;
+          v27[N27(dx, dy, dz)] =
+              ((Tsum != nullptr ? Tsum[q] : 0.0) + Tm[q]) * inv_m;
+        }
+    double k8[8];
+    double nact = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+      const int ei = i - ex, ej = j - ey, ek = k - ez;
+      const bool in = ei >= 0 && ej >= 0 && ek >= 0 && ei <= gf.nx - 2 &&
+                      ej <= gf.ny - 2 && ek <= gf.nz - 2;
+      k8[e] = in ? 1.0 : 0.0;
+      nact += k8[e];
+    }
+    double v = rhocf * gf.vol8 * nact * (Tm[n] - T0[n]) / Dt +
+               kf * stencil_apply(v27, k8, wts);
+    if (fine_gamma(gf, w, i, j, k))
+      v -= ((rho != nullptr ? rho[n] : 0.0) + Rm[n]) * inv_m;
+    src[n] = v;
+  }
+}
+
+void k_consistent_source(Launch L, const Geo& gf, const Window& w,
+                         const double* Tm, const double* T0, const double* Tsum,
+                         const double* rho, const double* Rm, int m, double Dt,
+                         double kf, double rhocf, double* src) {
+  hipLaunchKernelGGL(consistent_source_kernel, dim3(grid_for(gf.nreal)),
+                     dim3(kBlock), 0, (hipStream_t)L.stream, gf, w, Tm, T0,
+                     Tsum, rho, Rm, 1.0 / m, Dt, kf, rhocf, src);
+}
+
+__global__ void accumulate_kernel(double* __restrict__ dst,
+                                  const double* __restrict__ src, long n,
+                                  int assign) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n;
+       t += (long)gridDim.x * blockDim.x)
+    dst[t] = assign ? src[t] : dst[t] + src[t];
+}
+void k_accumulate(Launch L, double* dst, const double* src, long n, int assign) {
+  hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)L.stream, dst, src, n, assign);
 }
 
 // ---------------------------------------------------------------------------
@@ -2400,30 +2532,38 @@ void k_window_shift(Launch L, const Geo& gf, const Geo& gc, const Window& wn,
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 energy_kernel(Geo g, Region rg, MatDev m, const double* __restrict__ T,
-              double* partials) {
+              double lin, double* partials) {
   __shared__ double lds[kBlock / 64];
   double acc[1] = {0.0};
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nreal;
        t += gridDim.x * blockDim.x) {
     int i, j, k;
     node_ijk(g, t, i, j, k);
-    double nact = 0.0;
+    double nact = 0.0, nfict = 0.0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-      if (elem_active(g, rg, i - ex, j - ey, k - ez)) nact += 1.0;
+      if (elem_active(g, rg, i - ex, j - ey, k - ez)) {
+        if (elem_fictitious(rg, i - ex, j - ey, k - ez))
+          nfict += 1.0;
+        else
+          nact += 1.0;
+      }
     }
-    if (nact > 0.0) acc[0] += g.vol8 * nact * enthalpy(T[pidx(g, i, j, k)], m);
+    const double Tn = T[pidx(g, i, j, k)];
+    if (nact > 0.0) acc[0] += g.vol8 * nact * (enthalpy(Tn, m) + lin * Tn);
+    if (nfict > 0.0) acc[0] += g.vol8 * nfict * rg.rhocf * Tn;
   }
   block_sum<1>(acc, lds);
   if (threadIdx.x == 0) partials[kPartGen * kMaxBlocks + blockIdx.x] = acc[0];
 }
 
 void k_energy(Launch L, const Geo& g, const Region& rg, const MatDev& m,
-              const double* T, double* slot, int assign, double* partials) {
+              const double* T, double* slot, int assign, double* partials,
+              double lin) {
   const int nb = grid_for(g.nreal);
   hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, g, rg, m, T, partials);
+                     (hipStream_t)L.stream, g, rg, m, T, lin, partials);
   finalize_sum(L, partials + kPartGen * kMaxBlocks, nb, 1.0, slot, assign);
 }
 

@@ -75,6 +75,8 @@ struct Layout {
   size_t off_c[23], off_fd[10], off_fcg[12];
   size_t off_ccg32[12];   // FP32 coarse CG arrays (mixed composite solves)
   bool ccg32 = false;
+  size_t off_fx[2];       // consistent formulation: micro-step field sum,
+  bool fx = false;        // load from the local solution (fine)
   size_t off_scal, off_items, off_micro, off_ledger, off_partials, off_tpart,
       off_tpart2, off_gidx, off_gbuf;
   int tstride;   // per-tile partial slots per region (both levels)
@@ -109,6 +111,11 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   for (int a = 0; a < kFineCG; ++a) {
     L.off_ccg32[a] = off;
     if (L.ccg32) off += align_up((size_t)L.gc.npad * 4);
+  }
+  L.fx = op.coupling == TL_COUPLE_CONSISTENT;
+  for (int a = 0; a < 2; ++a) {
+    L.off_fx[a] = off;
+    if (L.fx) off += fbytes;
   }
   L.off_scal = off; off += align_up(2 * sizeof(LevelScalars));
   L.off_items = off; off += align_up(2 * sizeof(SolveItem));
@@ -348,7 +355,7 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
                            hipMemcpyHostToDevice, B.stream),
             "hipMemcpyAsync(scalars)");
   std::vector<int> act, built, round_iters;
-  int round = 0, per_a = 0, per_c = 0, per_p = 0, max_gamma = 0;
+  int round = 0, tiles_a = 0, tiles_c = 0, per_p = 0, max_gamma = 0;
   for (;;) {
     act.clear();
     for (int u = 0; u < nu; ++u)
@@ -366,8 +373,8 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
           max_gamma = std::max(max_gamma, jobs[2 * u + 1]->cpl.ngamma);
         }
       }
-      per_a = item_tile_blocks(most, na);
-      per_c = item_tile_blocks(most_c, na);
+      tiles_a = most;     // tiles of the largest item: each kernel sizes
+      tiles_c = most_c;   // its grid from its own residency
       // the prolongation: about four interface nodes per thread
       long most_face = 1;
       if (paired)
@@ -413,17 +420,17 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
     const SolveItem* ci = B.d_items + na;
     for (int rr = 0; rr < n_rounds; ++rr, ++round) {
       if (!paired) {
-        k_residual_batched<R>(B.L, fi, na, per_a, round);
-        k_cg_start_batched<R>(B.L, fi, na, per_a, round);
+        k_residual_batched<R>(B.L, fi, na, tiles_a, round);
+        k_cg_start_batched<R>(B.L, fi, na, tiles_a, round);
       } else {
         if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 0, 0);
-        k_residual_pair<R>(B.L, fi, na, per_a, round, fside);
+        k_residual_pair<R>(B.L, fi, na, tiles_a, round, fside);
         k_couple_gather<R>(B.L, ci, na, max_gamma, round, 0, 0);
-        k_residual_pair<R>(B.L, ci, na, per_c, round, kCoarseSide);
+        k_residual_pair<R>(B.L, ci, na, tiles_c, round, kCoarseSide);
         if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 1, 0);
-        k_cg_start_pair<R>(B.L, fi, na, per_a, round, fside);
+        k_cg_start_pair<R>(B.L, fi, na, tiles_a, round, fside);
         k_couple_gather<R>(B.L, ci, na, max_gamma, round, 1, 0);
-        k_cg_start_pair<R>(B.L, ci, na, per_c, round, kCoarseSide);
+        k_cg_start_pair<R>(B.L, ci, na, tiles_c, round, kCoarseSide);
       }
       for (int k = 0; k < n_launch; ++k) {
         // sampled event timing covers the plain CG kernel (not the pairs')
@@ -433,13 +440,13 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
         void* e0 = timed ? (void*)prof->ev[2 * prof->used] : nullptr;
         void* e1 = timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr;
         if (!paired) {
-          k_cg_iter_batched<R>(B.L, fi, na, per_a, round, k, e0, e1);
+          k_cg_iter_batched<R>(B.L, fi, na, tiles_a, round, k, e0, e1);
         } else {
           if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 2, k);
-          k_cg_iter_pair<R>(B.L, fi, na, per_a, round, k, fside, nullptr,
+          k_cg_iter_pair<R>(B.L, fi, na, tiles_a, round, k, fside, nullptr,
                             nullptr);
           k_couple_gather<R>(B.L, ci, na, max_gamma, round, 2, k);
-          k_cg_iter_pair<R>(B.L, ci, na, per_c, round, k, kCoarseSide,
+          k_cg_iter_pair<R>(B.L, ci, na, tiles_c, round, k, kCoarseSide,
                             nullptr, nullptr);
         }
         if (timed) {
@@ -643,6 +650,11 @@ struct tl_sim {
   // fpp: the micro step before fprev (extrapolated initial guesses)
   double *fstate, *fprev, *fcur, *ftrial, *falt, *fR, *fF, *rho, *fpp;
   double *cHold, *fHold;   // H(T_old) of the level's current solve
+  // consistent formulation: sum of the micro-step fields of the macro step,
+  // the load from the local solution, and the global problem's constant
+  // coefficients inside the window
+  double *fsum = nullptr, *fsrc = nullptr;
+  double kf = 0.0, rhocf = 0.0;
   CGBufs<double> fcg64;
   CGBufs<float> fcg32;
   LevelScalars *sc_c, *sc_f;
@@ -693,6 +705,18 @@ Region region_all() {
   Region rg{};
   rg.mode = kAllBottom;
   return rg;
+}
+// the consistent global problem: every coarse element, the window's with
+// the global problem's own coefficients
+Region region_fict(const tl_sim* s) {
+  Region rg = region_outside(s);
+  rg.mode = kFictitious;
+  rg.kf = s->kf;
+  rg.rhocf = s->rhocf;
+  return rg;
+}
+bool consistent(const tl_sim* s) {
+  return s->opts.coupling == TL_COUPLE_CONSISTENT;
 }
 // top-surface loss: convection and radiation on the fine level, convection
 // only on the coarse one (paper Section 2)
@@ -869,6 +893,14 @@ void energy_now(tl_sim* s, double* slot) {
   if (alternate(s)) {   // the global problem's own energy
     k_energy(s->L, s->gc, region_all(), s->mat_global, s->Tn, slot, 1,
              s->partials);
+    return;
+  }
+  if (consistent(s)) {
+    // plus the energy the global coefficients hold inside the window beyond
+    // the local field's: rhoc_f (sum m_in T+ - sum m_k T-)
+    k_energy(s->L, s->gc, region_fict(s), s->mat, s->Tn, slot, 1, s->partials);
+    k_energy(s->L, s->gf, region_window(s), s->mat, s->fstate, slot, 0,
+             s->partials, -s->rhocf);
     return;
   }
   k_energy(s->L, s->gc, region_outside(s), s->mat, s->Tn, slot, 1,
@@ -1260,6 +1292,10 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
           Told = st.s->fprev;
         },
         prof);
+    // the consistent formulation's sum of the micro-step fields
+    for (StepState* st : list)
+      if (!st->failed && consistent(st->s))
+        k_accumulate(st->s->L, st->s->fsum, st->s->fcur, st->s->gf.npad, j == 1);
     // after it, in one launch: reactions on the interface, bottom and
     // top-surface heat flows (the second half of the item table: its first
     // half may still be in flight to the device)
@@ -1309,7 +1345,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     tl_sim* s = st->s;
     if (alternate(s)) continue;
     fine_load(s, st->n, st->m, st->dt);
-    if (s->opts.coupling == TL_COUPLE_DN)   // the interface trace
+    if (s->opts.coupling == TL_COUPLE_DN || consistent(s))   // interface trace
       k_copy(s->L, s->lam, s->Tpred, s->gc.npad);
     if (st->m >= 2)   // extrapolated from the last two micro steps
       k_extrapolate(s->L, s->fcur, s->fprev, s->fpp, s->gf.npad);
@@ -1370,16 +1406,29 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     for (StepState* st : list) {
       if (st->failed) continue;
       tl_sim* s = st->s;
-      k_restrict(s->L, s->gf, s->gc, s->win, st->m > 1 ? s->rho : nullptr, s->fR,
-                 -1.0 / st->m, s->ext);
-      k_inject(s->L, s->gf, s->gc, s->win, s->fcur, s->ccur);
+      if (consistent(s)) {
+        // the global problem on the whole plate, loaded inside the window
+        // by P^T of the load from the local solution; no injection
+        k_consistent_source(s->L, s->gf, s->win, s->fcur, s->fstate,
+                            st->m > 1 ? s->fsum : nullptr,
+                            st->m > 1 ? s->rho : nullptr, s->fR, st->m, st->Dt,
+                            s->kf, s->rhocf, s->fsrc);
+        k_fill(s->L, s->ext, 0.0, s->gc.npad);
+        k_restrict_all(s->L, s->gf, s->gc, s->win, s->fsrc, s->ext);
+      } else {
+        k_restrict(s->L, s->gf, s->gc, s->win, st->m > 1 ? s->rho : nullptr,
+                   s->fR, -1.0 / st->m, s->ext);
+        k_inject(s->L, s->gf, s->gc, s->win, s->fcur, s->ccur);
+      }
       clist.push_back(st);
     }
     batch_solve<double>(
         B, clist, false,
         [](StepState& st) {
-          return make_job<double>(st.s, false, region_outside(st.s), st.Dt,
-                                  st.s->Tn, st.s->Fout, st.s->ext);
+          return make_job<double>(
+              st.s, false,
+              consistent(st.s) ? region_fict(st.s) : region_outside(st.s),
+              st.Dt, st.s->Tn, st.s->Fout, st.s->ext);
         },
         nullptr);
     // interface residuals lambda' - lambda, read back for all at once
@@ -1536,8 +1585,11 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
   if (op->newton_max < 1 || op->cg_max < 1 || op->dn_max < 1)
     return fail(TL_EINVAL, "iteration caps must be >= 1");
   if (op->coupling != TL_COUPLE_DN && op->coupling != TL_COUPLE_COMPOSITE &&
-      op->coupling != TL_COUPLE_ALTERNATE)
+      op->coupling != TL_COUPLE_ALTERNATE && op->coupling != TL_COUPLE_CONSISTENT)
     return fail(TL_EINVAL, "unknown coupling");
+  if (!finite_all({ma->k_fict, ma->rhoc_fict}) || ma->k_fict < 0 ||
+      ma->rhoc_fict < 0)
+    return fail(TL_EINVAL, "k_fict and rhoc_fict must be finite and >= 0");
   return TL_OK;
 }
 
@@ -1635,7 +1687,7 @@ tl_status batch_set_profiling(BatchTables* bt, int sample_every) {
   if (sample_every < 0) return fail(TL_EINVAL, "sample_every must be >= 0");
   if (sample_every > 0 && !b->prof.ev[0]) {
     for (int q = 0; q < 2 * kProfPairs; ++q)
-      HIP_OK(hipEventCreate(&b->prof.ev[q]));
+      HIP_OK(hipEventCreateWithFlags(&b->prof.ev[q], hipEventDisableSystemFence));
   }
   b->prof.every = sample_every;
   b->prof.count = 0;
@@ -1762,6 +1814,16 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   m.sens_full = 0.5 * (m.c_lo + m.c_hi) * (m.T_hi - m.T_lo);
   s->mat_global = m;
   if (opts->coupling == TL_COUPLE_ALTERNATE) s->mat_global.latent = 0.0;
+  {
+    // the consistent formulation's coefficients inside the window: given,
+    // or the law's conductivity and rho c at T_init
+    const double Ti = std::min(std::max(material->T_init, m.T_lo), m.T_hi);
+    s->kf = material->k_fict > 0 ? material->k_fict
+                                 : m.k_lo + m.kslope * (Ti - m.T_lo);
+    s->rhocf = material->rhoc_fict > 0
+                   ? material->rhoc_fict
+                   : m.rho * (m.c_lo + m.cslope * (Ti - m.T_lo));
+  }
   s->lay = lay;
   s->gc = lay.gc;
   s->gf = lay.gf;
@@ -1793,6 +1855,10 @@ static tl_status create_sim(const tl_mesh* mesh, const tl_material* material,
   s->falt = FD(4); s->fR = FD(5); s->fF = FD(6); s->rho = FD(7);
   s->fpp = FD(9);
   s->fHold = FD(8);
+  if (lay.fx) {
+    s->fsum = (double*)(s->ws + lay.off_fx[0]);
+    s->fsrc = (double*)(s->ws + lay.off_fx[1]);
+  }
   auto FC = [&](int a) { return (void*)(s->ws + lay.off_fcg[a]); };
   s->fcg64 = cgb64(FC);
   s->fcg32 = CGBufs<float>{(float*)FC(0), (float*)FC(1), (float*)FC(2),
@@ -2173,7 +2239,7 @@ tl_status tl_set_profiling(tl_sim* s, int sample_every) {
   if (sample_every < 0) return fail(TL_EINVAL, "sample_every must be >= 0");
   if (sample_every > 0 && !s->prof.ev[0]) {
     for (int q = 0; q < 2 * kProfPairs; ++q)
-      HIP_OK(hipEventCreate(&s->prof.ev[q]));
+      HIP_OK(hipEventCreateWithFlags(&s->prof.ev[q], hipEventDisableSystemFence));
   }
   s->prof.every = sample_every;
   s->prof.count = 0;

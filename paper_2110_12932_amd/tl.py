@@ -37,7 +37,8 @@ class tl_material(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("rho", "T_lo", "T_hi", "c_lo", "c_hi", "k_lo", "k_hi",
                                           "latent", "T_sol", "T_liq", "sharpness")] + \
                [("pc_kind", C.c_int), ("T_init", C.c_double), ("T_bottom", C.c_double),
-                ("h_conv", C.c_double), ("emissivity", C.c_double), ("T_amb", C.c_double)]
+                ("h_conv", C.c_double), ("emissivity", C.c_double), ("T_amb", C.c_double),
+                ("k_fict", C.c_double), ("rhoc_fict", C.c_double)]
 
 
 class tl_track(C.Structure):
@@ -183,7 +184,7 @@ def to_mesh(m):
 def to_material(m):
     return tl_material(m.rho, m.T_lo, m.T_hi, m.c_lo, m.c_hi, m.k_lo, m.k_hi, m.latent,
                        m.T_sol, m.T_liq, m.sharpness, m.pc_kind, m.T_init, m.T_bottom,
-                       m.h_conv, m.emissivity, m.T_amb)
+                       m.h_conv, m.emissivity, m.T_amb, m.k_fict, m.rhoc_fict)
 
 
 def to_scan(s):

@@ -70,7 +70,7 @@ def _check_vs_oracle(wl, n_macro, tol, coupling):
     assert st["window_moves"] == orc.stats["moves"]
     if coupling == W.COMPOSITE:   # one solve per macro step
         assert st["dn_iters"] == n_macro
-    elif coupling == W.DN:
+    elif coupling in (W.DN, W.CONSISTENT):
         assert st["dn_iters"] >= n_macro
     else:                         # no correction to iterate
         assert st["dn_iters"] == 0
@@ -269,3 +269,47 @@ def test_small_cg_budget(coupling):
     wl = W.single_track_1mm()
     wl = replace(wl, options=replace(wl.options, cg_max=2))
     _check_vs_oracle(wl, 8, 1e-9, coupling)
+
+
+# the consistent global formulation of Section 3: the global problem on
+# every coarse element, with constant coefficients of its own inside the
+# window (the law's values at T_init, or given ones), loaded there by the
+# local solution
+FICT = [pytest.param(0.0, 0.0, id="law-at-T_init"), pytest.param(50.0, 2.0e6, id="given")]
+
+
+@pytest.mark.parametrize("k_fict, rhoc_fict", FICT)
+@pytest.mark.parametrize("prec, tol", [(W.FP64, 1e-9), (W.MIXED, 1e-6)])
+def test_consistent_formulation_single_track(prec, tol, k_fict, rhoc_fict):
+    wl = W.single_track_1mm(prec)
+    wl = replace(wl, material=replace(wl.material, h_conv=1.0e4, k_fict=k_fict,
+                                      rhoc_fict=rhoc_fict))
+    _check_vs_oracle(wl, 12, tol, W.CONSISTENT)
+
+
+@pytest.mark.parametrize("name", ["r1m1", "r3m2", "fulldepth", "corner"])
+def test_consistent_formulation_small_cases(name):
+    wl = W.small_cases()[name]
+    wl = replace(wl, material=replace(wl.material, k_fict=50.0, rhoc_fict=2.0e6))
+    _check_vs_oracle(wl, wl.n_macro, 1e-9, W.CONSISTENT)
+
+
+def test_consistent_formulation_volume_sources():
+    wl = W.single_track_3d()
+    _check_vs_oracle(wl, wl.n_macro, 1e-9, W.CONSISTENT)
+
+
+def test_consistent_equal_levels_is_single_level():
+    """r = 1, m = 1: the global field is the single-level solution on the
+    whole plate, inside the window too (Section 3's stronger consistency)."""
+    wl = W.small_cases()["r1m1"]
+    wl = replace(wl, material=replace(wl.material, k_fict=50.0, rhoc_fict=2.0e6))
+    Tc, Tf, _, _, st = _run(_with(wl, W.CONSISTENT), wl.n_macro)
+    ref = oracle.twolevel.single_level_run(oracle.twolevel.coarse_grid(wl.mesh), wl.material,
+                                           wl.scan, wl.options.dt_coarse, wl.n_macro,
+                                           tol=1e-11)[-1]
+    c = oracle.twolevel.coarse_grid(wl.mesh)
+    e = rel_maxerr(Tc, ref.reshape(c.shape))
+    say("  consistent r = 1, m = 1 vs single level:", e, "moves", st["window_moves"])
+    assert e <= 1e-9
+    assert st["window_moves"] >= 1

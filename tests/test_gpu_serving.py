@@ -88,9 +88,9 @@ def test_result_same_alone_and_in_mix():
 
 
 def test_heterogeneous_mix_equals_alone():
-    """Requests with different two-level couplings, laser models and
-    precisions share the server's launches: each equals its own run through
-    a plain handle."""
+    """Requests with different two-level couplings (the consistent global
+    formulation among them), laser models and precisions share the server's
+    launches: each equals its own run through a plain handle."""
     base = W.single_track_1mm()
     reqs = {
         "dn": replace(base, name="dn", n_macro=4,
@@ -100,8 +100,11 @@ def test_heterogeneous_mix_equals_alone():
         "vol": replace(W.single_track_3d(), n_macro=3),
         "mixloss": replace(W.single_track_1mm(W.MIXED), name="mixloss", n_macro=4,
                            material=replace(base.material, h_conv=2e4, emissivity=0.8)),
+        "cons": replace(base, name="cons", n_macro=4,
+                        options=replace(base.options, coupling=W.CONSISTENT),
+                        material=replace(base.material, k_fict=50.0, rhoc_fict=2.0e6)),
     }
-    sv = tl.Server(_pool_bytes(reqs.values()), max_slots=4)
+    sv = tl.Server(_pool_bytes(reqs.values()), max_slots=5)
     ids = {k: sv.submit(w) for k, w in reqs.items()}
     log = _drain(sv)
     assert max(a for a, _, _ in log) >= 3
