@@ -70,6 +70,9 @@ def parse():
                     help="time every Nth fine operator launch with HIP events (0: off)")
     ap.add_argument("--k2-sweep", action="store_true",
                     help="also time the bare operator apply at several shapes")
+    ap.add_argument("--sync-probe", action="store_true",
+                    help="also measure a device-wide barrier against a kernel boundary "
+                         "between dependent sweeps, at the served and the large-window scale")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB buffer 3 times (known-size "
                          "reference for HBM byte counters)")
@@ -193,6 +196,31 @@ def k2_sweep(tl, W, torch):
                     "us_per_launch": round(us, 3), "GB/s": round(nbytes / (us * 1e-6) / 1e9, 1),
                     "frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
     del src, dst
+    return out
+
+
+def sync_probe(tl, torch):
+    """Per-sweep time of `rounds` dependent sweeps with one launch per sweep
+    against one cooperative launch with a grid barrier per sweep, over the
+    bytes one fine CG launch moves: the served batch (64 requests of
+    81 x 49 x 25 nodes, 13 FP32 arrays) and the large window (121 x 81 x 31
+    nodes, 13 FP64 arrays)."""
+    out = []
+    ctl = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    for name, nbytes in (("served batch, FP32", 13 * 4 * 64 * 81 * 49 * 25),
+                         ("large window, FP64", 13 * 8 * 121 * 81 * 31)):
+        n = nbytes // 16       # a sweep reads and writes each double: 16 B
+        data = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for blocks in (256, 1024):
+            row = {"data": name, "bytes_per_sweep": 16 * n, "blocks": blocks}
+            for barrier in (0, 1):
+                tl.tl_op_sync_probe(blocks, 2, barrier, data, ctl)     # warm-up
+                t1 = tl.tl_op_sync_probe(blocks, 1, barrier, data, ctl)
+                t21 = tl.tl_op_sync_probe(blocks, 21, barrier, data, ctl)
+                key = "barrier" if barrier else "launches"
+                row[key + "_us_per_sweep"] = round((t21 - t1) / 20, 2)
+            out.append(row)
+        del data
     return out
 
 
@@ -465,6 +493,8 @@ def main():
         out["calibrate_copy_bytes"] = n * 4
     if args.k2_sweep:
         out["k2_sweep"] = k2_sweep(tl, W, torch)
+    if args.sync_probe:
+        out["sync_probe"] = sync_probe(tl, torch)
     if not args.no_serving and args.workload == DEFAULT_WORKLOAD:
         out["serving"] = serving_summary(args, tl, W, torch)
     if not args.no_cpu_baseline:

@@ -51,6 +51,26 @@ tl_status tl_op_apply(const tl_grid* grid, int precision, const void* d,
                       const void* kappa, const void* v, void* y, int repeat,
                       void* hip_stream);
 
+/* Cost of a device-wide synchronisation between dependent steps on this
+ * GPU, for the choice between one launch per step and a persistent kernel
+ * that synchronises inside (the batched fine phase of the paper's local
+ * problems, Section 4, runs one launch per step).  `rounds` dependent sweeps
+ * over the n doubles of `data` (device memory; each entry is mixed with one
+ * 4099 entries on, so a sweep reads other workgroups' results of the one
+ * before) run on `blocks` workgroups of 256 threads: barrier = 0 launches
+ * one kernel per sweep; barrier = 1 runs all sweeps in one cooperative
+ * launch with a grid barrier after each (release arrival, bounded relaxed
+ * polling, acquire fence).  ctl: >= 1024 bytes of device memory the call
+ * zero-fills and uses for the barrier.  *us_out receives the elapsed time
+ * of the queued work in microseconds (HIP events on hip_stream).  Errors:
+ * TL_EINVAL for null pointers, n < 1, rounds < 1, blocks < 1, or a barrier
+ * run with more workgroups than the device holds at once (all must be
+ * resident); TL_EDEVICE if a HIP call fails or the barrier's bounded wait
+ * ran out. */
+tl_status tl_op_sync_probe(int blocks, int rounds, int barrier, double* data,
+                           size_t n, void* ctl, double* us_out,
+                           void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -397,6 +397,14 @@ void k_consistent_source(Launch L, const Geo& gf, const Window& w,
                          const double* Tm, const double* T0, const double* Tsum,
                          const double* rho, const double* Rm, int m, double Dt,
                          double kf, double rhocf, double* src);
+// Synchronisation-cost probe: `rounds` dependent sweeps over n doubles on
+// `blocks` workgroups, one launch per sweep (barrier = 0) or one cooperative
+// launch with a grid barrier between sweeps (barrier = 1; blocks must not
+// exceed sync_probe_resident()).  ctl: >= 1 KiB of zeroed device memory
+// (counter, generation word, timeout flag at ctl[128]).
+int sync_probe_resident();
+int k_sync_probe(Launch L, int blocks, int rounds, int barrier, double* data,
+                 long n, unsigned* ctl);   // returns a hipError_t
 // dst = src (assign) or dst += src, over n entries.
 void k_accumulate(Launch L, double* dst, const double* src, long n, int assign);
 

@@ -435,6 +435,11 @@ __device__ inline Tile tile_of(int b, int ntx, int nty) {
   return t;
 }
 
+// Tile b of a batched item (numbered x fastest, then y, z: each XCD's
+// contiguous chunk is a layer across z).
+__device__ inline Tile tile_at(const SolveItem& it, int b) {
+  return tile_of(b, it.ntx, it.nty);
+}
 // padded index of halo entry h of the tile, or -1 when it lies past the
 // ghost layer of the grid
 __device__ inline int halo_index(const Geo& g, const Tile& t, int h) {
@@ -900,8 +905,9 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   for (int q = 0; q < 8; ++q) w[q] = g.w[q];
   double* __restrict__ tp = it.tpart;
   const int ts = it.tstride;
-  // a tile's global inputs, loaded into registers in one batch: the next
-  // tile's while this tile's elements and nodes are computed
+  // a tile's global inputs, loaded into registers in one batch at the top
+  // of its turn (holding the next tile's during this one's work would take
+  // the kernel from 3 to 2 waves per SIMD)
   double hT[HPT];
   R hd[HPT];
   // o_H: T_old in the first round (H(T_old) is formed and kept), H(T_old)
@@ -941,10 +947,10 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     }
   };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
-  if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
     double acc[3] = {0.0, 0.0, 0.0};  // |R_free|^2, max|alpha dx|, r.z
-    const Tile t = tile_of(tile, it.ntx, it.nty);
+    const Tile t = tile_at(it, tile);
+    load_tile(t);
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     const bool active = i < g.nx && j < g.ny && k < g.nz;
     const int n = active ? pidx(g, i, j, k) : 0;
@@ -957,8 +963,6 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         t_s[h] = dx != nullptr ? trial_T(hT[q], alpha * (double)hd[q], m) : hT[q];
     }
     __syncthreads();
-    if (tile + tr.step < tr.last)
-      load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
     // conductivity of each element of the tile at its mean trial temperature
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -983,16 +987,10 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     }
     __syncthreads();
     if (active) {
-      double T27[27];
-#pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-          for (int dxx = -1; dxx <= 1; ++dxx)
-            T27[N27(dxx, dy, dz)] =
-                t_s[(t.tz + 1 + dz) * (HX * HY) + (t.ty + 1 + dy) * HX +
-                    (t.tx + 1 + dxx)];
+      const int c0 = (t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1);
+      auto TV = [&](int dxx, int dy, int dz) {
+        return t_s[c0 + dz * (HX * HY) + dy * HX + dxx];
+      };
       double k8[8];
       double nact = 0.0, nfict = 0.0;
       double diagK = 0.0;
@@ -1010,7 +1008,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         k8[e] = ke;
         diagK += ke;
       }
-      const double Tn = T27[13];
+      const double Tn = t_s[c0];
       const double mass = g.vol8 * nact;
       double Hn, dHn;
       enthalpy_and_slope(Tn, m, Hn, dHn);
@@ -1019,7 +1017,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         Ho = enthalpy(H_old, m);   // H_old holds T_old here
         it.Hold[n] = Ho;
       }
-      double Rn = mass * (Hn - Ho) / it.tau + stencil_apply(T27, k8, w) - F_n;
+      double Rn = mass * (Hn - Ho) / it.tau + stencil_elementwise(TV, k8, w) - F_n;
       // elements with the consistent global problem's own coefficients:
       // their lumped mass takes rhoc_f (T - T_old) / tau
       const double mfict = g.vol8 * nfict * it.rg.rhocf;
@@ -1192,7 +1190,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   bool run = false;
   if (nx.status == kRunning) {
     // the first tile's inputs are in flight during the reduction
-    if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
+    if (tr.first < tr.last) load_tile(tile_at(it, tr.first));
     // residual reductions over the item's tiles (every workgroup, same
     // order)
     const Couple& cp = it.cp;
@@ -1282,7 +1280,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
     R acc[2] = {(R)0, (R)0};
-    const Tile t = tile_of(tile, it.ntx, it.nty);
+    const Tile t = tile_at(it, tile);
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
@@ -1298,7 +1296,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int n = o_n;
     const R r_own = o_r, d_own = o_d;
     if (tile + tr.step < tr.last)
-      load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
+      load_tile(tile_at(it, tile + tr.step));
     if (active) {
       const R un = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
       R wn = d_own * un + stencil_lds(t, u_s, k_s, wts);
@@ -1355,10 +1353,11 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   const R* __restrict__ dinv = (const R*)it.dinv;
   // Every global input of a tile is loaded into registers in one batch:
   // the halo of r, w, s_{k-1}, Dinv (for u_{k+1}), the element
-  // conductivities, and the node's own d, p, x, s_{k-1}.  The first tile's
-  // batch is issued before the scalar reduction, each later tile's while the
-  // previous tile's stencil is computed, so a workgroup waits on memory
-  // about once per tile.
+  // conductivities, and the node's own d, p, x, s_{k-1}.  In FP32 the first
+  // tile's batch is issued before the scalar reduction, each later tile's
+  // while the previous tile's stencil is computed, so a workgroup waits on
+  // memory about once per tile; in FP64 each batch is issued at the top of
+  // its tile's turn (see below).
   R hr[HPT], hw[HPT], hs[HPT], hd[HPT], kr[EPT];
   R o_r = (R)0, o_w = (R)0, o_di = (R)0, o_d = (R)0, o_s = (R)0, o_p = (R)0,
     o_x = (R)0;
@@ -1422,7 +1421,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     }
   };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
-  if (tr.first < tr.last) load_tile(tile_of(tr.first, it.ntx, it.nty));
+  if constexpr (sizeof(R) == 4)
+    if (tr.first < tr.last) load_tile(tile_at(it, tr.first));
   // gamma_k, delta_k from the previous kernel's partials (CG start or
   // iteration k-1), held in the region pair this kernel does not write
   const int rd = (kit & 1) ? kTCG2 : kTCG;
@@ -1475,7 +1475,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
     R acc[2] = {(R)0, (R)0};
-    const Tile t = tile_of(tile, it.ntx, it.nty);
+    const Tile t = tile_at(it, tile);
+    if constexpr (sizeof(R) == 8) load_tile(t);
     // u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
@@ -1492,8 +1493,13 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int n = o_n;
     const R r_own = o_r, w_own = o_w, di_own = o_di, d_own = o_d,
             s_prev = o_s, p_own = o_p, x_own = o_x;
-    if (tile + tr.step < tr.last)
-      load_tile(tile_of(tile + tr.step, it.ntx, it.nty));
+    // FP32: the next tile's loads fly during this tile's stencil (the
+    // first tile's during the scalar reduction); FP64 would need 164
+    // registers for that (3 waves per SIMD) and loads each tile at the top
+    // of its turn instead, at 4 waves per SIMD
+    if constexpr (sizeof(R) == 4)
+      if (tile + tr.step < tr.last)
+        load_tile(tile_at(it, tile + tr.step));
     // the node's own recurrences and w_{k+1} = J u_{k+1}
     if (active) {
       // (a slaved interface node of a fine side keeps zero recurrences: its
@@ -1731,6 +1737,7 @@ int grid_tiles(const Geo& g, int& ntx, int& nty) {
   tiles_of(g, ntx, nty, ntz);
   return ntx * nty * ntz;
 }
+
 // Workgroups of a kernel that the device holds at once: the occupancy
 // limit per compute unit (set by its registers and LDS) times the compute
 // units.  Taken once per kernel.
@@ -2466,6 +2473,84 @@ __global__ void accumulate_kernel(double* __restrict__ dst,
 void k_accumulate(Launch L, double* dst, const double* src, long n, int assign) {
   hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
                      (hipStream_t)L.stream, dst, src, n, assign);
+}
+
+// ---------------------------------------------------------------------------
+// Cost of a device-wide synchronisation (tl_op_sync_probe): `rounds` sweeps
+// over n doubles (each entry mixed with one a few thousand entries away, so
+// a sweep depends on other workgroups' results of the sweep before), either
+// one kernel launch per sweep or all sweeps in one cooperative launch with a
+// grid barrier between them.  The barrier: every workgroup arrives with a
+// release increment of a counter, the last one resets it and bumps a
+// generation word, the others poll it with relaxed loads and take one
+// acquire fence; polling is bounded and a timeout sets *err instead of
+// hanging.
+// ---------------------------------------------------------------------------
+constexpr unsigned kSyncSpinMax = 1u << 22;
+
+__device__ inline void grid_barrier(unsigned* cnt, unsigned* gen, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g =
+        __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    if (a == gridDim.x - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSyncSpinMax) {
+          *err = 1;
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  __syncthreads();
+}
+
+template <int kBarrier>
+__global__ void __launch_bounds__(kBlock)
+sync_probe_kernel(double* __restrict__ data, long n, int rounds,
+                  unsigned* cnt, unsigned* gen, int* err) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (int r = 0; r < rounds; ++r) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += stride) {
+      const long j = i + 4099 < n ? i + 4099 : i + 4099 - n;
+      data[i] = 0.5 * data[i] + 0.25 * data[j] + 1.0;
+    }
+    if (kBarrier) grid_barrier(cnt, gen, err);
+  }
+}
+
+int sync_probe_resident() {
+  static const int res = resident_blocks(sync_probe_kernel<1>);
+  return res;
+}
+
+int k_sync_probe(Launch L, int blocks, int rounds, int barrier, double* data,
+                 long n, unsigned* ctl) {
+  if (!barrier) {
+    for (int r = 0; r < rounds; ++r)
+      hipLaunchKernelGGL(sync_probe_kernel<0>, dim3(blocks), dim3(kBlock), 0,
+                         (hipStream_t)L.stream, data, n, 1, ctl, ctl + 64,
+                         (int*)(ctl + 128));
+    return hipGetLastError();
+  }
+  unsigned* gen = ctl + 64;
+  int* err = (int*)(ctl + 128);
+  void* args[] = {&data, &n, &rounds, &ctl, &gen, &err};
+  return hipLaunchCooperativeKernel((void*)sync_probe_kernel<1>, dim3(blocks),
+                                   dim3(kBlock), args, 0,
+                                   (hipStream_t)L.stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -2317,6 +2317,47 @@ tl_status tl_op_unpack(const tl_grid* grid, int kind, int elem_bytes,
   return TL_OK;
 }
 
+tl_status tl_op_sync_probe(int blocks, int rounds, int barrier, double* data,
+                           size_t n, void* ctl, double* us_out,
+                           void* hip_stream) {
+  if (!data || !ctl || !us_out) return fail(TL_EINVAL, "null argument");
+  if (n < 1 || rounds < 1 || blocks < 1)
+    return fail(TL_EINVAL, "n, rounds and blocks must be >= 1");
+  if (barrier && blocks > sync_probe_resident())
+    return fail(TL_EINVAL, "a barrier run needs all workgroups resident: at most " +
+                               std::to_string(sync_probe_resident()));
+  const Launch L{hip_stream};
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(TL_EDEVICE, "hipEventCreate failed");
+  }
+  tl_status res = TL_OK;
+  int err = 0;
+  float ms = 0.0f;
+  k_zero_bytes(L, ctl, 1024);
+  hipError_t e = hipEventRecord(e0, st);
+  if (e == hipSuccess)
+    e = (hipError_t)k_sync_probe(L, blocks, rounds, barrier, data, (long)n,
+                                 (unsigned*)ctl);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess)
+    e = hipMemcpy(&err, (char*)ctl + 128 * sizeof(unsigned), sizeof(int),
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess)
+    res = fail(TL_EDEVICE, std::string("sync probe: ") + hipGetErrorString(e));
+  else if (err)
+    res = fail(TL_EDEVICE, "sync probe: the barrier's bounded wait ran out");
+  *us_out = 1e3 * ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
+}
+
 tl_status tl_op_apply(const tl_grid* grid, int precision, const void* d,
                       const void* kappa, const void* v, void* y, int repeat,
                       void* hip_stream) {

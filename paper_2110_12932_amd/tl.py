@@ -92,7 +92,8 @@ SYMBOLS = ["tl_workspace_bytes", "tl_create", "tl_create_static", "tl_step", "tl
            "tl_server_overhead_bytes", "tl_server_create", "tl_server_submit",
            "tl_server_tick", "tl_server_result", "tl_server_release", "tl_server_destroy",
            "tl_server_set_profiling", "tl_server_get_profile",
-           "tl_op_padded_size", "tl_op_pack", "tl_op_unpack", "tl_op_apply"]
+           "tl_op_padded_size", "tl_op_pack", "tl_op_unpack", "tl_op_apply",
+           "tl_op_sync_probe"]
 
 _lib = None
 
@@ -167,6 +168,9 @@ def load():
         f.argtypes = [C.POINTER(tl_grid), C.c_int, C.c_int, vp, vp, vp]
     lib.tl_op_apply.restype = C.c_int
     lib.tl_op_apply.argtypes = [C.POINTER(tl_grid), C.c_int, vp, vp, vp, vp, C.c_int, vp]
+    lib.tl_op_sync_probe.restype = C.c_int
+    lib.tl_op_sync_probe.argtypes = [C.c_int, C.c_int, C.c_int, vp, sz, vp,
+                                     C.POINTER(C.c_double), vp]
     _lib = lib
     return lib
 
@@ -495,3 +499,14 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tl_op_sync_probe(blocks, rounds, barrier, data, ctl, stream=None):
+    """data: torch float64 CUDA tensor; ctl: torch uint8 CUDA tensor of
+    >= 1024 bytes.  Returns the elapsed microseconds."""
+    us = C.c_double()
+    _check(load().tl_op_sync_probe(int(blocks), int(rounds), int(barrier),
+                                   C.c_void_p(data.data_ptr()), data.numel(),
+                                   C.c_void_p(ctl.data_ptr()), C.byref(us),
+                                   C.c_void_p(_stream_ptr(stream))))
+    return us.value
