@@ -150,3 +150,15 @@ def test_create_static_rejects_before_the_device():
     src = open(os.path.join(ROOT, "include", "tl.h")).read()
     m = re.search(r"#define TL_STATIC_WORKSPACE_BYTES \((\d+)u \* (\d+)u \* (\d+)u\)", src)
     assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == tl.TL_STATIC_WORKSPACE_BYTES
+
+
+def test_sync_probe_rejects_before_the_device():
+    """tl_op_sync_probe checks its arguments before any HIP call."""
+    import ctypes as C
+    lib = tl.load()
+    us = C.c_double()
+    assert lib.tl_op_sync_probe(256, 1, 0, None, 10, None, C.byref(us), None) == tl.TL_EINVAL
+    fake = C.c_void_p(256)   # never dereferenced: the counts fail first
+    assert lib.tl_op_sync_probe(256, 0, 0, fake, 10, fake, C.byref(us), None) == tl.TL_EINVAL
+    assert lib.tl_op_sync_probe(0, 1, 0, fake, 10, fake, C.byref(us), None) == tl.TL_EINVAL
+    assert lib.tl_op_sync_probe(256, 1, 0, fake, 0, fake, C.byref(us), None) == tl.TL_EINVAL
