@@ -472,6 +472,12 @@ def main():
                                         "coarse_solves", "line_search_halvings")},
         "ledger_rel_defect": ledger_defect(led),
     }
+    if args.profile_every > 0:
+        # GPU time per macro step of each phase (HIP events at the phase
+        # boundaries; the sampled CG-launch events run at the same time)
+        out["phase_ms_per_step"] = dict(zip(
+            ("window_loads_predictor", "micro_steps", "correction", "ledger_commit"),
+            (round(v / steps, 4) for v in st["phase_ms"])))
     if prec == W.FP64 and not args.no_mixed:
         # the mixed-precision path (FP32 operator and CG, FP64 residual, ledger
         # and coarse correction) on the same workload and steps

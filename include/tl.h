@@ -200,6 +200,11 @@ typedef struct {
   int64_t newton_corr, cg_corr;   /* the part of newton_fine / cg_fine spent in
                                      the two-level correction (its fine solves,
                                      or its composite solves)                */
+  double phase_ms[4];       /* GPU time of the macro steps' phases while
+                               profiling is on (tl_set_profiling): window
+                               update, coarse loads and predictor; micro
+                               steps 1..m-1; two-level correction; ledger
+                               and commit                                    */
 } tl_stats;
 
 typedef struct tl_sim tl_sim;
@@ -297,8 +302,9 @@ tl_status tl_load(tl_sim* sim, const void* host, size_t n);
 
 /* Time every sample_every-th launch of the fine CG operator kernel (the
  * fused direction update and matrix-free operator apply) with HIP events on
- * the handle's stream; the count and summed duration appear in tl_stats.
- * 0 switches timing off (the default). */
+ * the handle's stream; the count and summed duration appear in tl_stats,
+ * and so do the GPU times of each macro step's phases (phase_ms).  0
+ * switches timing off (the default). */
 tl_status tl_set_profiling(tl_sim* sim, int sample_every);
 
 void tl_destroy(tl_sim* sim);

@@ -147,6 +147,10 @@ struct CGBufs {
 // Sampled event timing of the fine CG iteration kernel.  Each timed launch
 // keeps its round and iteration index; after the host synchronises, only
 // launches that did work for some item are counted.
+// With profiling on, events at the phase boundaries of every macro step
+// give its GPU time per phase: window and coarse loads with the predictor,
+// the micro steps, the two-level correction, ledger and commit.
+constexpr int kPhases = 4;
 struct Profiler {
   int every = 0;
   long count = 0;
@@ -155,7 +159,36 @@ struct Profiler {
   int k[kProfPairs] = {};
   int round[kProfPairs] = {};
   tl_stats* stats = nullptr;
+  hipEvent_t pev[kPhases + 1] = {};
+  bool phases_pending = false;
 };
+// the boundary before phase q (q = kPhases: the end of the macro step)
+void phase_mark(Profiler* pr, int q, void* stream) {
+  if (pr == nullptr || pr->every <= 0 || pr->pev[0] == nullptr) return;
+  hip_check(hipEventRecord(pr->pev[q], (hipStream_t)stream), "hipEventRecord(phase)");
+  if (q == kPhases) pr->phases_pending = true;
+}
+// after the host has synchronised with the macro step: add its phase times
+void phase_flush(Profiler* pr, double* ms) {
+  if (pr == nullptr || !pr->phases_pending) return;
+  pr->phases_pending = false;
+  for (int q = 0; q < kPhases; ++q) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, pr->pev[q], pr->pev[q + 1]) == hipSuccess && ms)
+      ms[q] += t;
+  }
+}
+void phase_events(Profiler* pr, bool create) {
+  for (int q = 0; q <= kPhases; ++q) {
+    if (create && pr->pev[q] == nullptr)
+      hip_check(hipEventCreateWithFlags(&pr->pev[q], hipEventDisableSystemFence),
+                "hipEventCreate(phase)");
+    if (!create && pr->pev[q] != nullptr) {
+      (void)hipEventDestroy(pr->pev[q]);
+      pr->pev[q] = nullptr;
+    }
+  }
+}
 
 // Device/pinned tables of one batch context: solve items and scalars.
 struct BatchCtx {
@@ -1204,6 +1237,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     s->iqn.begin_step();
     st.it = 0;
   }
+  phase_mark(prof, 0, B.stream);
   // 1. window placement for the beam at t_{n+1}; 2. coarse loads
   for (StepState& st : steps) {
     tl_sim* s = st.s;
@@ -1255,6 +1289,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     std::swap(s->Tpred, s->ccur);
     k_copy(s->L, s->fprev, s->fstate, s->gf.npad);
   }
+  phase_mark(prof, 1, B.stream);
   // 3. micro steps j = 1..m-1 with blended Dirichlet data (j = 1..m with
   // the alternate formulation, which has no correction to iterate)
   auto last_micro = [](const StepState* st) {
@@ -1340,6 +1375,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     energy_now(s, &s->led->stored);
     s->stats.fine_dof_steps += fine_free_nodes(s->gf, s->win) * st->m;
   }
+  phase_mark(prof, 2, B.stream);
   // 4. two-level correction at t_{n+1}
   for (StepState* st : live(steps)) {
     tl_sim* s = st->s;
@@ -1474,6 +1510,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
       k_gamma_scatter(s->L, s->gidx, ng, s->gbuf, s->lam);
     }
   }
+  phase_mark(prof, 3, B.stream);
   // 5. ledger and commit of the new state
   for (StepState* st : live(steps)) {
     tl_sim* s = st->s;
@@ -1498,6 +1535,7 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
     energy_now(s, &s->led->stored);
     s->stats.fine_dof_steps += fine_free_nodes(s->gf, s->win) * st->m;
   }
+  phase_mark(prof, kPhases, B.stream);
 }
 
 // After a successful macro step: read the device ledger, count the step.
@@ -2037,7 +2075,8 @@ tl_status tl_step(tl_sim* s, int n_macro) {
       steps[0].s = s;
       macro_step_batch(steps, s->batch, &s->prof);
       if (steps[0].failed) throw NoConv{steps[0].err};
-      commit_step(s);
+      commit_step(s);   // synchronises with the stream
+      phase_flush(&s->prof, s->stats.phase_ms);
     } catch (const NoConv& e) {
       st = fail(TL_ENOCONV, e.msg);
     } catch (const DevErr& e) {
@@ -2240,6 +2279,11 @@ tl_status tl_set_profiling(tl_sim* s, int sample_every) {
   if (sample_every > 0 && !s->prof.ev[0]) {
     for (int q = 0; q < 2 * kProfPairs; ++q)
       HIP_OK(hipEventCreateWithFlags(&s->prof.ev[q], hipEventDisableSystemFence));
+    try {
+      phase_events(&s->prof, true);
+    } catch (const DevErr& e) {
+      return fail(TL_EDEVICE, e.msg);
+    }
   }
   s->prof.every = sample_every;
   s->prof.count = 0;
@@ -2252,6 +2296,7 @@ void tl_destroy(tl_sim* s) {
   else (void)hipDeviceSynchronize();
   if (s->prof.ev[0])
     for (int q = 0; q < 2 * kProfPairs; ++q) (void)hipEventDestroy(s->prof.ev[q]);
+  phase_events(&s->prof, false);
   auto hfree = [&](void* p) {
     if (!p) return;
     if (s->pinned_host) (void)hipHostFree(p);

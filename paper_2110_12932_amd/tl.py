@@ -72,7 +72,8 @@ class tl_stats(C.Structure):
                 ("fine_op_bytes", C.c_double), ("fine_op_applies", C.c_int64),
                 ("fine_op_timed", C.c_int64), ("fine_op_timed_ms", C.c_double),
                 ("fine_nodes", C.c_int * 3), ("coarse_nodes", C.c_int * 3),
-                ("newton_corr", C.c_int64), ("cg_corr", C.c_int64)]
+                ("newton_corr", C.c_int64), ("cg_corr", C.c_int64),
+                ("phase_ms", C.c_double * 4)]
 
 
 class tl_request_info(C.Structure):
@@ -271,7 +272,7 @@ def tl_get_stats(h):
     out = {}
     for n, _ in tl_stats._fields_:
         v = getattr(st, n)
-        out[n] = tuple(v) if n.endswith("_nodes") else v
+        out[n] = tuple(v) if n.endswith("_nodes") or n == "phase_ms" else v
     return out
 
 

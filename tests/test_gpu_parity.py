@@ -175,3 +175,41 @@ def test_nonconvergence_rolls_back():
     assert np.array_equal(T0, T1)
     assert tl.tl_get_time(sim.h)[1] == 0
     sim.close()
+
+
+@pytest.mark.parametrize("coupling", [W.DN, W.CONSISTENT])
+def test_two_level_iteration_cap_rolls_back(coupling):
+    """A two-level iteration capped at one pass cannot settle the interface
+    values: TL_ENOCONV, and the handle keeps the state of the last completed
+    macro step."""
+    wl = W.single_track_1mm()
+    sim = tl.Sim(replace(wl, options=replace(wl.options, coupling=coupling, dn_max=1)))
+    try:
+        Tc0, _ = sim.temperature(0)
+        Tf0, o0 = sim.temperature(1)
+        with pytest.raises(tl.TLError) as e:
+            sim.step(1)
+        assert e.value.status == tl.TL_ENOCONV
+        assert "two-level" in str(e.value)
+        Tc1, _ = sim.temperature(0)
+        Tf1, o1 = sim.temperature(1)
+        assert o1 == o0 and np.array_equal(Tc0, Tc1) and np.array_equal(Tf0, Tf1)
+        assert tl.tl_get_time(sim.h)[1] == 0
+    finally:
+        sim.close()
+
+
+def test_phase_times_cover_the_step():
+    """With profiling on, the four phase times of each macro step are
+    positive and add up to no more than the host's wall time of tl_step."""
+    sim = tl.Sim(W.single_track_1mm())
+    try:
+        tl.tl_set_profiling(sim.h, 4)
+        sim.step(3)
+        st = sim.stats()
+        ph = st["phase_ms"]
+        say("  phase ms", ph, "step ms", st["step_ms"])
+        assert all(p > 0.0 for p in ph)
+        assert sum(ph) <= st["step_ms"] * 1.05
+    finally:
+        sim.close()
