@@ -24,7 +24,8 @@ Chronopoulos-Gear PCG iteration fused with the matrix-free Q1 apply):
 algorithmic bytes per launch (read r, w, s_old, p, x, d, kappa, Dinv; write
 r', w', s, p, x) over its average launch duration, timed with HIP events on
 the library's stream for a sample of the fine micro steps' launches that
-did work inside the timed region.  `k2_sweep` times the bare operator apply
+did work inside the timed region (CG iterations after the first of each
+direction, which read and write all 13 arrays).  `k2_sweep` times the bare operator apply
 (read v, d, kappa; write y) at the workloads' fine shapes and at an
 HBM-resident grid.  `cpu_baseline` times the CPU oracle on a bounded sample
 of the same workload: whole macro steps where one takes a few seconds, else

@@ -1353,11 +1353,10 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   const R* __restrict__ dinv = (const R*)it.dinv;
   // Every global input of a tile is loaded into registers in one batch:
   // the halo of r, w, s_{k-1}, Dinv (for u_{k+1}), the element
-  // conductivities, and the node's own d, p, x, s_{k-1}.  In FP32 the first
-  // tile's batch is issued before the scalar reduction, each later tile's
+  // conductivities, and the node's own d, p, x, s_{k-1}.  The first tile's
+  // batch is issued before the scalar reduction; in FP32 each later tile's
   // while the previous tile's stencil is computed, so a workgroup waits on
-  // memory about once per tile; in FP64 each batch is issued at the top of
-  // its tile's turn (see below).
+  // memory about once per tile, in FP64 at the top of its tile's turn.
   R hr[HPT], hw[HPT], hs[HPT], hd[HPT], kr[EPT];
   R o_r = (R)0, o_w = (R)0, o_di = (R)0, o_d = (R)0, o_s = (R)0, o_p = (R)0,
     o_x = (R)0;
@@ -1421,8 +1420,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     }
   };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
-  if constexpr (sizeof(R) == 4)
-    if (tr.first < tr.last) load_tile(tile_at(it, tr.first));
+  if (tr.first < tr.last) load_tile(tile_at(it, tr.first));
   // gamma_k, delta_k from the previous kernel's partials (CG start or
   // iteration k-1), held in the region pair this kernel does not write
   const int rd = (kit & 1) ? kTCG2 : kTCG;
@@ -1476,7 +1474,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   for (int tile = tr.first; tile < tr.last; tile += tr.step) {
     R acc[2] = {(R)0, (R)0};
     const Tile t = tile_at(it, tile);
-    if constexpr (sizeof(R) == 8) load_tile(t);
+    if constexpr (sizeof(R) == 8)
+      if (tile != tr.first) load_tile(t);
     // u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
@@ -1493,10 +1492,9 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     const int n = o_n;
     const R r_own = o_r, w_own = o_w, di_own = o_di, d_own = o_d,
             s_prev = o_s, p_own = o_p, x_own = o_x;
-    // FP32: the next tile's loads fly during this tile's stencil (the
-    // first tile's during the scalar reduction); FP64 would need 164
-    // registers for that (3 waves per SIMD) and loads each tile at the top
-    // of its turn instead, at 4 waves per SIMD
+    // FP32: the next tile's loads fly during this tile's stencil; FP64
+    // loads each later tile at the top of its turn (overlapping the stencil
+    // as well would take 164 registers)
     if constexpr (sizeof(R) == 4)
       if (tile + tr.step < tr.last)
         load_tile(tile_at(it, tile + tr.step));

@@ -92,8 +92,8 @@ class ScanPath:
 
 @dataclass
 class Options:
-    """Production defaults: Newton and two-level tolerances 1e-8 K (FP64) --
-    use options_for(MIXED, ...) for the mixed path's 1e-6 K -- and inner CG
+    """Defaults: Newton and two-level tolerances 1e-8 K -- the workloads use
+    options_for, 1e-7 K (FP64) or 1e-5 K (mixed) -- and inner CG
     reduction 3e-2 (the Newton fixed point does not depend on it; the
     frozen-kappa Newton contracts by about 0.06 per step, so a tighter inner
     solve buys no fewer Newton steps).
@@ -143,11 +143,14 @@ class Workload:
 
 
 def options_for(precision, dt_coarse, m_time, **kw):
-    """Options with the tolerances suited to the precision: 1e-8 K for the
-    FP64 path (target 1e-9 relative), 1e-5 K for the mixed path (target
-    1e-6 relative, i.e. about 2e-3 K on a 2000 K field: the Newton and
-    two-level stopping errors stay two orders below it)."""
-    tol = 1e-8 if precision == FP64 else 1e-5
+    """Options with the tolerances suited to the precision: 1e-7 K for the
+    FP64 path (target 1e-9 relative, about 3e-7 K on the 300 K plate and
+    2e-6 K on a 2000 K field; the frozen-kappa Newton contracts by about
+    0.06 per step, so the error left after a last step of 1e-7 K is about
+    6e-9 K), 1e-5 K for the mixed path (target 1e-6 relative, i.e. about
+    2e-3 K on a 2000 K field: the Newton and two-level stopping errors stay
+    two orders below it)."""
+    tol = 1e-7 if precision == FP64 else 1e-5
     base = dict(dt_coarse=dt_coarse, m_time=m_time, precision=precision,
                 newton_tol=tol, dn_tol=tol)
     base.update(kw)
