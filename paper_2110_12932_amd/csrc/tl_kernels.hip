@@ -399,8 +399,9 @@ struct Tile {
 };
 
 // XCD-aware tile order.  Workgroups are dealt round-robin to the 8 XCDs
-// (blockIdx.x % 8), each with its own L2.  The tiles (x fastest, then y, z)
-// are cut into 8 contiguous chunks and chunk c is processed by the
+// (blockIdx.x % 8), each with its own L2.  The tiles (in the order of
+// tile_at for the batched kernels, x fastest then y, z for the bare
+// operator) are cut into 8 contiguous chunks and chunk c is processed by the
 // workgroups with blockIdx.x % 8 == c, so tiles that share halo entries sit
 // on the same L2.  The workgroup count nb is a multiple of 8 and the first
 // workgroup's index too; local workgroup b visits tiles first(b),
@@ -435,10 +436,23 @@ __device__ inline Tile tile_of(int b, int ntx, int nty) {
   return t;
 }
 
-// Tile b of a batched item (numbered x fastest, then y, z: each XCD's
-// contiguous chunk is a layer across z).
+// Tile b of a batched item, numbered x fastest, then z, then y: each XCD's
+// contiguous chunk (tile_range) is a slab across y, whose halo faces are
+// x-z planes -- smaller than the x-y planes of a chunk across z on the
+// shallow grids of this method -- while tiles next to each other in x,
+// which share 128-byte lines along their rows, still run side by side.
+// On the raster build's window this cut the CG iteration's fetched bytes
+// from 1.37 to 1.28 times the algorithmic reads.
 __device__ inline Tile tile_at(const SolveItem& it, int b) {
-  return tile_of(b, it.ntx, it.nty);
+  const int ntz = it.ntiles / (it.ntx * it.nty);
+  Tile t;
+  t.ox = (b % it.ntx) * TX;
+  t.oz = ((b / it.ntx) % ntz) * TZ;
+  t.oy = (b / (it.ntx * ntz)) * TY;
+  t.tx = threadIdx.x % TX;
+  t.ty = (threadIdx.x / TX) % TY;
+  t.tz = threadIdx.x / (TX * TY);
+  return t;
 }
 // padded index of halo entry h of the tile, or -1 when it lies past the
 // ghost layer of the grid
@@ -846,14 +860,42 @@ __device__ inline bool halo_gamma(const Geo& g, const Window& w, const Tile& t,
 // item's tiles -- for a composite pair, the fine tiles and then the coarse
 // tiles, the same order on both sides.  Per-thread sums; the caller reduces
 // over the workgroup.
+// Adds this thread's share of a region's tile partials to v: entries
+// threadIdx.x, threadIdx.x + kBlock, ... in that order.  The loads of up to
+// kSumBatch entries are issued together before any is added, so a
+// workgroup waits on memory once per kSumBatch * kBlock tiles rather than
+// once per kBlock (the order of the additions is unchanged).
+// Region reg + qmax (qmax >= 0) takes the maximum instead of the sum.
+constexpr int kSumBatch = 6;
+template <int NV, class T, int B = kSumBatch>
+__device__ inline void add_partials(const double* __restrict__ tp, int ts,
+                                    int nt, int reg, T (&v)[NV],
+                                    int qmax = -1) {
+  for (int b0 = threadIdx.x; b0 < nt; b0 += B * kBlock) {
+    double x[B][NV];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int b = b0 + u * kBlock;
+#pragma unroll
+      for (int q = 0; q < NV; ++q)
+        x[u][q] = b < nt ? tp[(reg + q) * ts + b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (b0 + u * kBlock < nt) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+          v[q] = q == qmax ? fmax(v[q], (T)x[u][q]) : v[q] + (T)x[u][q];
+      }
+  }
+}
+// (FP32 CG kernels keep one load per pass: their first tile's loads are
+// in flight at the same time, and batching measured slower there.)
 template <int NV, class T>
 __device__ inline void pair_partials(const Couple& cp, int reg, T (&v)[NV]) {
-  for (int b = threadIdx.x; b < cp.ntA; b += kBlock)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] += (T)cp.tpA[(reg + q) * cp.tsA + b];
-  for (int b = threadIdx.x; b < cp.ntB; b += kBlock)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] += (T)cp.tpB[(reg + q) * cp.tsB + b];
+  constexpr int B = sizeof(T) == 8 ? kSumBatch : 1;
+  add_partials<NV, T, B>(cp.tpA, cp.tsA, cp.ntA, reg, v);
+  add_partials<NV, T, B>(cp.tpB, cp.tsB, cp.ntB, reg, v);
 }
 
 // Every item of a batched launch has the same number of workgroups
@@ -1194,19 +1236,11 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     // residual reductions over the item's tiles (every workgroup, same
     // order)
     const Couple& cp = it.cp;
-    double v[2] = {0.0, 0.0};
-    double bm = 0.0;
-    for (int b = threadIdx.x; b < cp.ntA; b += kBlock) {
-      v[0] += cp.tpA[kTRes * cp.tsA + b];
-      v[1] += cp.tpA[(kTRes + 2) * cp.tsA + b];
-      bm = fmax(bm, cp.tpA[(kTRes + 1) * cp.tsA + b]);
-    }
-    for (int b = threadIdx.x; b < cp.ntB; b += kBlock) {
-      v[0] += cp.tpB[kTRes * cp.tsB + b];
-      v[1] += cp.tpB[(kTRes + 2) * cp.tsB + b];
-      bm = fmax(bm, cp.tpB[(kTRes + 1) * cp.tsB + b]);
-    }
-    bm = wave_max(bm);
+    double a3[3] = {0.0, 0.0, 0.0};   // |R|^2, max|dx|, r.z
+    add_partials<3, double, 2>(cp.tpA, cp.tsA, cp.ntA, kTRes, a3, 1);
+    add_partials<3, double, 2>(cp.tpB, cp.tsB, cp.ntB, kTRes, a3, 1);
+    double v[2] = {a3[0], a3[2]};
+    double bm = wave_max(a3[1]);
     block_sum<2>(v, lds);
     if ((threadIdx.x & 63) == 0) ldm[threadIdx.x >> 6] = bm;
     __syncthreads();
