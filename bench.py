@@ -83,22 +83,25 @@ def parse():
 
 
 def measured_traffic(path, workload, elem):
-    """HBM bytes per launch of the CG iteration kernel from the calibrated
-    rocprofv3 FETCH_SIZE/WRITE_SIZE record in profiles/, or None when there
-    is no record for this workload and precision or the kernel source has
-    changed since the counters were taken."""
+    """(HBM bytes per launch, kernel instance) of the CG iteration kernel from
+    the calibrated rocprofv3 FETCH_SIZE/WRITE_SIZE record in profiles/, or
+    (None, None) when there is no record for this workload and precision or
+    the kernel source has changed since the counters were taken.  The
+    instance names the stack depth the library chose for the workload's
+    window (`<R, 0, 2>`: stacks of two tiles)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    kname = "cg_iter_batched_kernel<%s, 0>" % ("double" if elem == 8 else "float")
+    prefix = "cg_iter_batched_kernel<%s, 0," % ("double" if elem == 8 else "float")
     if path is None:
         path = os.path.join(root, "profiles", f"cg_iter_{workload}_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     rec = json.load(open(path))
     src = open(os.path.join(root, "paper_2110_12932_amd", "csrc", "tl_kernels.hip"), "rb").read()
-    if rec.get("kernel") != kname or rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
-        return None
-    return rec.get("bytes_per_launch")
+    if (not str(rec.get("kernel", "")).startswith(prefix)
+            or rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest()):
+        return None, None
+    return rec.get("bytes_per_launch"), rec["kernel"]
 
 
 def cpu_baseline(wl, n_macro=2, budget_s=15.0):
@@ -144,8 +147,10 @@ def cpu_baseline(wl, n_macro=2, budget_s=15.0):
 
 
 def k2_sweep(tl, W, torch):
-    """Bare operator apply y = d v + K[kappa] v, timed with events on the
-    current stream (the library launches on it) over repeated launches."""
+    """Bare operator apply y = d v + K[kappa] v with each of its two kernels
+    (3D LDS tiles, z-marching columns), timed with events on the current
+    stream (the library launches on it) over repeated launches; `auto` marks
+    the kernel the library picks for the grid."""
     import numpy as np
     out = []
     shapes = [("single_track_2mm fine", 80, 40, 24), ("raster_10mm fine", 120, 80, 30),
@@ -162,21 +167,26 @@ def k2_sweep(tl, W, torch):
             v = torch.rand(npad, dtype=dt, device="cuda", generator=g) * 300
             y = torch.empty_like(v)
             reps = 20 if nodes > 1e7 else 200
-            tl.tl_op_apply(grid, prec, d, kap, v, y, 3)
-            # the median of 5 batches of `reps` launches
-            batch_us = []
-            for _ in range(5):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                tl.tl_op_apply(grid, prec, d, kap, v, y, reps)
-                e1.record()
-                torch.cuda.synchronize()
-                batch_us.append(e0.elapsed_time(e1) * 1e3 / reps)
-            us = float(np.median(batch_us))
-            gbs = 4 * eb * nodes / (us * 1e-6) / 1e9
-            out.append({"shape": name, "nodes": nodes, "dtype": "f64" if eb == 8 else "f32",
-                        "us_per_launch": round(us, 3), "GB/s": round(gbs, 1),
-                        "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            auto = tl.OP_ZMARCH if nodes > 4 * 2**20 and nz >= 8 else tl.OP_TILED
+            for kern in (tl.OP_TILED, tl.OP_ZMARCH):
+                tl.tl_op_apply(grid, prec, d, kap, v, y, 3, kernel=kern)
+                # the median of 5 batches of `reps` launches
+                batch_us = []
+                for _ in range(5):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    tl.tl_op_apply(grid, prec, d, kap, v, y, reps, kernel=kern)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    batch_us.append(e0.elapsed_time(e1) * 1e3 / reps)
+                us = float(np.median(batch_us))
+                gbs = 4 * eb * nodes / (us * 1e-6) / 1e9
+                out.append({"shape": name, "nodes": nodes, "dtype": "f64" if eb == 8 else "f32",
+                            "kernel": "tiled" if kern == tl.OP_TILED else "zmarch",
+                            "auto": kern == auto,
+                            "us_per_launch": round(us, 3), "GB/s": round(gbs, 1),
+                            "frac": round(gbs / HBM_PEAK_GBS, 4)})
             del d, kap, v, y
     # the practical HBM ceiling for reference: a device-to-device copy of
     # 1 GiB (read + write bytes over the time) and a read-only reduction
@@ -323,7 +333,7 @@ def main_serving(args):
         achieved = fine_bytes / (prof[1] * 1e-3 * max(1, args.profile_every)) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "cg_iter_batched_kernel<float, 0> (all requests of a tick)",
+                    "kernel": "cg_iter_batched_kernel<float, 0, S> (all requests of a tick)",
                     "avg_launch_us": prof[1] * 1e3 / prof[0],
                     "bytes_per_launch": fine_bytes / max(1.0, launches_work),
                     "launches_timed": prof[0], "fine_cg_item_iterations": fine_iters}
@@ -441,10 +451,11 @@ def main():
     if st["fine_op_timed"] > 0:
         avg_s = st["fine_op_timed_ms"] / st["fine_op_timed"] * 1e-3
         achieved = bytes_per_launch / avg_s / 1e9
-        traffic = measured_traffic(args.traffic, wl.name, elem)
+        traffic, kname = measured_traffic(args.traffic, wl.name, elem)
+        if kname is None:   # S: the stack depth of the CG work units
+            kname = "cg_iter_batched_kernel<%s, 0, S>" % ("double" if elem == 8 else "float")
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": "cg_iter_batched_kernel<%s, 0>" % ("double" if elem == 8 else "float"),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                     "launches_timed": st["fine_op_timed"]}
     out = {

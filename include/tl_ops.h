@@ -45,11 +45,21 @@ tl_status tl_op_unpack(const tl_grid* grid, int kind, int elem_bytes,
  * with K_e the exact Q1 element stiffness of an hx x hy x hz box (the
  * diffusion term of the paper's thermal model, Section 2.1, discretised
  * with trilinear hexahedra).  d, kappa, v, y are padded device arrays of
- * doubles (precision TL_FP64) or floats (TL_MIXED).  `repeat` >= 1 launches
- * the operator that many times back to back (for timing). */
-tl_status tl_op_apply(const tl_grid* grid, int precision, const void* d,
-                      const void* kappa, const void* v, void* y, int repeat,
-                      void* hip_stream);
+ * doubles (precision TL_FP64) or floats (TL_MIXED); y must not overlap the
+ * inputs.  kernel: 0 = chosen by grid size (z-marching above 4 Mi nodes with
+ * nz >= 8, else tiled), 1 = 3D tiles of 16 x 4 x 4 nodes staged with their
+ * halo in LDS, 2 = z-marching columns of 64 x 4 nodes with a sliding
+ * register window.  Every kernel sums each node's terms in the same order,
+ * so all choices give bitwise-equal y.  blocks: workgroups to launch, 0 for
+ * the kernel's own choice, else a positive multiple of 8 up to 2^20 (each
+ * workgroup strides over its share of tiles or columns).  `repeat` >= 1
+ * launches the operator that many times back to back (for timing).  The
+ * call waits for the launches on hip_stream.  Errors: TL_EINVAL for a bad
+ * grid, null pointers, repeat < 1, an unknown precision or kernel, or a bad
+ * workgroup count; TL_EDEVICE if a HIP call fails. */
+tl_status tl_op_apply(const tl_grid* grid, int precision, int kernel,
+                      int blocks, const void* d, const void* kappa,
+                      const void* v, void* y, int repeat, void* hip_stream);
 
 /* Cost of a device-wide synchronisation between dependent steps on this
  * GPU, for the choice between one launch per step and a persistent kernel

@@ -179,8 +179,12 @@ void k_copy(Launch L, double* dst, const double* src, long n);
 void k_extrapolate(Launch L, double* dst, const double* a, const double* b,
                    long n);
 
+// Bare operator kernels: chosen by grid size, 3D LDS tiles, z-marching
+// columns.  blocks > 0 (a multiple of 8) overrides the workgroup count.
+enum OpKernel { kOpAuto = 0, kOpTiled = 1, kOpZmarch = 2 };
 template <class R>
-void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v, R* y);
+void k_op_apply(Launch L, const Geo& g, int kernel, int blocks, const R* d,
+                const R* kap, const R* v, R* y);
 
 // Composite-grid coupling: the two-level correction solved as one system
 // over the free fine nodes and the coarse nodes outside the window interior,
@@ -276,8 +280,13 @@ int grid_tiles(const Geo& g, int& ntx, int& nty);
 constexpr double kResidentShare = 1.0;
 int item_tile_blocks(int ntiles, int n_items, int resident);
 
+// Stacks of two tiles along z on grid g (work units of the CG kernels on
+// large items).
+int cg_stacks(const Geo& g);
+
 // Batched launches of Newton round `round` over a device table of n_items
-// items whose largest has ntiles tiles (the grid follows item_tile_blocks).
+// items whose largest has ntiles tiles and nstacks stacks of two
+// (cg_stacks); the grid follows item_tile_blocks.
 // ev_start/ev_stop (hipEvent_t, may be null) are recorded with the CG
 // dispatch itself.
 template <class R>
@@ -285,11 +294,11 @@ void k_residual_batched(Launch L, const SolveItem* items, int n_items,
                         int ntiles, int round);
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int ntiles, int round);
+                        int ntiles, int nstacks, int round);
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int ntiles, int round, int kit, void* ev_start,
-                       void* ev_stop);
+                       int ntiles, int nstacks, int round, int kit,
+                       void* ev_start, void* ev_stop);
 // The same launches for the two sides of composite pairs (side =
 // kFineSide or kCoarseSide), and the gather between them over the coarse
 // sides' table: phase 0 after the residual, 1 after the CG start, 2 after
@@ -299,10 +308,10 @@ void k_residual_pair(Launch L, const SolveItem* items, int n_items,
                      int ntiles, int round, int side);
 template <class R>
 void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
-                     int ntiles, int round, int side);
+                     int ntiles, int nstacks, int round, int side);
 template <class R>
 void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
-                    int ntiles, int round, int kit, int side,
+                    int ntiles, int nstacks, int round, int kit, int side,
                     void* ev_start, void* ev_stop);
 template <class R>
 void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,

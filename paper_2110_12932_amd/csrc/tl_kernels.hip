@@ -291,33 +291,33 @@ __device__ inline R stencil_grouped(VF V, const R (&k8)[8], const R (&w)[8]) {
   const R fx0 = kz[0][0] + kz[0][1], fx1 = kz[1][0] + kz[1][1];
   const R fy0 = kz[0][0] + kz[1][0], fy1 = kz[0][1] + kz[1][1];
   const R fz0 = ky[0][0] + ky[1][0], fz1 = ky[0][1] + ky[1][1];
+  // every multiply-add is an explicit fma, so that no kernel's compiler
+  // can fuse a sum of two products the other way round: the result is the
+  // same bits in every kernel that calls this
   const R tot = fx0 + fx1;
-  R s1 = fx0 * V(1, 0, 0);
-  s1 += fx1 * V(-1, 0, 0);
-  R s2 = fy0 * V(0, 1, 0);
-  s2 += fy1 * V(0, -1, 0);
-  R s4 = fz0 * V(0, 0, 1);
-  s4 += fz1 * V(0, 0, -1);
+  const R s1 = fma(fx1, V(-1, 0, 0), fx0 * V(1, 0, 0));
+  const R s2 = fma(fy1, V(0, -1, 0), fy0 * V(0, 1, 0));
+  const R s4 = fma(fz1, V(0, 0, -1), fz0 * V(0, 0, 1));
   R s3 = (R)0, s5 = (R)0, s6 = (R)0, s7 = (R)0;
 #pragma unroll
   for (int a = -1; a <= 1; a += 2)
 #pragma unroll
     for (int b = -1; b <= 1; b += 2) {
-      s3 += kz[I(a)][I(b)] * V(a, b, 0);
-      s5 += ky[I(a)][I(b)] * V(a, 0, b);
-      s6 += kx[I(a)][I(b)] * V(0, a, b);
+      s3 = fma(kz[I(a)][I(b)], V(a, b, 0), s3);
+      s5 = fma(ky[I(a)][I(b)], V(a, 0, b), s5);
+      s6 = fma(kx[I(a)][I(b)], V(0, a, b), s6);
 #pragma unroll
       for (int c = -1; c <= 1; c += 2)
-        s7 += k8[I(a) + 2 * I(b) + 4 * I(c)] * V(a, b, c);
+        s7 = fma(k8[I(a) + 2 * I(b) + 4 * I(c)], V(a, b, c), s7);
     }
   R acc = w[0] * (tot * V(0, 0, 0));
-  acc += w[1] * s1;
-  acc += w[2] * s2;
-  acc += w[3] * s3;
-  acc += w[4] * s4;
-  acc += w[5] * s5;
-  acc += w[6] * s6;
-  acc += w[7] * s7;
+  acc = fma(w[1], s1, acc);
+  acc = fma(w[2], s2, acc);
+  acc = fma(w[3], s3, acc);
+  acc = fma(w[4], s4, acc);
+  acc = fma(w[5], s5, acc);
+  acc = fma(w[6], s6, acc);
+  acc = fma(w[7], s7, acc);
   return acc;
 }
 template <class R>
@@ -341,9 +341,9 @@ __device__ inline R stencil_elementwise(VF V, const R (&k8)[8],
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-      s += w[e ^ c] * V(cx - ex, cy - ey, cz - ez);
+      s = fma(w[e ^ c], V(cx - ex, cy - ey, cz - ez), s);
     }
-    acc += k8[e] * s;
+    acc = fma(k8[e], s, acc);
   }
   return acc;
 }
@@ -400,8 +400,8 @@ struct Tile {
 
 // XCD-aware tile order.  Workgroups are dealt round-robin to the 8 XCDs
 // (blockIdx.x % 8), each with its own L2.  The tiles (in the order of
-// tile_at for the batched kernels, x fastest then y, z for the bare
-// operator) are cut into 8 contiguous chunks and chunk c is processed by the
+// tile_at for the batched kernels, of tile_of for the bare operator) are
+// cut into 8 contiguous chunks and chunk c is processed by the
 // workgroups with blockIdx.x % 8 == c, so tiles that share halo entries sit
 // on the same L2.  The workgroup count nb is a multiple of 8 and the first
 // workgroup's index too; local workgroup b visits tiles first(b),
@@ -537,7 +537,7 @@ op_apply_tiled_kernel(Geo g, int ntx, int nty, int ntiles,
     if (i < g.nx && j < g.ny && k < g.nz) {
       const int n = pidx(g, i, j, k);
       const R vc = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-      y[n] = d[n] * vc + stencil_lds(t, u_s, k_s, wts);
+      y[n] = fma(d[n], vc, stencil_lds(t, u_s, k_s, wts));
     }
     __syncthreads();  // LDS is reused by the next tile
   }
@@ -750,9 +750,9 @@ op_apply_zmarch_kernel(Geo g, ZPlan zp, const R* __restrict__ d,
         };
         R yn;
         if constexpr (sizeof(R) == 8)
-          yn = dq0 * V0[4] + stencil_elementwise(V, k8, wts);
+          yn = fma(dq0, V0[4], stencil_elementwise(V, k8, wts));
         else
-          yn = dq0 * V0[4] + stencil_grouped(V, k8, wts);
+          yn = fma(dq0, V0[4], stencil_grouped(V, k8, wts));
         __builtin_nontemporal_store(yn, &y[(long)(k + 1) * g.pxy + doff]);
       }
       // plane k+2 replaces plane k, layer k+1 replaces layer k-1: both were
@@ -856,10 +856,6 @@ __device__ inline bool halo_gamma(const Geo& g, const Window& w, const Tile& t,
     return false;
   return fine_gamma(g, w, i, j, k);
 }
-// Sums of nv consecutive tile-partial regions starting at `reg` over an
-// item's tiles -- for a composite pair, the fine tiles and then the coarse
-// tiles, the same order on both sides.  Per-thread sums; the caller reduces
-// over the workgroup.
 // Adds this thread's share of a region's tile partials to v: entries
 // threadIdx.x, threadIdx.x + kBlock, ... in that order.  The loads of up to
 // kSumBatch entries are issued together before any is added, so a
@@ -889,8 +885,12 @@ __device__ inline void add_partials(const double* __restrict__ tp, int ts,
       }
   }
 }
-// (FP32 CG kernels keep one load per pass: their first tile's loads are
-// in flight at the same time, and batching measured slower there.)
+// Sums of NV consecutive tile-partial regions starting at `reg` over an
+// item's tiles -- for a composite pair, the fine tiles and then the coarse
+// tiles, the same order on both sides.  Per-thread sums; the caller reduces
+// over the workgroup.  (FP32 CG kernels keep one load per pass: their
+// first tile's loads are in flight at the same time, and batching measured
+// slower there.)
 template <int NV, class T>
 __device__ inline void pair_partials(const Couple& cp, int reg, T (&v)[NV]) {
   constexpr int B = sizeof(T) == 8 ? kSumBatch : 1;
@@ -1126,6 +1126,55 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   }
 }
 
+// Work units of the CG start and iteration kernels: stacks of S tiles
+// along z (S = 1 or 2), so a thread holds node (tx, ty, tz) of each of the
+// S tiles and a workgroup has S times the loads of one tile in flight.
+// Stacks are numbered like tile_at (x fastest, then z, then y), with the z
+// index in steps of S, and the partial sums stay per tile: the reductions
+// add the same numbers in the same order whatever S is.  A launch takes
+// stacks of two when each workgroup would walk two tiles (its largest item
+// has more tiles than the workgroups it gets, but at most twice as many):
+// one turn instead of two.  On the raster build's 1344-tile window that
+// took 3 % off the FP64 macro step.  With fewer tiles, stacks would leave
+// workgroups idle (the single track: 10 % slower); with many more tiles
+// per workgroup (the served mix: 64 workgroups for 546 tiles) stacks lose
+// the FP32 kernel's overlap of the next tile's loads with the stencil, and
+// serving ran 1.5 % slower.
+template <int S>
+struct Stack {
+  static constexpr int HN = HX * HY * (S * TZ + 2);   // halo nodes
+  static constexpr int EN = EX * EY * (S * TZ + 1);   // elements
+  static constexpr int HPT = (HN + kBlock - 1) / kBlock;
+  static constexpr int EPT = (EN + kBlock - 1) / kBlock;
+};
+__device__ inline int item_ntz(const SolveItem& it) {
+  return it.ntiles / (it.ntx * it.nty);
+}
+template <int S>
+__device__ inline int stack_count(const SolveItem& it) {
+  return it.ntx * it.nty * ((item_ntz(it) + S - 1) / S);
+}
+// Stack w: the tile of its lowest tile (this thread's node in it), the
+// index of that tile in tile_at's numbering (tile s of the stack is
+// b0 + s * ntx) and the number of tiles the stack holds (the top stack of
+// an odd column of tiles holds fewer than S).
+template <int S>
+__device__ inline Tile stack_at(const SolveItem& it, int w, int& b0,
+                                int& nsub) {
+  const int ntz = item_ntz(it), nwz = (ntz + S - 1) / S;
+  const int x = w % it.ntx, wz = (w / it.ntx) % nwz, y = w / (it.ntx * nwz);
+  b0 = x + it.ntx * (wz * S + ntz * y);
+  nsub = min(S, ntz - wz * S);
+  Tile t;
+  t.ox = x * TX;
+  t.oy = y * TY;
+  t.oz = wz * S * TZ;
+  t.tx = threadIdx.x % TX;
+  t.ty = (threadIdx.x / TX) % TY;
+  t.tz = threadIdx.x / (TX * TY);
+  return t;
+}
+
 // Newton state machine and CG start of round `round` (see the CG
 // recurrences below).  Every workgroup of an item computes the same next
 // state from the round's input state, the previous round's CG outcome and
@@ -1150,16 +1199,17 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 // leaves those rows out of its dot
 // products, the coarse side adds the gathered fine rows of w0 on its
 // interface nodes.
-template <class R, int CP>
+template <class R, int CP, int S>
 __global__ void __launch_bounds__(kBlock)
 cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                         int round) {
-  __shared__ R u_s[HN];
-  __shared__ R k_s[EN];
+  using ST = Stack<S>;
+  __shared__ R u_s[ST::HN];
+  __shared__ R k_s[ST::EN];
   __shared__ double lds[2 * kBlock / 64];
   __shared__ double ldm[kBlock / 64];
   __shared__ double bc[3];
-  __shared__ R ldr[2 * kBlock / 64];
+  __shared__ R ldr[2 * S * kBlock / 64];
   const SolveItem& it = items[item_of_block(per_item)];
   const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
@@ -1179,20 +1229,21 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       nx.dir_cut = cgp.done ? 0 : 1;
     }
   }
-  // inputs of w0 = J u0 for a tile, loaded into registers in one batch
+  // inputs of w0 = J u0 for a stack of tiles (the CG iteration's work
+  // units), loaded into registers in one batch
   const R* __restrict__ r = (const R*)it.r[0];
   const R* __restrict__ dinv = (const R*)it.dinv;
   const R* __restrict__ d = (const R*)it.d;
   const R* __restrict__ kap = (const R*)it.kap;
-  R hr[HPT], hd[HPT], kr[EPT];
-  R o_r = (R)0, o_d = (R)0;
-  int o_n = 0;
-  bool o_act = false, o_gam = false;
-  auto load_tile = [&](const Tile& t) {
+  R hr[ST::HPT], hd[ST::HPT], kr[ST::EPT];
+  R o_r[S], o_d[S];
+  int o_n[S];
+  bool o_act[S], o_gam[S];
+  auto load_stack = [&](const Tile& t) {
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
+    for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      const int n = h < HN ? halo_index(g, t, h) : -1;
+      const int n = h < ST::HN ? halo_index(g, t, h) : -1;
       int fi, fj, fk;
       if (CP == kFineSide && n >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
@@ -1211,28 +1262,41 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       }
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
+    for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      const int n = e < EN ? elem_index(g, t, e) : -1;
+      const int n = e < ST::EN ? elem_index(g, t, e) : -1;
       kr[q] = n >= 0 ? kap[n] : (R)0;
     }
-    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
-    o_act = i < g.nx && j < g.ny && k < g.nz;
-    o_n = o_act ? pidx(g, i, j, k) : 0;
-    if (CP == kFineSide || CP == kFineSideP)
-      o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
-    if (CP == kCoarseSide) o_gam = o_act && coarse_gamma(it.cp.w, i, j, k);
-    if (o_act) {
-      o_r = r[o_n];
-      o_d = d[o_n];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + u * TZ + t.tz;
+      o_act[u] = i < g.nx && j < g.ny && k < g.nz;
+      o_n[u] = o_act[u] ? pidx(g, i, j, k) : 0;
+      o_gam[u] = false;
+      if (CP == kFineSide || CP == kFineSideP)
+        o_gam[u] = o_act[u] && fine_gamma(g, it.cp.w, i, j, k);
+      if (CP == kCoarseSide) o_gam[u] = o_act[u] && coarse_gamma(it.cp.w, i, j, k);
+      o_r[u] = o_d[u] = (R)0;
+      if (o_act[u]) {
+        o_r[u] = r[o_n[u]];
+        o_d[u] = d[o_n[u]];
+      }
     }
   };
-  const TileRange tr = tile_range(blk, nblk, it.ntiles);
+  const TileRange tr = tile_range(blk, nblk, stack_count<S>(it));
+  int b0, nsub;
+  // Loads ahead of use: the first stack's during the reduction, the next
+  // one's during this one's stencil.  FP64 stacks of two load each stack at
+  // the top of its turn instead (with loads ahead they take 162 to 185
+  // registers and drop to 2 waves per SIMD on a composite side).
+  constexpr bool kAhead = sizeof(R) == 4 || S == 1;
   double rnorm2 = 0.0, dmax = 0.0, rz = 0.0;
   bool run = false;
   if (nx.status == kRunning) {
-    // the first tile's inputs are in flight during the reduction
-    if (tr.first < tr.last) load_tile(tile_at(it, tr.first));
+    // the first stack's inputs are in flight during the reduction (not in
+    // FP64 stacks of two: see below)
+    if (kAhead && tr.first < tr.last)
+      load_stack(stack_at<S>(it, tr.first, b0, nsub));
     // residual reductions over the item's tiles (every workgroup, same
     // order)
     const Couple& cp = it.cp;
@@ -1307,62 +1371,86 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     if (round > 0) sc->cg_log[(round - 1) % kRoundLog] = prev_iters;
   }
   if (!run) return;
-  // w0 = J u0, u0 = Dinv r0, on the tiles
+  // w0 = J u0, u0 = Dinv r0, on the stacks
   R* __restrict__ w = (R*)it.w[0];
   R wts[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
-    R acc[2] = {(R)0, (R)0};
-    const Tile t = tile_at(it, tile);
+  for (int ws = tr.first; ws < tr.last; ws += tr.step) {
+    R acc[2 * S];
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
+    for (int q = 0; q < 2 * S; ++q) acc[q] = (R)0;
+    const Tile t = stack_at<S>(it, ws, b0, nsub);
+    if (!kAhead) load_stack(t);
+#pragma unroll
+    for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      if (h < HN) u_s[h] = hd[q] * hr[q];
+      if (h < ST::HN) u_s[h] = hd[q] * hr[q];
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
+    for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      if (e < EN) k_s[e] = kr[q];
+      if (e < ST::EN) k_s[e] = kr[q];
     }
     __syncthreads();
-    const bool active = o_act, gam = o_gam;
-    const int n = o_n;
-    const R r_own = o_r, d_own = o_d;
-    if (tile + tr.step < tr.last)
-      load_tile(tile_at(it, tile + tr.step));
-    if (active) {
-      const R un = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-      R wn = d_own * un + stencil_lds(t, u_s, k_s, wts);
-      if (CP == kCoarseSide && gam) wn += ((const R*)it.cp.gDW)[n];
+    bool act[S], gam[S];
+    int nn[S];
+    R r_own[S], d_own[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      act[u] = o_act[u];
+      gam[u] = o_gam[u];
+      nn[u] = o_n[u];
+      r_own[u] = o_r[u];
+      d_own[u] = o_d[u];
+    }
+    if (kAhead && ws + tr.step < tr.last) {
+      int nb0, nns;
+      load_stack(stack_at<S>(it, ws + tr.step, nb0, nns));
+    }
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      if (!act[u]) continue;
+      Tile tu = t;
+      tu.tz += u * TZ;
+      const int n = nn[u];
+      const R un = u_s[(tu.tz + 1) * (HX * HY) + (tu.ty + 1) * HX + (tu.tx + 1)];
+      R wn = fma(d_own[u], un, stencil_lds(tu, u_s, k_s, wts));
+      if (CP == kCoarseSide && gam[u]) wn += ((const R*)it.cp.gDW)[n];
       w[n] = wn;
-      if ((CP != kFineSide && CP != kFineSideP) || !gam) {
-        acc[0] += r_own * un;
-        acc[1] += wn * un;
+      if ((CP != kFineSide && CP != kFineSideP) || !gam[u]) {
+        acc[2 * u] = fma(r_own[u], un, acc[2 * u]);
+        acc[2 * u + 1] = fma(wn, un, acc[2 * u + 1]);
       }
     }
-    block_sum<2>(acc, ldr);
+    block_sum<2 * S>(acc, ldr);
     if (threadIdx.x == 0) {
-      it.tpart[kTCG * it.tstride + tile] = (double)acc[0];
-      it.tpart[(kTCG + 1) * it.tstride + tile] = (double)acc[1];
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+        if (u < nsub) {
+          it.tpart[kTCG * it.tstride + b0 + u * it.ntx] = (double)acc[2 * u];
+          it.tpart[(kTCG + 1) * it.tstride + b0 + u * it.ntx] = (double)acc[2 * u + 1];
+        }
     }
-    __syncthreads();  // LDS is reused by the next tile
+    __syncthreads();  // LDS is reused by the next stack
   }
 }
 
-// One Chronopoulos-Gear PCG iteration `kit` for every item (LDS-tiled).
+// One Chronopoulos-Gear PCG iteration `kit` for every item (LDS-tiled, in
+// stacks of S tiles).
 // Composite pairs: the fine side takes its interface nodes' inputs
 // prolonged from the coarse vectors of iteration k (kFineSide here,
 // kFineSideP from couple_prolong_kernel) and leaves those rows out of its
 // dot products; the coarse side adds the
 // gathered fine rows of w_{k+1} on its interface nodes.
-template <class R, int CP>
+template <class R, int CP, int S>
 __global__ void __launch_bounds__(kBlock)
 cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
                        int round, int kit) {
-  __shared__ R u_s[HN];
-  __shared__ R k_s[EN];
-  __shared__ R lds[2 * kBlock / 64];
+  using ST = Stack<S>;
+  __shared__ R u_s[ST::HN];
+  __shared__ R k_s[ST::EN];
+  __shared__ R lds[2 * S * kBlock / 64];
   __shared__ R bc[2];
   const SolveItem& it = items[item_of_block(per_item)];
   // the state written by this round's CG-start kernel
@@ -1385,22 +1473,25 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   const R* __restrict__ d = (const R*)it.d;
   const R* __restrict__ kap = (const R*)it.kap;
   const R* __restrict__ dinv = (const R*)it.dinv;
-  // Every global input of a tile is loaded into registers in one batch:
+  // Every global input of a stack is loaded into registers in one batch:
   // the halo of r, w, s_{k-1}, Dinv (for u_{k+1}), the element
-  // conductivities, and the node's own d, p, x, s_{k-1}.  The first tile's
-  // batch is issued before the scalar reduction; in FP32 each later tile's
-  // while the previous tile's stencil is computed, so a workgroup waits on
-  // memory about once per tile, in FP64 at the top of its tile's turn.
-  R hr[HPT], hw[HPT], hs[HPT], hd[HPT], kr[EPT];
-  R o_r = (R)0, o_w = (R)0, o_di = (R)0, o_d = (R)0, o_s = (R)0, o_p = (R)0,
-    o_x = (R)0;
-  int o_n = 0;
-  bool o_act = false, o_gam = false;
-  auto load_tile = [&](const Tile& t) {
+  // conductivities, and each node's own d, p, x, s_{k-1}.  Single tiles:
+  // the first tile's batch is issued before the scalar reduction; in FP32
+  // each later tile's while the previous tile's stencil is computed, in
+  // FP64 at the top of its turn (overlapping the stencil as well takes 164
+  // registers), so a workgroup waits on memory about once per tile.  Stacks
+  // of two: FP32 as single tiles without the overlap with the stencil,
+  // FP64 each stack at the top of its turn (with the first in flight during
+  // the reduction the kernel takes 216 registers, 2 waves per SIMD).
+  R hr[ST::HPT], hw[ST::HPT], hs[ST::HPT], hd[ST::HPT], kr[ST::EPT];
+  R o_r[S], o_w[S], o_di[S], o_d[S], o_s[S], o_p[S], o_x[S];
+  int o_n[S];
+  bool o_act[S], o_gam[S];
+  auto load_stack = [&](const Tile& t) {
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
+    for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      const int n = h < HN ? halo_index(g, t, h) : -1;
+      const int n = h < ST::HN ? halo_index(g, t, h) : -1;
       int fi, fj, fk;
       if (CP == kFineSide && n >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
@@ -1430,31 +1521,41 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       }
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
+    for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      const int n = e < EN ? elem_index(g, t, e) : -1;
+      const int n = e < ST::EN ? elem_index(g, t, e) : -1;
       kr[q] = n >= 0 ? kap[n] : (R)0;
     }
-    const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
-    o_act = i < g.nx && j < g.ny && k < g.nz;
-    o_n = o_act ? pidx(g, i, j, k) : 0;
-    if (CP == kFineSide || CP == kFineSideP)
-      o_gam = o_act && fine_gamma(g, it.cp.w, i, j, k);
-    if (CP == kCoarseSide) o_gam = o_act && coarse_gamma(it.cp.w, i, j, k);
-    if (o_act) {
-      o_r = r_in[o_n];
-      o_w = w_in[o_n];
-      o_di = dinv[o_n];
-      o_d = d[o_n];
-      if (kit > 0) {
-        o_s = s_old[o_n];
-        o_p = p[o_n];
-        o_x = x[o_n];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + u * TZ + t.tz;
+      o_act[u] = i < g.nx && j < g.ny && k < g.nz;
+      o_n[u] = o_act[u] ? pidx(g, i, j, k) : 0;
+      o_gam[u] = false;
+      if (CP == kFineSide || CP == kFineSideP)
+        o_gam[u] = o_act[u] && fine_gamma(g, it.cp.w, i, j, k);
+      if (CP == kCoarseSide) o_gam[u] = o_act[u] && coarse_gamma(it.cp.w, i, j, k);
+      o_r[u] = o_w[u] = o_di[u] = o_d[u] = o_s[u] = o_p[u] = o_x[u] = (R)0;
+      if (o_act[u]) {
+        const int n = o_n[u];
+        o_r[u] = r_in[n];
+        o_w[u] = w_in[n];
+        o_di[u] = dinv[n];
+        o_d[u] = d[n];
+        if (kit > 0) {
+          o_s[u] = s_old[n];
+          o_p[u] = p[n];
+          o_x[u] = x[n];
+        }
       }
     }
   };
-  const TileRange tr = tile_range(blk, nblk, it.ntiles);
-  if (tr.first < tr.last) load_tile(tile_at(it, tr.first));
+  const TileRange tr = tile_range(blk, nblk, stack_count<S>(it));
+  int b0, nsub;
+  constexpr bool kPre = sizeof(R) == 4 || S == 1;
+  constexpr bool kNext = sizeof(R) == 4 && S == 1;
+  if (kPre && tr.first < tr.last)
+    load_stack(stack_at<S>(it, tr.first, b0, nsub));
   // gamma_k, delta_k from the previous kernel's partials (CG start or
   // iteration k-1), held in the region pair this kernel does not write
   const int rd = (kit & 1) ? kTCG2 : kTCG;
@@ -1505,61 +1606,84 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   R wts[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
-  for (int tile = tr.first; tile < tr.last; tile += tr.step) {
-    R acc[2] = {(R)0, (R)0};
-    const Tile t = tile_at(it, tile);
-    if constexpr (sizeof(R) == 8)
-      if (tile != tr.first) load_tile(t);
-    // u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo tile
+  for (int w = tr.first; w < tr.last; w += tr.step) {
+    R acc[2 * S];
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
+    for (int q = 0; q < 2 * S; ++q) acc[q] = (R)0;
+    const Tile t = stack_at<S>(it, w, b0, nsub);
+    if (!kNext && (!kPre || w != tr.first)) load_stack(t);
+    // u_{k+1} = Dinv (r_k - alpha (w_k + beta s_{k-1})) on the halo
+#pragma unroll
+    for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      if (h < HN) u_s[h] = hd[q] * (hr[q] - alpha * (hw[q] + beta * hs[q]));
+      if (h < ST::HN)
+        u_s[h] = hd[q] * fma(-alpha, fma(beta, hs[q], hw[q]), hr[q]);
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
+    for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      if (e < EN) k_s[e] = kr[q];
+      if (e < ST::EN) k_s[e] = kr[q];
     }
     __syncthreads();
-    const bool active = o_act, gam = o_gam;
-    const int n = o_n;
-    const R r_own = o_r, w_own = o_w, di_own = o_di, d_own = o_d,
-            s_prev = o_s, p_own = o_p, x_own = o_x;
-    // FP32: the next tile's loads fly during this tile's stencil; FP64
-    // loads each later tile at the top of its turn (overlapping the stencil
-    // as well would take 164 registers)
-    if constexpr (sizeof(R) == 4)
-      if (tile + tr.step < tr.last)
-        load_tile(tile_at(it, tile + tr.step));
-    // the node's own recurrences and w_{k+1} = J u_{k+1}
-    if (active) {
+    bool act[S], gamv[S];
+    int nn[S];
+    R r_own[S], w_own[S], di_own[S], d_own[S], s_prev[S], p_own[S], x_own[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      act[u] = o_act[u];
+      gamv[u] = o_gam[u];
+      nn[u] = o_n[u];
+      r_own[u] = o_r[u];
+      w_own[u] = o_w[u];
+      di_own[u] = o_di[u];
+      d_own[u] = o_d[u];
+      s_prev[u] = o_s[u];
+      p_own[u] = o_p[u];
+      x_own[u] = o_x[u];
+    }
+    if (kNext && w + tr.step < tr.last) {
+      int nb0, nns;
+      load_stack(stack_at<S>(it, w + tr.step, nb0, nns));
+    }
+    // the nodes' own recurrences and w_{k+1} = J u_{k+1}
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      if (!act[u]) continue;
+      const int n = nn[u];
+      Tile tu = t;
+      tu.tz += u * TZ;
       // (a slaved interface node of a fine side keeps zero recurrences: its
       // values come from the coarse side)
+      const bool gam = gamv[u];
       const bool slave = (CP == kFineSide || CP == kFineSideP) && gam;
-      const R s_k = slave ? (R)0 : w_own + beta * s_prev;
-      const R u_k = di_own * r_own;
-      const R pn = slave ? (R)0 : u_k + beta * p_own;
+      // (explicit fma throughout: every kernel instance rounds alike)
+      const R s_k = slave ? (R)0 : fma(beta, s_prev[u], w_own[u]);
+      const R u_k = di_own[u] * r_own[u];
+      const R pn = slave ? (R)0 : fma(beta, p_own[u], u_k);
       p[n] = pn;
       s_out[n] = s_k;
-      x[n] = x_own + alpha * pn;
-      const R r1 = slave ? (R)0 : r_own - alpha * s_k;
+      x[n] = fma(alpha, pn, x_own[u]);
+      const R r1 = slave ? (R)0 : fma(-alpha, s_k, r_own[u]);
       r_out[n] = r1;
-      const R u1 = u_s[(t.tz + 1) * (HX * HY) + (t.ty + 1) * HX + (t.tx + 1)];
-      R w1 = d_own * u1 + stencil_lds(t, u_s, k_s, wts);
+      const R u1 = u_s[(tu.tz + 1) * (HX * HY) + (tu.ty + 1) * HX + (tu.tx + 1)];
+      R w1 = fma(d_own[u], u1, stencil_lds(tu, u_s, k_s, wts));
       if (CP == kCoarseSide && gam) w1 += ((const R*)it.cp.gDW)[n];
       w_out[n] = w1;
       if ((CP != kFineSide && CP != kFineSideP) || !gam) {
-        acc[0] += r1 * u1;
-        acc[1] += w1 * u1;
+        acc[2 * u] = fma(r1, u1, acc[2 * u]);
+        acc[2 * u + 1] = fma(w1, u1, acc[2 * u + 1]);
       }
     }
-    block_sum<2>(acc, lds);
+    block_sum<2 * S>(acc, lds);
     if (threadIdx.x == 0) {
-      it.tpart[wr * ts + tile] = (double)acc[0];
-      it.tpart[(wr + 1) * ts + tile] = (double)acc[1];
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+        if (u < nsub) {
+          it.tpart[wr * ts + b0 + u * it.ntx] = (double)acc[2 * u];
+          it.tpart[(wr + 1) * ts + b0 + u * it.ntx] = (double)acc[2 * u + 1];
+        }
     }
-    __syncthreads();  // LDS is reused by the next tile
+    __syncthreads();  // LDS is reused by the next stack
   }
 }
 
@@ -1769,6 +1893,11 @@ int grid_tiles(const Geo& g, int& ntx, int& nty) {
   tiles_of(g, ntx, nty, ntz);
   return ntx * nty * ntz;
 }
+int cg_stacks(const Geo& g) {
+  int ntx, nty, ntz;
+  tiles_of(g, ntx, nty, ntz);
+  return ntx * nty * ((ntz + 1) / 2);
+}
 
 // Workgroups of a kernel that the device holds at once: the occupancy
 // limit per compute unit (set by its registers and LDS) times the compute
@@ -1806,30 +1935,56 @@ static void launch_residual(Launch L, const SolveItem* items, int n_items,
                      dim3(n_items * per_item), dim3(kBlock), 0,
                      (hipStream_t)L.stream, items, per_item, round);
 }
-template <class R, int CP>
-static void launch_cg_start(Launch L, const SolveItem* items, int n_items,
-                            int ntiles, int round) {
-  static const int resident = resident_blocks(cg_start_batched_kernel<R, CP>);
-  const int per_item = item_tile_blocks(ntiles, n_items, resident);
-  hipLaunchKernelGGL((cg_start_batched_kernel<R, CP>),
-                     dim3(n_items * per_item), dim3(kBlock), 0,
-                     (hipStream_t)L.stream, items, per_item, round);
+// The CG kernels in stacks of two when each workgroup would walk two
+// single tiles (see Stack).
+static inline bool use_stacks(int per1, int ntiles) {
+  return per1 < ntiles && ntiles <= 2 * per1;
 }
 template <class R, int CP>
-static void launch_cg_iter(Launch L, const SolveItem* items, int n_items,
-                           int ntiles, int round, int kit, void* ev_start,
-                           void* ev_stop) {
-  static const int resident = resident_blocks(cg_iter_batched_kernel<R, CP>);
-  const int per_item = item_tile_blocks(ntiles, n_items, resident);
+static void launch_cg_start(Launch L, const SolveItem* items, int n_items,
+                            int ntiles, int nstacks, int round) {
+  static const int res1 = resident_blocks(cg_start_batched_kernel<R, CP, 1>);
+  static const int res2 = resident_blocks(cg_start_batched_kernel<R, CP, 2>);
+  const int per1 = item_tile_blocks(ntiles, n_items, res1);
+  if (!use_stacks(per1, ntiles)) {
+    hipLaunchKernelGGL((cg_start_batched_kernel<R, CP, 1>),
+                       dim3(n_items * per1), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, items, per1, round);
+  } else {
+    const int per2 = item_tile_blocks(nstacks, n_items, res2);
+    hipLaunchKernelGGL((cg_start_batched_kernel<R, CP, 2>),
+                       dim3(n_items * per2), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, items, per2, round);
+  }
+}
+template <class R, int CP, int S>
+static void launch_cg_iter_s(Launch L, const SolveItem* items, int n_items,
+                             int per_item, int round, int kit, void* ev_start,
+                             void* ev_stop) {
   if (ev_start != nullptr)
-    hipExtLaunchKernelGGL((cg_iter_batched_kernel<R, CP>),
+    hipExtLaunchKernelGGL((cg_iter_batched_kernel<R, CP, S>),
                           dim3(n_items * per_item), dim3(kBlock), 0,
                           (hipStream_t)L.stream, (hipEvent_t)ev_start,
                           (hipEvent_t)ev_stop, 0, items, per_item, round, kit);
   else
-    hipLaunchKernelGGL((cg_iter_batched_kernel<R, CP>),
+    hipLaunchKernelGGL((cg_iter_batched_kernel<R, CP, S>),
                        dim3(n_items * per_item), dim3(kBlock), 0,
                        (hipStream_t)L.stream, items, per_item, round, kit);
+}
+template <class R, int CP>
+static void launch_cg_iter(Launch L, const SolveItem* items, int n_items,
+                           int ntiles, int nstacks, int round, int kit,
+                           void* ev_start, void* ev_stop) {
+  static const int res1 = resident_blocks(cg_iter_batched_kernel<R, CP, 1>);
+  static const int res2 = resident_blocks(cg_iter_batched_kernel<R, CP, 2>);
+  const int per1 = item_tile_blocks(ntiles, n_items, res1);
+  if (!use_stacks(per1, ntiles))
+    launch_cg_iter_s<R, CP, 1>(L, items, n_items, per1, round, kit, ev_start,
+                               ev_stop);
+  else
+    launch_cg_iter_s<R, CP, 2>(L, items, n_items,
+                               item_tile_blocks(nstacks, n_items, res2), round,
+                               kit, ev_start, ev_stop);
 }
 template <class R>
 void k_residual_batched(Launch L, const SolveItem* items, int n_items,
@@ -1838,15 +1993,15 @@ void k_residual_batched(Launch L, const SolveItem* items, int n_items,
 }
 template <class R>
 void k_cg_start_batched(Launch L, const SolveItem* items, int n_items,
-                        int ntiles, int round) {
-  launch_cg_start<R, kAlone>(L, items, n_items, ntiles, round);
+                        int ntiles, int nstacks, int round) {
+  launch_cg_start<R, kAlone>(L, items, n_items, ntiles, nstacks, round);
 }
 template <class R>
 void k_cg_iter_batched(Launch L, const SolveItem* items, int n_items,
-                       int ntiles, int round, int kit, void* ev_start,
-                       void* ev_stop) {
-  launch_cg_iter<R, kAlone>(L, items, n_items, ntiles, round, kit, ev_start,
-                            ev_stop);
+                       int ntiles, int nstacks, int round, int kit,
+                       void* ev_start, void* ev_stop) {
+  launch_cg_iter<R, kAlone>(L, items, n_items, ntiles, nstacks, round, kit,
+                            ev_start, ev_stop);
 }
 template <class R>
 void k_residual_pair(Launch L, const SolveItem* items, int n_items,
@@ -1860,27 +2015,27 @@ void k_residual_pair(Launch L, const SolveItem* items, int n_items,
 }
 template <class R>
 void k_cg_start_pair(Launch L, const SolveItem* items, int n_items,
-                     int ntiles, int round, int side) {
+                     int ntiles, int nstacks, int round, int side) {
   if (side == kFineSide)
-    launch_cg_start<R, kFineSide>(L, items, n_items, ntiles, round);
+    launch_cg_start<R, kFineSide>(L, items, n_items, ntiles, nstacks, round);
   else if (side == kFineSideP)
-    launch_cg_start<R, kFineSideP>(L, items, n_items, ntiles, round);
+    launch_cg_start<R, kFineSideP>(L, items, n_items, ntiles, nstacks, round);
   else
-    launch_cg_start<R, kCoarseSide>(L, items, n_items, ntiles, round);
+    launch_cg_start<R, kCoarseSide>(L, items, n_items, ntiles, nstacks, round);
 }
 template <class R>
 void k_cg_iter_pair(Launch L, const SolveItem* items, int n_items,
-                    int ntiles, int round, int kit, int side,
+                    int ntiles, int nstacks, int round, int kit, int side,
                     void* ev_start, void* ev_stop) {
   if (side == kFineSide)
-    launch_cg_iter<R, kFineSide>(L, items, n_items, ntiles, round, kit,
-                                 ev_start, ev_stop);
+    launch_cg_iter<R, kFineSide>(L, items, n_items, ntiles, nstacks, round,
+                                 kit, ev_start, ev_stop);
   else if (side == kFineSideP)
-    launch_cg_iter<R, kFineSideP>(L, items, n_items, ntiles, round, kit,
-                                  ev_start, ev_stop);
+    launch_cg_iter<R, kFineSideP>(L, items, n_items, ntiles, nstacks, round,
+                                  kit, ev_start, ev_stop);
   else
-    launch_cg_iter<R, kCoarseSide>(L, items, n_items, ntiles, round, kit,
-                                   ev_start, ev_stop);
+    launch_cg_iter<R, kCoarseSide>(L, items, n_items, ntiles, nstacks, round,
+                                   kit, ev_start, ev_stop);
 }
 template <class R>
 void k_couple_prolong(Launch L, const SolveItem* fine_items, int n_items,
@@ -1901,15 +2056,15 @@ void k_couple_gather(Launch L, const SolveItem* coarse_items, int n_items,
   template void k_residual_batched<R>(Launch, const SolveItem*, int, int,    \
                                       int);                                  \
   template void k_cg_start_batched<R>(Launch, const SolveItem*, int, int,    \
-                                      int);                                  \
+                                      int, int);                             \
   template void k_cg_iter_batched<R>(Launch, const SolveItem*, int, int, int, \
-                                     int, void*, void*);                     \
+                                     int, int, void*, void*);                \
   template void k_residual_pair<R>(Launch, const SolveItem*, int, int, int,  \
                                    int);                                     \
   template void k_cg_start_pair<R>(Launch, const SolveItem*, int, int, int,  \
-                                   int);                                     \
+                                   int, int);                                \
   template void k_cg_iter_pair<R>(Launch, const SolveItem*, int, int, int,   \
-                                  int, int, void*, void*);                   \
+                                  int, int, int, void*, void*);              \
   template void k_couple_gather<R>(Launch, const SolveItem*, int, int, int,  \
                                    int, int);                                \
   template void k_couple_prolong<R>(Launch, const SolveItem*, int, int, int, \
@@ -1923,12 +2078,15 @@ TL_BATCH_INST(double)
 constexpr long kZmarchNodes = 4l << 20;
 
 template <class R>
-void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
-                R* y) {
-  if ((long)g.nreal > kZmarchNodes && g.nz >= 8) {
+void k_op_apply(Launch L, const Geo& g, int kernel, int blocks, const R* d,
+                const R* kap, const R* v, R* y) {
+  if (kernel == kOpAuto)
+    kernel = (long)g.nreal > kZmarchNodes && g.nz >= 8 ? kOpZmarch : kOpTiled;
+  if (kernel == kOpZmarch) {
     const ZPlan zp = zplan_of<R>(g);
     const int units = zp.ncx * zp.ncy * zp.nrun;
-    hipLaunchKernelGGL(op_apply_zmarch_kernel<R>, dim3(tiled_grid(units)),
+    hipLaunchKernelGGL(op_apply_zmarch_kernel<R>,
+                       dim3(blocks > 0 ? blocks : tiled_grid(units)),
                        dim3(kBlock), 0, (hipStream_t)L.stream, g, zp, d, kap,
                        v, y);
     return;
@@ -1936,13 +2094,14 @@ void k_op_apply(Launch L, const Geo& g, const R* d, const R* kap, const R* v,
   int ntx, nty, ntz;
   tiles_of(g, ntx, nty, ntz);
   const int ntiles = ntx * nty * ntz;
-  hipLaunchKernelGGL(op_apply_tiled_kernel<R>, dim3(tiled_grid(ntiles)),
+  hipLaunchKernelGGL(op_apply_tiled_kernel<R>,
+                     dim3(blocks > 0 ? blocks : tiled_grid(ntiles)),
                      dim3(kBlock), 0, (hipStream_t)L.stream, g, ntx, nty,
                      ntiles, d, kap, v, y);
 }
-template void k_op_apply<float>(Launch, const Geo&, const float*, const float*,
-                                const float*, float*);
-template void k_op_apply<double>(Launch, const Geo&, const double*,
+template void k_op_apply<float>(Launch, const Geo&, int, int, const float*,
+                                const float*, const float*, float*);
+template void k_op_apply<double>(Launch, const Geo&, int, int, const double*,
                                  const double*, const double*, double*);
 
 // ---------------------------------------------------------------------------

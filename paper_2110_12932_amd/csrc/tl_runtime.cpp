@@ -389,7 +389,8 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
                            hipMemcpyHostToDevice, B.stream),
             "hipMemcpyAsync(scalars)");
   std::vector<int> act, built, round_iters;
-  int round = 0, tiles_a = 0, tiles_c = 0, per_p = 0, max_gamma = 0;
+  int round = 0, tiles_a = 0, tiles_c = 0, stacks_a = 0, stacks_c = 0;
+  int per_p = 0, max_gamma = 0;
   for (;;) {
     act.clear();
     for (int u = 0; u < nu; ++u)
@@ -398,12 +399,17 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
     const int na = (int)act.size();
     if (act != built) {
       int most = 1, most_c = 1;
+      stacks_a = stacks_c = 1;
       max_gamma = 0;
       for (int u : act) {
         int ntx, nty;
-        most = std::max(most, grid_tiles(jobs[paired ? 2 * u : u]->g, ntx, nty));
+        const Geo& ga = jobs[paired ? 2 * u : u]->g;
+        most = std::max(most, grid_tiles(ga, ntx, nty));
+        stacks_a = std::max(stacks_a, cg_stacks(ga));
         if (paired) {
-          most_c = std::max(most_c, grid_tiles(jobs[2 * u + 1]->g, ntx, nty));
+          const Geo& gc = jobs[2 * u + 1]->g;
+          most_c = std::max(most_c, grid_tiles(gc, ntx, nty));
+          stacks_c = std::max(stacks_c, cg_stacks(gc));
           max_gamma = std::max(max_gamma, jobs[2 * u + 1]->cpl.ngamma);
         }
       }
@@ -455,16 +461,17 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
     for (int rr = 0; rr < n_rounds; ++rr, ++round) {
       if (!paired) {
         k_residual_batched<R>(B.L, fi, na, tiles_a, round);
-        k_cg_start_batched<R>(B.L, fi, na, tiles_a, round);
+        k_cg_start_batched<R>(B.L, fi, na, tiles_a, stacks_a, round);
       } else {
         if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 0, 0);
         k_residual_pair<R>(B.L, fi, na, tiles_a, round, fside);
         k_couple_gather<R>(B.L, ci, na, max_gamma, round, 0, 0);
         k_residual_pair<R>(B.L, ci, na, tiles_c, round, kCoarseSide);
         if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 1, 0);
-        k_cg_start_pair<R>(B.L, fi, na, tiles_a, round, fside);
+        k_cg_start_pair<R>(B.L, fi, na, tiles_a, stacks_a, round, fside);
         k_couple_gather<R>(B.L, ci, na, max_gamma, round, 1, 0);
-        k_cg_start_pair<R>(B.L, ci, na, tiles_c, round, kCoarseSide);
+        k_cg_start_pair<R>(B.L, ci, na, tiles_c, stacks_c, round,
+                           kCoarseSide);
       }
       for (int k = 0; k < n_launch; ++k) {
         // sampled event timing covers the plain CG kernel (not the pairs'),
@@ -476,14 +483,15 @@ void solve_batch(BatchCtx& B, std::vector<Job<R>*>& jobs, Profiler* prof,
         void* e0 = timed ? (void*)prof->ev[2 * prof->used] : nullptr;
         void* e1 = timed ? (void*)prof->ev[2 * prof->used + 1] : nullptr;
         if (!paired) {
-          k_cg_iter_batched<R>(B.L, fi, na, tiles_a, round, k, e0, e1);
+          k_cg_iter_batched<R>(B.L, fi, na, tiles_a, stacks_a, round, k, e0,
+                               e1);
         } else {
           if (prolong) k_couple_prolong<R>(B.L, fi, na, per_p, round, 2, k);
-          k_cg_iter_pair<R>(B.L, fi, na, tiles_a, round, k, fside, nullptr,
-                            nullptr);
-          k_couple_gather<R>(B.L, ci, na, max_gamma, round, 2, k);
-          k_cg_iter_pair<R>(B.L, ci, na, tiles_c, round, k, kCoarseSide,
+          k_cg_iter_pair<R>(B.L, fi, na, tiles_a, stacks_a, round, k, fside,
                             nullptr, nullptr);
+          k_couple_gather<R>(B.L, ci, na, max_gamma, round, 2, k);
+          k_cg_iter_pair<R>(B.L, ci, na, tiles_c, stacks_c, round, k,
+                            kCoarseSide, nullptr, nullptr);
         }
         if (timed) {
           prof->k[prof->used] = k;
@@ -2406,24 +2414,29 @@ tl_status tl_op_sync_probe(int blocks, int rounds, int barrier, double* data,
   return res;
 }
 
-tl_status tl_op_apply(const tl_grid* grid, int precision, const void* d,
-                      const void* kappa, const void* v, void* y, int repeat,
-                      void* hip_stream) {
+tl_status tl_op_apply(const tl_grid* grid, int precision, int kernel,
+                      int blocks, const void* d, const void* kappa,
+                      const void* v, void* y, int repeat, void* hip_stream) {
   tl_status st = check_grid(grid);
   if (st != TL_OK) return st;
   if (!d || !kappa || !v || !y || repeat < 1)
     return fail(TL_EINVAL, "bad operator arguments");
   if (precision != TL_FP64 && precision != TL_MIXED)
     return fail(TL_EINVAL, "unknown precision");
+  if (kernel != kOpAuto && kernel != kOpTiled && kernel != kOpZmarch)
+    return fail(TL_EINVAL, "unknown operator kernel");
+  if (blocks < 0 || blocks % 8 != 0 || blocks > (1 << 20))
+    return fail(TL_EINVAL, "workgroup count must be 0 or a positive multiple "
+                           "of 8 up to 2^20");
   Launch L{hip_stream};
   const Geo g = geo_of(grid);
   for (int q = 0; q < repeat; ++q) {
     if (precision == TL_FP64)
-      k_op_apply<double>(L, g, (const double*)d, (const double*)kappa,
-                         (const double*)v, (double*)y);
+      k_op_apply<double>(L, g, kernel, blocks, (const double*)d,
+                         (const double*)kappa, (const double*)v, (double*)y);
     else
-      k_op_apply<float>(L, g, (const float*)d, (const float*)kappa,
-                        (const float*)v, (float*)y);
+      k_op_apply<float>(L, g, kernel, blocks, (const float*)d,
+                        (const float*)kappa, (const float*)v, (float*)y);
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize((hipStream_t)hip_stream));

@@ -168,7 +168,8 @@ def load():
         f.restype = C.c_int
         f.argtypes = [C.POINTER(tl_grid), C.c_int, C.c_int, vp, vp, vp]
     lib.tl_op_apply.restype = C.c_int
-    lib.tl_op_apply.argtypes = [C.POINTER(tl_grid), C.c_int, vp, vp, vp, vp, C.c_int, vp]
+    lib.tl_op_apply.argtypes = [C.POINTER(tl_grid), C.c_int, C.c_int, C.c_int, vp, vp, vp, vp,
+                                C.c_int, vp]
     lib.tl_op_sync_probe.restype = C.c_int
     lib.tl_op_sync_probe.argtypes = [C.c_int, C.c_int, C.c_int, vp, sz, vp,
                                      C.POINTER(C.c_double), vp]
@@ -331,8 +332,13 @@ def tl_op_unpack(grid, kind, padded, plain, stream=None):
                                C.c_void_p(_stream_ptr(stream))))
 
 
-def tl_op_apply(grid, precision, d, kappa, v, y, repeat=1, stream=None):
-    _check(load().tl_op_apply(C.byref(grid), precision, C.c_void_p(d.data_ptr()),
+OP_AUTO, OP_TILED, OP_ZMARCH = 0, 1, 2
+
+
+def tl_op_apply(grid, precision, d, kappa, v, y, repeat=1, stream=None, kernel=OP_AUTO,
+                blocks=0):
+    _check(load().tl_op_apply(C.byref(grid), precision, int(kernel), int(blocks),
+                              C.c_void_p(d.data_ptr()),
                               C.c_void_p(kappa.data_ptr()), C.c_void_p(v.data_ptr()),
                               C.c_void_p(y.data_ptr()), int(repeat),
                               C.c_void_p(_stream_ptr(stream))))

@@ -162,3 +162,22 @@ def test_sync_probe_rejects_before_the_device():
     assert lib.tl_op_sync_probe(256, 0, 0, fake, 10, fake, C.byref(us), None) == tl.TL_EINVAL
     assert lib.tl_op_sync_probe(0, 1, 0, fake, 10, fake, C.byref(us), None) == tl.TL_EINVAL
     assert lib.tl_op_sync_probe(256, 1, 0, fake, 0, fake, C.byref(us), None) == tl.TL_EINVAL
+
+
+def test_op_apply_rejects_before_the_device():
+    """tl_op_apply checks the kernel choice and the workgroup count before
+    any HIP call."""
+    import ctypes as C
+    lib = tl.load()
+    grid = tl.to_grid(8, 8, 8, 1e-5, 1e-5, 1e-5)
+    fake = C.c_void_p(256)   # never dereferenced: the arguments fail first
+    call = lambda prec, kern, blocks, rep=1: lib.tl_op_apply(
+        C.byref(grid), prec, kern, blocks, fake, fake, fake, fake, rep, None)
+    assert call(tl.TL_FP64, 3, 0) == tl.TL_EINVAL
+    assert call(tl.TL_FP64, -1, 0) == tl.TL_EINVAL
+    for blocks in (-8, 4, 12, 2**20 + 8):
+        assert call(tl.TL_FP64, tl.OP_TILED, blocks) == tl.TL_EINVAL
+    assert call(7, tl.OP_TILED, 0) == tl.TL_EINVAL
+    assert call(tl.TL_MIXED, tl.OP_ZMARCH, 8, rep=0) == tl.TL_EINVAL
+    assert lib.tl_op_apply(C.byref(grid), tl.TL_FP64, 0, 0, None, fake, fake, fake, 1,
+                           None) == tl.TL_EINVAL

@@ -12,6 +12,8 @@ tests/golden/make_golden.py for given macro-step counts:
 * requests 0, 1 and 2 of the served stream after 4 macro steps each, at the
   served shape (81 x 49 x 25 fine window), served in a mix of the stream's
   first 64 requests.
+The raster window's CG kernels run on stacks of two tiles alone and on
+single tiles beside a second request: the two agree bitwise.
 Bars: FP64 path <= 1e-9, mixed and served <= 1e-6 relative max-norm on both
 levels.  Where no golden is stored, properties that hold at any size: the
 mixed path agrees with the FP64 path to 1e-6, the ledger closes, fields are
@@ -164,3 +166,33 @@ def test_served_shape_mix_of_64_against_oracle_and_alone():
         Cs, Fs, _, _, _ = res[q]
         assert np.array_equal(Ca, Cs) and np.array_equal(Fa, Fs), q
     say("  alone == in the mix of 64, bitwise, for requests 0, 1, 2, 31, 63")
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
+def test_raster_window_stacked_and_single_tiles_agree_bitwise(prec):
+    """The raster build's 1344-tile window runs its CG kernels on stacks of
+    two tiles when alone (each workgroup would walk two tiles) and on single
+    tiles when a second request shares the launches (more tiles per
+    workgroup); the per-tile partial sums are the same numbers in the same
+    order, so the fields after 2 macro steps are bitwise equal (the run
+    alone is checked against the oracle by the golden test above)."""
+    wl = W.raster_10mm(prec)
+    Ca, Fa, _, _, _ = _run(wl, 2)
+    pool = 2 * (tl.tl_workspace_bytes(wl.mesh, wl.options) + 4096)
+    pool += tl.tl_server_overhead_bytes(2) + (1 << 20)
+    say("raster_10mm twice in one server, precision", prec)
+    sv = tl.Server(pool, max_slots=2)
+    try:
+        ids = [sv.submit(wl, n_macro=2) for _ in range(2)]
+        most = 0
+        for _ in range(50):
+            active, queued, _ = sv.tick()
+            most = max(most, active)
+            if active == 0 and queued == 0:
+                break
+        assert most == 2
+        res = [sv.result(i) for i in ids]
+    finally:
+        sv.close()
+    for Cs, Fs, _, _, _ in res:
+        assert np.array_equal(Ca, Cs) and np.array_equal(Fa, Fs)

@@ -126,6 +126,47 @@ def test_op_apply_large_grid_sampled(prec):
     assert err.max() < tol, err.max()
 
 
+# Both kernels sum each node's terms in the same order, so the 3D-tiled
+# kernel (16 x 4 x 4 LDS tiles) and the z-marching one (64 x 4 columns, two
+# LDS planes), at their own workgroup counts and at a few others (8: one
+# workgroup per XCD walks its whole chunk, reusing LDS from tile to tile),
+# must agree bitwise: a missing barrier or a wrong halo shows up as a
+# difference.  y starts as NaN, so a node left unwritten shows too.
+@pytest.mark.parametrize("cells", [(13, 9, 5), (70, 37, 23), (300, 120, 132)])
+@pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
+def test_op_apply_kernels_and_workgroup_counts_agree_bitwise(cells, prec):
+    nx, ny, nz = cells
+    h = (5.3e-6, 4.1e-6, 6.7e-6)
+    g = G.Grid(nx, ny, nz, *h)
+    rng = np.random.default_rng(5)
+    d = rng.uniform(1e-4, 1e-3, g.n_nodes)
+    kap = rng.uniform(10.0, 30.0, g.n_elems)
+    v = rng.normal(300.0, 50.0, g.n_nodes)
+    dt = torch.float64 if prec == W.FP64 else torch.float32
+    grid = tl.to_grid(nx, ny, nz, *h)
+    npad = tl.tl_op_padded_size(grid)
+    dev = lambda a: torch.tensor(a, dtype=dt, device="cuda")
+    pads = [torch.empty(npad, dtype=dt, device="cuda") for _ in range(4)]
+    tl.tl_op_pack(grid, 0, dev(d), pads[0])
+    tl.tl_op_pack(grid, 1, dev(kap), pads[1])
+    tl.tl_op_pack(grid, 0, dev(v), pads[2])
+    out = {}
+    for kern, blocks in [(tl.OP_TILED, 0), (tl.OP_TILED, 8), (tl.OP_TILED, 40),
+                         (tl.OP_ZMARCH, 0), (tl.OP_ZMARCH, 8), (tl.OP_ZMARCH, 24),
+                         (tl.OP_AUTO, 0)]:
+        say("op_apply", cells, prec, "kernel", kern, "workgroups", blocks)
+        pads[3].fill_(float("nan"))
+        tl.tl_op_apply(grid, prec, pads[0], pads[1], pads[2], pads[3], kernel=kern,
+                       blocks=blocks)
+        y = torch.empty(g.n_nodes, dtype=dt, device="cuda")
+        tl.tl_op_unpack(grid, 0, pads[3], y)
+        out[kern, blocks] = y.cpu().numpy()
+    ref = out[tl.OP_TILED, 0]
+    assert np.isfinite(ref).all()
+    for key, y in out.items():
+        assert np.array_equal(y, ref), (key, int((y != ref).sum()))
+
+
 def test_rollback_after_window_move_restores_every_buffer():
     """A step that fails after the window has moved and after its fine
     micro steps rolled the field buffers leaves exactly the committed state:
