@@ -2388,12 +2388,13 @@ micro_post_kernel(const MicroItem* __restrict__ items, int per_item) {
   }
 }
 
-// One workgroup per simulation: the nblk partials of region reg
-// (in order) times scale, added into the slot the item names for that sum.
+// One wave per simulation: the nblk partials of region reg times scale,
+// added into the slot the item names for that sum.  Lane l adds partials
+// l, l + 64, ... in order, then the wave's fixed shuffle tree: the same
+// order every time, whatever else the launch holds.
 __global__ void __launch_bounds__(64)
 micro_finalize_kernel(const MicroItem* __restrict__ items, int post) {
   const MicroItem& it = items[blockIdx.x];
-  if (threadIdx.x != 0) return;
   for (int reg = 0; reg < (post ? 2 : 1); ++reg) {
     double* slot = post ? (reg == 0 ? it.slot_bottom : it.slot_surf) : it.slot_abs;
     const double scale = post ? (reg == 0 ? it.scale_bottom : it.scale_surf)
@@ -2402,8 +2403,10 @@ micro_finalize_kernel(const MicroItem* __restrict__ items, int post) {
     if (post && reg == 0 && !it.w.bottom) continue;
     if (post && reg == 1 && it.sf.h == 0.0 && it.sf.es == 0.0) continue;
     double sum = 0.0;
-    for (int b = 0; b < it.nblk; ++b) sum += it.part[reg * kMaxBlocks + b];
-    *slot += scale * sum;
+    for (int b = threadIdx.x; b < it.nblk; b += 64)
+      sum += it.part[reg * kMaxBlocks + b];
+    sum = wave_sum(sum);
+    if (threadIdx.x == 0) *slot += scale * sum;
   }
 }
 

@@ -12,7 +12,10 @@ Usage:
   python tests/golden/make_golden.py served_tracks 4 --requests 0,1,2
     (requests q of the served stream, each alone, after 4 macro steps:
      tests/golden/served_req<q>_n4.npz)
+  python tests/golden/make_golden.py single_track_2mm 20 --snap 3,20 --coupling consistent
+    (another two-level correction: tests/golden/<name>_<coupling>_n<steps>.npz)
 """
+from dataclasses import replace
 import argparse
 import os
 import sys
@@ -61,6 +64,8 @@ def main():
                     help="comma-separated step counts to store (default: the last)")
     ap.add_argument("--requests", default="0",
                     help="served_tracks: comma-separated request numbers")
+    ap.add_argument("--coupling", default=None, choices=["dn", "alternate", "consistent"],
+                    help="two-level correction other than the workload's (composite)")
     a = ap.parse_args()
     snaps = {a.steps} if a.snap is None else {int(s) for s in a.snap.split(",")}
     if a.name == "served_tracks":
@@ -69,7 +74,13 @@ def main():
             wl = stream[q][1]
             run(wl, wl.name, min(a.steps, wl.n_macro), snaps)
         return
-    run(W.by_name(a.name), a.name, a.steps, snaps)
+    wl = W.by_name(a.name)
+    name = a.name
+    if a.coupling is not None:
+        code = {"dn": W.DN, "alternate": W.ALTERNATE, "consistent": W.CONSISTENT}[a.coupling]
+        wl = replace(wl, options=replace(wl.options, coupling=code))
+        name = f"{a.name}_{a.coupling}"
+    run(wl, name, a.steps, snaps)
 
 
 if __name__ == "__main__":

@@ -196,3 +196,31 @@ def test_raster_window_stacked_and_single_tiles_agree_bitwise(prec):
         sv.close()
     for Cs, Fs, _, _, _ in res:
         assert np.array_equal(Ca, Cs) and np.array_equal(Fa, Fs)
+
+
+@pytest.mark.parametrize("steps", [3, 20])
+@pytest.mark.parametrize("coupling", ["consistent", "alternate"])
+@pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
+def test_single_track_2mm_other_formulations_against_oracle_golden(prec, coupling, steps):
+    """The consistent and the alternate global formulations at config 1's
+    size, over the first 3 macro steps and over the 20 that include the
+    window's first moves, against the oracle's fields for the same
+    formulation."""
+    code = {"consistent": W.CONSISTENT, "alternate": W.ALTERNATE}[coupling]
+    wl = W.single_track_2mm(prec)
+    wl = replace(wl, options=replace(wl.options, coupling=code))
+    st = _check(f"single_track_2mm_{coupling}", wl, steps)
+    if steps == 20:
+        assert st["window_moves"] >= 1
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.MIXED])
+def test_single_track_2mm_dn_against_composite_golden(prec):
+    """The Dirichlet-Neumann iteration converges to the composite-grid
+    solution (to its own tolerance, well inside the bars), so the DN form
+    at config 1's size matches the composite oracle's fields after the 20
+    macro steps the benchmark times for this workload."""
+    wl = W.single_track_2mm(prec)
+    wl = replace(wl, options=replace(wl.options, coupling=W.DN))
+    st = _check("single_track_2mm", wl, 20)
+    assert st["dn_iters"] >= 20
