@@ -254,3 +254,78 @@ def test_phase_times_cover_the_step():
         assert sum(ph) <= st["step_ms"] * 1.05
     finally:
         sim.close()
+
+
+class _Gathered:
+    """Values of a flat array at a few indices, read like the array."""
+
+    def __init__(self, idx, vals):
+        self.m = dict(zip(idx.tolist(), vals.tolist()))
+
+    def __getitem__(self, i):
+        return self.m[int(i)]
+
+
+# The largest grid tl_op_apply takes: 1246^3 cells, 1.997e9 padded entries
+# per array, just under the 2e9 limit (all indices fit an int).  FP32: 8 GB
+# per padded array, about 70 GB of device memory in all.  Both kernels
+# write every node (y starts as NaN) and agree bitwise; sampled nodes,
+# including the grid's far corner, match the element-by-element sum.
+def test_op_apply_at_the_largest_grid():
+    n = 1246
+    h = (5.3e-6, 4.1e-6, 6.7e-6)
+    grid = tl.to_grid(n, n, n, *h)
+    npad = tl.tl_op_padded_size(grid)
+    px = (n + 3 + 31) // 32 * 32
+    assert npad == px * (n + 3) * (n + 3) and 1.9e9 < npad <= 2.0e9
+    free, _ = torch.cuda.mem_get_info()
+    if free < 90 * 2**30:
+        pytest.skip("needs about 70 GB of free device memory")
+    say("op_apply largest grid", (n, n, n), "padded entries", npad)
+    g = G.Grid(n, n, n, *h)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    dt = torch.float32
+    d = torch.empty(g.n_nodes, dtype=dt, device="cuda").uniform_(1e-4, 1e-3, generator=gen)
+    v = torch.empty(g.n_nodes, dtype=dt, device="cuda").normal_(300.0, 50.0, generator=gen)
+    kap = torch.empty(g.n_elems, dtype=dt, device="cuda").uniform_(10.0, 30.0, generator=gen)
+    rng = np.random.default_rng(13)
+    nodes = [(0, 0, 0), (n, n, n), (n, 0, n), (0, n, 0), (n - 1, n, 1), (645, 3, n)]
+    nodes += [tuple(int(t) for t in rng.integers(0, n + 1, 3)) for _ in range(60)]
+    # the inputs the reference needs: 27 node values and 8 elements per node
+    nid, eid = set(), set()
+    for (i, j, k) in nodes:
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    a, b, c = i + dx, j + dy, k + dz
+                    if 0 <= a <= n and 0 <= b <= n and 0 <= c <= n:
+                        nid.add(g.node(a, b, c))
+                    if 0 <= a < n and 0 <= b < n and 0 <= c < n:
+                        eid.add(a + n * (b + n * c))
+    nid = np.array(sorted(nid), dtype=np.int64)
+    eid = np.array(sorted(eid), dtype=np.int64)
+    pick = lambda t, ix: t[torch.from_numpy(ix).cuda()].double().cpu().numpy()
+    dg, vg = _Gathered(nid, pick(d, nid)), _Gathered(nid, pick(v, nid))
+    kg = _Gathered(eid, pick(kap, eid))
+    pads = [torch.empty(npad, dtype=dt, device="cuda") for _ in range(3)]
+    tl.tl_op_pack(grid, 0, d, pads[0])
+    tl.tl_op_pack(grid, 1, kap, pads[1])
+    tl.tl_op_pack(grid, 0, v, pads[2])
+    del d, kap
+    ys = []
+    for kern in (tl.OP_TILED, tl.OP_ZMARCH):
+        y = torch.full((npad,), float("nan"), dtype=dt, device="cuda")
+        tl.tl_op_apply(grid, W.MIXED, pads[0], pads[1], pads[2], y, kernel=kern)
+        ys.append(y)
+    # (ghost and pitch entries of y stay NaN in both)
+    same = (ys[0] == ys[1]) | (torch.isnan(ys[0]) & torch.isnan(ys[1]))
+    assert bool(same.all())
+    del ys[1], same
+    tl.tl_op_unpack(grid, 0, ys[0], v)   # reuse v's storage for y
+    assert bool(torch.isfinite(v).all())
+    flat = np.array([g.node(*q) for q in nodes], dtype=np.int64)
+    got = pick(v, flat)
+    ref, scale = _op_rows(g, G.element_stiffness(*h), dg, kg, vg, nodes)
+    err = np.abs(got - ref) / scale
+    say("  largest grid: max rel err", err.max())
+    assert err.max() < 2e-6, err.max()
