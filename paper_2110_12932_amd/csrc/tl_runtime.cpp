@@ -5,10 +5,10 @@
 // fine micro steps with time-blended Dirichlet data, the two-level
 // correction (one composite-grid solve, the Dirichlet-Neumann iteration with
 // interface quasi-Newton relaxation, the consistent global formulation, or
-// the alternate one), injection, and the FP64 energy ledger.  Each implicit step is a frozen-kappa Newton iteration with a
-// backtracking line search whose linear systems are solved by
-// Jacobi-preconditioned CG in FP64, or in FP32 for the fine level of the
-// mixed-precision path.  All arithmetic on fields runs in the HIP kernels of
+// the alternate one), injection, and the FP64 energy ledger.  Each implicit
+// step is a frozen-kappa Newton iteration with a backtracking line search
+// whose linear systems are solved by Jacobi-preconditioned CG in FP64, or in
+// FP32 for the fine level of the mixed-precision path.  All arithmetic on fields runs in the HIP kernels of
 // tl_kernels.hip.  Newton, its line search and the CG control run on the
 // device (a state machine in the CG-start kernel); the host queues several
 // Newton rounds at a time and reads the solvers' states back once per group
