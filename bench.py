@@ -14,8 +14,9 @@ starts from the initial state, so its fields are compared with the oracle's
 fields for the same number of macro steps where tests/golden holds them
 (`oracle_rel_err`: max-norm error relative to the largest temperature, and
 to the largest rise above the plate).  `mixed` repeats the run with the
-mixed-precision path (FP32 operator and CG, FP64 residual, ledger and
-coarse-level correction) and reports its speedup over the FP64 path.
+mixed-precision path (FP32 operator and CG on both levels under an FP64
+residual, Newton iteration and ledger) and reports its speedup over the
+FP64 path.
 `serving` runs the served stream of 64 single-track requests (closed loop,
 then Poisson arrivals at 1.5x that capacity) with its p50/p99 latency.
 
@@ -491,8 +492,9 @@ def main():
             ("window_loads_predictor", "micro_steps", "correction", "ledger_commit"),
             (round(v / steps, 4) for v in st["phase_ms"])))
     if prec == W.FP64 and not args.no_mixed:
-        # the mixed-precision path (FP32 operator and CG, FP64 residual, ledger
-        # and coarse correction) on the same workload and steps
+        # the mixed-precision path (FP32 operator and CG on both levels under
+        # an FP64 residual, Newton iteration and ledger) on the same workload
+        # and steps
         wm = make_wl(W.MIXED)
         mr = timed_run(tl, torch, wm, steps, min(args.warmup, 1), 0)
         mv = mr["st"]["fine_dof_steps"] / mr["el"]

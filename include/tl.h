@@ -36,9 +36,9 @@ typedef enum {
   TL_EBUSY = -6     /* server queue or slots are full                        */
 } tl_status;
 
-/* Arithmetic of the linear solves inside each Newton iteration.  The nonlinear
- * residual, the Dirichlet data, the coarse level and the energy ledger are
- * always FP64. */
+/* Arithmetic of the linear solves inside each Newton iteration (TL_MIXED:
+ * FP32 CG on both levels).  The nonlinear residual, the Newton iteration,
+ * the Dirichlet data, the fields and the energy ledger are always FP64. */
 typedef enum { TL_FP64 = 0, TL_MIXED = 1 } tl_precision;
 
 /* Coarse plate [0,lx]x[0,ly]x[0,lz] with nx x ny x nz Q1 cells (spacing

@@ -74,7 +74,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   Geo gc, gf;
   size_t off_c[23], off_fd[10], off_fcg[12];
-  size_t off_ccg32[12];   // FP32 coarse CG arrays (mixed composite solves)
+  size_t off_ccg32[12];   // FP32 coarse CG arrays (the mixed path)
   bool ccg32 = false;
   size_t off_fx[2];       // consistent formulation: micro-step field sum,
   bool fx = false;        // load from the local solution (fine)
@@ -105,10 +105,11 @@ Layout make_layout(const tl_mesh& me, const tl_options& op) {
   for (int a = 0; a < kCoarseArrays; ++a) { L.off_c[a] = off; off += cbytes; }
   for (int a = 0; a < kFineD; ++a) { L.off_fd[a] = off; off += fbytes; }
   for (int a = 0; a < kFineCG; ++a) { L.off_fcg[a] = off; off += fcg; }
-  // A mixed-precision composite solve runs its coarse side in FP32 too; it
-  // gets arrays of its own, since the stencils rely on zero ghost entries
-  // that an FP32 view of the FP64 arrays would not keep.
-  L.ccg32 = op.precision == TL_MIXED && op.coupling == TL_COUPLE_COMPOSITE;
+  // The mixed-precision path runs the coarse predictor's CG and the
+  // composite solve's coarse side in FP32 too; they get arrays of their
+  // own, since the stencils rely on zero ghost entries that an FP32 view of
+  // the FP64 arrays would not keep.
+  L.ccg32 = op.precision == TL_MIXED;
   for (int a = 0; a < kFineCG; ++a) {
     L.off_ccg32[a] = off;
     if (L.ccg32) off += align_up((size_t)L.gc.npad * 4);
@@ -689,7 +690,7 @@ struct tl_sim {
   // fine diagonal and J u rows of a composite solve
   double *Tn, *Tpred, *ccur, *ctrial, *lam, *gdw, *cR, *Fall, *Fout, *ext;
   CGBufs<double> ccg;
-  CGBufs<float> ccg32;   // coarse CG arrays of a mixed composite solve
+  CGBufs<float> ccg32;   // coarse CG arrays of the mixed path
   // fine fields
   // fpp: the micro step before fprev (extrapolated initial guesses)
   double *fstate, *fprev, *fcur, *ftrial, *falt, *fR, *fF, *rho, *fpp;
@@ -1048,8 +1049,7 @@ CGBufs<double>& cg_of<double>(tl_sim* s, bool fine) {
 }
 template <>
 CGBufs<float>& cg_of<float>(tl_sim* s, bool fine) {
-  (void)fine;
-  return s->fcg32;
+  return fine ? s->fcg32 : s->ccg32;
 }
 
 // Solve one fine (fine = true) or coarse step for every listed simulation
@@ -1284,14 +1284,24 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
                     "source holds");
     k_copy(L, s->ccur, s->Tn, s->gc.npad);
   }
-  // coarse predictor over the whole plate
+  // coarse predictor over the whole plate: FP64 residual and Newton, the
+  // CG in the path's precision
   {
-    std::vector<StepState*> list = live(steps);
+    std::vector<StepState*> p64, p32;
+    for (StepState* st : live(steps))
+      (st->s->opts.precision == TL_MIXED ? p32 : p64).push_back(st);
     batch_solve<double>(
-        B, list, false,
+        B, p64, false,
         [](StepState& st) {
           return make_job<double>(st.s, false, region_all(), st.Dt, st.s->Tn,
                                   st.s->Fall, nullptr);
+        },
+        nullptr);
+    batch_solve<float>(
+        B, p32, false,
+        [](StepState& st) {
+          return make_job<float>(st.s, false, region_all(), st.Dt, st.s->Tn,
+                                 st.s->Fall, nullptr);
         },
         nullptr);
   }
