@@ -1479,10 +1479,23 @@ void macro_step_batch(std::vector<StepState>& steps, BatchCtx& B,
       }
       clist.push_back(st);
     }
+    // the coarse solves, the CG in the path's precision
+    std::vector<StepState*> c64, c32;
+    for (StepState* st : clist)
+      (st->s->opts.precision == TL_MIXED ? c32 : c64).push_back(st);
     batch_solve<double>(
-        B, clist, false,
+        B, c64, false,
         [](StepState& st) {
           return make_job<double>(
+              st.s, false,
+              consistent(st.s) ? region_fict(st.s) : region_outside(st.s),
+              st.Dt, st.s->Tn, st.s->Fout, st.s->ext);
+        },
+        nullptr);
+    batch_solve<float>(
+        B, c32, false,
+        [](StepState& st) {
+          return make_job<float>(
               st.s, false,
               consistent(st.s) ? region_fict(st.s) : region_outside(st.s),
               st.Dt, st.s->Tn, st.s->Fout, st.s->ext);
