@@ -25,6 +25,41 @@ namespace tl {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Arrays reached through the item tables are plain pointers there, and
+// loads through them would compile to flat instructions: a 64-bit address
+// per lane, and every such load counted against the LDS counter as well,
+// so that a wait for an LDS result also waits for the loads in flight.
+// Taken as global-address-space pointers they compile to global loads and
+// stores (a scalar base plus a 32-bit offset per lane).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+// Whole-struct copies from and to global memory, word by word (a struct's
+// implicit copy works in the generic address space only).
+template <class T>
+__device__ __forceinline__ T gload(gptr<const T> p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  unsigned w[sizeof(T) / 4];
+  const gptr<const unsigned> src = (gptr<const unsigned>)p;
+#pragma unroll
+  for (unsigned q = 0; q < sizeof(T) / 4; ++q) w[q] = src[q];
+  T v;
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+template <class T>
+__device__ __forceinline__ void gstore(gptr<T> p, const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  unsigned w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+  const gptr<unsigned> dst = (gptr<unsigned>)p;
+#pragma unroll
+  for (unsigned q = 0; q < sizeof(T) / 4; ++q) dst[q] = w[q];
+}
+
 static inline int grid_for(long n) {
   long b = (n + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -864,7 +899,7 @@ __device__ inline bool halo_gamma(const Geo& g, const Window& w, const Tile& t,
 // Region reg + qmax (qmax >= 0) takes the maximum instead of the sum.
 constexpr int kSumBatch = 6;
 template <int NV, class T, int B = kSumBatch>
-__device__ inline void add_partials(const double* __restrict__ tp, int ts,
+__device__ inline void add_partials(gptr<const double> __restrict__ tp, int ts,
                                     int nt, int reg, T (&v)[NV],
                                     int qmax = -1) {
   for (int b0 = threadIdx.x; b0 < nt; b0 += B * kBlock) {
@@ -894,8 +929,8 @@ __device__ inline void add_partials(const double* __restrict__ tp, int ts,
 template <int NV, class T>
 __device__ inline void pair_partials(const Couple& cp, int reg, T (&v)[NV]) {
   constexpr int B = sizeof(T) == 8 ? kSumBatch : 1;
-  add_partials<NV, T, B>(cp.tpA, cp.tsA, cp.ntA, reg, v);
-  add_partials<NV, T, B>(cp.tpB, cp.tsB, cp.ntB, reg, v);
+  add_partials<NV, T, B>(gmem(cp.tpA), cp.tsA, cp.ntA, reg, v);
+  add_partials<NV, T, B>(gmem(cp.tpB), cp.tsB, cp.ntB, reg, v);
 }
 
 // Every item of a batched launch has the same number of workgroups
@@ -923,29 +958,36 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   __shared__ double k_s[EN];
   __shared__ double lds[6 * kBlock / 64];
   const SolveItem& it = items[item_of_block(per_item)];
-  const NewtonState& st = it.sc->ns[round & 1];
+  const gptr<const LevelScalars> lsc = gmem((const LevelScalars*)it.sc);
+  const auto& st = lsc->ns[round & 1];
   if (st.status != kRunning) return;
   if (st.pending) {
     // the CG that should have produced the direction broke down at once:
     // the CG-start kernel of this round records the failure
-    const CGScalars& cgp = it.sc->cg[(round + 1) & 1];
+    const auto& cgp = lsc->cg[(round + 1) & 1];
     if (cgp.breakdown && cgp.iters == 0) return;
   }
   const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
   const MatDev& m = it.m;
-  const double* __restrict__ T = it.Tb[st.cur];
-  double* __restrict__ Tt = it.Tb[1 - st.cur];
-  const R* __restrict__ dx = st.first ? nullptr : (const R*)it.xb[st.xi];
+  const gptr<const double> __restrict__ T = gmem((const double*)it.Tb[st.cur]);
+  const gptr<double> __restrict__ Tt = gmem(it.Tb[1 - st.cur]);
+  const gptr<const R> __restrict__ dx =
+      st.first ? nullptr : gmem((const R*)it.xb[st.xi]);
+  const gptr<const double> __restrict__ Told = gmem(it.Told);
+  const gptr<double> __restrict__ Hold = gmem(it.Hold);
+  const gptr<const double> __restrict__ Fn = gmem(it.F);
+  const gptr<const double> __restrict__ Fext = gmem(it.Fext);
+  const gptr<double> __restrict__ Rout = gmem(it.R);
   const double alpha = st.alpha;
-  R* __restrict__ kap = (R*)it.kap;
-  R* __restrict__ d = (R*)it.d;
-  R* __restrict__ dinv = (R*)it.dinv;
-  R* __restrict__ r = (R*)it.r[0];
+  const gptr<R> __restrict__ kap = gmem((R*)it.kap);
+  const gptr<R> __restrict__ d = gmem((R*)it.d);
+  const gptr<R> __restrict__ dinv = gmem((R*)it.dinv);
+  const gptr<R> __restrict__ r = gmem((R*)it.r[0]);
   double w[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) w[q] = g.w[q];
-  double* __restrict__ tp = it.tpart;
+  const gptr<double> __restrict__ tp = gmem(it.tpart);
   const int ts = it.tstride;
   // a tile's global inputs, loaded into registers in one batch at the top
   // of its turn (holding the next tile's during this one's work would cost
@@ -965,8 +1007,9 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       if (CP == kFineSide && hn >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
         // interface node: P of the coarse trial, no step of its own
-        const double* Tc = it.cp.oT[st.cur];
-        const R* dxc = st.first ? nullptr : (const R*)it.cp.ox[st.xi];
+        const gptr<const double> Tc = gmem(it.cp.oT[st.cur]);
+        const gptr<const R> dxc =
+            st.first ? nullptr : gmem((const R*)it.cp.ox[st.xi]);
         double v = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
           v += wt * (dxc != nullptr ? trial_T(Tc[cn], alpha * (double)dxc[cn], m)
@@ -983,9 +1026,9 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     if (i < g.nx && j < g.ny && k < g.nz) {
       const int n = pidx(g, i, j, k);
       o_T = T[n];
-      o_H = first ? it.Told[n] : it.Hold[n];
-      o_F = it.F[n];
-      if (it.Fext != nullptr) o_Fx = it.Fext[n];
+      o_H = first ? Told[n] : Hold[n];
+      o_F = Fn[n];
+      if (Fext != nullptr) o_Fx = Fext[n];
     }
   };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
@@ -1057,37 +1100,32 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       double Ho = H_old;
       if (first) {
         Ho = enthalpy(H_old, m);   // H_old holds T_old here
-        it.Hold[n] = Ho;
+        Hold[n] = Ho;
       }
       // K T, element by element.  Each element reads its eight corners from
       // LDS afresh (the empty asm keeps the compiler from holding all 27
-      // values in registers across elements): 126 registers instead of 154,
-      // 4 waves per SIMD instead of 3, and the same sums in the same order.
-      // A composite pair's fine side still needs 131 there, so it keeps
-      // the values.
+      // values in registers across elements): 117-118 registers instead of
+      // 146-154, 4 waves per SIMD instead of 3, and the same sums in the
+      // same order as stencil_elementwise.
       double st_acc = 0.0;
-      if constexpr (CP == kFineSide) {
-        st_acc = stencil_elementwise(TV, k8, w);
-      } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-          double sk = 0.0;
+      for (int e = 0; e < 8; ++e) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+        double sk = 0.0;
 #pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-            sk = fma(w[e ^ c], TV(cx - ex, cy - ey, cz - ez), sk);
-          }
-          st_acc = fma(k8[e], sk, st_acc);
-          asm volatile("" ::: "memory");
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          sk = fma(w[e ^ c], TV(cx - ex, cy - ey, cz - ez), sk);
         }
+        st_acc = fma(k8[e], sk, st_acc);
+        asm volatile("" ::: "memory");
       }
       double Rn = mass * (Hn - Ho) / it.tau + st_acc - F_n;
       // elements with the consistent global problem's own coefficients:
       // their lumped mass takes rhoc_f (T - T_old) / tau
       const double mfict = g.vol8 * nfict * it.rg.rhocf;
-      if (nfict > 0.0) Rn += mfict * (Tn - it.Told[n]) / it.tau;
-      if (it.Fext != nullptr) Rn -= Fx_n;
+      if (nfict > 0.0) Rn += mfict * (Tn - Told[n]) / it.tau;
+      if (Fext != nullptr) Rn -= Fx_n;
       // heat loss through the top surface and its (exact) slope
       double sd = 0.0;
       if (k == g.nz - 1 && (it.sf.h != 0.0 || it.sf.es != 0.0)) {
@@ -1111,12 +1149,12 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       }
       if constexpr (CP == kCoarseSide) {
         if (coarse_gamma(it.cp.w, i, j, k)) {
-          Rn += it.cp.gR[n];
-          diag += ((const double*)it.cp.gDW)[n];
+          Rn += gmem(it.cp.gR)[n];
+          diag += gmem((const double*)it.cp.gDW)[n];
         }
       }
       Tt[n] = Tn;
-      it.R[n] = Rn;
+      Rout[n] = Rn;
       // this node owns the element whose lowest corner it is (k8[0])
       kap[n] = (R)kown;
       d[n] = (R)dn;
@@ -1236,9 +1274,9 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   const SolveItem& it = items[item_of_block(per_item)];
   const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
-  LevelScalars* sc = it.sc;
-  const NewtonState st = sc->ns[round & 1];
-  const CGScalars& cgp = sc->cg[(round + 1) & 1];  // previous round's CG
+  const gptr<LevelScalars> sc = gmem(it.sc);
+  const NewtonState st = gload<NewtonState>(&sc->ns[round & 1]);
+  const auto& cgp = sc->cg[(round + 1) & 1];  // previous round's CG
   NewtonState nx = st;
   const int prev_iters = round > 0 ? cgp.iters : 0;
   if (st.status == kRunning && st.pending) {
@@ -1254,10 +1292,10 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   }
   // inputs of w0 = J u0 for a stack of tiles (the CG iteration's work
   // units), loaded into registers in one batch
-  const R* __restrict__ r = (const R*)it.r[0];
-  const R* __restrict__ dinv = (const R*)it.dinv;
-  const R* __restrict__ d = (const R*)it.d;
-  const R* __restrict__ kap = (const R*)it.kap;
+  const gptr<const R> __restrict__ r = gmem((const R*)it.r[0]);
+  const gptr<const R> __restrict__ dinv = gmem((const R*)it.dinv);
+  const gptr<const R> __restrict__ d = gmem((const R*)it.d);
+  const gptr<const R> __restrict__ kap = gmem((const R*)it.kap);
   R hr[ST::HPT], hd[ST::HPT], kr[ST::EPT];
   R o_r[S], o_d[S];
   int o_n[S];
@@ -1271,8 +1309,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       if (CP == kFineSide && n >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
         // interface node: u0 = P (Dinv r0) of the coarse side
-        const R* rc = (const R*)it.cp.orr[0];
-        const R* dc = (const R*)it.cp.odinv;
+        const gptr<const R> rc = gmem((const R*)it.cp.orr[0]);
+        const gptr<const R> dc = gmem((const R*)it.cp.odinv);
         double v = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
           v += wt * (double)(dc[cn] * rc[cn]);
@@ -1324,8 +1362,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     // order)
     const Couple& cp = it.cp;
     double a3[3] = {0.0, 0.0, 0.0};   // |R|^2, max|dx|, r.z
-    add_partials<3, double, 2>(cp.tpA, cp.tsA, cp.ntA, kTRes, a3, 1);
-    add_partials<3, double, 2>(cp.tpB, cp.tsB, cp.ntB, kTRes, a3, 1);
+    add_partials<3, double, 2>(gmem(cp.tpA), cp.tsA, cp.ntA, kTRes, a3, 1);
+    add_partials<3, double, 2>(gmem(cp.tpB), cp.tsB, cp.ntB, kTRes, a3, 1);
     double v[2] = {a3[0], a3[2]};
     double bm = wave_max(a3[1]);
     block_sum<2>(v, lds);
@@ -1381,8 +1419,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
     }
   }
   if (blk == 0 && threadIdx.x == 0) {
-    sc->ns[(round + 1) & 1] = nx;
-    CGScalars& cg = sc->cg[round & 1];
+    gstore<NewtonState>(&sc->ns[(round + 1) & 1], nx);
+    auto& cg = sc->cg[round & 1];
     cg.rz0 = rz;
     cg.iters = 0;
     cg.done = run ? 0 : 1;
@@ -1395,7 +1433,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   }
   if (!run) return;
   // w0 = J u0, u0 = Dinv r0, on the stacks
-  R* __restrict__ w = (R*)it.w[0];
+  const gptr<R> __restrict__ w = gmem((R*)it.w[0]);
   R wts[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wts[q] = (R)g.w[q];
@@ -1439,7 +1477,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       const int n = nn[u];
       const R un = u_s[(tu.tz + 1) * (HX * HY) + (tu.ty + 1) * HX + (tu.tx + 1)];
       R wn = fma(d_own[u], un, stencil_lds(tu, u_s, k_s, wts));
-      if (CP == kCoarseSide && gam[u]) wn += ((const R*)it.cp.gDW)[n];
+      if (CP == kCoarseSide && gam[u]) wn += gmem((const R*)it.cp.gDW)[n];
       w[n] = wn;
       if ((CP != kFineSide && CP != kFineSideP) || !gam[u]) {
         acc[2 * u] = fma(r_own[u], un, acc[2 * u]);
@@ -1451,8 +1489,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
       for (int u = 0; u < S; ++u)
         if (u < nsub) {
-          it.tpart[kTCG * it.tstride + b0 + u * it.ntx] = (double)acc[2 * u];
-          it.tpart[(kTCG + 1) * it.tstride + b0 + u * it.ntx] = (double)acc[2 * u + 1];
+          gmem(it.tpart)[kTCG * it.tstride + b0 + u * it.ntx] = (double)acc[2 * u];
+          gmem(it.tpart)[(kTCG + 1) * it.tstride + b0 + u * it.ntx] = (double)acc[2 * u + 1];
         }
     }
     __syncthreads();  // LDS is reused by the next stack
@@ -1477,25 +1515,26 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   __shared__ R bc[2];
   const SolveItem& it = items[item_of_block(per_item)];
   // the state written by this round's CG-start kernel
-  const NewtonState& nst = it.sc->ns[(round + 1) & 1];
-  CGScalars* sc = &it.sc->cg[round & 1];
+  const gptr<LevelScalars> lsc = gmem(it.sc);
+  const auto& nst = lsc->ns[(round + 1) & 1];
+  const gptr<CGScalars> sc = &lsc->cg[round & 1];
   // past the item's own budget (other items of the batch may run more): no
   // work, so the item's result does not depend on the batch
   if (sc->done || kit >= nst.budget) return;
   const int blk = blockIdx.x % per_item, nblk = per_item;
   const Geo& g = it.g;
   const int a = kit & 1;
-  const R* __restrict__ r_in = (const R*)it.r[a];
-  const R* __restrict__ w_in = (const R*)it.w[a];
-  const R* __restrict__ s_old = (const R*)it.s[1 - a];
-  R* __restrict__ r_out = (R*)it.r[1 - a];
-  R* __restrict__ w_out = (R*)it.w[1 - a];
-  R* __restrict__ s_out = (R*)it.s[a];
-  R* __restrict__ p = (R*)it.p;
-  R* __restrict__ x = (R*)it.xb[nst.xi];
-  const R* __restrict__ d = (const R*)it.d;
-  const R* __restrict__ kap = (const R*)it.kap;
-  const R* __restrict__ dinv = (const R*)it.dinv;
+  const gptr<const R> __restrict__ r_in = gmem((const R*)it.r[a]);
+  const gptr<const R> __restrict__ w_in = gmem((const R*)it.w[a]);
+  const gptr<const R> __restrict__ s_old = gmem((const R*)it.s[1 - a]);
+  const gptr<R> __restrict__ r_out = gmem((R*)it.r[1 - a]);
+  const gptr<R> __restrict__ w_out = gmem((R*)it.w[1 - a]);
+  const gptr<R> __restrict__ s_out = gmem((R*)it.s[a]);
+  const gptr<R> __restrict__ p = gmem((R*)it.p);
+  const gptr<R> __restrict__ x = gmem((R*)it.xb[nst.xi]);
+  const gptr<const R> __restrict__ d = gmem((const R*)it.d);
+  const gptr<const R> __restrict__ kap = gmem((const R*)it.kap);
+  const gptr<const R> __restrict__ dinv = gmem((const R*)it.dinv);
   // Every global input of a stack is loaded into registers in one batch:
   // the halo of r, w, s_{k-1}, Dinv (for u_{k+1}), the element
   // conductivities, and each node's own d, p, x, s_{k-1}.  Single tiles:
@@ -1521,10 +1560,10 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         // interface node: P (Dinv r), P (Dinv w), P (Dinv s) of the coarse
         // side with a unit preconditioner, so that the recurrence below
         // gives u_{k+1} = P (Dinv (r - alpha (w + beta s))) there
-        const R* rc = (const R*)it.cp.orr[a];
-        const R* wc = (const R*)it.cp.ow[a];
-        const R* scs = (const R*)it.cp.os[1 - a];
-        const R* dc = (const R*)it.cp.odinv;
+        const gptr<const R> rc = gmem((const R*)it.cp.orr[a]);
+        const gptr<const R> wc = gmem((const R*)it.cp.ow[a]);
+        const gptr<const R> scs = gmem((const R*)it.cp.os[1 - a]);
+        const gptr<const R> dc = gmem((const R*)it.cp.odinv);
         double vr = 0.0, vw = 0.0, vs = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
           const R dv = dc[cn];
@@ -1690,7 +1729,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       r_out[n] = r1;
       const R u1 = u_s[(tu.tz + 1) * (HX * HY) + (tu.ty + 1) * HX + (tu.tx + 1)];
       R w1 = fma(d_own[u], u1, stencil_lds(tu, u_s, k_s, wts));
-      if (CP == kCoarseSide && gam) w1 += ((const R*)it.cp.gDW)[n];
+      if (CP == kCoarseSide && gam) w1 += gmem((const R*)it.cp.gDW)[n];
       w_out[n] = w1;
       if ((CP != kFineSide && CP != kFineSideP) || !gam) {
         acc[2 * u] = fma(r1, u1, acc[2 * u]);
@@ -1702,8 +1741,8 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
       for (int u = 0; u < S; ++u)
         if (u < nsub) {
-          it.tpart[wr * ts + b0 + u * it.ntx] = (double)acc[2 * u];
-          it.tpart[(wr + 1) * ts + b0 + u * it.ntx] = (double)acc[2 * u + 1];
+          gmem(it.tpart)[wr * ts + b0 + u * it.ntx] = (double)acc[2 * u];
+          gmem(it.tpart)[(wr + 1) * ts + b0 + u * it.ntx] = (double)acc[2 * u + 1];
         }
     }
     __syncthreads();  // LDS is reused by the next stack
@@ -1728,19 +1767,19 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
   __shared__ double lds[2 * kBlock / 64];
   const SolveItem& it = items[blockIdx.x / per_item];
   const Couple& cp = it.cp;
-  const LevelScalars* sc = it.sc;
+  const gptr<const LevelScalars> sc = gmem((const LevelScalars*)it.sc);
   if (phase == 0) {
-    const NewtonState& st = sc->ns[round & 1];
+    const auto& st = sc->ns[round & 1];
     if (st.status != kRunning) return;
     if (st.pending) {
-      const CGScalars& cgp = sc->cg[(round + 1) & 1];
+      const auto& cgp = sc->cg[(round + 1) & 1];
       if (cgp.breakdown && cgp.iters == 0) return;
     }
   } else {
-    const NewtonState& nx = sc->ns[(round + 1) & 1];
+    const auto& nx = sc->ns[(round + 1) & 1];
     if (nx.status != kRunning || !nx.pending) return;
     if (phase == 2) {
-      const CGScalars& c = sc->cg[round & 1];
+      const auto& c = sc->cg[round & 1];
       if (c.done || kit >= nx.budget) return;
     }
   }
@@ -1749,14 +1788,15 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
   const Geo& gc = it.g;
   const Geo& gf = cp.go;
   const Window& w = cp.w;
-  const int n = cp.gidx[q];
+  const int n = gmem(cp.gidx)[q];
   const int I = n % gc.px - 1, J = (n / gc.px) % (gc.ny + 2) - 1,
             K = n / gc.pxy - 1;
   const int r = w.r, span = 2 * r - 1;
   // fine coordinates of the coarse node
   const int ci = r * (I - w.I0), cj = r * (J - w.J0), ck = r * (K - w.K0);
-  const R* fw = (const R*)cp.fw[phase == 2 ? 1 - (kit & 1) : 0];
-  const R* fdg = (const R*)cp.fdiag;
+  const gptr<const R> fw = gmem((const R*)cp.fw[phase == 2 ? 1 - (kit & 1) : 0]);
+  const gptr<const R> fdg = gmem((const R*)cp.fdiag);
+  const gptr<const double> fR = gmem(cp.fR);
   double a[2] = {0.0, 0.0};
   for (int face = 0; face < 5; ++face) {
     const bool on =
@@ -1784,7 +1824,7 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
       const double wt = pweight(fi - ci, fj - cj, fk - ck, r);
       const int fn = pidx(gf, fi, fj, fk);
       if (phase == 0) {
-        a[0] += wt * cp.fR[fn];
+        a[0] += wt * fR[fn];
         a[1] += wt * wt * (double)fdg[fn];
       } else {
         a[0] += wt * (double)fw[fn];
@@ -1794,10 +1834,10 @@ couple_gather_kernel(const SolveItem* __restrict__ items, int per_item,
   block_sum<2>(a, lds);
   if (threadIdx.x == 0) {
     if (phase == 0) {
-      cp.gR[n] = a[0];
-      ((double*)cp.gDW)[n] = a[1];
+      gmem(cp.gR)[n] = a[0];
+      gmem((double*)cp.gDW)[n] = a[1];
     } else {
-      ((R*)cp.gDW)[n] = (R)a[0];
+      gmem((R*)cp.gDW)[n] = (R)a[0];
     }
   }
 }
@@ -1819,17 +1859,17 @@ couple_prolong_kernel(const SolveItem* __restrict__ items, int per_item,
                       int round, int phase, int kit) {
   const SolveItem& it = items[blockIdx.x / per_item];
   const int blk = blockIdx.x % per_item;
-  const LevelScalars* sc = it.sc;
-  const NewtonState& st = sc->ns[round & 1];
+  const gptr<const LevelScalars> sc = gmem((const LevelScalars*)it.sc);
+  const auto& st = sc->ns[round & 1];
   if (phase <= 1) {
     if (st.status != kRunning) return;
     if (st.pending) {
-      const CGScalars& cgp = sc->cg[(round + 1) & 1];
+      const auto& cgp = sc->cg[(round + 1) & 1];
       if (cgp.breakdown && cgp.iters == 0) return;
     }
   } else {
-    const NewtonState& nx = sc->ns[(round + 1) & 1];
-    const CGScalars& c = sc->cg[round & 1];
+    const auto& nx = sc->ns[(round + 1) & 1];
+    const auto& c = sc->cg[round & 1];
     if (c.done || kit >= nx.budget) return;
   }
   const Geo& g = it.g;
@@ -1875,28 +1915,29 @@ couple_prolong_kernel(const SolveItem* __restrict__ items, int per_item,
       continue;
     const int n = pidx(g, i, j, k);
     if (phase == 0) {
-      const double* Tc = cp.oT[st.cur];
-      const R* dxc = st.first ? nullptr : (const R*)cp.ox[st.xi];
+      const gptr<const double> Tc = gmem(cp.oT[st.cur]);
+      const gptr<const R> dxc =
+          st.first ? nullptr : gmem((const R*)cp.ox[st.xi]);
       double v = 0.0;
       prolong_each(cp.go, w, i, j, k, [&](int cn, double wt) {
         v += wt * (dxc != nullptr ? trial_T(Tc[cn], st.alpha * (double)dxc[cn], it.m)
                                   : Tc[cn]);
       });
-      it.Tb[st.cur][n] = v;
+      gmem(it.Tb[st.cur])[n] = v;
     } else if (phase == 1) {
-      const R* rc = (const R*)cp.orr[0];
-      const R* dc = (const R*)cp.odinv;
+      const gptr<const R> rc = gmem((const R*)cp.orr[0]);
+      const gptr<const R> dc = gmem((const R*)cp.odinv);
       double v = 0.0;
       prolong_each(cp.go, w, i, j, k, [&](int cn, double wt) {
         v += wt * (double)(dc[cn] * rc[cn]);
       });
-      ((R*)it.r[0])[n] = (R)v;
-      ((R*)it.dinv)[n] = (R)1;
+      gmem((R*)it.r[0])[n] = (R)v;
+      gmem((R*)it.dinv)[n] = (R)1;
     } else {
-      const R* rc = (const R*)cp.orr[a];
-      const R* wc = (const R*)cp.ow[a];
-      const R* scs = (const R*)cp.os[1 - a];
-      const R* dc = (const R*)cp.odinv;
+      const gptr<const R> rc = gmem((const R*)cp.orr[a]);
+      const gptr<const R> wc = gmem((const R*)cp.ow[a]);
+      const gptr<const R> scs = gmem((const R*)cp.os[1 - a]);
+      const gptr<const R> dc = gmem((const R*)cp.odinv);
       double vr = 0.0, vw = 0.0, vs = 0.0;
       prolong_each(cp.go, w, i, j, k, [&](int cn, double wt) {
         const R dv = dc[cn];
@@ -1904,9 +1945,9 @@ couple_prolong_kernel(const SolveItem* __restrict__ items, int per_item,
         vw += wt * (double)(dv * wc[cn]);
         if (kit > 0) vs += wt * (double)(dv * scs[cn]);
       });
-      ((R*)it.r[a])[n] = (R)vr;
-      ((R*)it.w[a])[n] = (R)vw;
-      ((R*)it.s[1 - a])[n] = (R)vs;
+      gmem((R*)it.r[a])[n] = (R)vr;
+      gmem((R*)it.w[a])[n] = (R)vw;
+      gmem((R*)it.s[1 - a])[n] = (R)vs;
     }
   }
 }
