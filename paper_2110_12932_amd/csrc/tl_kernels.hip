@@ -497,12 +497,35 @@ __device__ inline int halo_index(const Geo& g, const Tile& t, int h) {
   if (i > g.nx || j > g.ny || k > g.nz) return -1;
   return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
 }
+// The same for the batched kernels, -1 also on the ghost layer itself:
+// ghost nodes enter the stencil only through ghost elements, whose
+// conductivity is zero, so the value taken for them does not change any
+// sum as long as it is finite; zero is used and the ghost rows and planes
+// are not fetched.
+__device__ inline int halo_index_real(const Geo& g, const Tile& t, int h) {
+  const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+  const int i = t.ox + hx - 1, j = t.oy + hy - 1, k = t.oz + hz - 1;
+  if (i < 0 || j < 0 || k < 0 || i >= g.nx || j >= g.ny || k >= g.nz)
+    return -1;
+  return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+}
 // padded index of element entry e (element with lowest corner at
 // (ox-1+ex, ...)), or -1 past the ghost layer
 __device__ inline int elem_index(const Geo& g, const Tile& t, int e) {
   const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
   const int i = t.ox + ex - 1, j = t.oy + ey - 1, k = t.oz + ez - 1;
   if (i > g.nx || j > g.ny || k > g.nz) return -1;
+  return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
+}
+// The same, -1 for every element outside the grid (their stored
+// conductivity is zero: never written on the ghost layer, written as zero
+// by the residual kernel for the element past a grid's last node)
+__device__ inline int elem_index_real(const Geo& g, const Tile& t, int e) {
+  const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
+  const int i = t.ox + ex - 1, j = t.oy + ey - 1, k = t.oz + ez - 1;
+  if (i < 0 || j < 0 || k < 0 || i >= g.nx - 1 || j >= g.ny - 1 ||
+      k >= g.nz - 1)
+    return -1;
   return (k + 1) * g.pxy + (j + 1) * g.px + (i + 1);
 }
 
@@ -1002,7 +1025,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      const int hn = h < HN ? halo_index(g, t, h) : -1;
+      const int hn = h < HN ? halo_index_real(g, t, h) : -1;
       int fi, fj, fk;
       if (CP == kFineSide && hn >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
@@ -1304,7 +1327,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      const int n = h < ST::HN ? halo_index(g, t, h) : -1;
+      const int n = h < ST::HN ? halo_index_real(g, t, h) : -1;
       int fi, fj, fk;
       if (CP == kFineSide && n >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
@@ -1325,7 +1348,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      const int n = e < ST::EN ? elem_index(g, t, e) : -1;
+      const int n = e < ST::EN ? elem_index_real(g, t, e) : -1;
       kr[q] = n >= 0 ? kap[n] : (R)0;
     }
 #pragma unroll
@@ -1553,7 +1576,11 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      const int n = h < ST::HN ? halo_index(g, t, h) : -1;
+      // (a composite fine side keeps the ghost loads: the extra tests
+      // would take it past 168 registers, to 2 waves per SIMD)
+      const int n = h >= ST::HN ? -1
+                    : CP == kFineSide ? halo_index(g, t, h)
+                                      : halo_index_real(g, t, h);
       int fi, fj, fk;
       if (CP == kFineSide && n >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
@@ -1585,7 +1612,9 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      const int n = e < ST::EN ? elem_index(g, t, e) : -1;
+      const int n = e >= ST::EN ? -1
+                    : CP == kFineSide ? elem_index(g, t, e)
+                                      : elem_index_real(g, t, e);
       kr[q] = n >= 0 ? kap[n] : (R)0;
     }
 #pragma unroll
