@@ -67,15 +67,56 @@ static inline int grid_for(long n) {
   return (int)b;
 }
 
+// Wave-wide reductions with DPP lane moves (no trip through the LDS
+// crossbar): pairs within quads, then half rows and rows by mirroring,
+// then rows 1 and 3 take the last lane of the row before them and rows 2
+// and 3 that of row 1, so that lane 63 holds the result, which is then
+// read by every lane (the rows a broadcast skips take a dummy zero, which
+// never reaches lane 63).  A fixed pattern: the same order of operations
+// on every call.  Every lane of the wave must be active.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xf, false);
+}
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_move<kCtrl, kRowMask>((int)b);
+  const int hi = dpp_move<kCtrl, kRowMask>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(
+      float, dpp_move<kCtrl, kRowMask>(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+  v = op(v, dpp_move<0xb1>(v));        // quad_perm [1,0,3,2]
+  v = op(v, dpp_move<0x4e>(v));        // quad_perm [2,3,0,1]
+  v = op(v, dpp_move<0x141>(v));       // row_half_mirror
+  v = op(v, dpp_move<0x140>(v));       // row_mirror
+  v = op(v, dpp_move<0x142, 0xa>(v));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp_move<0x143, 0xc>(v));  // row_bcast:31 into rows 2, 3
+  return lane63(v);
+}
 template <class T>
 __device__ inline T wave_sum(T v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  return wave_reduce(v, [](T a, T b) { return a + b; });
 }
 template <class T>
 __device__ inline T wave_max(T v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  return v;
+  return wave_reduce(v, [](T a, T b) { return fmax(a, b); });
 }
 
 // Block-wide sum of NV values per thread; result valid in thread 0.
@@ -2490,7 +2531,7 @@ micro_post_kernel(const MicroItem* __restrict__ items, int per_item) {
 
 // One wave per simulation: the nblk partials of region reg times scale,
 // added into the slot the item names for that sum.  Lane l adds partials
-// l, l + 64, ... in order, then the wave's fixed shuffle tree: the same
+// l, l + 64, ... in order, then the wave's fixed DPP reduction: the same
 // order every time, whatever else the launch holds.
 __global__ void __launch_bounds__(64)
 micro_finalize_kernel(const MicroItem* __restrict__ items, int post) {
