@@ -37,6 +37,15 @@ template <class T>
 __device__ __forceinline__ gptr<T> gmem(T* p) {
   return (gptr<T>)p;
 }
+// Element n (>= 0) of an array of a level or of its tables, addressed with
+// a 32-bit byte offset: a level holds at most 2e8 padded nodes (1.6 GB in
+// FP64), so the offset fits, and a load or store takes the array's scalar
+// base plus one 32-bit offset per lane, which every array indexed with the
+// same n shares.
+template <class T>
+__device__ __forceinline__ gptr<T> at(gptr<T> p, int n) {
+  return (gptr<T>)((gptr<const char>)p + (unsigned)n * (unsigned)sizeof(T));
+}
 // Whole-struct copies from and to global memory, word by word (a struct's
 // implicit copy works in the generic address space only).
 template <class T>
@@ -1076,23 +1085,23 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
             st.first ? nullptr : gmem((const R*)it.cp.ox[st.xi]);
         double v = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
-          v += wt * (dxc != nullptr ? trial_T(Tc[cn], alpha * (double)dxc[cn], m)
-                                    : Tc[cn]);
+          v += wt * (dxc != nullptr ? trial_T(*at(Tc, cn), alpha * (double)*at(dxc, cn), m)
+                                    : *at(Tc, cn));
         });
         hT[q] = v;
         hd[q] = (R)0;
       } else {
-        hT[q] = hn >= 0 ? T[hn] : 0.0;
-        hd[q] = (hn >= 0 && dx != nullptr) ? dx[hn] : (R)0;
+        hT[q] = hn >= 0 ? *at(T, hn) : 0.0;
+        hd[q] = (hn >= 0 && dx != nullptr) ? *at(dx, hn) : (R)0;
       }
     }
     const int i = t.ox + t.tx, j = t.oy + t.ty, k = t.oz + t.tz;
     if (i < g.nx && j < g.ny && k < g.nz) {
       const int n = pidx(g, i, j, k);
-      o_T = T[n];
-      o_H = first ? Told[n] : Hold[n];
-      o_F = Fn[n];
-      if (Fext != nullptr) o_Fx = Fext[n];
+      o_T = *at(T, n);
+      o_H = first ? *at(Told, n) : *at(Hold, n);
+      o_F = *at(Fn, n);
+      if (Fext != nullptr) o_Fx = *at(Fext, n);
     }
   };
   const TileRange tr = tile_range(blk, nblk, it.ntiles);
@@ -1164,7 +1173,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       double Ho = H_old;
       if (first) {
         Ho = enthalpy(H_old, m);   // H_old holds T_old here
-        Hold[n] = Ho;
+        *at(Hold, n) = Ho;
       }
       // K T, element by element.  Each element reads its eight corners from
       // LDS afresh (the empty asm keeps the compiler from holding all 27
@@ -1188,7 +1197,7 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       // elements with the consistent global problem's own coefficients:
       // their lumped mass takes rhoc_f (T - T_old) / tau
       const double mfict = g.vol8 * nfict * it.rg.rhocf;
-      if (nfict > 0.0) Rn += mfict * (Tn - Told[n]) / it.tau;
+      if (nfict > 0.0) Rn += mfict * (Tn - *at(Told, n)) / it.tau;
       if (Fext != nullptr) Rn -= Fx_n;
       // heat loss through the top surface and its (exact) slope
       double sd = 0.0;
@@ -1217,16 +1226,16 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
           diag += gmem((const double*)it.cp.gDW)[n];
         }
       }
-      Tt[n] = Tn;
-      Rout[n] = Rn;
+      *at(Tt, n) = Tn;
+      *at(Rout, n) = Rn;
       // this node owns the element whose lowest corner it is (k8[0])
-      kap[n] = (R)kown;
-      d[n] = (R)dn;
+      *at(kap, n) = (R)kown;
+      *at(d, n) = (R)dn;
       const R di = dir ? (R)0 : (R)(1.0 / diag);
-      dinv[n] = keep_diag ? (R)diag : di;
+      *at(dinv, n) = keep_diag ? (R)diag : di;
       const R rn = dir ? (R)0 : (R)Rn;
       const R zn = di * rn;
-      r[n] = rn;
+      *at(r, n) = rn;
       if (!dir) {
         acc[0] += Rn * Rn;
         acc[1] = fmax(acc[1], fabs(Tn - Tc0));
@@ -1243,9 +1252,9 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       double bm = lds[2 * kBlock / 64];
       for (int wv = 1; wv < kBlock / 64; ++wv)
         bm = fmax(bm, lds[2 * kBlock / 64 + wv]);
-      tp[kTRes * ts + tile] = sums[0];
-      tp[(kTRes + 1) * ts + tile] = bm;
-      tp[(kTRes + 2) * ts + tile] = sums[1];
+      *at(tp, kTRes * ts + tile) = sums[0];
+      *at(tp, (kTRes + 1) * ts + tile) = bm;
+      *at(tp, (kTRes + 2) * ts + tile) = sums[1];
     }
     __syncthreads();  // LDS is reused by the next tile
   }
@@ -1377,20 +1386,20 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         const gptr<const R> dc = gmem((const R*)it.cp.odinv);
         double v = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
-          v += wt * (double)(dc[cn] * rc[cn]);
+          v += wt * (double)(*at(dc, cn) * *at(rc, cn));
         });
         hr[q] = (R)v;
         hd[q] = (R)1;
       } else {
-        hr[q] = n >= 0 ? r[n] : (R)0;
-        hd[q] = n >= 0 ? dinv[n] : (R)0;
+        hr[q] = n >= 0 ? *at(r, n) : (R)0;
+        hd[q] = n >= 0 ? *at(dinv, n) : (R)0;
       }
     }
 #pragma unroll
     for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
       const int n = e < ST::EN ? elem_index_real(g, t, e) : -1;
-      kr[q] = n >= 0 ? kap[n] : (R)0;
+      kr[q] = n >= 0 ? *at(kap, n) : (R)0;
     }
 #pragma unroll
     for (int u = 0; u < S; ++u) {
@@ -1403,8 +1412,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       if (CP == kCoarseSide) o_gam[u] = o_act[u] && coarse_gamma(it.cp.w, i, j, k);
       o_r[u] = o_d[u] = (R)0;
       if (o_act[u]) {
-        o_r[u] = r[o_n[u]];
-        o_d[u] = d[o_n[u]];
+        o_r[u] = *at(r, o_n[u]);
+        o_d[u] = *at(d, o_n[u]);
       }
     }
   };
@@ -1542,7 +1551,7 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       const R un = u_s[(tu.tz + 1) * (HX * HY) + (tu.ty + 1) * HX + (tu.tx + 1)];
       R wn = fma(d_own[u], un, stencil_lds(tu, u_s, k_s, wts));
       if (CP == kCoarseSide && gam[u]) wn += gmem((const R*)it.cp.gDW)[n];
-      w[n] = wn;
+      *at(w, n) = wn;
       if ((CP != kFineSide && CP != kFineSideP) || !gam[u]) {
         acc[2 * u] = fma(r_own[u], un, acc[2 * u]);
         acc[2 * u + 1] = fma(wn, un, acc[2 * u + 1]);
@@ -1634,20 +1643,20 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
         const gptr<const R> dc = gmem((const R*)it.cp.odinv);
         double vr = 0.0, vw = 0.0, vs = 0.0;
         prolong_each(it.cp.go, it.cp.w, fi, fj, fk, [&](int cn, double wt) {
-          const R dv = dc[cn];
-          vr += wt * (double)(dv * rc[cn]);
-          vw += wt * (double)(dv * wc[cn]);
-          if (kit > 0) vs += wt * (double)(dv * scs[cn]);
+          const R dv = *at(dc, cn);
+          vr += wt * (double)(dv * *at(rc, cn));
+          vw += wt * (double)(dv * *at(wc, cn));
+          if (kit > 0) vs += wt * (double)(dv * *at(scs, cn));
         });
         hr[q] = (R)vr;
         hw[q] = (R)vw;
         hs[q] = (R)vs;
         hd[q] = (R)1;
       } else {
-        hr[q] = n >= 0 ? r_in[n] : (R)0;
-        hw[q] = n >= 0 ? w_in[n] : (R)0;
-        hs[q] = (n >= 0 && kit > 0) ? s_old[n] : (R)0;
-        hd[q] = n >= 0 ? dinv[n] : (R)0;
+        hr[q] = n >= 0 ? *at(r_in, n) : (R)0;
+        hw[q] = n >= 0 ? *at(w_in, n) : (R)0;
+        hs[q] = (n >= 0 && kit > 0) ? *at(s_old, n) : (R)0;
+        hd[q] = n >= 0 ? *at(dinv, n) : (R)0;
       }
     }
 #pragma unroll
@@ -1656,7 +1665,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       const int n = e >= ST::EN ? -1
                     : CP == kFineSide ? elem_index(g, t, e)
                                       : elem_index_real(g, t, e);
-      kr[q] = n >= 0 ? kap[n] : (R)0;
+      kr[q] = n >= 0 ? *at(kap, n) : (R)0;
     }
 #pragma unroll
     for (int u = 0; u < S; ++u) {
@@ -1670,14 +1679,14 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       o_r[u] = o_w[u] = o_di[u] = o_d[u] = o_s[u] = o_p[u] = o_x[u] = (R)0;
       if (o_act[u]) {
         const int n = o_n[u];
-        o_r[u] = r_in[n];
-        o_w[u] = w_in[n];
-        o_di[u] = dinv[n];
-        o_d[u] = d[n];
+        o_r[u] = *at(r_in, n);
+        o_w[u] = *at(w_in, n);
+        o_di[u] = *at(dinv, n);
+        o_d[u] = *at(d, n);
         if (kit > 0) {
-          o_s[u] = s_old[n];
-          o_p[u] = p[n];
-          o_x[u] = x[n];
+          o_s[u] = *at(s_old, n);
+          o_p[u] = *at(p, n);
+          o_x[u] = *at(x, n);
         }
       }
     }
@@ -1792,15 +1801,15 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       const R s_k = slave ? (R)0 : fma(beta, s_prev[u], w_own[u]);
       const R u_k = di_own[u] * r_own[u];
       const R pn = slave ? (R)0 : fma(beta, p_own[u], u_k);
-      p[n] = pn;
-      s_out[n] = s_k;
-      x[n] = fma(alpha, pn, x_own[u]);
+      *at(p, n) = pn;
+      *at(s_out, n) = s_k;
+      *at(x, n) = fma(alpha, pn, x_own[u]);
       const R r1 = slave ? (R)0 : fma(-alpha, s_k, r_own[u]);
-      r_out[n] = r1;
+      *at(r_out, n) = r1;
       const R u1 = u_s[(tu.tz + 1) * (HX * HY) + (tu.ty + 1) * HX + (tu.tx + 1)];
       R w1 = fma(d_own[u], u1, stencil_lds(tu, u_s, k_s, wts));
       if (CP == kCoarseSide && gam) w1 += gmem((const R*)it.cp.gDW)[n];
-      w_out[n] = w1;
+      *at(w_out, n) = w1;
       if ((CP != kFineSide && CP != kFineSideP) || !gam) {
         acc[2 * u] = fma(r1, u1, acc[2 * u]);
         acc[2 * u + 1] = fma(w1, u1, acc[2 * u + 1]);
