@@ -1177,9 +1177,9 @@ residual_batched_kernel(const SolveItem* __restrict__ items, int per_item,
       }
       // K T, element by element.  Each element reads its eight corners from
       // LDS afresh (the empty asm keeps the compiler from holding all 27
-      // values in registers across elements): 117-118 registers instead of
-      // 146-154, 4 waves per SIMD instead of 3, and the same sums in the
-      // same order as stencil_elementwise.
+      // values in registers across elements): 114-117 registers, 4 waves
+      // per SIMD, where holding them took 146-154 and 3 waves; the same
+      // sums in the same order as stencil_elementwise.
       double st_acc = 0.0;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -1421,8 +1421,8 @@ cg_start_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   int b0, nsub;
   // Loads ahead of use: the first stack's during the reduction, the next
   // one's during this one's stencil.  FP64 stacks of two load each stack at
-  // the top of its turn instead (with loads ahead they take 162 to 185
-  // registers and drop to 2 waves per SIMD on a composite side).
+  // the top of its turn instead (with loads ahead they take 168 to 179
+  // registers and drop to 2 waves per SIMD, or spill when held to 3).
   constexpr bool kAhead = sizeof(R) == 4 || S == 1;
   double rnorm2 = 0.0, dmax = 0.0, rz = 0.0;
   bool run = false;
@@ -1617,7 +1617,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
   // registers), so a workgroup waits on memory about once per tile.  Stacks
   // of two: FP32 as single tiles without the overlap with the stencil,
   // FP64 each stack at the top of its turn (with the first in flight during
-  // the reduction the kernel takes 216 registers, 2 waves per SIMD).
+  // the reduction the kernel takes 208 registers, 2 waves per SIMD).
   R hr[ST::HPT], hw[ST::HPT], hs[ST::HPT], hd[ST::HPT], kr[ST::EPT];
   R o_r[S], o_w[S], o_di[S], o_d[S], o_s[S], o_p[S], o_x[S];
   int o_n[S];
@@ -1626,11 +1626,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < ST::HPT; ++q) {
       const int h = threadIdx.x + q * kBlock;
-      // (a composite fine side keeps the ghost loads: the extra tests
-      // would take it past 168 registers, to 2 waves per SIMD)
-      const int n = h >= ST::HN ? -1
-                    : CP == kFineSide ? halo_index(g, t, h)
-                                      : halo_index_real(g, t, h);
+      const int n = h < ST::HN ? halo_index_real(g, t, h) : -1;
       int fi, fj, fk;
       if (CP == kFineSide && n >= 0 &&
           halo_gamma(g, it.cp.w, t, h, fi, fj, fk)) {
@@ -1662,9 +1658,7 @@ cg_iter_batched_kernel(const SolveItem* __restrict__ items, int per_item,
 #pragma unroll
     for (int q = 0; q < ST::EPT; ++q) {
       const int e = threadIdx.x + q * kBlock;
-      const int n = e >= ST::EN ? -1
-                    : CP == kFineSide ? elem_index(g, t, e)
-                                      : elem_index_real(g, t, e);
+      const int n = e < ST::EN ? elem_index_real(g, t, e) : -1;
       kr[q] = n >= 0 ? *at(kap, n) : (R)0;
     }
 #pragma unroll
