@@ -30,7 +30,8 @@ namespace tl {
 // per lane, and every such load counted against the LDS counter as well,
 // so that a wait for an LDS result also waits for the loads in flight.
 // Taken as global-address-space pointers they compile to global loads and
-// stores (a scalar base plus a 32-bit offset per lane).
+// stores, which count against the vector-memory counter only, and uniform
+// reads of an item's state to scalar loads.
 template <class T>
 using gptr = __attribute__((address_space(1))) T*;
 template <class T>
