@@ -1603,7 +1603,9 @@ tl_status validate(const tl_mesh* me, const tl_material* ma,
       me->win_nx > me->nx || me->win_ny > me->ny || me->win_nz > me->nz)
     return fail(TL_EINVAL, "window must fit inside the plate");
   // padded node counts in floating point (no integer overflow for any
-  // input); every index of a grid below the limit fits an int
+  // input); every index of a grid below the limit fits an int, and every
+  // byte offset into one of its FP64 arrays fits the 32-bit offsets the
+  // batched kernels address their arrays with (2e8 x 8 B < 2^32)
   auto padded = [](double nx, double ny, double nz) {
     return (std::floor((nx + 34.0) / 32.0) * 32.0) * (ny + 3.0) * (nz + 3.0);
   };
